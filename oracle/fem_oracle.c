@@ -1,0 +1,395 @@
+/*
+ * fem_oracle.c -- plain FP64 reference integrator for P1 element residuals.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark may load this file's library. The product path
+ * (the HIP library) never calls it, and the two share no code, headers or
+ * tables.
+ *
+ * What it computes (paper, Section 2 "Formulation", Eq. (2), the bracket
+ * before assembly): for every element e
+ *
+ *     R_e = B^T W f0(u^q, grad u^q) + sum_k D_k^T W f1^k(u^q, grad u^q)
+ *
+ * with u^q and grad u^q evaluated at the quadrature points from tabulated
+ * basis values, f0/f1 the pointwise physics, and W the quadrature weights
+ * times |det J|. Everything is FP64, in plain loops, in that order: geometry,
+ * then per quadrature point (field values, physics, weighting), then the sum
+ * back onto the basis functions. No blocking, no fusion, no P1 shortcut:
+ * gradients are recomputed from the tabulation at every quadrature point.
+ *
+ * Readings where the paper is silent (they are the conventions of this
+ * project):
+ *  - reference element: unit simplex {xi >= 0, sum xi <= 1}, basis
+ *    phi_0 = 1 - sum xi, phi_k = xi_k (k = 1..d);
+ *  - J[i][k] = (x_k - x_0)_i, the inverse is stored row-major
+ *    invJ[k][i] = d xi_k / d x_i, and physical gradients are J^{-T} grad phi;
+ *  - the measure factor is |det J|;
+ *  - rules: triangle, three points with barycentric (2/3, 1/6, 1/6) and its
+ *    permutations (point q has 2/3 at vertex q), weights 1/6; tetrahedron,
+ *    four points with barycentric (a, b, b, b), a = (5 + 3 sqrt 5)/20,
+ *    b = (5 - sqrt 5)/20 (point q has a at vertex q), weights 1/24;
+ *    centroid rule, one point, weight 1/d!;
+ *  - physics: Laplacian f1 = kappa grad u (Section 2; f0 = 0);
+ *    linear elasticity f1 = lambda tr(eps) I + 2 mu eps, eps the symmetric
+ *    gradient (the paper's Lame function in Section 6 is lambda = 0,
+ *    mu = 1/2); mass/reaction f0 = kappa u, f1 = 0;
+ *  - coefficients live on quadrature points (Section 5 allows this on the
+ *    CPU side).
+ *
+ * Adjoint: L = sum_e w_e . R_e is linear in u for fixed coefficients and
+ * linear in the coefficients for fixed u, so dL/du_j = w . R(u = unit_j) and
+ * dL/dcoef_{m,q} = w . R(coef = unit_{m,q}) hold exactly; the oracle computes
+ * the adjoint that way, from the forward definition alone.
+ *
+ * "absmode" evaluates the same sums with |.| applied to every factor; the
+ * result bounds every partial sum and is the scale of the rounding-error
+ * measure used by the parity tests.
+ *
+ * Layouts (structure of arrays, n = n_elem):
+ *   coords [n_vert][dim], conn [n_elem][dim+1] (0-based),
+ *   inv_j [dim*dim][n] (row k*dim+i), det_j [n],
+ *   u, w, elem_vec [N_b*N_comp][n] (row b*N_comp+c),
+ *   coef [N_coef][N_q][n].
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#define OR_MAXD 3
+#define OR_MAXB 4
+#define OR_MAXQ 4
+#define OR_MAXC 3
+#define OR_MAXCOEF 2
+
+enum { OR_LAPLACE = 0, OR_ELASTICITY = 1, OR_MASS = 2 };
+enum { OR_RULE_TRI3 = 0, OR_RULE_TET4 = 1, OR_RULE_CENTROID = 2 };
+
+int fem_oracle_n_qpts(int dim, int rule)
+{
+    if (dim != 2 && dim != 3) return -1;
+    if (rule == OR_RULE_TRI3) return dim == 2 ? 3 : -1;
+    if (rule == OR_RULE_TET4) return dim == 3 ? 4 : -1;
+    if (rule == OR_RULE_CENTROID) return 1;
+    return -1;
+}
+
+/* Quadrature points xi[q][dim] on the unit simplex and weights wts[q].
+ * Returns the number of points, or -1 for an unknown (dim, rule). */
+int fem_oracle_rule(int dim, int rule, double *xi, double *wts)
+{
+    int nq = fem_oracle_n_qpts(dim, rule);
+    if (nq < 0) return -1;
+    double lam[OR_MAXQ][OR_MAXB];
+    double w = 0.0;
+    for (int q = 0; q < nq; ++q) {
+        for (int b = 0; b <= dim; ++b) {
+            if (rule == OR_RULE_TRI3)
+                lam[q][b] = (b == q) ? 2.0 / 3.0 : 1.0 / 6.0;
+            else if (rule == OR_RULE_TET4)
+                lam[q][b] = (b == q) ? (5.0 + 3.0 * sqrt(5.0)) / 20.0 : (5.0 - sqrt(5.0)) / 20.0;
+            else
+                lam[q][b] = 1.0 / (double)(dim + 1);
+        }
+    }
+    if (rule == OR_RULE_TRI3) w = 1.0 / 6.0;
+    else if (rule == OR_RULE_TET4) w = 1.0 / 24.0;
+    else w = (dim == 2) ? 0.5 : 1.0 / 6.0;
+    for (int q = 0; q < nq; ++q) {
+        /* reference coordinates are the barycentric weights of vertices 1..d */
+        for (int k = 0; k < dim; ++k) xi[q * dim + k] = lam[q][k + 1];
+        wts[q] = w;
+    }
+    return nq;
+}
+
+/* Tabulation of the P1 basis at the quadrature points:
+ * B[q][b] = phi_b(xi_q), D[q][b][k] = d phi_b / d xi_k (xi_q). */
+typedef struct {
+    int dim, nb, nq;
+    double w[OR_MAXQ];
+    double B[OR_MAXQ][OR_MAXB];
+    double D[OR_MAXQ][OR_MAXB][OR_MAXD];
+} or_tab;
+
+static int or_tabulate(int dim, int rule, or_tab *t)
+{
+    double xi[OR_MAXQ * OR_MAXD];
+    int nq = fem_oracle_rule(dim, rule, xi, t->w);
+    if (nq < 0) return -1;
+    t->dim = dim;
+    t->nb = dim + 1;
+    t->nq = nq;
+    for (int q = 0; q < nq; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < dim; ++k) s += xi[q * dim + k];
+        t->B[q][0] = 1.0 - s;
+        for (int b = 1; b <= dim; ++b) t->B[q][b] = xi[q * dim + (b - 1)];
+        for (int k = 0; k < dim; ++k) {
+            t->D[q][0][k] = -1.0;
+            for (int b = 1; b <= dim; ++b) t->D[q][b][k] = (b - 1 == k) ? 1.0 : 0.0;
+        }
+    }
+    return nq;
+}
+
+static int or_ncomp(int dim, int physics) { return physics == OR_ELASTICITY ? dim : 1; }
+static int or_ncoef(int physics) { return physics == OR_ELASTICITY ? 2 : 1; }
+static int or_physics_ok(int physics)
+{
+    return physics == OR_LAPLACE || physics == OR_ELASTICITY || physics == OR_MASS;
+}
+
+/* Pointwise physics at one quadrature point.
+ * uq[c], gu[c][i] = d u_c / d x_i, cq[m] = coefficient m at this point.
+ * Outputs f0[c] and f1[c][i]. In absmode every input is already >= 0. */
+static void or_physics(int dim, int physics, const double *uq, double gu[OR_MAXC][OR_MAXD],
+                       const double *cq, double *f0, double f1[OR_MAXC][OR_MAXD])
+{
+    int nc = or_ncomp(dim, physics);
+    for (int c = 0; c < nc; ++c) {
+        f0[c] = 0.0;
+        for (int i = 0; i < dim; ++i) f1[c][i] = 0.0;
+    }
+    if (physics == OR_LAPLACE) {
+        for (int i = 0; i < dim; ++i) f1[0][i] = cq[0] * gu[0][i];
+    } else if (physics == OR_ELASTICITY) {
+        double eps[OR_MAXC][OR_MAXD];
+        double tr = 0.0;
+        for (int c = 0; c < dim; ++c)
+            for (int i = 0; i < dim; ++i) eps[c][i] = 0.5 * (gu[c][i] + gu[i][c]);
+        for (int i = 0; i < dim; ++i) tr += eps[i][i];
+        for (int c = 0; c < dim; ++c)
+            for (int i = 0; i < dim; ++i)
+                f1[c][i] = (c == i ? cq[0] * tr : 0.0) + 2.0 * cq[1] * eps[c][i];
+    } else { /* OR_MASS */
+        f0[0] = cq[0] * uq[0];
+    }
+}
+
+/* Residual of one element (Eq. (2) bracket).
+ * ij[k][i] = invJ, sdet = |det J|, ub[b][c] nodal values, cf[m][q] coefficients.
+ * R[b][c] is overwritten. */
+static void or_element(const or_tab *t, int physics, double ij[OR_MAXD][OR_MAXD], double sdet,
+                       double ub[OR_MAXB][OR_MAXC], double cf[OR_MAXCOEF][OR_MAXQ],
+                       double R[OR_MAXB][OR_MAXC], int absmode)
+{
+    int dim = t->dim, nb = t->nb;
+    int nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < nc; ++c) R[b][c] = 0.0;
+    for (int q = 0; q < t->nq; ++q) {
+        double G[OR_MAXB][OR_MAXD];   /* physical basis gradients J^{-T} grad phi_b */
+        double Bq[OR_MAXB];
+        for (int b = 0; b < nb; ++b) {
+            Bq[b] = absmode ? fabs(t->B[q][b]) : t->B[q][b];
+            for (int i = 0; i < dim; ++i) {
+                double g = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double d = absmode ? fabs(t->D[q][b][k]) : t->D[q][b][k];
+                    g += ij[k][i] * d;
+                }
+                G[b][i] = g;
+            }
+        }
+        double uq[OR_MAXC], gu[OR_MAXC][OR_MAXD];
+        for (int c = 0; c < nc; ++c) {
+            uq[c] = 0.0;
+            for (int b = 0; b < nb; ++b) uq[c] += Bq[b] * ub[b][c];
+            for (int i = 0; i < dim; ++i) {
+                gu[c][i] = 0.0;
+                for (int b = 0; b < nb; ++b) gu[c][i] += ub[b][c] * G[b][i];
+            }
+        }
+        double cq[OR_MAXCOEF] = {0.0, 0.0};
+        for (int m = 0; m < ncoef; ++m) cq[m] = cf[m][q];
+        double f0[OR_MAXC], f1[OR_MAXC][OR_MAXD];
+        or_physics(dim, physics, uq, gu, cq, f0, f1);
+        double s = t->w[q] * sdet;
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) {
+                double v = Bq[b] * f0[c];
+                for (int i = 0; i < dim; ++i) v += G[b][i] * f1[c][i];
+                R[b][c] += s * v;
+            }
+    }
+}
+
+/* Affine geometry of one element from its vertices.
+ * x[b][i] vertex coordinates. Returns det J; fills ij[k][i] = (J^{-1})[k][i]. */
+static double or_geometry_one(int dim, double x[OR_MAXB][OR_MAXD], double ij[OR_MAXD][OR_MAXD])
+{
+    double J[OR_MAXD][OR_MAXD] = {{0.0}};
+    for (int i = 0; i < dim; ++i)
+        for (int k = 0; k < dim; ++k) J[i][k] = x[k + 1][i] - x[0][i];
+    double det;
+    if (dim == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        ij[0][0] = J[1][1] / det;
+        ij[0][1] = -J[0][1] / det;
+        ij[1][0] = -J[1][0] / det;
+        ij[1][1] = J[0][0] / det;
+    } else {
+        /* cofactors C[i][k] of J; inverse = C^T / det */
+        double C[3][3];
+        C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+        C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+        C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+        C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+        C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 3; ++i) ij[k][i] = C[i][k] / det;
+    }
+    return det;
+}
+
+/* Geometry for all elements. Returns the number of degenerate elements
+ * (det J == 0 or not finite), or -1 on bad arguments / out-of-range vertex. */
+int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const double *coords,
+                            const int32_t *conn, double *inv_j, double *det_j)
+{
+    if ((dim != 2 && dim != 3) || n_elem < 0 || n_vert < 0) return -1;
+    int nb = dim + 1;
+    int64_t ndeg = 0;
+    for (int64_t e = 0; e < n_elem; ++e) {
+        double x[OR_MAXB][OR_MAXD], ij[OR_MAXD][OR_MAXD];
+        for (int b = 0; b < nb; ++b) {
+            int64_t v = conn[e * nb + b];
+            if (v < 0 || v >= n_vert) return -1;
+            for (int i = 0; i < dim; ++i) x[b][i] = coords[v * dim + i];
+        }
+        double det = or_geometry_one(dim, x, ij);
+        if (det == 0.0 || !isfinite(det)) ++ndeg;
+        for (int k = 0; k < dim; ++k)
+            for (int i = 0; i < dim; ++i) inv_j[(int64_t)(k * dim + i) * n_elem + e] = ij[k][i];
+        det_j[e] = det;
+    }
+    return ndeg;
+}
+
+/* Element residuals from precomputed geometry. Returns 0, or -1 on bad
+ * arguments. absmode != 0 gives the absolute-value bound described above. */
+int fem_oracle_integrate(int dim, int physics, int rule, int64_t n_elem, const double *inv_j,
+                         const double *det_j, const double *u, const double *coef,
+                         double *elem_vec, int absmode)
+{
+    or_tab t;
+    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
+    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int64_t n = n_elem;
+    for (int64_t e = 0; e < n; ++e) {
+        double ij[OR_MAXD][OR_MAXD], ub[OR_MAXB][OR_MAXC], cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        for (int k = 0; k < dim; ++k)
+            for (int i = 0; i < dim; ++i) {
+                double v = inv_j[(int64_t)(k * dim + i) * n + e];
+                ij[k][i] = absmode ? fabs(v) : v;
+            }
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) {
+                double v = u[(int64_t)(b * nc + c) * n + e];
+                ub[b][c] = absmode ? fabs(v) : v;
+            }
+        for (int m = 0; m < ncoef; ++m)
+            for (int q = 0; q < nq; ++q) {
+                double v = coef[(int64_t)(m * nq + q) * n + e];
+                cf[m][q] = absmode ? fabs(v) : v;
+            }
+        or_element(&t, physics, ij, fabs(det_j[e]), ub, cf, R, absmode);
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) elem_vec[(int64_t)(b * nc + c) * n + e] = R[b][c];
+    }
+    return 0;
+}
+
+/* Coordinates and connectivity to element residuals, one element at a time
+ * (geometry, then integration). Returns the number of degenerate elements,
+ * or -1 on bad arguments. */
+int64_t fem_oracle_residual(int dim, int physics, int rule, int64_t n_elem, int64_t n_vert,
+                            const double *coords, const int32_t *conn, const double *u,
+                            const double *coef, double *elem_vec)
+{
+    or_tab t;
+    if (!or_physics_ok(physics) || n_elem < 0 || n_vert < 0 || or_tabulate(dim, rule, &t) < 0)
+        return -1;
+    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int64_t n = n_elem, ndeg = 0;
+    for (int64_t e = 0; e < n; ++e) {
+        double x[OR_MAXB][OR_MAXD], ij[OR_MAXD][OR_MAXD];
+        double ub[OR_MAXB][OR_MAXC], cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        for (int b = 0; b < nb; ++b) {
+            int64_t v = conn[e * nb + b];
+            if (v < 0 || v >= n_vert) return -1;
+            for (int i = 0; i < dim; ++i) x[b][i] = coords[v * dim + i];
+        }
+        double det = or_geometry_one(dim, x, ij);
+        if (det == 0.0 || !isfinite(det)) ++ndeg;
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) ub[b][c] = u[(int64_t)(b * nc + c) * n + e];
+        for (int m = 0; m < ncoef; ++m)
+            for (int q = 0; q < nq; ++q) cf[m][q] = coef[(int64_t)(m * nq + q) * n + e];
+        or_element(&t, physics, ij, fabs(det), ub, cf, R, 0);
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) elem_vec[(int64_t)(b * nc + c) * n + e] = R[b][c];
+    }
+    return ndeg;
+}
+
+/* Adjoint of L = sum_e w_e . R_e. du [N_bt][n] and dcoef [N_coef][N_q][n]
+ * may each be NULL. Returns 0, or -1 on bad arguments. */
+int fem_oracle_backward(int dim, int physics, int rule, int64_t n_elem, const double *inv_j,
+                        const double *det_j, const double *u, const double *coef,
+                        const double *w, double *du, double *dcoef)
+{
+    or_tab t;
+    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
+    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int64_t n = n_elem;
+    for (int64_t e = 0; e < n; ++e) {
+        double ij[OR_MAXD][OR_MAXD], ub[OR_MAXB][OR_MAXC], wb[OR_MAXB][OR_MAXC];
+        double cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        for (int k = 0; k < dim; ++k)
+            for (int i = 0; i < dim; ++i) ij[k][i] = inv_j[(int64_t)(k * dim + i) * n + e];
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) {
+                ub[b][c] = u[(int64_t)(b * nc + c) * n + e];
+                wb[b][c] = w[(int64_t)(b * nc + c) * n + e];
+            }
+        for (int m = 0; m < ncoef; ++m)
+            for (int q = 0; q < nq; ++q) cf[m][q] = coef[(int64_t)(m * nq + q) * n + e];
+        double sdet = fabs(det_j[e]);
+        if (du) {
+            /* dL/du_j = w . R(unit_j): R is linear in u */
+            for (int j = 0; j < nb * nc; ++j) {
+                double unit[OR_MAXB][OR_MAXC];
+                for (int b = 0; b < nb; ++b)
+                    for (int c = 0; c < nc; ++c) unit[b][c] = (b * nc + c == j) ? 1.0 : 0.0;
+                or_element(&t, physics, ij, sdet, unit, cf, R, 0);
+                double s = 0.0;
+                for (int b = 0; b < nb; ++b)
+                    for (int c = 0; c < nc; ++c) s += wb[b][c] * R[b][c];
+                du[(int64_t)j * n + e] = s;
+            }
+        }
+        if (dcoef) {
+            /* dL/dcoef_{m,q} = w . R(coef = unit_{m,q}): R is linear in the coefficients */
+            for (int m = 0; m < ncoef; ++m)
+                for (int q = 0; q < nq; ++q) {
+                    double unit[OR_MAXCOEF][OR_MAXQ];
+                    for (int mm = 0; mm < ncoef; ++mm)
+                        for (int qq = 0; qq < nq; ++qq) unit[mm][qq] = (mm == m && qq == q) ? 1.0 : 0.0;
+                    or_element(&t, physics, ij, sdet, ub, unit, R, 0);
+                    double s = 0.0;
+                    for (int b = 0; b < nb; ++b)
+                        for (int c = 0; c < nc; ++c) s += wb[b][c] * R[b][c];
+                    dcoef[(int64_t)(m * nq + q) * n + e] = s;
+                }
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,142 @@
+"""ctypes front end of the FP64 reference integrator (fem_oracle.c).
+
+TEST INFRASTRUCTURE: see the package docstring. Arrays use the library's
+structure-of-arrays layouts: inv_j [d*d][n], det_j [n], u/w/R [N_bt][n],
+coef [N_coef][N_q][n]; coords [n_vert][d] and conn [n][d+1].
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import numpy as np
+
+_LIB = None
+_HERE = pathlib.Path(__file__).resolve().parent
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def load():
+    global _LIB
+    if _LIB is None:
+        path = _HERE / "liboracle.so"
+        if not path.exists():
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(str(path))
+        lib.fem_oracle_n_qpts.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.fem_oracle_n_qpts.restype = ctypes.c_int
+        lib.fem_oracle_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        lib.fem_oracle_rule.restype = ctypes.c_int
+        lib.fem_oracle_geometry.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _dp, _ip, _dp, _dp]
+        lib.fem_oracle_geometry.restype = ctypes.c_int64
+        lib.fem_oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                             _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.fem_oracle_integrate.restype = ctypes.c_int
+        lib.fem_oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                            ctypes.c_int64, _dp, _ip, _dp, _dp, _dp]
+        lib.fem_oracle_residual.restype = ctypes.c_int64
+        lib.fem_oracle_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                            _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.fem_oracle_backward.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _ncomp(dim, physics):
+    return dim if physics == 1 else 1
+
+
+def _ncoef(physics):
+    return 2 if physics == 1 else 1
+
+
+def n_qpts(dim: int, rule: int) -> int:
+    n = load().fem_oracle_n_qpts(dim, rule)
+    if n < 0:
+        raise ValueError(f"no rule {rule} in {dim}D")
+    return n
+
+
+def rule(dim: int, rule_id: int):
+    """(xi[N_q, dim], weights[N_q]) of a quadrature rule on the unit simplex."""
+    nq = n_qpts(dim, rule_id)
+    xi = np.zeros((nq, dim))
+    w = np.zeros(nq)
+    load().fem_oracle_rule(dim, rule_id, _p(xi), _p(w))
+    return xi, w
+
+
+def geometry(coords, conn):
+    """(inv_j[d*d, n], det_j[n], n_degenerate) in FP64."""
+    coords, conn = _f64(coords), _i32(conn)
+    dim = coords.shape[1]
+    n = conn.shape[0]
+    inv_j = np.zeros((dim * dim, n))
+    det_j = np.zeros(n)
+    r = load().fem_oracle_geometry(dim, n, coords.shape[0], _p(coords), _p(conn, _ip), _p(inv_j), _p(det_j))
+    if r < 0:
+        raise ValueError("oracle geometry: bad arguments or vertex index out of range")
+    return inv_j, det_j, int(r)
+
+
+def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode):
+    inv_j, det_j, u, coef = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef)
+    n = det_j.shape[0]
+    nb = dim + 1
+    R = np.zeros((nb * _ncomp(dim, physics), n))
+    r = load().fem_oracle_integrate(dim, physics, rule_id, n, _p(inv_j), _p(det_j), _p(u), _p(coef),
+                                    _p(R), int(absmode))
+    if r != 0:
+        raise ValueError("oracle integrate: bad arguments")
+    return R
+
+
+def integrate(dim, physics, rule_id, inv_j, det_j, u, coef):
+    """Element residuals R[N_bt, n] from precomputed geometry (Eq. (2) bracket)."""
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False)
+
+
+def integrate_abs(dim, physics, rule_id, inv_j, det_j, u, coef):
+    """Same sums with |.| on every factor: the scale of the rounding measure."""
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, True)
+
+
+def residual(dim, physics, rule_id, coords, conn, u, coef):
+    """Coordinates/connectivity to residuals R[N_bt, n]; returns (R, n_degenerate)."""
+    coords, conn, u, coef = _f64(coords), _i32(conn), _f64(u), _f64(coef)
+    n = conn.shape[0]
+    R = np.zeros(((dim + 1) * _ncomp(dim, physics), n))
+    r = load().fem_oracle_residual(dim, physics, rule_id, n, coords.shape[0], _p(coords), _p(conn, _ip),
+                                   _p(u), _p(coef), _p(R))
+    if r < 0:
+        raise ValueError("oracle residual: bad arguments")
+    return R, int(r)
+
+
+def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want_dcoef=True):
+    """Adjoint of L = sum w.R: (du[N_bt, n] or None, dcoef[N_coef, N_q, n] or None)."""
+    inv_j, det_j, u, coef, w = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef), _f64(w)
+    n = det_j.shape[0]
+    nq = n_qpts(dim, rule_id)
+    du = np.zeros(((dim + 1) * _ncomp(dim, physics), n)) if want_du else None
+    dcoef = np.zeros((_ncoef(physics), nq, n)) if want_dcoef else None
+    r = load().fem_oracle_backward(dim, physics, rule_id, n, _p(inv_j), _p(det_j), _p(u), _p(coef), _p(w),
+                                   _p(du), _p(dcoef))
+    if r != 0:
+        raise ValueError("oracle backward: bad arguments")
+    return du, dcoef
