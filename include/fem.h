@@ -1,0 +1,215 @@
+/*
+ * fem.h -- C ABI of libfemq: P1 finite-element residual integration on
+ * AMD MI355X (gfx950).
+ *
+ * The library evaluates, for every element e of a simplex mesh, the element
+ * residual vector of the paper's Eq. (2) (Section 2, "Formulation"), before
+ * assembly:
+ *
+ *     R_e = B^T W f0(u^q, grad u^q) + sum_k D_k^T W f1^k(u^q, grad u^q),
+ *
+ * with u^q and grad u^q evaluated at quadrature points from tabulated P1
+ * basis values and W the quadrature weights times |det J|. The kernel inputs
+ * follow the paper's integration routine (Appendix): per-element geometry
+ * (inverse Jacobian and determinant), the element closure of u, and per
+ * element outputs. Auxiliary coefficients live on quadrature points
+ * (Section 5, "Variable Coefficients").
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are DEVICE pointers owned by the caller. The library
+ *    never allocates, frees or synchronizes on them (plans below own their
+ *    own descriptor memory).
+ *  - Layouts are structure of arrays over elements, n = n_elem:
+ *      inv_j   [dim*dim][n]  row k*dim+i holds d xi_k / d x_i (J^{-1}, row-major)
+ *      det_j   [n]           det J, signed; the measure factor is |det J|
+ *      u, w, elem_vec, du    [N_b*N_comp][n], row b*N_comp + c
+ *      coef, dcoef           [N_coef][N_q][n]
+ *    with N_b = dim+1, N_comp = 1 (Laplacian, mass) or dim (elasticity),
+ *    N_coef = 1 (kappa) or 2 (lambda, mu), N_q from the rule.
+ *    Real arrays are float (FEM_F32) or double (FEM_F64) as selected.
+ *  - Reference element: unit simplex, phi_0 = 1 - sum xi, phi_k = xi_k.
+ *    Rules: FEM_RULE_TRI3 (dim 2; barycentric (2/3,1/6,1/6), point q has 2/3
+ *    at vertex q; weights 1/6), FEM_RULE_TET4 (dim 3; (a,b,b,b) with
+ *    a = (5+3 sqrt 5)/20, point q has a at vertex q; weights 1/24),
+ *    FEM_RULE_CENTROID (one point, weight 1/dim!; the paper's N_q = 1 model).
+ *  - Inputs are read-only; outputs are fully overwritten (no accumulation),
+ *    except the counters of fem_geometry, which are added to.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Calls are
+ *    asynchronous on that stream.
+ *  - Arguments are validated before any HIP call: bad values give
+ *    FEM_ERR_INVALID_ARG or FEM_ERR_UNSUPPORTED with a message in
+ *    fem_last_error(). A failed launch gives FEM_ERR_HIP. n_elem == 0 returns
+ *    FEM_OK without launching. No C++ exception crosses this interface.
+ *  - Results do not depend on the launch configuration: each element's
+ *    arithmetic is fixed, so repeated calls are bitwise identical.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fem_status;
+
+#define FEM_OK 0
+#define FEM_ERR_INVALID_ARG (-1)
+#define FEM_ERR_UNSUPPORTED (-2)
+#define FEM_ERR_DEGENERATE (-3)
+#define FEM_ERR_HIP (-4)
+#define FEM_ERR_NO_TUNING (-5)
+
+enum fem_dtype { FEM_F32 = 0, FEM_F64 = 1 };
+
+/* Pointwise physics (paper Section 2 and Section 6):
+ *  FEM_LAPLACE     f0 = 0, f1 = kappa grad u                     (N_comp 1, N_coef 1)
+ *  FEM_ELASTICITY  f0 = 0, f1 = lambda tr(eps) I + 2 mu eps,
+ *                  eps = (grad u + grad u^T)/2; the paper's Lame
+ *                  function is lambda = 0, mu = 1/2             (N_comp dim, N_coef 2)
+ *  FEM_MASS        f0 = kappa u, f1 = 0 (exercises the B^T W f0 term)
+ *                                                                (N_comp 1, N_coef 1) */
+enum fem_physics { FEM_LAPLACE = 0, FEM_ELASTICITY = 1, FEM_MASS = 2 };
+
+enum fem_rule { FEM_RULE_TRI3 = 0, FEM_RULE_TET4 = 1, FEM_RULE_CENTROID = 2 };
+
+/* Kernel strategies (see fem_tuning).
+ *  FEM_STRATEGY_LANE       each lane owns whole elements; the quadrature and
+ *                          basis phases run in registers.
+ *  FEM_STRATEGY_TRANSPOSE  the paper's thread transposition (Section 3):
+ *                          lanes work per (element, quadrature point) in the
+ *                          quadrature phase, write weighted f0/f1 to LDS, and
+ *                          switch to one lane per (element, basis function)
+ *                          for the basis phase, with no cross-lane reduction. */
+enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1 };
+
+/* ------------------------------------------------------------------ */
+/* Geometry (paper Section 3: the kernel reads precomputed Jacobian    */
+/* inverses and determinants; this call produces them).                */
+/* ------------------------------------------------------------------ */
+
+/* For each element, gather its dim+1 vertices, form J[i][k] = (x_k - x_0)_i,
+ * and write det J and J^{-1}. Arithmetic is FP64 for both output types; for
+ * FEM_F32 the results are rounded once at the store.
+ *   coords [n_vert][dim] double, conn [n_elem][dim+1] int32 (0-based).
+ *   counts, if not NULL, points to 2 int32 on the device that are ADDED to:
+ *     counts[0] += elements with det J == 0, non-finite, or a vertex index
+ *                  outside [0, n_vert) (these get NaN geometry, and no
+ *                  out-of-range coordinate is read);
+ *     counts[1] += poorly shaped elements, |det J| < 1e-3 prod_k |J[:,k]|.
+ * Errors: FEM_ERR_INVALID_ARG (dim not 2/3, negative sizes, NULL arrays with
+ * n_elem > 0, n_vert == 0 with n_elem > 0), FEM_ERR_UNSUPPORTED (dtype),
+ * FEM_ERR_HIP. */
+fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* coords,
+                        const int32_t* conn, int out_dtype, void* inv_j, void* det_j,
+                        int32_t* counts, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Residual (paper Eq. (2); Section 3 quadrature and basis phases).    */
+/* ------------------------------------------------------------------ */
+
+/* elem_vec = per-element residual R_e as defined at the top of this file.
+ * Errors: FEM_ERR_INVALID_ARG (negative n_elem, NULL arrays with
+ * n_elem > 0), FEM_ERR_UNSUPPORTED (dim/physics/rule/dtype combination),
+ * FEM_ERR_HIP. */
+fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int64_t n_elem,
+                                  const void* inv_j, const void* det_j, const void* u,
+                                  const void* coef, void* elem_vec, void* stream);
+
+/* Adjoint of L = sum_e w_e . R_e (not in the paper; the gradient of the
+ * residual for automatic differentiation):
+ *   du    = dL/du     [N_bt][n]           (may be NULL: not computed)
+ *   dcoef = dL/dcoef  [N_coef][N_q][n]    (may be NULL: not computed)
+ * All three physics are symmetric bilinear forms in (u, test function), so
+ * du_e = R_e evaluated with u replaced by w_e; dcoef at point q is the
+ * weighted pointwise derivative, e.g. w_q |det J| grad u . grad w for the
+ * Laplacian. u is not read when dcoef is NULL.
+ * Errors as fem_integrate_residual. */
+fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int dtype,
+                                           int64_t n_elem, const void* inv_j, const void* det_j,
+                                           const void* u, const void* coef, const void* w,
+                                           void* du, void* dcoef, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Batched persistent launch over many meshes (not in the paper; its   */
+/* nearest analog is the assignment of cell chunks to thread blocks,   */
+/* Section 3).                                                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct fem_mesh_desc {
+    int dim, physics, rule;
+    int64_t n_elem;
+    const void* inv_j;
+    const void* det_j;
+    const void* u;
+    const void* coef;
+    void* elem_vec;
+} fem_mesh_desc;
+
+typedef struct fem_batch_plan fem_batch_plan;
+
+/* Copies the descriptors (the arrays they point to stay owned by the
+ * caller and must outlive the plan) into device memory owned by the plan,
+ * and builds the tile list. All meshes share one dtype. The plan is bound to
+ * the device current at creation. */
+fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dtype,
+                                 fem_batch_plan** out);
+/* One persistent launch covering every mesh, on `stream`. */
+fem_status fem_batch_run(fem_batch_plan* plan, void* stream);
+/* Record the persistent launch into a HIP graph (captured on `stream`, which
+ * must not be capturing already) and instantiate it. */
+fem_status fem_batch_capture(fem_batch_plan* plan, void* stream);
+/* Launch the instantiated graph on `stream`; FEM_ERR_INVALID_ARG if not
+ * captured. */
+fem_status fem_batch_replay(fem_batch_plan* plan, void* stream);
+/* Frees the plan's device memory and graph. Safe on NULL. */
+void fem_batch_plan_destroy(fem_batch_plan* plan);
+
+/* ------------------------------------------------------------------ */
+/* Launch configuration and autotuning (analog of the paper's sweep of  */
+/* blocks per batch and batches per chunk, Section 6, Table 2).         */
+/* ------------------------------------------------------------------ */
+
+typedef struct fem_tuning {
+    int strategy;        /* enum fem_strategy */
+    int vec;             /* elements per lane in the coalesced load/store phases: 1, 2 or 4 */
+    int waves_per_block; /* 1, 2, 4 or 8 (wave64) */
+    int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */
+} fem_tuning;
+
+/* The configuration used for (dim, physics, rule, dtype): the last one set
+ * or tuned in this process, else a built-in default. */
+fem_status fem_get_tuning(int dim, int physics, int rule, int dtype, fem_tuning* out);
+/* Override the configuration for (dim, physics, rule, dtype) in this process. */
+fem_status fem_set_tuning(int dim, int physics, int rule, int dtype, const fem_tuning* t);
+/* Sweep launch configurations on synthetic device data of n_elem_probe
+ * elements (allocated and freed here, on the current device), time each
+ * with HIP events, keep the fastest for this process, and, if cache_path is
+ * not NULL, merge it into that JSON cache file. Synchronizes the device. */
+fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_elem_probe,
+                        const char* cache_path);
+/* Load tuned configurations from a JSON cache written by fem_autotune.
+ * Returns FEM_ERR_NO_TUNING if the file is missing or holds no entry for
+ * this device's architecture (defaults stay in force). */
+fem_status fem_load_tuning(const char* cache_path);
+
+/* ------------------------------------------------------------------ */
+/* Measurement helpers                                                  */
+/* ------------------------------------------------------------------ */
+
+/* dst[0..n_bytes) = src[0..n_bytes) with a plain streaming copy kernel
+ * (16-byte vector loads and stores; n_bytes and both pointers must be
+ * multiples of 16). Used to measure the achievable HBM bandwidth and to
+ * calibrate hardware byte counters. */
+fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* fem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_H */

@@ -1,0 +1,105 @@
+"""ctypes loader of libfemq.so (the HIP library behind include/fem.h).
+
+The library is loaded on first use. If it has not been built this raises: the
+package has no other compute path. torch is imported first so that the HIP
+runtime torch ships is the one the library binds to (both name the same
+soname), which lets the library run on torch's streams and memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+import re
+
+LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfemq.so"
+HEADER = pathlib.Path(__file__).resolve().parents[1] / "include" / "fem.h"
+
+FEM_OK = 0
+FEM_ERR_INVALID_ARG = -1
+FEM_ERR_UNSUPPORTED = -2
+FEM_ERR_DEGENERATE = -3
+FEM_ERR_HIP = -4
+FEM_ERR_NO_TUNING = -5
+
+STATUS_NAMES = {0: "FEM_OK", -1: "FEM_ERR_INVALID_ARG", -2: "FEM_ERR_UNSUPPORTED",
+                -3: "FEM_ERR_DEGENERATE", -4: "FEM_ERR_HIP", -5: "FEM_ERR_NO_TUNING"}
+
+F32, F64 = 0, 1
+STRATEGY_LANE, STRATEGY_TRANSPOSE = 0, 1
+
+
+class FemError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class fem_tuning(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int), ("vec", ctypes.c_int),
+                ("waves_per_block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
+
+
+class fem_mesh_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("physics", ctypes.c_int), ("rule", ctypes.c_int),
+                ("n_elem", ctypes.c_int64),
+                ("inv_j", ctypes.c_void_p), ("det_j", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p), ("elem_vec", ctypes.c_void_p)]
+
+
+_c = ctypes
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+
+SIGNATURES = {
+    "fem_geometry": (_i, [_i, _i64, _i64, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
+    "fem_batch_run": (_i, [_vp, _vp]),
+    "fem_batch_capture": (_i, [_vp, _vp]),
+    "fem_batch_replay": (_i, [_vp, _vp]),
+    "fem_batch_plan_destroy": (None, [_vp]),
+    "fem_get_tuning": (_i, [_i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
+    "fem_set_tuning": (_i, [_i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
+    "fem_autotune": (_i, [_i, _i, _i, _i, _i64, ctypes.c_char_p]),
+    "fem_load_tuning": (_i, [ctypes.c_char_p]),
+    "fem_stream_copy": (_i, [_vp, _vp, _i64, _vp]),
+    "fem_last_error": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/fem.h declares."""
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(there is no fallback compute path)")
+        import torch  # noqa: F401  -- bind to torch's HIP runtime
+        lib_ = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib_, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib_
+    return _LIB
+
+
+def last_error() -> str:
+    msg = lib().fem_last_error()
+    return msg.decode() if msg else ""
+
+
+def check(status: int, what: str = "") -> int:
+    if status != FEM_OK:
+        raise FemError(status, f"{what}: {last_error()}" if what else last_error())
+    return status

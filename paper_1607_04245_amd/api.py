@@ -1,0 +1,245 @@
+"""Python binding of the libfemq C ABI (include/fem.h): argument marshalling.
+
+The ``fem_*`` functions mirror the C entry points one to one and take torch
+tensors on the GPU; every step of the computation runs in the HIP library on
+the current torch stream. Output tensors may be passed in (no allocation) or
+are allocated with torch (plumbing only).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as N
+from .meshgen import ELASTICITY
+
+_DT = {torch.float32: N.F32, torch.float64: N.F64}
+_TORCH_DT = {N.F32: torch.float32, N.F64: torch.float64}
+
+
+def n_comp(dim: int, physics: int) -> int:
+    return dim if physics == ELASTICITY else 1
+
+
+def n_coef(physics: int) -> int:
+    return 2 if physics == ELASTICITY else 1
+
+
+def n_qpts(dim: int, rule: int) -> int:
+    return 1 if rule == 2 else dim + 1
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU (libfemq has no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def fem_geometry(coords: torch.Tensor, conn: torch.Tensor, dtype=torch.float32, inv_j=None, det_j=None,
+                 counts=None):
+    """(inv_j [d*d, n], det_j [n]) from coords [n_vert, d] float64 and conn [n, d+1] int32.
+
+    ``counts`` (int32 [2] on the GPU, added to) receives the number of
+    degenerate and of poorly shaped elements.
+    """
+    _need(coords, "coords", torch.float64)
+    dim = coords.shape[1]
+    _need(conn, "conn", torch.int32)
+    if conn.dim() != 2 or conn.shape[1] != dim + 1:
+        raise ValueError(f"conn must be [n_elem, {dim + 1}]")
+    n = conn.shape[0]
+    if inv_j is None:
+        inv_j = torch.empty((dim * dim, n), dtype=dtype, device=coords.device)
+    if det_j is None:
+        det_j = torch.empty((n,), dtype=dtype, device=coords.device)
+    _need(inv_j, "inv_j", dtype, (dim * dim, n))
+    _need(det_j, "det_j", dtype, (n,))
+    if counts is not None:
+        _need(counts, "counts", torch.int32, (2,))
+    N.check(N.lib().fem_geometry(dim, n, coords.shape[0], _ptr(coords), _ptr(conn), _DT[dtype], _ptr(inv_j),
+                                 _ptr(det_j), _ptr(counts), _stream()), "fem_geometry")
+    return inv_j, det_j
+
+
+def _shapes(dim, physics, rule, n):
+    nbt = (dim + 1) * n_comp(dim, physics)
+    return (dim * dim, n), (n,), (nbt, n), (n_coef(physics), n_qpts(dim, rule), n)
+
+
+def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, out=None):
+    """Element residuals R [N_bt, n] (paper Eq. (2), before assembly)."""
+    dtype = det_j.dtype
+    if dtype not in _DT:
+        raise TypeError("geometry must be float32 or float64")
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(u, "u", dtype, su)
+    _need(coef, "coef", dtype, scf)
+    if out is None:
+        out = torch.empty(su, dtype=dtype, device=u.device)
+    _need(out, "out", dtype, su)
+    N.check(N.lib().fem_integrate_residual(dim, physics, rule, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u),
+                                           _ptr(coef), _ptr(out), _stream()), "fem_integrate_residual")
+    return out
+
+
+def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
+                                    want_du=True, want_dcoef=True, du=None, dcoef=None):
+    """(du [N_bt, n] or None, dcoef [N_coef, N_q, n] or None) for L = sum w . R."""
+    dtype = det_j.dtype
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(w, "w", dtype, su)
+    if want_du:
+        _need(coef, "coef", dtype, scf)
+        if du is None:
+            du = torch.empty(su, dtype=dtype, device=w.device)
+        _need(du, "du", dtype, su)
+    else:
+        du = None
+    if want_dcoef:
+        _need(u, "u", dtype, su)
+        if dcoef is None:
+            dcoef = torch.empty(scf, dtype=dtype, device=w.device)
+        _need(dcoef, "dcoef", dtype, scf)
+    else:
+        dcoef = None
+    N.check(N.lib().fem_integrate_residual_backward(
+        dim, physics, rule, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
+        _ptr(coef) if want_du else None, _ptr(w), _ptr(du), _ptr(dcoef), _stream()),
+        "fem_integrate_residual_backward")
+    return du, dcoef
+
+
+def fem_stream_copy(src: torch.Tensor, dst: torch.Tensor):
+    _need(src, "src")
+    _need(dst, "dst")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    N.check(N.lib().fem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream()), "fem_stream_copy")
+
+
+# ------------------------------------------------------------------ tuning --
+
+def fem_get_tuning(dim, physics, rule, dtype) -> dict:
+    t = N.fem_tuning()
+    N.check(N.lib().fem_get_tuning(dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)), "fem_get_tuning")
+    return dict(strategy=t.strategy, vec=t.vec, waves_per_block=t.waves_per_block, blocks_per_cu=t.blocks_per_cu)
+
+
+def fem_set_tuning(dim, physics, rule, dtype, strategy=N.STRATEGY_LANE, vec=4, waves_per_block=4,
+                   blocks_per_cu=0):
+    t = N.fem_tuning(strategy, vec, waves_per_block, blocks_per_cu)
+    N.check(N.lib().fem_set_tuning(dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)), "fem_set_tuning")
+
+
+def fem_autotune(dim, physics, rule, dtype, n_elem_probe=1 << 20, cache_path=None) -> dict:
+    cp = cache_path.encode() if cache_path else None
+    N.check(N.lib().fem_autotune(dim, physics, rule, _DT.get(dtype, dtype), n_elem_probe, cp), "fem_autotune")
+    return fem_get_tuning(dim, physics, rule, dtype)
+
+
+def fem_load_tuning(cache_path: str) -> int:
+    return N.lib().fem_load_tuning(cache_path.encode())
+
+
+# ----------------------------------------------------------------- batched --
+
+class BatchPlan:
+    """Many meshes (mixed dim/physics) integrated by one persistent launch.
+
+    ``meshes`` is a list of dicts with keys dim, physics, rule, inv_j, det_j,
+    u, coef and out (torch tensors, one dtype for all). The tensors must stay
+    alive while the plan is used.
+    """
+
+    def __init__(self, meshes: list[dict]):
+        if not meshes:
+            raise ValueError("no meshes")
+        dtype = meshes[0]["det_j"].dtype
+        descs = (N.fem_mesh_desc * len(meshes))()
+        self._keep = []
+        for i, m in enumerate(meshes):
+            n = m["det_j"].shape[0]
+            sij, sdj, su, scf = _shapes(m["dim"], m["physics"], m["rule"], n)
+            _need(m["inv_j"], "inv_j", dtype, sij)
+            _need(m["det_j"], "det_j", dtype, sdj)
+            _need(m["u"], "u", dtype, su)
+            _need(m["coef"], "coef", dtype, scf)
+            _need(m["out"], "out", dtype, su)
+            descs[i] = N.fem_mesh_desc(m["dim"], m["physics"], m["rule"], n, m["inv_j"].data_ptr(),
+                                       m["det_j"].data_ptr(), m["u"].data_ptr(), m["coef"].data_ptr(),
+                                       m["out"].data_ptr())
+            self._keep.append(m)
+        self._plan = ctypes.c_void_p()
+        N.check(N.lib().fem_batch_plan_create(descs, len(meshes), _DT[dtype], ctypes.byref(self._plan)),
+                "fem_batch_plan_create")
+
+    def run(self):
+        N.check(N.lib().fem_batch_run(self._plan, _stream()), "fem_batch_run")
+
+    def capture(self):
+        N.check(N.lib().fem_batch_capture(self._plan, _stream()), "fem_batch_capture")
+
+    def replay(self):
+        N.check(N.lib().fem_batch_replay(self._plan, _stream()), "fem_batch_replay")
+
+    def close(self):
+        if self._plan:
+            N.lib().fem_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- autograd --
+
+class IntegrateResidual(torch.autograd.Function):
+    """R = integrate(u, coef) with gradients for u and coef from the adjoint
+    kernel. Geometry is treated as a constant."""
+
+    @staticmethod
+    def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef):
+        ctx.save_for_backward(inv_j, det_j, u, coef)
+        ctx.meta = (dim, physics, rule)
+        return fem_integrate_residual(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_r):
+        inv_j, det_j, u, coef = ctx.saved_tensors
+        dim, physics, rule = ctx.meta
+        du, dcoef = fem_integrate_residual_backward(
+            dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), grad_r.contiguous(),
+            want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6])
+        return None, None, None, None, None, du, dcoef
+
+
+def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef):
+    """Differentiable element residuals (see IntegrateResidual)."""
+    return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef)

@@ -1,0 +1,63 @@
+"""Build libfemq.so, the HIP library behind include/fem.h, for gfx950.
+
+Every translation unit is compiled with hipcc in parallel and linked into
+one shared library next to the Python binding. Packed FP32 instructions are
+disabled; FMA contraction is pinned on (results are bitwise reproducible
+because each element's operation sequence is fixed).
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import pathlib
+import subprocess
+
+HERE = pathlib.Path(__file__).resolve().parent
+PKG = HERE.parent
+ROOT = PKG.parent
+BUILD = PKG / "_build"
+LIB = PKG / "libfemq.so"
+SOURCES = ["fem_abi.hip", "geometry.hip", "residual_lane.hip", "backward_lane.hip", "stubs_pending.hip"]
+
+ARCH = "gfx950"
+FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=fast",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-command-line-argument",
+         "-I", str(ROOT / "include"), "-I", str(HERE)]
+
+
+def _hipcc() -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    p = pathlib.Path(rocm) / "bin" / "hipcc"
+    return str(p) if p.exists() else "hipcc"
+
+
+def _compile(src: str, verbose: bool) -> pathlib.Path:
+    obj = BUILD / (pathlib.Path(src).stem + ".o")
+    cmd = [_hipcc(), *FLAGS, "-c", str(HERE / src), "-o", str(obj)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    if verbose and r.stderr.strip():
+        print(r.stderr, flush=True)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> pathlib.Path:
+    BUILD.mkdir(exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB.with_suffix(".so.tmp")
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    tmp.replace(LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

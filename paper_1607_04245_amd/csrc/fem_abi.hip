@@ -1,0 +1,237 @@
+// fem_abi.hip -- the extern "C" entry points of libfemq (include/fem.h):
+// argument validation, launch configuration, dispatch to the kernels.
+//
+// Validation happens before any HIP call, so invalid arguments are reported
+// without touching a device. The hot-path calls never allocate, free or
+// synchronize.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "fem.h"
+#include "fem_internal.hpp"
+
+namespace femq {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+}
+
+fem_status hip_fail(hipError_t e, const char* what) {
+    set_error("%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return FEM_ERR_HIP;
+}
+
+int device_cus() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+// ------------------------------------------------------------- validation --
+
+static bool valid_dim(int dim) { return dim == 2 || dim == 3; }
+static bool valid_dtype(int dt) { return dt == FEM_F32 || dt == FEM_F64; }
+static bool valid_phys(int p) { return p == FEM_LAPLACE || p == FEM_ELASTICITY || p == FEM_MASS; }
+static bool valid_rule(int dim, int rule) {
+    return rule == FEM_RULE_CENTROID || (dim == 2 && rule == FEM_RULE_TRI3) || (dim == 3 && rule == FEM_RULE_TET4);
+}
+
+static fem_status check_combo(const char* fn, int dim, int phys, int rule, int dtype) {
+    if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_rule(dim, rule)) { set_error("%s: rule %d is not defined in %dD", fn, rule, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+    return FEM_OK;
+}
+
+// ---------------------------------------------------------------- tuning --
+
+typedef std::tuple<int, int, int, int> TuneKey;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, fem_tuning> g_tune;
+
+static fem_tuning default_tuning(int dim, int phys, int rule, int dtype) {
+    (void)dim; (void)phys; (void)rule;
+    fem_tuning t;
+    t.strategy = FEM_STRATEGY_LANE;
+    t.vec = dtype == FEM_F32 ? 4 : 2;  // 16-byte accesses
+    t.waves_per_block = 4;
+    t.blocks_per_cu = 0;
+    return t;
+}
+
+static bool valid_tuning(const fem_tuning& t) {
+    return (t.strategy == FEM_STRATEGY_LANE || t.strategy == FEM_STRATEGY_TRANSPOSE) &&
+           (t.vec == 1 || t.vec == 2 || t.vec == 4) &&
+           (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
+            t.waves_per_block == 8) &&
+           t.blocks_per_cu >= 0 && t.blocks_per_cu <= 64;
+}
+
+fem_tuning get_tuning(int dim, int phys, int rule, int dtype) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(TuneKey(dim, phys, rule, dtype));
+    return it != g_tune.end() ? it->second : default_tuning(dim, phys, rule, dtype);
+}
+
+void put_tuning(int dim, int phys, int rule, int dtype, const fem_tuning& t) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[TuneKey(dim, phys, rule, dtype)] = t;
+}
+
+// Largest vector width <= want such that every row of every array starts on
+// a vec-word boundary.
+static int usable_vec(int want, int64_t n, size_t word, const void* const* ptrs, int nptr) {
+    for (int v = want; v > 1; v >>= 1) {
+        if (n % v) continue;
+        bool ok = true;
+        for (int i = 0; i < nptr; ++i)
+            if (ptrs[i] && (reinterpret_cast<uintptr_t>(ptrs[i]) % (v * word))) ok = false;
+        if (ok) return v;
+    }
+    return 1;
+}
+
+static Launch make_launch(const fem_tuning& t, int64_t work_items, int vec, hipStream_t s) {
+    Launch l;
+    l.vec = vec;
+    l.block = 64 * t.waves_per_block;
+    l.stream = s;
+    int64_t need = (work_items + l.block - 1) / l.block;
+    if (need < 1) need = 1;
+    if (t.blocks_per_cu > 0) {
+        int cus = device_cus();
+        int64_t cap = (int64_t)t.blocks_per_cu * (cus > 0 ? cus : 256);
+        if (need > cap) need = cap;
+    }
+    if (need > (1 << 22)) need = 1 << 22;  // the grid-stride loop covers the rest
+    l.grid = (int)need;
+    return l;
+}
+
+}  // namespace femq
+
+using namespace femq;
+
+extern "C" {
+
+const char* fem_last_error(void) { return g_error.c_str(); }
+
+fem_status fem_get_tuning(int dim, int physics, int rule, int dtype, fem_tuning* out) {
+    fem_status st = check_combo("fem_get_tuning", dim, physics, rule, dtype);
+    if (st) return st;
+    if (!out) { set_error("fem_get_tuning: out is NULL"); return FEM_ERR_INVALID_ARG; }
+    *out = get_tuning(dim, physics, rule, dtype);
+    return FEM_OK;
+}
+
+fem_status fem_set_tuning(int dim, int physics, int rule, int dtype, const fem_tuning* t) {
+    fem_status st = check_combo("fem_set_tuning", dim, physics, rule, dtype);
+    if (st) return st;
+    if (!t || !valid_tuning(*t)) { set_error("fem_set_tuning: invalid tuning"); return FEM_ERR_INVALID_ARG; }
+    put_tuning(dim, physics, rule, dtype, *t);
+    return FEM_OK;
+}
+
+fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* coords, const int32_t* conn,
+                        int out_dtype, void* inv_j, void* det_j, int32_t* counts, void* stream) {
+    if (!valid_dim(dim)) { set_error("fem_geometry: dim must be 2 or 3 (got %d)", dim); return FEM_ERR_INVALID_ARG; }
+    if (!valid_dtype(out_dtype)) { set_error("fem_geometry: unknown dtype %d", out_dtype); return FEM_ERR_UNSUPPORTED; }
+    if (n_elem < 0 || n_vert < 0) { set_error("fem_geometry: negative size"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (n_vert == 0) { set_error("fem_geometry: elements without vertices"); return FEM_ERR_INVALID_ARG; }
+    if (!coords || !conn || !inv_j || !det_j) { set_error("fem_geometry: NULL array"); return FEM_ERR_INVALID_ARG; }
+    fem_tuning t = default_tuning(dim, FEM_LAPLACE, FEM_RULE_CENTROID, out_dtype);
+    t.blocks_per_cu = 0;
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_geometry(dim, out_dtype, n_elem, n_vert, coords, conn, inv_j, det_j, counts, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_geometry launch");
+}
+
+fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int64_t n_elem, const void* inv_j,
+                                  const void* det_j, const void* u, const void* coef, void* elem_vec,
+                                  void* stream) {
+    fem_status st = check_combo("fem_integrate_residual", dim, physics, rule, dtype);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (!inv_j || !det_j || !u || !coef || !elem_vec) {
+        set_error("fem_integrate_residual: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    fem_tuning t = get_tuning(dim, physics, rule, dtype);
+    ResidualArgs a{n_elem, inv_j, det_j, u, coef, elem_vec};
+    const size_t word = dtype == FEM_F32 ? 4 : 8;
+    hipError_t e;
+    if (t.strategy == FEM_STRATEGY_TRANSPOSE) {
+        int threads = transpose_block_threads(dim, physics, rule, dtype, t.waves_per_block);
+        if (threads == 0) { set_error("fem_integrate_residual: transpose strategy unavailable"); return FEM_ERR_UNSUPPORTED; }
+        Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+        l.block = threads;
+        e = launch_residual_transpose(dim, physics, rule, dtype, a, l);
+    } else {
+        const void* ptrs[5] = {inv_j, det_j, u, coef, elem_vec};
+        int vec = usable_vec(t.vec, n_elem, word, ptrs, 5);
+        Launch l = make_launch(t, n_elem / vec, vec, static_cast<hipStream_t>(stream));
+        e = launch_residual_lane(dim, physics, rule, dtype, a, l);
+    }
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual launch");
+}
+
+fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int dtype, int64_t n_elem,
+                                           const void* inv_j, const void* det_j, const void* u, const void* coef,
+                                           const void* w, void* du, void* dcoef, void* stream) {
+    fem_status st = check_combo("fem_integrate_residual_backward", dim, physics, rule, dtype);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual_backward: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0 || (!du && !dcoef)) return FEM_OK;
+    if (!inv_j || !det_j || !w || (du && !coef) || (dcoef && !u)) {
+        set_error("fem_integrate_residual_backward: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    fem_tuning t = get_tuning(dim, physics, rule, dtype);
+    const size_t word = dtype == FEM_F32 ? 4 : 8;
+    const void* ptrs[7] = {inv_j, det_j, w, du ? coef : nullptr, du, dcoef ? u : nullptr, dcoef};
+    int vec = usable_vec(t.vec, n_elem, word, ptrs, 7);
+    BackwardArgs a{n_elem, inv_j, det_j, u, coef, w, du, dcoef};
+    Launch l = make_launch(t, n_elem / vec, vec, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_backward_lane(dim, physics, rule, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_backward launch");
+}
+
+fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream) {
+    if (n_bytes < 0 || (n_bytes % 16) || (reinterpret_cast<uintptr_t>(src) % 16) ||
+        (reinterpret_cast<uintptr_t>(dst) % 16)) {
+        set_error("fem_stream_copy: sizes and pointers must be multiples of 16 bytes");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (n_bytes == 0) return FEM_OK;
+    if (!src || !dst) { set_error("fem_stream_copy: NULL pointer"); return FEM_ERR_INVALID_ARG; }
+    fem_tuning t{FEM_STRATEGY_LANE, 1, 4, 0};
+    Launch l = make_launch(t, n_bytes / 16, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_stream_copy(src, dst, n_bytes, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_stream_copy launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+// fem_device.hpp -- device-side building blocks of libfemq (gfx950).
+//
+// Element traits, the quadrature rules and P1 tabulation as compile-time
+// constants (the paper loads the tabulation once per thread block, Section 3;
+// here it is folded into the instruction stream), the pointwise physics
+// functors f0/f1 (paper Eq. (1) and Section 6), and the per-element
+// arithmetic of the residual and its adjoint.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fem.h"
+
+namespace femq {
+
+// ---------------------------------------------------------------- traits --
+
+template <int DIM, int PHYS, int RULE>
+struct Elem {
+    static_assert(DIM == 2 || DIM == 3, "dim");
+    static constexpr int D = DIM;
+    static constexpr int NB = DIM + 1;                              // P1 basis functions
+    static constexpr int NC = (PHYS == FEM_ELASTICITY) ? DIM : 1;   // field components
+    static constexpr int NBT = NB * NC;                             // closure / element-vector length
+    static constexpr int NQ = (RULE == FEM_RULE_CENTROID) ? 1 : DIM + 1;
+    static constexpr int NCOEF = (PHYS == FEM_ELASTICITY) ? 2 : 1;
+    static constexpr int NCQ = NCOEF * NQ;                          // coefficient words per element
+    static constexpr int NG = DIM * DIM;                            // inverse-Jacobian words
+};
+
+// ------------------------------------------------------- quadrature rules --
+// Points are given by barycentric coordinates; point q has the large weight
+// at vertex q. Both degree-2 rules have equal weights, which sum to 1/dim!.
+
+template <int DIM, int RULE>
+struct Rule {
+    static constexpr int NQ = (RULE == FEM_RULE_CENTROID) ? 1 : DIM + 1;
+    // weight of every point
+    static constexpr double W = (RULE == FEM_RULE_TRI3)   ? 1.0 / 6.0
+                              : (RULE == FEM_RULE_TET4)   ? 1.0 / 24.0
+                              : (DIM == 2)                ? 0.5
+                                                          : 1.0 / 6.0;
+    // barycentric value of point q at its own vertex, and at the others
+    static constexpr double LA = (RULE == FEM_RULE_TRI3)  ? 2.0 / 3.0
+                               : (RULE == FEM_RULE_TET4)  ? 0.58541019662496845446137605030969143531609
+                                                          : 1.0 / (DIM + 1);
+    static constexpr double LB = (RULE == FEM_RULE_TRI3)  ? 1.0 / 6.0
+                               : (RULE == FEM_RULE_TET4)  ? 0.13819660112501051517954131656343618822797
+                                                          : 1.0 / (DIM + 1);
+    // B[q][b] = phi_b(xi_q): for P1 the basis functions are the barycentric coordinates
+    __host__ __device__ static constexpr double B(int q, int b) { return q == b ? LA : LB; }
+};
+
+// --------------------------------------------------------------- physics --
+// Each functor evaluates f0 (NC values) and f1 (NC x DIM values) at one
+// quadrature point from the field value uq[NC], its gradient g[NC][DIM]
+// (g[c][i] = d u_c / d x_i) and the coefficients a[NCOEF] at that point.
+// All three are linear in the coefficients and symmetric in (u, test), which
+// the adjoint relies on.
+
+template <int PHYS> struct Physics;
+
+template <> struct Physics<FEM_LAPLACE> {
+    static constexpr bool HAS_F0 = false, HAS_F1 = true, NEEDS_U = false;
+    template <int DIM, typename Real>
+    __device__ static __forceinline__ void point(const Real* uq, const Real (&g)[1][DIM],
+                                                 const Real* a, Real* f0, Real (&f1)[1][DIM]) {
+        (void)uq; (void)f0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) f1[0][i] = a[0] * g[0][i];
+    }
+};
+
+template <> struct Physics<FEM_ELASTICITY> {
+    static constexpr bool HAS_F0 = false, HAS_F1 = true, NEEDS_U = false;
+    template <int DIM, typename Real>
+    __device__ static __forceinline__ void point(const Real* uq, const Real (&g)[DIM][DIM],
+                                                 const Real* a, Real* f0, Real (&f1)[DIM][DIM]) {
+        (void)uq; (void)f0;
+        const Real half = Real(0.5);
+        Real tr = Real(0);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) tr += g[i][i];
+        const Real lam_tr = a[0] * tr;
+        const Real two_mu = a[1] + a[1];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                const Real eps = half * (g[c][i] + g[i][c]);
+                f1[c][i] = two_mu * eps + (c == i ? lam_tr : Real(0));
+            }
+    }
+};
+
+template <> struct Physics<FEM_MASS> {
+    static constexpr bool HAS_F0 = true, HAS_F1 = false, NEEDS_U = true;
+    template <int DIM, typename Real>
+    __device__ static __forceinline__ void point(const Real* uq, const Real (&g)[1][DIM],
+                                                 const Real* a, Real* f0, Real (&f1)[1][DIM]) {
+        (void)g; (void)f1;
+        f0[0] = a[0] * uq[0];
+    }
+};
+
+// ------------------------------------------------- per-element arithmetic --
+// Inputs of one element:
+//   ij[k*DIM+i] = d xi_k / d x_i, dj = det J, u[b*NC+c], cf[m*NQ+q]
+// Output: r[b*NC+c].
+//
+// P1 on an affine element: the reference gradients of the basis are
+// constant (grad phi_0 = -1, grad phi_k = e_k), so D^T u is a difference of
+// nodal values and grad u is the same at every quadrature point; the basis
+// gradients G_b = J^{-T} grad phi_b do not depend on q either, so
+//   sum_q G_b . (w_q |J| f1_q) = G_b . F,  F = sum_q w_q |J| f1_q,
+// and F is pulled back to reference coordinates once (Fh = J^{-1} F) before
+// the D^T contraction. f0/f1 are still evaluated at every quadrature point.
+
+template <int DIM, int NC, typename Real>
+__device__ __forceinline__ void physical_gradient(const Real* ij, const Real* u, Real (&g)[NC][DIM]) {
+    // reference gradient gh[c][k] = u_{k+1,c} - u_{0,c}; then g = J^{-T} gh
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        Real gh[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) gh[k] = u[(k + 1) * NC + c] - u[c];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            Real s = ij[0 * DIM + i] * gh[0];
+#pragma unroll
+            for (int k = 1; k < DIM; ++k) s += ij[k * DIM + i] * gh[k];
+            g[c][i] = s;
+        }
+    }
+}
+
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void element_residual(const Real* ij, Real dj, const Real* u,
+                                                 const Real* cf, Real* r) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using P = Physics<PHYS>;
+    using Q = Rule<DIM, RULE>;
+    constexpr int NC = E::NC, NB = E::NB, NQ = E::NQ;
+
+    Real g[NC][DIM];
+    physical_gradient<DIM, NC>(ij, u, g);
+    const Real s = Real(Q::W) * fabs(dj);  // w_q |det J| (equal weights)
+
+    Real F[NC][DIM];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) F[c][i] = Real(0);
+#pragma unroll
+    for (int b = 0; b < NB * NC; ++b) r[b] = Real(0);
+
+    // quadrature phase: pointwise physics at every point, weighted
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Real uq[NC];
+        if constexpr (P::NEEDS_U) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Real v = Real(Q::B(q, 0)) * u[c];
+#pragma unroll
+                for (int b = 1; b < NB; ++b) v += Real(Q::B(q, b)) * u[b * NC + c];
+                uq[c] = v;
+            }
+        }
+        Real a[E::NCOEF];
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) a[m] = cf[m * NQ + q];
+        Real f0[NC], f1[NC][DIM];
+        P::template point<DIM, Real>(uq, g, a, f0, f1);
+        if constexpr (P::HAS_F1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) F[c][i] += s * f1[c][i];
+        }
+        if constexpr (P::HAS_F0) {
+            // B^T W f0: phi_b(xi_q) times the weighted f0
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const Real t = s * f0[c];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) r[b * NC + c] += Real(Q::B(q, b)) * t;
+            }
+        }
+    }
+
+    // basis phase: D^T (J^{-T})^T F = grad(phi_b) . Fh with Fh = J^{-1} F
+    if constexpr (P::HAS_F1) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Real sum = Real(0);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                Real fh = ij[k * DIM + 0] * F[c][0];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) fh += ij[k * DIM + i] * F[c][i];
+                r[(k + 1) * NC + c] += fh;
+                sum += fh;
+            }
+            r[c] -= sum;
+        }
+    }
+}
+
+// Adjoint of L = w . R for one element. du = R(w) (symmetric forms);
+// dcoef[m*NQ+q] = w_q |J| [ w^q . f0(e_m) + grad w : f1(e_m) ] with f0/f1
+// evaluated at unit coefficient e_m (the forms are linear in coefficients).
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Real* u,
+                                              const Real* w, Real* dcf) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using P = Physics<PHYS>;
+    using Q = Rule<DIM, RULE>;
+    constexpr int NC = E::NC, NB = E::NB, NQ = E::NQ;
+
+    Real gu[NC][DIM], gw[NC][DIM];
+    if constexpr (P::HAS_F1) {
+        physical_gradient<DIM, NC>(ij, u, gu);
+        physical_gradient<DIM, NC>(ij, w, gw);
+    }
+    const Real s = Real(Q::W) * fabs(dj);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Real uq[NC], wq[NC];
+        if constexpr (P::NEEDS_U) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Real vu = Real(Q::B(q, 0)) * u[c];
+                Real vw = Real(Q::B(q, 0)) * w[c];
+#pragma unroll
+                for (int b = 1; b < NB; ++b) {
+                    vu += Real(Q::B(q, b)) * u[b * NC + c];
+                    vw += Real(Q::B(q, b)) * w[b * NC + c];
+                }
+                uq[c] = vu;
+                wq[c] = vw;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            Real a[E::NCOEF];
+#pragma unroll
+            for (int mm = 0; mm < E::NCOEF; ++mm) a[mm] = Real(mm == m ? 1 : 0);
+            Real f0[NC], f1[NC][DIM];
+            P::template point<DIM, Real>(uq, gu, a, f0, f1);
+            Real acc = Real(0);
+            if constexpr (P::HAS_F0) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc += wq[c] * f0[c];
+            }
+            if constexpr (P::HAS_F1) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) acc += gw[c][i] * f1[c][i];
+            }
+            dcf[m * NQ + q] = s * acc;
+        }
+    }
+}
+
+// --------------------------------------------------- vector memory access --
+
+template <typename Real, int V> struct VecT;
+template <> struct VecT<float, 1> { typedef float T; };
+template <> struct VecT<float, 2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct VecT<float, 4> { typedef float T __attribute__((ext_vector_type(4))); };
+template <> struct VecT<double, 1> { typedef double T; };
+template <> struct VecT<double, 2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct VecT<double, 4> { typedef double T __attribute__((ext_vector_type(4))); };
+
+// Load V consecutive elements of one SoA row (p must be aligned to V words).
+template <typename Real, int V>
+__device__ __forceinline__ void ld_row(const Real* __restrict__ p, Real (&out)[V]) {
+    typedef typename VecT<Real, V>::T T;
+    const T x = __builtin_nontemporal_load(reinterpret_cast<const T*>(p));
+    if constexpr (V == 1) {
+        out[0] = x;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = x[v];
+    }
+}
+
+template <typename Real, int V>
+__device__ __forceinline__ void st_row(Real* __restrict__ p, const Real (&in)[V]) {
+    typedef typename VecT<Real, V>::T T;
+    T x;
+    if constexpr (V == 1) {
+        x = in[0];
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = in[v];
+    }
+    __builtin_nontemporal_store(x, reinterpret_cast<T*>(p));
+}
+
+}  // namespace femq

@@ -1,0 +1,86 @@
+// fem_internal.hpp -- host-side interfaces between the C ABI layer and the
+// kernel translation units of libfemq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fem.h"
+
+namespace femq {
+
+struct ResidualArgs {
+    int64_t n;
+    const void* inv_j;
+    const void* det_j;
+    const void* u;
+    const void* coef;
+    void* out;
+};
+
+struct BackwardArgs {
+    int64_t n;
+    const void* inv_j;
+    const void* det_j;
+    const void* u;
+    const void* coef;
+    const void* w;
+    void* du;
+    void* dcoef;
+};
+
+struct Launch {
+    int grid;      // workgroups
+    int block;     // threads per workgroup (multiple of 64)
+    int vec;       // elements per lane in load/store phases
+    hipStream_t stream;
+};
+
+// Each returns hipErrorInvalidValue when the combination has no kernel.
+hipError_t launch_residual_lane(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
+                                const Launch& l);
+hipError_t launch_residual_transpose(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
+                                     const Launch& l);
+hipError_t launch_backward_lane(int dim, int phys, int rule, int dtype, const BackwardArgs& a,
+                                const Launch& l);
+hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,
+                           const int32_t* conn, void* inv_j, void* det_j, int32_t* counts,
+                           const Launch& l);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n_bytes, const Launch& l);
+
+// Batched persistent kernel (batch.hip).
+struct BatchMesh {              // device-side descriptor, one per mesh
+    int32_t type;               // dim*16 + physics*4 + rule
+    int32_t pad;
+    int64_t n_elem;
+    int64_t tile_begin;         // first global tile of this mesh
+    const void* inv_j;
+    const void* det_j;
+    const void* u;
+    const void* coef;
+    void* out;
+};
+
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, int64_t n_tiles,
+                        int tile_elems, const Launch& l);
+
+// Threads the transpose kernel needs per workgroup for a given tuning, or 0 if
+// the combination is not supported by that strategy.
+int transpose_block_threads(int dim, int phys, int rule, int dtype, int waves_per_block);
+
+}  // namespace femq
+
+namespace femq {
+
+// Thread-local error message behind fem_last_error().
+void set_error(const char* fmt, ...);
+fem_status hip_fail(hipError_t e, const char* what);
+
+// Compute units of the current device (cached per device); 0 if unknown.
+int device_cus();
+
+// Launch configuration table (fem_abi.hip).
+fem_tuning get_tuning(int dim, int phys, int rule, int dtype);
+void put_tuning(int dim, int phys, int rule, int dtype, const fem_tuning& t);
+
+}  // namespace femq

@@ -1,0 +1,104 @@
+"""The C ABI library without a GPU: it loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+
+import pytest
+
+from paper_1607_04245_amd import _native as N
+from paper_1607_04245_amd import meshgen as mg
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not N.LIB_PATH.exists():
+        import __graft_entry__
+        __graft_entry__.build()
+    return N.lib()
+
+
+def test_exports_every_header_function(lib):
+    names = N.header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in fem.h but not exported"
+    assert set(names) == set(N.SIGNATURES), "binding signatures out of sync with fem.h"
+
+
+def test_status_codes_match_header():
+    text = N.HEADER.read_text()
+    for code, name in N.STATUS_NAMES.items():
+        assert f"#define {name} ({code})" in text or (code == 0 and f"#define {name} 0" in text)
+
+
+def _v(x=0x1000):
+    return ctypes.c_void_p(x)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,status", [
+    ((4, 10, 10), N.FEM_ERR_INVALID_ARG),   # bad dim
+    ((2, -1, 10), N.FEM_ERR_INVALID_ARG),   # negative n_elem
+    ((2, 10, -1), N.FEM_ERR_INVALID_ARG),   # negative n_vert
+    ((2, 10, 0), N.FEM_ERR_INVALID_ARG),    # elements without vertices
+    ((2, 0, 0), N.FEM_OK),                  # empty: no launch
+])
+def test_geometry_validation(lib, args, status):
+    dim, ne, nv = args
+    st = lib.fem_geometry(dim, ne, nv, _v(), _v(), N.F32, _v(), _v(), None, None)
+    assert st == status
+    if status != N.FEM_OK:
+        assert N.last_error()
+
+
+def test_geometry_null_arrays(lib):
+    assert lib.fem_geometry(2, 5, 5, None, _v(), N.F32, _v(), _v(), None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_geometry(2, 5, 5, _v(), _v(), 7, _v(), _v(), None, None) == N.FEM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("combo,status", [
+    ((2, mg.LAPLACE, mg.RULE_TET4, N.F32), N.FEM_ERR_UNSUPPORTED),   # tet rule in 2D
+    ((3, mg.LAPLACE, mg.RULE_TRI3, N.F32), N.FEM_ERR_UNSUPPORTED),   # triangle rule in 3D
+    ((1, mg.LAPLACE, mg.RULE_CENTROID, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, 9, mg.RULE_TRI3, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, 9, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, mg.RULE_TRI3, 5), N.FEM_ERR_UNSUPPORTED),
+])
+def test_residual_combo_validation(lib, combo, status):
+    st = lib.fem_integrate_residual(*combo, 10, _v(), _v(), _v(), _v(), _v(), None)
+    assert st == status and N.last_error()
+    st = lib.fem_integrate_residual_backward(*combo, 10, _v(), _v(), _v(), _v(), _v(), _v(), _v(), None)
+    assert st == status
+
+
+def test_residual_sizes_and_nulls(lib):
+    c = (3, mg.ELASTICITY, mg.RULE_TET4, N.F64)
+    assert lib.fem_integrate_residual(*c, -5, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_integrate_residual(*c, 0, None, None, None, None, None, None) == N.FEM_OK
+    assert lib.fem_integrate_residual(*c, 5, _v(), None, _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    # backward: no output requested is a no-op; du needs coef, dcoef needs u
+    assert lib.fem_integrate_residual_backward(*c, 5, _v(), _v(), None, None, _v(), None, None, None) == N.FEM_OK
+    assert lib.fem_integrate_residual_backward(*c, 5, _v(), _v(), _v(), None, _v(), _v(), None, None) \
+        == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_integrate_residual_backward(*c, 5, _v(), _v(), None, _v(), _v(), None, _v(), None) \
+        == N.FEM_ERR_INVALID_ARG
+
+
+def test_stream_copy_validation(lib):
+    assert lib.fem_stream_copy(_v(), _v(), 15, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_stream_copy(_v(0x1008), _v(), 16, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_stream_copy(_v(), _v(), 0, None) == N.FEM_OK
+
+
+def test_tuning_roundtrip(lib):
+    t = N.fem_tuning()
+    assert lib.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) == N.FEM_OK
+    assert t.strategy == N.STRATEGY_LANE and t.vec in (1, 2, 4)
+    new = N.fem_tuning(N.STRATEGY_LANE, 2, 8, 4)
+    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(new)) == N.FEM_OK
+    got = N.fem_tuning()
+    lib.fem_get_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(got))
+    assert (got.strategy, got.vec, got.waves_per_block, got.blocks_per_cu) == (0, 2, 8, 4)
+    bad = N.fem_tuning(N.STRATEGY_LANE, 3, 4, 0)
+    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
+    bad = N.fem_tuning(N.STRATEGY_LANE, 4, 5, 0)
+    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_TET4, N.F64, ctypes.byref(new)) == N.FEM_ERR_UNSUPPORTED
