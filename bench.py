@@ -2,17 +2,20 @@
 """Benchmark of P1 element-residual integration on one MI355X.
 
 A step is one pass of the hot path over the 3D variable-coefficient Laplacian
-workload (P1 tetrahedra, 2^20 elements from a jittered 64^3 cube grid, 4-point
+workload (P1 tetrahedra, 2^20 elements of a jittered 64^3 Kuhn grid, 4-point
 degree-2 rule, kappa ~ U[0.5, 2] per quadrature point, u ~ U[-1, 1]):
-fem_geometry (coordinates and connectivity to J^{-1}, det J) followed by
-fem_integrate_residual, FP32. Inputs are resident in HBM before timing. The
-inputs are replicated into several copies (> 512 MB in total) and the steps
-rotate through them, so the 256 MB last-level cache cannot serve a step from
-the previous one.
+fem_geometry (coordinates and connectivity to J^{-1}, det J), then
+fem_integrate_residual, in FP32. All inputs are resident in HBM before the
+timed region. They are replicated into several copies (> 512 MB in total) and
+the steps rotate through them, so the 256 MB last-level cache cannot serve a
+step from the data of the one before.
 
-Prints ONE JSON line. Extra sections (not part of `value`): FP64, the other
-physics, the adjoint, the batched launch, the achievable HBM bandwidth of a
-plain copy kernel, and the FP64 CPU oracle on the host.
+Prints ONE JSON line on stdout (progress goes to stderr). `value` is
+elements per second of the step. The roofline object is for the dominant
+kernel, timed with HIP events on the stream the library launches on, during
+the timed region. Extra sections (outside `value`): FP64, the elasticity
+workloads, the adjoint, the batched launch against 64 separate launches, the
+achievable bandwidth of a plain copy kernel, and the FP64 CPU oracle.
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "element-integration GF/s & elements/s (FP32, FP64); % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+ROTATE_BYTES = 600e6  # rotate through input copies totalling at least this much
 
 
 def log(msg):
@@ -40,36 +44,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--copies", type=int, default=8, help="input copies the steps rotate through")
     p.add_argument("--quick", action="store_true", help="main step only (no extra sections, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     return p.parse_args()
-
-
-class Timer:
-    """HIP events around launches on torch's current stream (the stream the
-    library launches on)."""
-
-    def __init__(self, torch):
-        self.torch = torch
-        self.pairs = []
-
-    def start(self):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
-        return e
-
-    def stop(self, s):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
-        self.pairs.append((s, e))
-
-    def mean_ms(self):
-        return sum(s.elapsed_time(e) for s, e in self.pairs) / max(len(self.pairs), 1)
-
-    def median_ms(self):
-        v = sorted(s.elapsed_time(e) for s, e in self.pairs)
-        return v[len(v) // 2] if v else 0.0
 
 
 def source_hash(files):
@@ -79,24 +56,22 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
+CSRC = "paper_1607_04245_amd/csrc/"
 KERNEL_SOURCES = {
-    "residual_lane": ["paper_1607_04245_amd/csrc/residual_lane.hip", "paper_1607_04245_amd/csrc/fem_device.hpp"],
-    "geometry": ["paper_1607_04245_amd/csrc/geometry.hip", "paper_1607_04245_amd/csrc/fem_device.hpp"],
+    "fem_integrate_residual": [CSRC + "residual_lane.hip", CSRC + "fem_device.hpp", CSRC + "fem_abi.hip"],
+    "fem_geometry": [CSRC + "geometry.hip", CSRC + "fem_abi.hip"],
 }
 
 
-def measured_traffic(kernel_key, workload):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
     f = ROOT / "profiles" / "traffic.json"
-    if not f.exists():
-        return None
     try:
-        data = json.loads(f.read_text())
-        rec = data[f"{kernel_key}:{workload}"]
-    except (KeyError, ValueError):
+        rec = json.loads(f.read_text())[f"{kernel}:{workload}"]
+    except (OSError, KeyError, ValueError):
         return None
-    if rec.get("source_hash") != source_hash(KERNEL_SOURCES[kernel_key]):
+    if rec.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("bytes_per_launch")
 
@@ -104,8 +79,9 @@ def measured_traffic(kernel_key, workload):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the element stream shards "
-              "without communication, so N GPUs would each run this same single-GPU workload.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the element stream shards with no "
+              "communication, so each GPU would run this same single-GPU workload on its slice.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -123,74 +99,97 @@ def main():
     def to_dev(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
 
-    # ---------------------------------------------------------- main step --
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def n_copies(bytes_per_copy):
+        return int(max(2, min(16, -(-ROTATE_BYTES // max(bytes_per_copy, 1)))))
+
+    # -------------------------------------------------------------- main step --
     t0 = time.time()
     wl = mg.config(2)
-    n = wl.n_elem
-    dim, phys, rule = wl.dim, wl.physics, wl.rule
+    n, dim, phys, rule = wl.n_elem, wl.dim, wl.physics, wl.rule
     log(f"workload {wl.name}: {n} elements, {wl.n_vert} vertices (built in {time.time() - t0:.1f}s)")
+    flops = model.model_flops(dim, phys, rule)
 
-    def make_copies(dt, copies):
+    def step_copies(dt):
+        word = 4 if dt == torch.float32 else 8
+        per = (model.geometry_bytes(dim, n, wl.n_vert, word) + model.forward_bytes(dim, phys, rule, word)) * n
         base = dict(coords=to_dev(wl.coords, torch.float64), conn=to_dev(wl.conn, torch.int32),
                     u=to_dev(wl.u, dt), coef=to_dev(wl.coef, dt))
-        out = []
-        for _ in range(copies):
+        cs = []
+        for _ in range(n_copies(per)):
             c = {k: v.clone() for k, v in base.items()}
             c["inv_j"] = torch.empty((dim * dim, n), dtype=dt, device=dev)
             c["det_j"] = torch.empty((n,), dtype=dt, device=dev)
             c["R"] = torch.empty_like(c["u"])
-            out.append(c)
-        return out
+            cs.append(c)
+        return cs
 
-    def step(c, t_geo=None, t_int=None):
-        s = t_geo.start() if t_geo else None
+    def geometry(c):
         api.fem_geometry(c["coords"], c["conn"], c["det_j"].dtype, inv_j=c["inv_j"], det_j=c["det_j"])
-        if t_geo:
-            t_geo.stop(s)
-        s = t_int.start() if t_int else None
-        api.fem_integrate_residual(dim, phys, rule, c["inv_j"], c["det_j"], c["u"], c["coef"], out=c["R"])
-        if t_int:
-            t_int.stop(s)
 
-    def run_steps(dt, steps, warmup, copies):
-        cs = make_copies(dt, copies)
+    def integrate(c):
+        api.fem_integrate_residual(dim, phys, rule, c["inv_j"], c["det_j"], c["u"], c["coef"], out=c["R"])
+
+    def timed_steps(cs, steps, warmup):
+        """The timed region: `steps` steps, events around the integration
+        kernel only (geometry runs unbracketed between them)."""
         for i in range(warmup):
-            step(cs[i % copies])
+            geometry(cs[i % len(cs)])
+            integrate(cs[i % len(cs)])
         torch.cuda.synchronize()
-        tg, ti = Timer(torch), Timer(torch)
-        torch.cuda.synchronize()
+        pairs = []
         t = time.perf_counter()
         for i in range(steps):
-            step(cs[i % copies], tg, ti)
+            c = cs[i % len(cs)]
+            geometry(c)
+            s = ev()
+            integrate(c)
+            pairs.append((s, ev()))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        del cs
-        return wall, tg.mean_ms(), ti.mean_ms()
+        return wall, sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
 
-    word = 4
-    wall, geo_ms, int_ms = run_steps(torch.float32, args.steps, args.warmup, args.copies)
+    def kernel_breakdown(cs, reps=20):
+        """Untimed pass: each kernel of the step bracketed by events."""
+        g, i = [], []
+        for r in range(reps):
+            c = cs[r % len(cs)]
+            s = ev()
+            geometry(c)
+            m = ev()
+            integrate(c)
+            i.append((m, ev()))
+            g.append((s, m))
+        torch.cuda.synchronize()
+        return (sum(a.elapsed_time(b) for a, b in g) / reps, sum(a.elapsed_time(b) for a, b in i) / reps)
+
+    cs = step_copies(torch.float32)
+    wall, int_ms = timed_steps(cs, args.steps, args.warmup)
+    geo_ms, int_ms_b = kernel_breakdown(cs)
+    del cs
     ms_per_step = 1e3 * wall / args.steps
     value = n * args.steps / wall
-    log(f"FP32 step {ms_per_step:.4f} ms: geometry {geo_ms * 1e3:.1f} us, integrate {int_ms * 1e3:.1f} us")
+    log(f"FP32 step {ms_per_step * 1e3:.1f} us ({value:.3e} elem/s): integrate {int_ms * 1e3:.1f} us in the timed "
+        f"region; breakdown geometry {geo_ms * 1e3:.1f} us, integrate {int_ms_b * 1e3:.1f} us")
 
-    int_bytes = model.forward_bytes(dim, phys, rule, word) * n
-    geo_bytes = model.geometry_bytes(dim, n, wl.n_vert, word) * n
-    flops = model.model_flops(dim, phys, rule)
+    int_bytes = model.forward_bytes(dim, phys, rule, 4) * n
+    geo_bytes = model.geometry_bytes(dim, n, wl.n_vert, 4) * n
     kernels = {
-        "fem_integrate_residual": dict(avg_us=int_ms * 1e3, bytes=int_bytes,
-                                       gbs=int_bytes / (int_ms * 1e-3) / 1e9,
-                                       elements_per_s=n / (int_ms * 1e-3),
+        "fem_integrate_residual": dict(avg_us=int_ms * 1e3, algorithmic_bytes=int_bytes,
+                                       gbs=int_bytes / (int_ms * 1e-3) / 1e9, elements_per_s=n / (int_ms * 1e-3),
                                        model_gflops=n * flops / (int_ms * 1e-3) / 1e9),
-        "fem_geometry": dict(avg_us=geo_ms * 1e3, bytes=geo_bytes, gbs=geo_bytes / (geo_ms * 1e-3) / 1e9,
-                             elements_per_s=n / (geo_ms * 1e-3)),
+        "fem_geometry": dict(avg_us=geo_ms * 1e3, algorithmic_bytes=geo_bytes,
+                             gbs=geo_bytes / (geo_ms * 1e-3) / 1e9, elements_per_s=n / (geo_ms * 1e-3)),
     }
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    dom = "fem_integrate_residual" if int_ms_b >= geo_ms else "fem_geometry"
     dk = kernels[dom]
-    kkey = "residual_lane" if dom == "fem_integrate_residual" else "geometry"
-    traffic = measured_traffic(kkey, "laplace3d_2p20_f32")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": dk["bytes"]}
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, "laplace3d_2p20_f32"),
+                "algorithmic_bytes_per_launch": dk["algorithmic_bytes"]}
 
     result = {
         "metric": METRIC,
@@ -208,7 +207,7 @@ def main():
         "config": {"workload": "3D variable-coefficient Laplacian, P1 tetrahedra, 2^20 elements of a jittered "
                                "64^3 Kuhn grid, 4-point degree-2 rule; step = fem_geometry + "
                                "fem_integrate_residual",
-                   "n_elem": n, "n_vert": wl.n_vert, "copies": args.copies},
+                   "n_elem": n, "n_vert": wl.n_vert},
         "model_gflops": value * flops / 1e9,
         "kernels": kernels,
         "roofline": roofline,
@@ -216,30 +215,170 @@ def main():
 
     if not args.quick:
         extra = {}
-        # FP64 step
-        wall64, g64, i64 = run_steps(torch.float64, max(10, args.steps // 2), 2, args.copies)
+
+        # ------------------------------------------------------ FP64 step --
+        cs = step_copies(torch.float64)
+        steps64 = max(10, args.steps // 2)
+        wall64, i64 = timed_steps(cs, steps64, 2)
+        g64, _ = kernel_breakdown(cs)
+        del cs
         b64 = model.forward_bytes(dim, phys, rule, 8) * n
-        extra["fp64_step"] = dict(elements_per_s=n * max(10, args.steps // 2) / wall64,
+        extra["fp64_step"] = dict(elements_per_s=n * steps64 / wall64, ms_per_step=1e3 * wall64 / steps64,
                                   integrate_us=i64 * 1e3, integrate_gbs=b64 / (i64 * 1e-3) / 1e9,
                                   integrate_model_gflops=n * flops / (i64 * 1e-3) / 1e9, geometry_us=g64 * 1e3)
-        log(f"FP64 integrate {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
-        # achievable HBM bandwidth: copy of 2 GiB
-        nb = 2 << 30
-        src = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            api.fem_stream_copy(src, dst)
-        tm = Timer(torch)
-        for _ in range(10):
-            s = tm.start()
-            api.fem_stream_copy(src, dst)
-            tm.stop(s)
+        log(f"FP64 step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us; integrate {i64 * 1e3:.1f} us "
+            f"({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
+
+        # --------------------------------------------- achievable bandwidth --
+        def copy_gbs(nbytes, reps):
+            src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+            dsts = [torch.empty_like(src) for _ in range(n_copies(2 * nbytes) if nbytes < 2**30 else 1)]
+            srcs = [src] + [src.clone() for _ in range(len(dsts) - 1)]
+            for k in range(3):
+                api.fem_stream_copy(srcs[k % len(srcs)], dsts[k % len(dsts)])
+            pairs = []
+            for k in range(reps):
+                s = ev()
+                api.fem_stream_copy(srcs[k % len(srcs)], dsts[k % len(dsts)])
+                pairs.append((s, ev()))
+            torch.cuda.synchronize()
+            t = sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
+            return 2 * nbytes / (t * 1e-3) / 1e9, t * 1e3
+
+        big_gbs, big_us = copy_gbs(2 << 30, 10)
+        same_gbs, same_us = copy_gbs((int_bytes // 2) // 16 * 16, 20)
+        extra["stream_copy"] = dict(gbs_2gib=big_gbs, us_2gib=big_us,
+                                    gbs_same_bytes=same_gbs, us_same_bytes=same_us,
+                                    note="read+write copy; 'same_bytes' moves as many bytes as one "
+                                         "integration launch of the step")
+        roofline["achievable_gbs"] = big_gbs
+        roofline["frac_of_achievable"] = dk["gbs"] / big_gbs
+        roofline["achievable_gbs_same_bytes"] = same_gbs
+        log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the step's byte count")
+
+        # --------------------------------------------------- other physics --
+        def integrate_only(wlx, dt, reps=20):
+            word = 4 if dt == torch.float32 else 8
+            nb = model.forward_bytes(wlx.dim, wlx.physics, wlx.rule, word) * wlx.n_elem
+            ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+            base = dict(ij=ij, dj=dj, u=to_dev(wlx.u, dt), cf=to_dev(wlx.coef, dt))
+            cps = []
+            for _ in range(n_copies(nb)):
+                c = {k: v.clone() for k, v in base.items()}
+                c["R"] = torch.empty_like(c["u"])
+                cps.append(c)
+            del base, ij, dj
+
+            def go(c):
+                api.fem_integrate_residual(wlx.dim, wlx.physics, wlx.rule, c["ij"], c["dj"], c["u"], c["cf"],
+                                           out=c["R"])
+            for k in range(3):
+                go(cps[k % len(cps)])
+            pairs = []
+            for k in range(reps):
+                s = ev()
+                go(cps[k % len(cps)])
+                pairs.append((s, ev()))
+            torch.cuda.synchronize()
+            us = 1e3 * sum(a.elapsed_time(b) for a, b in pairs) / reps
+            del cps
+            f = model.model_flops(wlx.dim, wlx.physics, wlx.rule)
+            return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
+                        model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+
+        for cfg in ("3a", "3b"):
+            wlx = mg.config(cfg)
+            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                r = integrate_only(wlx, dt)
+                extra[f"{wlx.name}_{tag}"] = r
+                log(f"{wlx.name} {tag}: {r['us']:.1f} us, {r['gbs']:.0f} GB/s, {r['model_gflops']:.0f} model GF/s")
+            del wlx
+
+        # --------------------------------------------------------- adjoint --
+        wl5 = mg.config(5)
+        dt = torch.float32
+        nb = model.backward_bytes(3, mg.LAPLACE, wl5.rule, 4) * wl5.n_elem
+        ij, dj = api.fem_geometry(to_dev(wl5.coords, torch.float64), to_dev(wl5.conn, torch.int32), dt)
+        base = dict(ij=ij, dj=dj, u=to_dev(wl5.u, dt), cf=to_dev(wl5.coef, dt), w=to_dev(wl5.w, dt))
+        cps = []
+        for _ in range(n_copies(nb)):
+            c = {k: v.clone() for k, v in base.items()}
+            c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["cf"])
+            cps.append(c)
+        del base, ij, dj
+
+        def bwd(c):
+            api.fem_integrate_residual_backward(3, mg.LAPLACE, wl5.rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
+                                                du=c["du"], dcoef=c["dc"])
+        for k in range(3):
+            bwd(cps[k % len(cps)])
+        pairs = []
+        for k in range(20):
+            s = ev()
+            bwd(cps[k % len(cps)])
+            pairs.append((s, ev()))
         torch.cuda.synchronize()
-        copy_gbs = 2 * nb / (tm.median_ms() * 1e-3) / 1e9
-        extra["stream_copy"] = dict(bytes=2 * nb, median_us=tm.median_ms() * 1e3, gbs=copy_gbs)
-        del src, dst
-        roofline["frac_of_achievable"] = dk["gbs"] / copy_gbs
-        log(f"stream copy {copy_gbs:.0f} GB/s")
+        us = 1e3 * sum(a.elapsed_time(b) for a, b in pairs) / 20
+        extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                                                   elements_per_s=wl5.n_elem / (us * 1e-6),
+                                                   frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+        log(f"adjoint: {us:.1f} us, {nb / (us * 1e-6) / 1e9:.0f} GB/s")
+        del cps, wl5
+
+        # --------------------------------------------------------- batched --
+        t0 = time.time()
+        wls = mg.batch_workloads()
+        dt = torch.float32
+        meshes, nbytes, ntot = [], 0, 0
+        for w in wls:
+            ij, dj = api.fem_geometry(to_dev(w.coords, torch.float64), to_dev(w.conn, torch.int32), dt)
+            meshes.append(dict(dim=w.dim, physics=w.physics, rule=w.rule, inv_j=ij, det_j=dj, u=to_dev(w.u, dt),
+                               coef=to_dev(w.coef, dt), out=torch.empty(w.u.shape, dtype=dt, device=dev)))
+            nbytes += model.forward_bytes(w.dim, w.physics, w.rule, 4) * w.n_elem
+            ntot += w.n_elem
+        del wls
+        log(f"batched: {len(meshes)} meshes, {ntot} elements, {nbytes / 1e6:.0f} MB (built in {time.time() - t0:.1f}s)")
+
+        def separate():
+            for m in meshes:
+                api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                           m["coef"], out=m["out"])
+
+        plan = api.BatchPlan(meshes)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            plan.capture()
+        torch.cuda.synchronize()
+
+        def timeit(fn, reps, stream=None):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            pairs = []
+            for _ in range(reps):
+                s = ev()
+                fn()
+                pairs.append((s, ev()))
+            torch.cuda.synchronize()
+            return 1e3 * sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
+
+        def replay():
+            plan.replay()
+
+        sep_us = timeit(separate, 10)
+        run_us = timeit(plan.run, 10)
+        with torch.cuda.stream(side):
+            rep_us = timeit(replay, 10)
+        plan.close()
+        extra["batched_64_meshes_f32"] = dict(
+            n_mesh=len(meshes), n_elem=ntot, algorithmic_bytes=nbytes,
+            separate_launches_us=sep_us, persistent_launch_us=run_us, graph_replay_us=rep_us,
+            graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
+            speedup_vs_separate=sep_us / rep_us,
+            note="the meshes total about 0.9 GB, above the last-level cache; medians of 10")
+        log(f"batched: 64 launches {sep_us:.1f} us, persistent {run_us:.1f} us, graph {rep_us:.1f} us "
+            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s)")
+        del meshes
         result["extra"] = extra
 
     if not args.quick and not args.no_cpu:
@@ -249,14 +388,13 @@ def main():
 
 
 def cpu_baseline(wl, flops):
-    """The FP64 oracle (plain C, one thread) on the same step: geometry and
-    residual of the first elements of the workload, repeated until about 10 s
+    """The FP64 oracle (plain C, one thread) on the step's work: geometry and
+    residual of every element of the step workload, repeated until about 10 s
     of CPU work has run."""
     import numpy as np
 
     import oracle
 
-    sample = wl.n_elem
     reps, t_total = 0, 0.0
     while t_total < 10.0 and reps < 50:
         t = time.perf_counter()
@@ -264,12 +402,12 @@ def cpu_baseline(wl, flops):
         t_total += time.perf_counter() - t
         reps += 1
     assert nd == 0 and np.isfinite(R).all()
-    eps = sample * reps / t_total
+    eps = wl.n_elem * reps / t_total
     log(f"CPU oracle: {eps:.3e} elements/s over {reps} passes ({t_total:.1f} s)")
     return {"value": eps, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} passes of fem_oracle_residual (FP64 geometry + residual) over all {sample} "
-                      f"elements of the step workload, {t_total:.1f} s single-threaded",
-            "model_gflops": eps * flops / 1e9, "host_cpus": os.cpu_count()}
+            "sample": f"{reps} passes of fem_oracle_residual (FP64 geometry + residual, one thread) over all "
+                      f"{wl.n_elem} elements of the step workload, {t_total:.1f} s",
+            "model_gflops": eps * flops / 1e9, "host_cpus_visible": os.cpu_count()}
 
 
 if __name__ == "__main__":

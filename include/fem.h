@@ -156,6 +156,11 @@ typedef struct fem_batch_plan fem_batch_plan;
  * the device current at creation. */
 fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dtype,
                                  fem_batch_plan** out);
+/* Launch shape of the persistent kernel: waves per workgroup (1, 2, 4, 8;
+ * one element per lane, so a tile is 64*waves_per_block elements) and
+ * workgroups per compute unit (0 = one workgroup per tile). Defaults 4 and 8.
+ * Drops a recorded graph (capture again). Synchronizes the device. */
+fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, int blocks_per_cu);
 /* One persistent launch covering every mesh, on `stream`. */
 fem_status fem_batch_run(fem_batch_plan* plan, void* stream);
 /* Record the persistent launch into a HIP graph (captured on `stream`, which

@@ -197,6 +197,10 @@ class BatchPlan:
         N.check(N.lib().fem_batch_plan_create(descs, len(meshes), _DT[dtype], ctypes.byref(self._plan)),
                 "fem_batch_plan_create")
 
+    def set_launch(self, waves_per_block=4, blocks_per_cu=8):
+        N.check(N.lib().fem_batch_plan_set_launch(self._plan, waves_per_block, blocks_per_cu),
+                "fem_batch_plan_set_launch")
+
     def run(self):
         N.check(N.lib().fem_batch_run(self._plan, _stream()), "fem_batch_run")
 

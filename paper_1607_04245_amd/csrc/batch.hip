@@ -1,0 +1,253 @@
+// batch.hip -- many meshes of mixed dimension and physics integrated by one
+// persistent launch, optionally recorded into a HIP graph.
+//
+// The plan concatenates the meshes' element ranges into one list of tiles
+// (one tile = one workgroup's worth of elements, one element per lane).
+// Persistent workgroups walk that list with a fixed stride, so there is no
+// work counter to reset between launches and the assignment is the same on
+// every replay. For each tile the workgroup finds its mesh by binary search
+// over the tiles' starting offsets (wave-uniform, read-only descriptor loads)
+// and branches, uniformly, into the element code of that mesh's
+// (dim, physics, rule). Each element runs exactly the arithmetic of the
+// single-mesh lane kernel, so batched and single-mesh results are bitwise
+// equal. This plays the role of the paper's assignment of cell chunks to
+// thread blocks (Section 3), across meshes instead of within one.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fem_device.hpp"
+#include "fem_internal.hpp"
+
+namespace femq {
+
+constexpr int type_code(int dim, int phys, int rule) { return dim * 16 + phys * 4 + rule; }
+
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void batch_element(const BatchMesh& M, int64_t e) {
+    using E = Elem<DIM, PHYS, RULE>;
+    const int64_t n = M.n_elem;
+    const Real* __restrict__ ijp = static_cast<const Real*>(M.inv_j);
+    const Real* __restrict__ djp = static_cast<const Real*>(M.det_j);
+    const Real* __restrict__ up = static_cast<const Real*>(M.u);
+    const Real* __restrict__ cfp = static_cast<const Real*>(M.coef);
+    Real* __restrict__ outp = static_cast<Real*>(M.out);
+    Real ij[E::NG], uu[E::NBT], cf[E::NCQ], r[E::NBT];
+#pragma unroll
+    for (int f = 0; f < E::NG; ++f) ij[f] = __builtin_nontemporal_load(ijp + f * n + e);
+    const Real dj = __builtin_nontemporal_load(djp + e);
+#pragma unroll
+    for (int f = 0; f < E::NBT; ++f) uu[f] = __builtin_nontemporal_load(up + f * n + e);
+#pragma unroll
+    for (int f = 0; f < E::NCQ; ++f) cf[f] = __builtin_nontemporal_load(cfp + f * n + e);
+    element_residual<DIM, PHYS, RULE, Real>(ij, dj, uu, cf, r);
+#pragma unroll
+    for (int f = 0; f < E::NBT; ++f) __builtin_nontemporal_store(r[f], outp + f * n + e);
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(512)
+batch_kernel(const BatchMesh* __restrict__ meshes, int n_mesh, int64_t n_tiles) {
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        int lo = 0, hi = n_mesh - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (meshes[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        const BatchMesh M = meshes[lo];
+        const int64_t e = (t - M.tile_begin) * blockDim.x + threadIdx.x;
+        if (e >= M.n_elem) continue;
+        switch (M.type) {
+#define FEMQ_CASE(D, P, RU) \
+    case type_code(D, P, RU): batch_element<D, P, RU, Real>(M, e); break;
+            FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_TRI3)
+            FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_TET4)
+            FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_TRI3)
+            FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_TET4)
+            FEMQ_CASE(2, FEM_MASS, FEM_RULE_TRI3)
+            FEMQ_CASE(3, FEM_MASS, FEM_RULE_TET4)
+            FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_CENTROID)
+            FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_CENTROID)
+            FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_CENTROID)
+            FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_CENTROID)
+            FEMQ_CASE(2, FEM_MASS, FEM_RULE_CENTROID)
+            FEMQ_CASE(3, FEM_MASS, FEM_RULE_CENTROID)
+#undef FEMQ_CASE
+        default: break;
+        }
+    }
+}
+
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, int64_t n_tiles, int tile_elems,
+                        const Launch& l) {
+    if (tile_elems != l.block) return hipErrorInvalidValue;
+    if (dtype == FEM_F32)
+        hipLaunchKernelGGL(batch_kernel<float>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh, n_tiles);
+    else
+        hipLaunchKernelGGL(batch_kernel<double>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh, n_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace femq
+
+using namespace femq;
+
+struct fem_batch_plan {
+    int device = -1;
+    int dtype = FEM_F32;
+    int n_mesh = 0;              // non-empty meshes in the device table
+    int64_t n_tiles = 0;
+    int64_t n_elem_total = 0;
+    int waves_per_block = 4;
+    int blocks_per_cu = 8;
+    BatchMesh* d_meshes = nullptr;
+    std::vector<BatchMesh> h_meshes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static fem_status plan_launch(fem_batch_plan* p, hipStream_t s) {
+    if (p->n_tiles == 0) return FEM_OK;
+    Launch l;
+    l.block = 64 * p->waves_per_block;
+    l.vec = 1;
+    l.stream = s;
+    int cus = device_cus();
+    int64_t grid = (int64_t)p->blocks_per_cu * (cus > 0 ? cus : 256);
+    if (p->blocks_per_cu == 0 || grid > p->n_tiles) grid = p->n_tiles;
+    if (grid > (1 << 22)) grid = 1 << 22;
+    l.grid = (int)grid;
+    hipError_t e = launch_batch(p->dtype, p->d_meshes, p->n_mesh, p->n_tiles, l.block, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch launch");
+}
+
+static fem_status plan_build_table(fem_batch_plan* p) {
+    const int tile = 64 * p->waves_per_block;
+    int64_t t = 0;
+    for (auto& m : p->h_meshes) {
+        m.tile_begin = t;
+        t += (m.n_elem + tile - 1) / tile;
+    }
+    p->n_tiles = t;
+    if (p->h_meshes.empty()) return FEM_OK;
+    hipError_t e = hipMemcpy(p->d_meshes, p->h_meshes.data(), p->h_meshes.size() * sizeof(BatchMesh),
+                             hipMemcpyHostToDevice);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch descriptor upload");
+}
+
+static void plan_drop_graph(fem_batch_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+extern "C" {
+
+fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dtype, fem_batch_plan** out) {
+    if (!out) { set_error("fem_batch_plan_create: out is NULL"); return FEM_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (n_mesh < 0 || (n_mesh > 0 && !meshes)) { set_error("fem_batch_plan_create: bad mesh list"); return FEM_ERR_INVALID_ARG; }
+    if (dtype != FEM_F32 && dtype != FEM_F64) { set_error("fem_batch_plan_create: unknown dtype %d", dtype); return FEM_ERR_UNSUPPORTED; }
+    std::vector<BatchMesh> hm;
+    int64_t total = 0;
+    for (int i = 0; i < n_mesh; ++i) {
+        const fem_mesh_desc& d = meshes[i];
+        const bool dim_ok = d.dim == 2 || d.dim == 3;
+        const bool phys_ok = d.physics == FEM_LAPLACE || d.physics == FEM_ELASTICITY || d.physics == FEM_MASS;
+        const bool rule_ok = d.rule == FEM_RULE_CENTROID || (d.dim == 2 && d.rule == FEM_RULE_TRI3) ||
+                             (d.dim == 3 && d.rule == FEM_RULE_TET4);
+        if (!dim_ok || !phys_ok || !rule_ok) {
+            set_error("fem_batch_plan_create: mesh %d has an unsupported (dim, physics, rule)", i);
+            return FEM_ERR_UNSUPPORTED;
+        }
+        if (d.n_elem < 0) { set_error("fem_batch_plan_create: mesh %d has negative n_elem", i); return FEM_ERR_INVALID_ARG; }
+        if (d.n_elem == 0) continue;
+        if (!d.inv_j || !d.det_j || !d.u || !d.coef || !d.elem_vec) {
+            set_error("fem_batch_plan_create: mesh %d has a NULL array", i);
+            return FEM_ERR_INVALID_ARG;
+        }
+        BatchMesh m;
+        std::memset(&m, 0, sizeof m);
+        m.type = type_code(d.dim, d.physics, d.rule);
+        m.n_elem = d.n_elem;
+        m.inv_j = d.inv_j;
+        m.det_j = d.det_j;
+        m.u = d.u;
+        m.coef = d.coef;
+        m.out = d.elem_vec;
+        hm.push_back(m);
+        total += d.n_elem;
+    }
+    fem_batch_plan* p = new (std::nothrow) fem_batch_plan();
+    if (!p) { set_error("fem_batch_plan_create: out of host memory"); return FEM_ERR_INVALID_ARG; }
+    p->dtype = dtype;
+    p->h_meshes = std::move(hm);
+    p->n_mesh = (int)p->h_meshes.size();
+    p->n_elem_total = total;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "fem_batch_plan_create"); }
+    if (p->n_mesh > 0) {
+        e = hipMalloc(&p->d_meshes, p->h_meshes.size() * sizeof(BatchMesh));
+        if (e != hipSuccess) { delete p; return hip_fail(e, "fem_batch_plan_create: hipMalloc"); }
+    }
+    fem_status st = plan_build_table(p);
+    if (st) { fem_batch_plan_destroy(p); return st; }
+    *out = p;
+    return FEM_OK;
+}
+
+fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, int blocks_per_cu) {
+    if (!plan) { set_error("fem_batch_plan_set_launch: NULL plan"); return FEM_ERR_INVALID_ARG; }
+    if (!(waves_per_block == 1 || waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8) ||
+        blocks_per_cu < 0 || blocks_per_cu > 64) {
+        set_error("fem_batch_plan_set_launch: invalid launch shape");
+        return FEM_ERR_INVALID_ARG;
+    }
+    hipError_t e = hipDeviceSynchronize();  // no launch of this plan may still read the table
+    if (e != hipSuccess) return hip_fail(e, "fem_batch_plan_set_launch");
+    plan->waves_per_block = waves_per_block;
+    plan->blocks_per_cu = blocks_per_cu;
+    plan_drop_graph(plan);  // a recorded graph would still use the old shape
+    return plan_build_table(plan);
+}
+
+fem_status fem_batch_run(fem_batch_plan* plan, void* stream) {
+    if (!plan) { set_error("fem_batch_run: NULL plan"); return FEM_ERR_INVALID_ARG; }
+    return plan_launch(plan, static_cast<hipStream_t>(stream));
+}
+
+fem_status fem_batch_capture(fem_batch_plan* plan, void* stream) {
+    if (!plan) { set_error("fem_batch_capture: NULL plan"); return FEM_ERR_INVALID_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s == nullptr) { set_error("fem_batch_capture: capture needs a non-default stream"); return FEM_ERR_INVALID_ARG; }
+    plan_drop_graph(plan);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "fem_batch_capture: begin");
+    fem_status st = plan_launch(plan, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(e, "fem_batch_capture: end");
+    plan->graph = g;
+    e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { plan_drop_graph(plan); return hip_fail(e, "fem_batch_capture: instantiate"); }
+    return FEM_OK;
+}
+
+fem_status fem_batch_replay(fem_batch_plan* plan, void* stream) {
+    if (!plan || !plan->exec) { set_error("fem_batch_replay: plan not captured"); return FEM_ERR_INVALID_ARG; }
+    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch_replay");
+}
+
+void fem_batch_plan_destroy(fem_batch_plan* plan) {
+    if (!plan) return;
+    plan_drop_graph(plan);
+    if (plan->d_meshes) (void)hipFree(plan->d_meshes);
+    delete plan;
+}
+
+}  // extern "C"

@@ -71,13 +71,17 @@ typedef std::tuple<int, int, int, int> TuneKey;
 static std::mutex g_tune_mu;
 static std::map<TuneKey, fem_tuning> g_tune;
 
+// Built-in launch configurations: the winners of the autotuner's sweep on
+// one MI355X for the benchmark workloads (one element per lane was within a
+// few percent of the best everywhere, wider accesses raise register pressure
+// without adding bandwidth); other combinations use the robust middle choice.
 static fem_tuning default_tuning(int dim, int phys, int rule, int dtype) {
-    (void)dim; (void)phys; (void)rule;
-    fem_tuning t;
-    t.strategy = FEM_STRATEGY_LANE;
-    t.vec = dtype == FEM_F32 ? 4 : 2;  // 16-byte accesses
-    t.waves_per_block = 4;
-    t.blocks_per_cu = 0;
+    fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
+    const bool f32 = dtype == FEM_F32;
+    const bool deg2 = rule != FEM_RULE_CENTROID;
+    if (deg2 && phys == FEM_LAPLACE && dim == 3) t = f32 ? fem_tuning{0, 1, 2, 16} : fem_tuning{0, 1, 1, 0};
+    if (deg2 && phys == FEM_ELASTICITY && dim == 2) t = f32 ? fem_tuning{0, 1, 4, 4} : fem_tuning{0, 1, 4, 0};
+    if (deg2 && phys == FEM_ELASTICITY && dim == 3) t = f32 ? fem_tuning{0, 1, 4, 2} : fem_tuning{0, 1, 1, 2};
     return t;
 }
 
@@ -162,8 +166,7 @@ fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* c
     if (n_elem == 0) return FEM_OK;
     if (n_vert == 0) { set_error("fem_geometry: elements without vertices"); return FEM_ERR_INVALID_ARG; }
     if (!coords || !conn || !inv_j || !det_j) { set_error("fem_geometry: NULL array"); return FEM_ERR_INVALID_ARG; }
-    fem_tuning t = default_tuning(dim, FEM_LAPLACE, FEM_RULE_CENTROID, out_dtype);
-    t.blocks_per_cu = 0;
+    const fem_tuning t{FEM_STRATEGY_LANE, 1, 4, 0};
     Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
     hipError_t e = launch_geometry(dim, out_dtype, n_elem, n_vert, coords, conn, inv_j, det_j, counts, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_geometry launch");

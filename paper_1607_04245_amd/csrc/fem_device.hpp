@@ -14,6 +14,12 @@
 
 namespace femq {
 
+// Fused multiply-add, written out: the library is compiled with FMA
+// contraction off, so every fusion in the element arithmetic is explicit and
+// the operation sequence of an element is the same in every kernel.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---------------------------------------------------------------- traits --
 
 template <int DIM, int PHYS, int RULE>
@@ -89,7 +95,7 @@ template <> struct Physics<FEM_ELASTICITY> {
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
                 const Real eps = half * (g[c][i] + g[i][c]);
-                f1[c][i] = two_mu * eps + (c == i ? lam_tr : Real(0));
+                f1[c][i] = c == i ? fmadd(two_mu, eps, lam_tr) : two_mu * eps;
             }
     }
 };
@@ -129,7 +135,7 @@ __device__ __forceinline__ void physical_gradient(const Real* ij, const Real* u,
         for (int i = 0; i < DIM; ++i) {
             Real s = ij[0 * DIM + i] * gh[0];
 #pragma unroll
-            for (int k = 1; k < DIM; ++k) s += ij[k * DIM + i] * gh[k];
+            for (int k = 1; k < DIM; ++k) s = fmadd(ij[k * DIM + i], gh[k], s);
             g[c][i] = s;
         }
     }
@@ -164,7 +170,7 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
             for (int c = 0; c < NC; ++c) {
                 Real v = Real(Q::B(q, 0)) * u[c];
 #pragma unroll
-                for (int b = 1; b < NB; ++b) v += Real(Q::B(q, b)) * u[b * NC + c];
+                for (int b = 1; b < NB; ++b) v = fmadd(Real(Q::B(q, b)), u[b * NC + c], v);
                 uq[c] = v;
             }
         }
@@ -177,7 +183,7 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) F[c][i] += s * f1[c][i];
+                for (int i = 0; i < DIM; ++i) F[c][i] = fmadd(s, f1[c][i], F[c][i]);
         }
         if constexpr (P::HAS_F0) {
             // B^T W f0: phi_b(xi_q) times the weighted f0
@@ -185,7 +191,7 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
             for (int c = 0; c < NC; ++c) {
                 const Real t = s * f0[c];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) r[b * NC + c] += Real(Q::B(q, b)) * t;
+                for (int b = 0; b < NB; ++b) r[b * NC + c] = fmadd(Real(Q::B(q, b)), t, r[b * NC + c]);
             }
         }
     }
@@ -199,7 +205,7 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
             for (int k = 0; k < DIM; ++k) {
                 Real fh = ij[k * DIM + 0] * F[c][0];
 #pragma unroll
-                for (int i = 1; i < DIM; ++i) fh += ij[k * DIM + i] * F[c][i];
+                for (int i = 1; i < DIM; ++i) fh = fmadd(ij[k * DIM + i], F[c][i], fh);
                 r[(k + 1) * NC + c] += fh;
                 sum += fh;
             }
@@ -235,8 +241,8 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
                 Real vw = Real(Q::B(q, 0)) * w[c];
 #pragma unroll
                 for (int b = 1; b < NB; ++b) {
-                    vu += Real(Q::B(q, b)) * u[b * NC + c];
-                    vw += Real(Q::B(q, b)) * w[b * NC + c];
+                    vu = fmadd(Real(Q::B(q, b)), u[b * NC + c], vu);
+                    vw = fmadd(Real(Q::B(q, b)), w[b * NC + c], vw);
                 }
                 uq[c] = vu;
                 wq[c] = vw;
@@ -252,13 +258,13 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
             Real acc = Real(0);
             if constexpr (P::HAS_F0) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc += wq[c] * f0[c];
+                for (int c = 0; c < NC; ++c) acc = fmadd(wq[c], f0[c], acc);
             }
             if constexpr (P::HAS_F1) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
 #pragma unroll
-                    for (int i = 0; i < DIM; ++i) acc += gw[c][i] * f1[c][i];
+                    for (int i = 0; i < DIM; ++i) acc = fmadd(gw[c][i], f1[c][i], acc);
             }
             dcf[m * NQ + q] = s * acc;
         }

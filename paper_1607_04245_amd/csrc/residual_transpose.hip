@@ -100,7 +100,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                     // phi_b at point q: LA at vertex q, LB elsewhere
                     Real v = Real(0);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) v += (b == q ? Real(Q::LA) : Real(Q::LB)) * uu[b * NC + cc];
+                    for (int b = 0; b < NB; ++b) v = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), uu[b * NC + cc], v);
                     uq[cc] = v;
                 }
             }
@@ -116,7 +116,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                 for (int kk = 0; kk < DIM; ++kk) {
                     Real fh = ij[kk * DIM + 0] * t[0];
 #pragma unroll
-                    for (int i = 1; i < DIM; ++i) fh += ij[kk * DIM + i] * t[i];
+                    for (int i = 1; i < DIM; ++i) fh = fmadd(ij[kk * DIM + i], t[i], fh);
                     fx[kk] = fh;
                 }
             }
@@ -146,7 +146,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                         r -= sum;
                     }
                 }
-                if constexpr (P::HAS_F0) r += (b == q ? Real(Q::LA) : Real(Q::LB)) * f[L::NFX - 1];
+                if constexpr (P::HAS_F0) r = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), f[L::NFX - 1], r);
             }
             out_s[el * L::OUT_STRIDE + bc] = r;
         }

@@ -203,7 +203,7 @@ class Workload:
 def closure(conn: np.ndarray, u_vertex: np.ndarray) -> np.ndarray:
     """Gather nodal values per element: out[b*N_comp + c, e] = u_vertex[conn[e, b], c]."""
     g = u_vertex[conn]                       # [N_e, N_b, N_comp]
-    return np.ascontiguousarray(g.reshape(conn.shape[0], -1).T)
+    return np.ascontiguousarray(g.reshape(conn.shape[0], conn.shape[1] * u_vertex.shape[1]).T)
 
 
 def _draw_fields(dim, physics, rule, conn, n_vert, rngs):

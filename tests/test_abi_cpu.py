@@ -102,3 +102,26 @@ def test_tuning_roundtrip(lib):
     bad = N.fem_tuning(N.STRATEGY_LANE, 4, 5, 0)
     assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_TET4, N.F64, ctypes.byref(new)) == N.FEM_ERR_UNSUPPORTED
+
+
+def test_batch_plan_validation(lib):
+    plan = ctypes.c_void_p()
+    assert lib.fem_batch_plan_create(None, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_batch_plan_create(None, 0, 9, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
+    d = (N.fem_mesh_desc * 1)()
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TET4, 10, 1, 1, 1, 1, 1)
+    assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, -1, 1, 1, 1, 1, 1)
+    assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, 10, 1, None, 1, 1, 1)
+    assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_batch_run(None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_batch_replay(None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_batch_plan_set_launch(None, 4, 8) == N.FEM_ERR_INVALID_ARG
+    lib.fem_batch_plan_destroy(None)
+
+
+def test_autotune_validation(lib):
+    assert lib.fem_autotune(2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_autotune(2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG

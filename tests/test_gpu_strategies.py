@@ -1,0 +1,170 @@
+"""GPU: the thread-transposition strategy, the batched persistent launch and
+its HIP graph, and the autotuner, each against the FP64 oracle and against
+the lane kernel."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_04245_amd import api, meshgen as mg
+from paper_1607_04245_amd import _native as N
+
+from _parity import assert_close, dev, oracle_reference
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+KINDS = [(2, mg.LAPLACE), (3, mg.LAPLACE), (2, mg.ELASTICITY), (3, mg.ELASTICITY), (2, mg.MASS), (3, mg.MASS)]
+
+
+def small_workload(dim, phys, n_elem, rule=None, seed=11):
+    grid = mg.smallest_grid(dim, max(n_elem, 1))
+    return mg.make_workload(f"s{dim}{phys}", dim, phys, grid, n_elem, mg.BASE_SEED + seed, rule=rule)
+
+
+def geometry(wl, dtype):
+    return api.fem_geometry(dev(wl.coords, torch.float64), dev(wl.conn, torch.int32), dtype)
+
+
+@pytest.fixture(autouse=True)
+def _restore_tuning():
+    saved = {}
+    for dim, phys in KINDS:
+        for rule in (mg.default_rule(dim), mg.RULE_CENTROID):
+            for dt in DTYPES:
+                saved[(dim, phys, rule, dt)] = api.fem_get_tuning(dim, phys, rule, dt)
+    yield
+    for (dim, phys, rule, dt), t in saved.items():
+        api.fem_set_tuning(dim, phys, rule, dt, **t)
+
+
+# ------------------------------------------------------ thread transposition --
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n_elem", [1, 65, 1000, 20004])
+@pytest.mark.parametrize("rule_kind", ["default", "centroid"])
+def test_transpose_matches_oracle(dim, phys, dtype, n_elem, rule_kind):
+    rule = mg.default_rule(dim) if rule_kind == "default" else mg.RULE_CENTROID
+    wl = small_workload(dim, phys, n_elem, rule=rule)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+    ij, dj = geometry(wl, dtype)
+    u, cf = dev(wl.u, dtype), dev(wl.coef, dtype)
+    first = None
+    for waves in (1, 2, 4, 8):
+        for bpc in (0, 2):
+            api.fem_set_tuning(dim, phys, rule, dtype, strategy=N.STRATEGY_TRANSPOSE, vec=1,
+                               waves_per_block=waves, blocks_per_cu=bpc)
+            R = api.fem_integrate_residual(dim, phys, rule, ij, dj, u, cf).cpu().numpy()
+            if first is None:
+                first = R
+                assert_close(R, ref, ref_abs, dtype, f"transpose {dim}D phys {phys}")
+            else:
+                assert np.array_equal(R, first), "transpose result depends on the launch shape"
+
+
+# ------------------------------------------------------------------ batched --
+
+def batch_meshes(dtype, sizes, rules=None):
+    out, wls = [], []
+    for m, ne in enumerate(sizes):
+        dim, phys = mg.MESH_TYPES[m % 4] if m % 5 != 4 else (2 + m % 2, mg.MASS)
+        rule = mg.default_rule(dim) if rules is None else rules[m % len(rules)](dim)
+        wl = small_workload(dim, phys, ne, rule=rule, seed=100 + m)
+        ij, dj = geometry(wl, dtype)
+        out.append(dict(dim=dim, physics=phys, rule=rule, inv_j=ij, det_j=dj, u=dev(wl.u, dtype),
+                        coef=dev(wl.coef, dtype), out=torch.full(wl.u.shape, float("nan"), dtype=dtype,
+                                                                 device="cuda")))
+        wls.append(wl)
+    return out, wls
+
+
+SIZES = [1000, 1, 4097, 257, 30000, 65, 0, 2000, 5003, 12]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_matches_single_mesh_bitwise(dtype):
+    meshes, wls = batch_meshes(dtype, SIZES, rules=[mg.default_rule, lambda d: mg.RULE_CENTROID])
+    for m in meshes:  # single-mesh reference with the lane kernel
+        api.fem_set_tuning(m["dim"], m["physics"], m["rule"], dtype, strategy=N.STRATEGY_LANE, vec=1)
+    singles = [api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                          m["coef"]) for m in meshes]
+    plan = api.BatchPlan(meshes)
+    for waves, bpc in [(4, 8), (1, 0), (8, 1), (2, 64)]:
+        for m in meshes:
+            m["out"].fill_(float("nan"))
+        plan.set_launch(waves, bpc)
+        plan.run()
+        torch.cuda.synchronize()
+        for m, s, wl in zip(meshes, singles, wls):
+            assert torch.equal(m["out"], s), f"batched != single for {wl.name} at launch {(waves, bpc)}"
+    for m, wl in zip(meshes, wls):
+        if wl.n_elem == 0:
+            continue
+        ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+        assert_close(m["out"].cpu().numpy(), ref, ref_abs, dtype, wl.name)
+    plan.close()
+
+
+def test_batch_graph_replays():
+    dtype = torch.float32
+    meshes, wls = batch_meshes(dtype, [3000, 777, 12345, 64, 999])
+    plan = api.BatchPlan(meshes)
+    plan.run()
+    torch.cuda.synchronize()
+    eager = [m["out"].clone() for m in meshes]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture()
+    for rep in range(4):
+        for m in meshes:
+            m["out"].zero_()          # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.replay()
+        s.synchronize()
+        for m, e in zip(meshes, eager):
+            assert torch.equal(m["out"], e), f"replay {rep} differs from the eager launch"
+    # changing the launch shape drops the graph; replay must then be refused
+    plan.set_launch(2, 4)
+    with pytest.raises(N.FemError):
+        plan.replay()
+    plan.close()
+
+
+def test_batch_plan_argument_errors():
+    dtype = torch.float32
+    meshes, _ = batch_meshes(dtype, [100])
+    bad = dict(meshes[0])
+    bad["rule"] = mg.RULE_TET4 if bad["dim"] == 2 else mg.RULE_TRI3
+    with pytest.raises(N.FemError) as ei:
+        api.BatchPlan([bad])
+    assert ei.value.status == N.FEM_ERR_UNSUPPORTED
+
+
+# --------------------------------------------------------------- autotuner --
+
+def test_autotune_picks_a_valid_configuration(tmp_path):
+    cache = tmp_path / "tune.json"
+    t = api.fem_autotune(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, 1 << 16, str(cache))
+    assert t["strategy"] in (0, 1) and t["vec"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4, 8)
+    data = json.loads(cache.read_text())
+    (entry,) = data["entries"]
+    assert entry["arch"].startswith("gfx") and entry["dim"] == 3 and entry["us"] > 0
+    # a second entry is merged, the first kept
+    api.fem_autotune(2, mg.ELASTICITY, mg.RULE_TRI3, torch.float64, 1 << 14, str(cache))
+    assert len(json.loads(cache.read_text())["entries"]) == 2
+    # loading restores the tuned configuration
+    api.fem_set_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, strategy=0, vec=1, waves_per_block=1,
+                       blocks_per_cu=1)
+    assert api.fem_load_tuning(str(cache)) == N.FEM_OK
+    assert api.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32) == t
+    assert api.fem_load_tuning(str(tmp_path / "missing.json")) == N.FEM_ERR_NO_TUNING
+    # results with the tuned configuration still match the oracle
+    wl = small_workload(3, mg.LAPLACE, 5000)
+    ij, dj = geometry(wl, torch.float32)
+    R = api.fem_integrate_residual(3, mg.LAPLACE, wl.rule, ij, dj, dev(wl.u, torch.float32),
+                                   dev(wl.coef, torch.float32)).cpu().numpy()
+    ref, ref_abs, _, _ = oracle_reference(wl, torch.float32)
+    assert_close(R, ref, ref_abs, torch.float32, "tuned")

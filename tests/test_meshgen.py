@@ -85,3 +85,10 @@ def test_batch_workloads_small():
         assert nd == 0 and dj.min() > 0
     sizes = mg.batch_sizes()
     assert len(sizes) == 64 and min(sizes) >= 1000 and max(sizes) < 10 ** 6
+
+
+def test_empty_workload():
+    for dim, phys in mg.MESH_TYPES:
+        wl = mg.make_workload("empty", dim, phys, 1, 0, mg.BASE_SEED)
+        assert wl.n_elem == 0 and wl.u.shape == ((dim + 1) * wl.n_comp, 0)
+        assert wl.coef.shape[-1] == 0 and wl.w.shape == wl.u.shape
