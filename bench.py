@@ -3,9 +3,11 @@
 
 A step is one pass of the hot path over the 3D variable-coefficient Laplacian
 workload (P1 tetrahedra, 2^20 elements of a jittered 64^3 Kuhn grid, 4-point
-degree-2 rule, kappa ~ U[0.5, 2] per quadrature point, u ~ U[-1, 1]):
-fem_geometry (coordinates and connectivity to J^{-1}, det J), then
-fem_integrate_residual, in FP32. All inputs are resident in HBM before the
+degree-2 rule, kappa ~ U[0.5, 2] per quadrature point, u ~ U[-1, 1]): element
+residuals from coordinates, connectivity, closure and coefficients, in FP32,
+with geometry and integration fused in one kernel
+(fem_integrate_residual_mesh). The same step as two calls (fem_geometry, then
+fem_integrate_residual) is reported beside it. All inputs are resident in HBM before the
 timed region. They are replicated into several copies (> 512 MB in total) and
 the steps rotate through them, so the 256 MB last-level cache cannot serve a
 step from the data of the one before.
@@ -58,6 +60,7 @@ def source_hash(files):
 
 CSRC = "paper_1607_04245_amd/csrc/"
 KERNEL_SOURCES = {
+    "fem_integrate_residual_mesh": [CSRC + "residual_mesh.hip", CSRC + "fem_device.hpp", CSRC + "fem_abi.hip"],
     "fem_integrate_residual": [CSRC + "residual_lane.hip", CSRC + "fem_device.hpp", CSRC + "fem_abi.hip"],
     "fem_geometry": [CSRC + "geometry.hip", CSRC + "fem_abi.hip"],
 }
@@ -128,68 +131,109 @@ def main():
             cs.append(c)
         return cs
 
+    def fused(c):
+        api.fem_integrate_residual_mesh(dim, phys, rule, c["coords"], c["conn"], c["u"], c["coef"], out=c["R"])
+
     def geometry(c):
         api.fem_geometry(c["coords"], c["conn"], c["det_j"].dtype, inv_j=c["inv_j"], det_j=c["det_j"])
 
     def integrate(c):
         api.fem_integrate_residual(dim, phys, rule, c["inv_j"], c["det_j"], c["u"], c["coef"], out=c["R"])
 
-    def timed_steps(cs, steps, warmup):
-        """The timed region: `steps` steps, events around the integration
-        kernel only (geometry runs unbracketed between them)."""
+    def timed_fused(cs, steps, warmup):
+        """The timed region: `steps` fused steps, each bracketed by events."""
         for i in range(warmup):
-            geometry(cs[i % len(cs)])
-            integrate(cs[i % len(cs)])
+            fused(cs[i % len(cs)])
         torch.cuda.synchronize()
         pairs = []
         t = time.perf_counter()
         for i in range(steps):
-            c = cs[i % len(cs)]
-            geometry(c)
             s = ev()
-            integrate(c)
+            fused(cs[i % len(cs)])
             pairs.append((s, ev()))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         return wall, sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
 
-    def kernel_breakdown(cs, reps=20):
-        """Untimed pass: each kernel of the step bracketed by events."""
-        g, i = [], []
-        for r in range(reps):
+    def timed_split(cs, steps, warmup):
+        """The same step as two calls (geometry stored, then integration):
+        wall time with nothing bracketed, then a pass with each kernel
+        bracketed by events."""
+        for i in range(warmup):
+            geometry(cs[i % len(cs)])
+            integrate(cs[i % len(cs)])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            geometry(cs[i % len(cs)])
+            integrate(cs[i % len(cs)])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        g, it = [], []
+        for r in range(20):
             c = cs[r % len(cs)]
             s = ev()
             geometry(c)
             m = ev()
             integrate(c)
-            i.append((m, ev()))
+            it.append((m, ev()))
             g.append((s, m))
         torch.cuda.synchronize()
-        return (sum(a.elapsed_time(b) for a, b in g) / reps, sum(a.elapsed_time(b) for a, b in i) / reps)
+        return wall, sum(a.elapsed_time(b) for a, b in g) / 20, sum(a.elapsed_time(b) for a, b in it) / 20
 
     cs = step_copies(torch.float32)
-    wall, int_ms = timed_steps(cs, args.steps, args.warmup)
-    geo_ms, int_ms_b = kernel_breakdown(cs)
+    wall, fused_ms = timed_fused(cs, args.steps, args.warmup)
+    swall, geo_ms, int_ms = timed_split(cs, args.steps, args.warmup)
     del cs
     ms_per_step = 1e3 * wall / args.steps
     value = n * args.steps / wall
-    log(f"FP32 step {ms_per_step * 1e3:.1f} us ({value:.3e} elem/s): integrate {int_ms * 1e3:.1f} us in the timed "
-        f"region; breakdown geometry {geo_ms * 1e3:.1f} us, integrate {int_ms_b * 1e3:.1f} us")
+    log(f"FP32 fused step {ms_per_step * 1e3:.1f} us ({value:.3e} elem/s), kernel {fused_ms * 1e3:.1f} us; "
+        f"two-call step {1e6 * swall / args.steps:.1f} us (geometry {geo_ms * 1e3:.1f} us, integrate "
+        f"{int_ms * 1e3:.1f} us)")
 
+    fused_bytes = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 4) * n
     int_bytes = model.forward_bytes(dim, phys, rule, 4) * n
     geo_bytes = model.geometry_bytes(dim, n, wl.n_vert, 4) * n
     kernels = {
+        "fem_integrate_residual_mesh": dict(avg_us=fused_ms * 1e3, algorithmic_bytes=fused_bytes,
+                                            gbs=fused_bytes / (fused_ms * 1e-3) / 1e9,
+                                            elements_per_s=n / (fused_ms * 1e-3),
+                                            model_gflops=n * flops / (fused_ms * 1e-3) / 1e9),
         "fem_integrate_residual": dict(avg_us=int_ms * 1e3, algorithmic_bytes=int_bytes,
                                        gbs=int_bytes / (int_ms * 1e-3) / 1e9, elements_per_s=n / (int_ms * 1e-3),
                                        model_gflops=n * flops / (int_ms * 1e-3) / 1e9),
         "fem_geometry": dict(avg_us=geo_ms * 1e3, algorithmic_bytes=geo_bytes,
                              gbs=geo_bytes / (geo_ms * 1e-3) / 1e9, elements_per_s=n / (geo_ms * 1e-3)),
     }
-    dom = "fem_integrate_residual" if int_ms_b >= geo_ms else "fem_geometry"
+    dom = "fem_integrate_residual_mesh"
     dk = kernels[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, "laplace3d_2p20_f32"),
                 "algorithmic_bytes_per_launch": dk["algorithmic_bytes"]}
+
+    # ------------------------------------------------- achievable bandwidth --
+    def copy_gbs(nbytes, reps):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        k = 1 if nbytes >= 2**30 else n_copies(2 * nbytes)
+        srcs = [src] + [src.clone() for _ in range(k - 1)]
+        dsts = [torch.empty_like(src) for _ in range(k)]
+        for i in range(3):
+            api.fem_stream_copy(srcs[i % k], dsts[i % k])
+        pairs = []
+        for i in range(reps):
+            s = ev()
+            api.fem_stream_copy(srcs[i % k], dsts[i % k])
+            pairs.append((s, ev()))
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
+        return 2 * nbytes / (t * 1e-3) / 1e9, t * 1e3
+
+    big_gbs, big_us = copy_gbs(2 << 30, 10)
+    same_gbs, same_us = copy_gbs(int(dk["algorithmic_bytes"] // 2) // 16 * 16, 20)
+    roofline["achievable_gbs"] = big_gbs
+    roofline["frac_of_achievable"] = dk["gbs"] / big_gbs
+    roofline["achievable_gbs_same_bytes"] = same_gbs
+    log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the fused kernel's byte count")
 
     result = {
         "metric": METRIC,
@@ -205,12 +249,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "3D variable-coefficient Laplacian, P1 tetrahedra, 2^20 elements of a jittered "
-                               "64^3 Kuhn grid, 4-point degree-2 rule; step = fem_geometry + "
-                               "fem_integrate_residual",
+                               "64^3 Kuhn grid, 4-point degree-2 rule; step = element residuals from coordinates, "
+                               "connectivity, closure and coefficients (fem_integrate_residual_mesh: geometry and "
+                               "integration in one pass)",
                    "n_elem": n, "n_vert": wl.n_vert},
         "model_gflops": value * flops / 1e9,
         "kernels": kernels,
         "roofline": roofline,
+        "two_call_step": dict(elements_per_s=n * args.steps / swall, ms_per_step=1e3 * swall / args.steps,
+                              note="fem_geometry (geometry stored) then fem_integrate_residual"),
+        "stream_copy": dict(gbs_2gib=big_gbs, us_2gib=big_us, gbs_same_bytes=same_gbs, us_same_bytes=same_us),
     }
 
     if not args.quick:
@@ -219,42 +267,19 @@ def main():
         # ------------------------------------------------------ FP64 step --
         cs = step_copies(torch.float64)
         steps64 = max(10, args.steps // 2)
-        wall64, i64 = timed_steps(cs, steps64, 2)
-        g64, _ = kernel_breakdown(cs)
+        wall64, f64 = timed_fused(cs, steps64, 2)
+        swall64, g64, i64 = timed_split(cs, steps64, 2)
         del cs
         b64 = model.forward_bytes(dim, phys, rule, 8) * n
+        fb64 = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 8) * n
         extra["fp64_step"] = dict(elements_per_s=n * steps64 / wall64, ms_per_step=1e3 * wall64 / steps64,
+                                  fused_us=f64 * 1e3, fused_gbs=fb64 / (f64 * 1e-3) / 1e9,
+                                  fused_model_gflops=n * flops / (f64 * 1e-3) / 1e9,
+                                  two_call_elements_per_s=n * steps64 / swall64,
                                   integrate_us=i64 * 1e3, integrate_gbs=b64 / (i64 * 1e-3) / 1e9,
                                   integrate_model_gflops=n * flops / (i64 * 1e-3) / 1e9, geometry_us=g64 * 1e3)
-        log(f"FP64 step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us; integrate {i64 * 1e3:.1f} us "
-            f"({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
-
-        # --------------------------------------------- achievable bandwidth --
-        def copy_gbs(nbytes, reps):
-            src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-            dsts = [torch.empty_like(src) for _ in range(n_copies(2 * nbytes) if nbytes < 2**30 else 1)]
-            srcs = [src] + [src.clone() for _ in range(len(dsts) - 1)]
-            for k in range(3):
-                api.fem_stream_copy(srcs[k % len(srcs)], dsts[k % len(dsts)])
-            pairs = []
-            for k in range(reps):
-                s = ev()
-                api.fem_stream_copy(srcs[k % len(srcs)], dsts[k % len(dsts)])
-                pairs.append((s, ev()))
-            torch.cuda.synchronize()
-            t = sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
-            return 2 * nbytes / (t * 1e-3) / 1e9, t * 1e3
-
-        big_gbs, big_us = copy_gbs(2 << 30, 10)
-        same_gbs, same_us = copy_gbs((int_bytes // 2) // 16 * 16, 20)
-        extra["stream_copy"] = dict(gbs_2gib=big_gbs, us_2gib=big_us,
-                                    gbs_same_bytes=same_gbs, us_same_bytes=same_us,
-                                    note="read+write copy; 'same_bytes' moves as many bytes as one "
-                                         "integration launch of the step")
-        roofline["achievable_gbs"] = big_gbs
-        roofline["frac_of_achievable"] = dk["gbs"] / big_gbs
-        roofline["achievable_gbs_same_bytes"] = same_gbs
-        log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the step's byte count")
+        log(f"FP64 fused step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us ({extra['fp64_step']['fused_gbs']:.0f}"
+            f" GB/s); integrate alone {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
 
         # --------------------------------------------------- other physics --
         def integrate_only(wlx, dt, reps=20):

@@ -85,6 +85,14 @@ enum fem_rule { FEM_RULE_TRI3 = 0, FEM_RULE_TET4 = 1, FEM_RULE_CENTROID = 2 };
  *                          for the basis phase, with no cross-lane reduction. */
 enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1 };
 
+/* Operations; each has its own launch configuration (see fem_tuning). */
+enum fem_op {
+    FEM_OP_RESIDUAL = 0,       /* fem_integrate_residual */
+    FEM_OP_RESIDUAL_MESH = 1,  /* fem_integrate_residual_mesh */
+    FEM_OP_GEOMETRY = 2,       /* fem_geometry (physics and rule ignored) */
+    FEM_OP_BACKWARD = 3        /* fem_integrate_residual_backward */
+};
+
 /* ------------------------------------------------------------------ */
 /* Geometry (paper Section 3: the kernel reads precomputed Jacobian    */
 /* inverses and determinants; this call produces them).                */
@@ -117,6 +125,21 @@ fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* c
 fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int64_t n_elem,
                                   const void* inv_j, const void* det_j, const void* u,
                                   const void* coef, void* elem_vec, void* stream);
+
+/* Residual straight from the mesh: geometry and integration fused in one
+ * pass over the elements, with no round trip of J^{-1} and det J through
+ * memory. The geometry is computed exactly as fem_geometry computes it (FP64,
+ * rounded once to `dtype`) and the integration is that of
+ * fem_integrate_residual, so elem_vec is bitwise equal to calling the two in
+ * turn. inv_j and det_j are optional outputs (both NULL, or both set: then
+ * they receive what fem_geometry would write); counts as in fem_geometry
+ * (may be NULL). Layouts as above; coords [n_vert][dim] double, conn
+ * [n_elem][dim+1] int32.
+ * Errors: as fem_integrate_residual and fem_geometry. */
+fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int dtype, int64_t n_elem,
+                                       int64_t n_vert, const double* coords, const int32_t* conn,
+                                       const void* u, const void* coef, void* elem_vec,
+                                       void* inv_j, void* det_j, int32_t* counts, void* stream);
 
 /* Adjoint of L = sum_e w_e . R_e (not in the paper; the gradient of the
  * residual for automatic differentiation):
@@ -178,22 +201,26 @@ void fem_batch_plan_destroy(fem_batch_plan* plan);
 /* ------------------------------------------------------------------ */
 
 typedef struct fem_tuning {
-    int strategy;        /* enum fem_strategy */
-    int vec;             /* elements per lane in the coalesced load/store phases: 1, 2 or 4 */
+    int strategy;        /* enum fem_strategy; FEM_STRATEGY_TRANSPOSE only for FEM_OP_RESIDUAL */
+    int vec;             /* elements per lane: RESIDUAL and BACKWARD read 1, 2 or 4
+                          * consecutive elements per vector access; GEOMETRY (1, 2, 4)
+                          * and RESIDUAL_MESH (1, 2) give each lane that many elements
+                          * 64 apart, to overlap their dependent vertex gathers */
     int waves_per_block; /* 1, 2, 4 or 8 (wave64) */
     int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */
 } fem_tuning;
 
-/* The configuration used for (dim, physics, rule, dtype): the last one set
- * or tuned in this process, else a built-in default. */
-fem_status fem_get_tuning(int dim, int physics, int rule, int dtype, fem_tuning* out);
-/* Override the configuration for (dim, physics, rule, dtype) in this process. */
-fem_status fem_set_tuning(int dim, int physics, int rule, int dtype, const fem_tuning* t);
-/* Sweep launch configurations on synthetic device data of n_elem_probe
- * elements (allocated and freed here, on the current device), time each
- * with HIP events, keep the fastest for this process, and, if cache_path is
- * not NULL, merge it into that JSON cache file. Synchronizes the device. */
-fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_elem_probe,
+/* The configuration used for (op, dim, physics, rule, dtype): the last one
+ * set or tuned in this process, else a built-in default. */
+fem_status fem_get_tuning(int op, int dim, int physics, int rule, int dtype, fem_tuning* out);
+/* Override the configuration for (op, dim, physics, rule, dtype) in this process. */
+fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, const fem_tuning* t);
+/* Sweep launch configurations of `op` on synthetic device data of
+ * n_elem_probe elements (a structured mesh for the mesh operations;
+ * allocated and freed here, on the current device), time each with HIP
+ * events, keep the fastest for this process, and, if cache_path is not NULL,
+ * merge it into that JSON cache file. Synchronizes the device. */
+fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64_t n_elem_probe,
                         const char* cache_path);
 /* Load tuned configurations from a JSON cache written by fem_autotune.
  * Returns FEM_ERR_NO_TUNING if the file is missing or holds no entry for

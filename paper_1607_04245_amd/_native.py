@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "FEM_OK", -1: "FEM_ERR_INVALID_ARG", -2: "FEM_ERR_UNSUPPORTED
 
 F32, F64 = 0, 1
 STRATEGY_LANE, STRATEGY_TRANSPOSE = 0, 1
+OP_RESIDUAL, OP_RESIDUAL_MESH, OP_GEOMETRY, OP_BACKWARD = 0, 1, 2, 3
 
 
 class FemError(RuntimeError):
@@ -54,6 +55,7 @@ _i64 = ctypes.c_int64
 SIGNATURES = {
     "fem_geometry": (_i, [_i, _i64, _i64, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual_mesh": (_i, [_i, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),
@@ -61,9 +63,9 @@ SIGNATURES = {
     "fem_batch_capture": (_i, [_vp, _vp]),
     "fem_batch_replay": (_i, [_vp, _vp]),
     "fem_batch_plan_destroy": (None, [_vp]),
-    "fem_get_tuning": (_i, [_i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
-    "fem_set_tuning": (_i, [_i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
-    "fem_autotune": (_i, [_i, _i, _i, _i, _i64, ctypes.c_char_p]),
+    "fem_get_tuning": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
+    "fem_set_tuning": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
+    "fem_autotune": (_i, [_i, _i, _i, _i, _i, _i64, ctypes.c_char_p]),
     "fem_load_tuning": (_i, [ctypes.c_char_p]),
     "fem_stream_copy": (_i, [_vp, _vp, _i64, _vp]),
     "fem_last_error": (ctypes.c_char_p, []),

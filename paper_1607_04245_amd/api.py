@@ -102,6 +102,39 @@ def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, c
     return out
 
 
+def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn, u, coef, out=None,
+                                inv_j=None, det_j=None, counts=None):
+    """Element residuals straight from coordinates and connectivity (geometry
+    fused into the integration; bitwise equal to fem_geometry followed by
+    fem_integrate_residual). Pass inv_j and det_j to also receive the geometry."""
+    dtype = u.dtype
+    if dtype not in _DT:
+        raise TypeError("u must be float32 or float64")
+    _need(coords, "coords", torch.float64)
+    _need(conn, "conn", torch.int32)
+    if coords.dim() != 2 or coords.shape[1] != dim or conn.dim() != 2 or conn.shape[1] != dim + 1:
+        raise ValueError(f"coords must be [n_vert, {dim}] and conn [n_elem, {dim + 1}]")
+    n = conn.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    _need(u, "u", dtype, su)
+    _need(coef, "coef", dtype, scf)
+    if out is None:
+        out = torch.empty(su, dtype=dtype, device=u.device)
+    _need(out, "out", dtype, su)
+    if (inv_j is None) != (det_j is None):
+        raise ValueError("pass both inv_j and det_j, or neither")
+    if inv_j is not None:
+        _need(inv_j, "inv_j", dtype, sij)
+        _need(det_j, "det_j", dtype, sdj)
+    if counts is not None:
+        _need(counts, "counts", torch.int32, (2,))
+    N.check(N.lib().fem_integrate_residual_mesh(dim, physics, rule, _DT[dtype], n, coords.shape[0], _ptr(coords),
+                                                _ptr(conn), _ptr(u), _ptr(coef), _ptr(out), _ptr(inv_j),
+                                                _ptr(det_j), _ptr(counts), _stream()),
+            "fem_integrate_residual_mesh")
+    return out
+
+
 def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
                                     want_du=True, want_dcoef=True, du=None, dcoef=None):
     """(du [N_bt, n] or None, dcoef [N_coef, N_q, n] or None) for L = sum w . R."""
@@ -143,22 +176,23 @@ def fem_stream_copy(src: torch.Tensor, dst: torch.Tensor):
 
 # ------------------------------------------------------------------ tuning --
 
-def fem_get_tuning(dim, physics, rule, dtype) -> dict:
+def fem_get_tuning(dim, physics, rule, dtype, op=N.OP_RESIDUAL) -> dict:
     t = N.fem_tuning()
-    N.check(N.lib().fem_get_tuning(dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)), "fem_get_tuning")
+    N.check(N.lib().fem_get_tuning(op, dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)), "fem_get_tuning")
     return dict(strategy=t.strategy, vec=t.vec, waves_per_block=t.waves_per_block, blocks_per_cu=t.blocks_per_cu)
 
 
-def fem_set_tuning(dim, physics, rule, dtype, strategy=N.STRATEGY_LANE, vec=4, waves_per_block=4,
-                   blocks_per_cu=0):
+def fem_set_tuning(dim, physics, rule, dtype, strategy=N.STRATEGY_LANE, vec=1, waves_per_block=2,
+                   blocks_per_cu=0, op=N.OP_RESIDUAL):
     t = N.fem_tuning(strategy, vec, waves_per_block, blocks_per_cu)
-    N.check(N.lib().fem_set_tuning(dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)), "fem_set_tuning")
+    N.check(N.lib().fem_set_tuning(op, dim, physics, rule, _DT.get(dtype, dtype), ctypes.byref(t)),
+            "fem_set_tuning")
 
 
-def fem_autotune(dim, physics, rule, dtype, n_elem_probe=1 << 20, cache_path=None) -> dict:
+def fem_autotune(dim, physics, rule, dtype, n_elem_probe=1 << 20, cache_path=None, op=N.OP_RESIDUAL) -> dict:
     cp = cache_path.encode() if cache_path else None
-    N.check(N.lib().fem_autotune(dim, physics, rule, _DT.get(dtype, dtype), n_elem_probe, cp), "fem_autotune")
-    return fem_get_tuning(dim, physics, rule, dtype)
+    N.check(N.lib().fem_autotune(op, dim, physics, rule, _DT.get(dtype, dtype), n_elem_probe, cp), "fem_autotune")
+    return fem_get_tuning(dim, physics, rule, dtype, op=op)
 
 
 def fem_load_tuning(cache_path: str) -> int:

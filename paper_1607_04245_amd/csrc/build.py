@@ -19,7 +19,8 @@ PKG = HERE.parent
 ROOT = PKG.parent
 BUILD = PKG / "_build"
 LIB = PKG / "libfemq.so"
-SOURCES = ["fem_abi.hip", "geometry.hip", "residual_lane.hip", "residual_transpose.hip", "backward_lane.hip",
+SOURCES = ["fem_abi.hip", "geometry.hip", "residual_lane.hip", "residual_transpose.hip", "residual_mesh.hip",
+           "backward_lane.hip",
            "batch.hip", "tune.hip"]
 
 ARCH = "gfx950"

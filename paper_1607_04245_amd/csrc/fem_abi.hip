@@ -67,17 +67,29 @@ static fem_status check_combo(const char* fn, int dim, int phys, int rule, int d
 
 // ---------------------------------------------------------------- tuning --
 
-typedef std::tuple<int, int, int, int> TuneKey;
+typedef std::tuple<int, int, int, int, int> TuneKey;
 static std::mutex g_tune_mu;
 static std::map<TuneKey, fem_tuning> g_tune;
 
+static bool valid_op(int op) {
+    return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD;
+}
+
+// The geometry does not depend on physics or rule: one key per (dim, dtype).
+static TuneKey tune_key(int op, int dim, int phys, int rule, int dtype) {
+    if (op == FEM_OP_GEOMETRY) phys = rule = 0;
+    return TuneKey(op, dim, phys, rule, dtype);
+}
+
 // Built-in launch configurations: the winners of the autotuner's sweep on
 // one MI355X for the benchmark workloads (one element per lane was within a
-// few percent of the best everywhere, wider accesses raise register pressure
+// few percent of the best everywhere; wider accesses raise register pressure
 // without adding bandwidth); other combinations use the robust middle choice.
-static fem_tuning default_tuning(int dim, int phys, int rule, int dtype) {
+static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype) {
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
+    if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
+    if (op == FEM_OP_RESIDUAL_MESH) return f32 ? fem_tuning{FEM_STRATEGY_LANE, 1, 2, 8} : fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool deg2 = rule != FEM_RULE_CENTROID;
     if (deg2 && phys == FEM_LAPLACE && dim == 3) t = f32 ? fem_tuning{0, 1, 2, 16} : fem_tuning{0, 1, 1, 0};
     if (deg2 && phys == FEM_ELASTICITY && dim == 2) t = f32 ? fem_tuning{0, 1, 4, 4} : fem_tuning{0, 1, 4, 0};
@@ -85,23 +97,26 @@ static fem_tuning default_tuning(int dim, int phys, int rule, int dtype) {
     return t;
 }
 
-static bool valid_tuning(const fem_tuning& t) {
-    return (t.strategy == FEM_STRATEGY_LANE || t.strategy == FEM_STRATEGY_TRANSPOSE) &&
-           (t.vec == 1 || t.vec == 2 || t.vec == 4) &&
+static bool valid_tuning(int op, const fem_tuning& t) {
+    const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
+                             (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
+    const bool vec_ok = op == FEM_OP_RESIDUAL_MESH ? (t.vec == 1 || t.vec == 2)
+                                                   : (t.vec == 1 || t.vec == 2 || t.vec == 4);
+    return strategy_ok && vec_ok &&
            (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
             t.waves_per_block == 8) &&
            t.blocks_per_cu >= 0 && t.blocks_per_cu <= 64;
 }
 
-fem_tuning get_tuning(int dim, int phys, int rule, int dtype) {
+fem_tuning get_tuning(int op, int dim, int phys, int rule, int dtype) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tune.find(TuneKey(dim, phys, rule, dtype));
-    return it != g_tune.end() ? it->second : default_tuning(dim, phys, rule, dtype);
+    auto it = g_tune.find(tune_key(op, dim, phys, rule, dtype));
+    return it != g_tune.end() ? it->second : default_tuning(op, dim, phys, rule, dtype);
 }
 
-void put_tuning(int dim, int phys, int rule, int dtype, const fem_tuning& t) {
+void put_tuning(int op, int dim, int phys, int rule, int dtype, const fem_tuning& t) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[TuneKey(dim, phys, rule, dtype)] = t;
+    g_tune[tune_key(op, dim, phys, rule, dtype)] = t;
 }
 
 // Largest vector width <= want such that every row of every array starts on
@@ -134,6 +149,23 @@ static Launch make_launch(const fem_tuning& t, int64_t work_items, int vec, hipS
     return l;
 }
 
+// Kernels that give each wave tiles of 64*ept elements.
+static Launch make_tile_launch(const fem_tuning& t, int64_t n, hipStream_t s) {
+    const int64_t tiles = (n + 64 * t.vec - 1) / (64 * t.vec);
+    Launch l = make_launch(t, tiles * 64, t.vec, s);
+    return l;
+}
+
+static fem_status check_tuning_args(const char* fn, int op, int dim, int physics, int rule, int dtype) {
+    if (!valid_op(op)) { set_error("%s: unknown op %d", fn, op); return FEM_ERR_UNSUPPORTED; }
+    if (op == FEM_OP_GEOMETRY) {
+        if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
+        if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+        return FEM_OK;
+    }
+    return check_combo(fn, dim, physics, rule, dtype);
+}
+
 }  // namespace femq
 
 using namespace femq;
@@ -142,19 +174,19 @@ extern "C" {
 
 const char* fem_last_error(void) { return g_error.c_str(); }
 
-fem_status fem_get_tuning(int dim, int physics, int rule, int dtype, fem_tuning* out) {
-    fem_status st = check_combo("fem_get_tuning", dim, physics, rule, dtype);
+fem_status fem_get_tuning(int op, int dim, int physics, int rule, int dtype, fem_tuning* out) {
+    fem_status st = check_tuning_args("fem_get_tuning", op, dim, physics, rule, dtype);
     if (st) return st;
     if (!out) { set_error("fem_get_tuning: out is NULL"); return FEM_ERR_INVALID_ARG; }
-    *out = get_tuning(dim, physics, rule, dtype);
+    *out = get_tuning(op, dim, physics, rule, dtype);
     return FEM_OK;
 }
 
-fem_status fem_set_tuning(int dim, int physics, int rule, int dtype, const fem_tuning* t) {
-    fem_status st = check_combo("fem_set_tuning", dim, physics, rule, dtype);
+fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, const fem_tuning* t) {
+    fem_status st = check_tuning_args("fem_set_tuning", op, dim, physics, rule, dtype);
     if (st) return st;
-    if (!t || !valid_tuning(*t)) { set_error("fem_set_tuning: invalid tuning"); return FEM_ERR_INVALID_ARG; }
-    put_tuning(dim, physics, rule, dtype, *t);
+    if (!t || !valid_tuning(op, *t)) { set_error("fem_set_tuning: invalid tuning for op %d", op); return FEM_ERR_INVALID_ARG; }
+    put_tuning(op, dim, physics, rule, dtype, *t);
     return FEM_OK;
 }
 
@@ -166,8 +198,8 @@ fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* c
     if (n_elem == 0) return FEM_OK;
     if (n_vert == 0) { set_error("fem_geometry: elements without vertices"); return FEM_ERR_INVALID_ARG; }
     if (!coords || !conn || !inv_j || !det_j) { set_error("fem_geometry: NULL array"); return FEM_ERR_INVALID_ARG; }
-    const fem_tuning t{FEM_STRATEGY_LANE, 1, 4, 0};
-    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    const fem_tuning t = get_tuning(FEM_OP_GEOMETRY, dim, 0, 0, out_dtype);
+    Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
     hipError_t e = launch_geometry(dim, out_dtype, n_elem, n_vert, coords, conn, inv_j, det_j, counts, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_geometry launch");
 }
@@ -183,7 +215,7 @@ fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int
         set_error("fem_integrate_residual: NULL array");
         return FEM_ERR_INVALID_ARG;
     }
-    fem_tuning t = get_tuning(dim, physics, rule, dtype);
+    fem_tuning t = get_tuning(FEM_OP_RESIDUAL, dim, physics, rule, dtype);
     ResidualArgs a{n_elem, inv_j, det_j, u, coef, elem_vec};
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     hipError_t e;
@@ -202,6 +234,25 @@ fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual launch");
 }
 
+fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int dtype, int64_t n_elem, int64_t n_vert,
+                                       const double* coords, const int32_t* conn, const void* u, const void* coef,
+                                       void* elem_vec, void* inv_j, void* det_j, int32_t* counts, void* stream) {
+    fem_status st = check_combo("fem_integrate_residual_mesh", dim, physics, rule, dtype);
+    if (st) return st;
+    if (n_elem < 0 || n_vert < 0) { set_error("fem_integrate_residual_mesh: negative size"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (n_vert == 0) { set_error("fem_integrate_residual_mesh: elements without vertices"); return FEM_ERR_INVALID_ARG; }
+    if (!coords || !conn || !u || !coef || !elem_vec || (!inv_j) != (!det_j)) {
+        set_error("fem_integrate_residual_mesh: NULL array (inv_j and det_j must both be set or both NULL)");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_MESH, dim, physics, rule, dtype);
+    MeshArgs a{n_elem, n_vert, coords, conn, u, coef, elem_vec, inv_j, det_j, counts};
+    Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_residual_mesh(dim, physics, rule, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_mesh launch");
+}
+
 fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int dtype, int64_t n_elem,
                                            const void* inv_j, const void* det_j, const void* u, const void* coef,
                                            const void* w, void* du, void* dcoef, void* stream) {
@@ -213,7 +264,7 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int d
         set_error("fem_integrate_residual_backward: NULL array");
         return FEM_ERR_INVALID_ARG;
     }
-    fem_tuning t = get_tuning(dim, physics, rule, dtype);
+    fem_tuning t = get_tuning(FEM_OP_BACKWARD, dim, physics, rule, dtype);
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     const void* ptrs[7] = {inv_j, det_j, w, du ? coef : nullptr, du, dcoef ? u : nullptr, dcoef};
     int vec = usable_vec(t.vec, n_elem, word, ptrs, 7);

@@ -271,6 +271,168 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
     }
 }
 
+// ---------------------------------------------------------------- geometry --
+// Affine geometry of one element in FP64: J[i][k] = (x_k - x_0)_i, det J, and
+// inv[k][i] = (J^{-1})[k][i] = d xi_k / d x_i. Shared by the geometry kernel
+// and the fused mesh kernel, so both produce the same bits.
+
+// Poor shape: |det J| below this fraction of the product of edge lengths.
+constexpr double kPoorShape = 1e-3;
+
+template <int DIM>
+__device__ __forceinline__ double element_geometry(const double (&x)[DIM + 1][DIM], double (&inv)[DIM][DIM],
+                                                   double& edge_product) {
+    double J[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) J[i][k] = x[k + 1][i] - x[0][i];
+    double det;
+    if constexpr (DIM == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double r = 1.0 / det;
+        inv[0][0] = J[1][1] * r;
+        inv[0][1] = -J[0][1] * r;
+        inv[1][0] = -J[1][0] * r;
+        inv[1][1] = J[0][0] * r;
+    } else {
+        // cofactors C[i][k]; J^{-1}[k][i] = C[i][k] / det
+        double C[3][3];
+        C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+        const double r = 1.0 / det;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) inv[k][i] = C[i][k] * r;
+    }
+    double len = 1.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) s += J[i][k] * J[i][k];
+        len *= sqrt(s);
+    }
+    edge_product = len;
+    return det;
+}
+
+// Loads the dim+1 vertex indices of element e (16-byte load for tets when the
+// array is 16-byte aligned) and reports whether all are in [0, nv).
+template <int DIM, bool VEC_CONN>
+__device__ __forceinline__ bool load_conn(const int32_t* __restrict__ conn, int64_t e, int64_t nv,
+                                          int32_t (&v)[DIM + 1]) {
+    if constexpr (VEC_CONN && DIM == 3) {
+        typedef int32_t I4 __attribute__((ext_vector_type(4)));
+        const I4 c = __builtin_nontemporal_load(reinterpret_cast<const I4*>(conn + e * 4));
+        v[0] = c[0]; v[1] = c[1]; v[2] = c[2]; v[3] = c[3];
+    } else {
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b) v[b] = __builtin_nontemporal_load(conn + e * (DIM + 1) + b);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) ok = ok && v[b] >= 0 && (int64_t)v[b] < nv;
+    return ok;
+}
+
+// Gathers the vertex coordinates; an element with a bad index reads vertex 0
+// (never outside the array) and is flagged degenerate by the caller.
+// With VEC (coordinate array 16-byte aligned) each vertex takes two loads
+// instead of dim: in 2D one 16-byte load; in 3D the 24-byte vertex is read as
+// an aligned 16-byte pair plus one 8-byte word, whose positions depend on the
+// parity of the vertex index (even: (x, y) then z; odd: x then (y, z)), chosen
+// without branching. Fewer, wider gathers cut the address-processing work of
+// the scattered loads.
+template <int DIM, bool VEC>
+__device__ __forceinline__ void gather_coords(const double* __restrict__ X, const int32_t (&v)[DIM + 1], bool ok,
+                                              double (&x)[DIM + 1][DIM]) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        const int64_t vi = ok ? (int64_t)v[b] : 0;
+        if constexpr (!VEC) {
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[b][i] = X[vi * DIM + i];
+        } else if constexpr (DIM == 2) {
+            const D2 p = *reinterpret_cast<const D2*>(X + vi * 2);
+            x[b][0] = p[0];
+            x[b][1] = p[1];
+        } else {
+            const int64_t odd = vi & 1;
+            const D2 p = *reinterpret_cast<const D2*>(X + vi * 3 + odd);   // 16-byte aligned pair
+            const double s = X[vi * 3 + (odd ? 0 : 2)];                     // the remaining word
+            x[b][0] = odd ? s : p[0];
+            x[b][1] = odd ? p[0] : p[1];
+            x[b][2] = odd ? p[1] : s;
+        }
+    }
+}
+
+// Classifies the element and replaces the geometry of a degenerate one by NaN.
+// Returns 1 for degenerate, 2 for poorly shaped, 0 otherwise.
+template <int DIM>
+__device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&inv)[DIM][DIM], double edge_product) {
+    const bool degenerate = !ok || det == 0.0 || !isfinite(det);
+    if (degenerate) {
+        const double nan = __builtin_nan("");
+        if (!ok) det = nan;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) inv[k][i] = nan;
+        return 1;
+    }
+    return fabs(det) < kPoorShape * edge_product ? 2 : 0;
+}
+
+// XCD-aware work split for kernels that gather vertices. Workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2; numbering the
+// workgroups so that XCD k holds a contiguous run of logical indices, and
+// giving each logical workgroup a contiguous range of element tiles, keeps
+// the vertices an XCD gathers in a compact slice of the mesh, which fits its
+// L2 instead of spilling to the shared last-level cache.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t g) {
+    const int64_t per = (g + kXcds - 1) / kXcds;  // logical blocks of the fuller XCDs
+    const int64_t rem = g % kXcds;                // XCDs holding `per` blocks (all, if 0)
+    const int64_t xcd = b % kXcds, slot = b / kXcds;
+    const int64_t start = (rem == 0 || xcd < rem) ? xcd * per : rem * per + (xcd - rem) * (per - 1);
+    return start + slot;
+}
+
+// The wave-tile range [begin, end) of this workgroup; its waves take tiles
+// begin + wave, begin + wave + waves_per_block, ...
+__device__ __forceinline__ void block_tile_range(int64_t n_tiles, int64_t& begin, int64_t& end) {
+    const int64_t L = xcd_logical_block(blockIdx.x, gridDim.x);
+    begin = L * n_tiles / gridDim.x;
+    end = (L + 1) * n_tiles / gridDim.x;
+}
+
+// Adds per-wave sums of the two counters (every lane of the wave active).
+__device__ __forceinline__ void add_counts(int32_t* counts, int ndeg, int npoor) {
+    if (counts == nullptr) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ndeg += __shfl_xor(ndeg, off, 64);
+        npoor += __shfl_xor(npoor, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (ndeg) atomicAdd(&counts[0], ndeg);
+        if (npoor) atomicAdd(&counts[1], npoor);
+    }
+}
+
 // --------------------------------------------------- vector memory access --
 
 template <typename Real, int V> struct VecT;

@@ -29,6 +29,19 @@ struct BackwardArgs {
     void* dcoef;
 };
 
+struct MeshArgs {
+    int64_t n;
+    int64_t n_vert;
+    const double* coords;
+    const int32_t* conn;
+    const void* u;
+    const void* coef;
+    void* out;
+    void* inv_j;      // optional geometry outputs (both or neither)
+    void* det_j;
+    int32_t* counts;  // optional
+};
+
 struct Launch {
     int grid;      // workgroups
     int block;     // threads per workgroup (multiple of 64)
@@ -41,6 +54,7 @@ hipError_t launch_residual_lane(int dim, int phys, int rule, int dtype, const Re
                                 const Launch& l);
 hipError_t launch_residual_transpose(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
                                      const Launch& l);
+hipError_t launch_residual_mesh(int dim, int phys, int rule, int dtype, const MeshArgs& a, const Launch& l);
 hipError_t launch_backward_lane(int dim, int phys, int rule, int dtype, const BackwardArgs& a,
                                 const Launch& l);
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,
@@ -79,8 +93,8 @@ fem_status hip_fail(hipError_t e, const char* what);
 // Compute units of the current device (cached per device); 0 if unknown.
 int device_cus();
 
-// Launch configuration table (fem_abi.hip).
-fem_tuning get_tuning(int dim, int phys, int rule, int dtype);
-void put_tuning(int dim, int phys, int rule, int dtype, const fem_tuning& t);
+// Launch configuration table (fem_abi.hip), keyed by operation.
+fem_tuning get_tuning(int op, int dim, int phys, int rule, int dtype);
+void put_tuning(int op, int dim, int phys, int rule, int dtype, const fem_tuning& t);
 
 }  // namespace femq

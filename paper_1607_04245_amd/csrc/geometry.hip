@@ -15,117 +15,82 @@
 
 namespace femq {
 
-// Poor shape: |det J| below this fraction of the product of edge lengths.
-constexpr double kPoorShape = 1e-3;
-
-template <int DIM, typename Out, bool VEC_CONN>
+// Each wave owns tiles of 64*EPT consecutive elements; lane l handles
+// elements l, l+64, ..., so every load and store instruction of the wave
+// covers 64 consecutive elements. All connectivity loads of a tile are
+// issued before the vertex gathers that depend on them, which gives each lane
+// EPT independent gather chains in flight. Workgroups own contiguous tile
+// ranges laid out XCD by XCD (block_tile_range).
+template <int DIM, typename Out, int EPT>
 __global__ void __launch_bounds__(512)
 geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,
-                Out* __restrict__ inv_j, Out* __restrict__ det_j, int32_t* __restrict__ counts) {
+                bool vec_conn, bool vec_coords, Out* __restrict__ inv_j, Out* __restrict__ det_j, int32_t* __restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    const int64_t n_tiles = (n + 64 * EPT - 1) / (64 * EPT);
+    int64_t t_begin, t_end;
+    block_tile_range(n_tiles, t_begin, t_end);
     int ndeg = 0, npoor = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        int32_t v[DIM + 1];
-        if constexpr (VEC_CONN && DIM == 3) {
-            typedef int32_t I4 __attribute__((ext_vector_type(4)));
-            const I4 c = __builtin_nontemporal_load(reinterpret_cast<const I4*>(conn + e * 4));
-            v[0] = c[0]; v[1] = c[1]; v[2] = c[2]; v[3] = c[3];
-        } else {
+    for (int64_t tile = t_begin + wave; tile < t_end; tile += waves) {
+        int64_t e[EPT];
+        bool ok[EPT];
+        int32_t v[EPT][DIM + 1];
 #pragma unroll
-            for (int b = 0; b <= DIM; ++b) v[b] = conn[e * (DIM + 1) + b];
+        for (int j = 0; j < EPT; ++j) {
+            e[j] = tile * (64 * EPT) + j * 64 + lane;
+            ok[j] = false;
+            if (e[j] < n)
+                ok[j] = vec_conn ? load_conn<DIM, true>(conn, e[j], nv, v[j]) : load_conn<DIM, false>(conn, e[j], nv, v[j]);
         }
-        bool ok = true;
+        double x[EPT][DIM + 1][DIM];
 #pragma unroll
-        for (int b = 0; b <= DIM; ++b) ok = ok && v[b] >= 0 && (int64_t)v[b] < nv;
-        double x[DIM + 1][DIM];
+        for (int j = 0; j < EPT; ++j)
+            if (e[j] < n) {
+                if (vec_coords) gather_coords<DIM, true>(X, v[j], ok[j], x[j]);
+                else gather_coords<DIM, false>(X, v[j], ok[j], x[j]);
+            }
 #pragma unroll
-        for (int b = 0; b <= DIM; ++b) {
-            const int64_t vi = ok ? (int64_t)v[b] : 0;  // never read outside coords
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) x[b][i] = X[vi * DIM + i];
-        }
-        double J[DIM][DIM];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) J[i][k] = x[k + 1][i] - x[0][i];
-        double det, inv[DIM][DIM];
-        if constexpr (DIM == 2) {
-            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-            const double r = 1.0 / det;
-            inv[0][0] = J[1][1] * r;
-            inv[0][1] = -J[0][1] * r;
-            inv[1][0] = -J[1][0] * r;
-            inv[1][1] = J[0][0] * r;
-        } else {
-            // cofactors C[i][k]; J^{-1}[k][i] = C[i][k] / det
-            double C[3][3];
-            C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-            C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-            C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-            C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-            C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-            C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-            C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-            C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-            C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-            det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
-            const double r = 1.0 / det;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) inv[k][i] = C[i][k] * r;
-        }
-        const bool degenerate = !ok || det == 0.0 || !isfinite(det);
-        if (degenerate) {
-            const double nan = __builtin_nan("");
-            if (!ok) det = nan;
+        for (int j = 0; j < EPT; ++j) {
+            if (e[j] >= n) continue;
+            double inv[DIM][DIM], ep;
+            double det = element_geometry<DIM>(x[j], inv, ep);
+            const int flag = finish_geometry<DIM>(ok[j], det, inv, ep);
+            ndeg += flag == 1;
+            npoor += flag == 2;
 #pragma unroll
             for (int k = 0; k < DIM; ++k)
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) inv[k][i] = nan;
-            ++ndeg;
-        } else {
-            double len = 1.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) s += J[i][k] * J[i][k];
-                len *= sqrt(s);
-            }
-            if (fabs(det) < kPoorShape * len) ++npoor;
-        }
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) inv_j[(int64_t)(k * DIM + i) * n + e] = static_cast<Out>(inv[k][i]);
-        det_j[e] = static_cast<Out>(det);
-    }
-    if (counts != nullptr) {
-        // wave-level sums (every lane of the wave is active here), one atomic per wave
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            ndeg += __shfl_xor(ndeg, off, 64);
-            npoor += __shfl_xor(npoor, off, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            if (ndeg) atomicAdd(&counts[0], ndeg);
-            if (npoor) atomicAdd(&counts[1], npoor);
+                for (int i = 0; i < DIM; ++i)
+                    __builtin_nontemporal_store(static_cast<Out>(inv[k][i]), inv_j + (int64_t)(k * DIM + i) * n + e[j]);
+            __builtin_nontemporal_store(static_cast<Out>(det), det_j + e[j]);
         }
     }
+    add_counts(counts, ndeg, npoor);
 }
 
 template <int DIM, typename Out>
 static hipError_t launch_d(int64_t n, int64_t nv, const double* X, const int32_t* conn, void* ij, void* dj,
                            int32_t* counts, const Launch& l) {
     const bool vec = DIM == 3 && (reinterpret_cast<uintptr_t>(conn) % 16) == 0;
-    if (vec)
-        hipLaunchKernelGGL((geometry_kernel<DIM, Out, true>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X,
-                           conn, static_cast<Out*>(ij), static_cast<Out*>(dj), counts);
-    else
-        hipLaunchKernelGGL((geometry_kernel<DIM, Out, false>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv,
-                           X, conn, static_cast<Out*>(ij), static_cast<Out*>(dj), counts);
+    const bool vc = (reinterpret_cast<uintptr_t>(X) % 16) == 0;
+    Out* o_ij = static_cast<Out*>(ij);
+    Out* o_dj = static_cast<Out*>(dj);
+    switch (l.vec) {
+    case 1:
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 1>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
+                           vec, vc, o_ij, o_dj, counts);
+        break;
+    case 2:
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 2>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
+                           vec, vc, o_ij, o_dj, counts);
+        break;
+    case 4:
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 4>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
+                           vec, vc, o_ij, o_dj, counts);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

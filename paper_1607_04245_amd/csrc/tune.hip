@@ -47,6 +47,49 @@ static hipError_t fill(int dtype, void* p, int64_t n, uint64_t seed, double lo, 
     return hipGetLastError();
 }
 
+// Structured probe mesh: n_c^dim cells of the unit square/cube, two
+// triangles or six Kuhn tetrahedra per cell, vertex (i, j[, k]) at
+// (i, j[, k]) / n_c. Only used to time the mesh operations.
+template <int DIM>
+__global__ void __launch_bounds__(256)
+probe_mesh_kernel(int64_t n_elem, int nc, int32_t* __restrict__ conn, double* __restrict__ X, int64_t n_vert) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t m = nc + 1;
+    const double h = 1.0 / nc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vert; i += stride) {
+        int64_t r = i;
+        for (int d = DIM - 1; d >= 0; --d) {
+            X[i * DIM + d] = h * (double)(r % m);
+            r /= m;
+        }
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        if constexpr (DIM == 2) {
+            const int64_t cell = e / 2, ci = cell / nc, cj = cell % nc;
+            const int32_t v00 = (int32_t)(ci * m + cj), v10 = (int32_t)((ci + 1) * m + cj);
+            const int32_t v01 = v00 + 1, v11 = v10 + 1;
+            int32_t* c = conn + e * 3;
+            c[0] = v00;
+            c[1] = (e & 1) ? v11 : v10;
+            c[2] = (e & 1) ? v01 : v11;
+        } else {
+            const int64_t cell = e / 6, t = e % 6;
+            const int64_t ci = cell / ((int64_t)nc * nc), cj = (cell / nc) % nc, ck = cell % nc;
+            const int p0 = (int)(t / 2), p1 = (p0 + 1 + (int)(t & 1)) % 3;  // two distinct axes
+            int off0[3] = {0, 0, 0}, off1[3] = {0, 0, 0};
+            off0[p0] = 1;
+            off1[p0] = 1;
+            off1[p1] = 1;
+            auto vid = [&](int a, int b, int c) { return (int32_t)(((ci + a) * m + (cj + b)) * m + (ck + c)); };
+            int32_t* c = conn + e * 4;
+            c[0] = vid(0, 0, 0);
+            c[1] = vid(off0[0], off0[1], off0[2]);
+            c[2] = vid(off1[0], off1[1], off1[2]);
+            c[3] = vid(1, 1, 1);
+        }
+    }
+}
+
 static std::string device_arch() {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -59,13 +102,13 @@ static std::string device_arch() {
 // ------------------------------------------------------------ JSON cache --
 // Format written here:
 // {"version": 1, "entries": [
-//   {"arch": "gfx950", "dim": 3, "physics": 0, "rule": 1, "dtype": 0,
+//   {"arch": "gfx950", "op": 0, "dim": 3, "physics": 0, "rule": 1, "dtype": 0,
 //    "strategy": 0, "vec": 4, "waves_per_block": 4, "blocks_per_cu": 0, "us": 12.5},
 //   ...]}
 
 struct CacheEntry {
     std::string arch;
-    int dim = 0, physics = 0, rule = 0, dtype = 0;
+    int op = 0, dim = 0, physics = 0, rule = 0, dtype = 0;
     fem_tuning t{0, 1, 4, 0};
     double us = 0.0;
 };
@@ -116,7 +159,8 @@ static std::vector<CacheEntry> parse_cache(const std::string& s) {
                 char* end = nullptr;
                 double x = std::strtod(obj.c_str() + v, &end);
                 size_t used = end ? (size_t)(end - obj.c_str()) : v;
-                if (key == "dim") e.dim = (int)x;
+                if (key == "op") e.op = (int)x;
+                else if (key == "dim") e.dim = (int)x;
                 else if (key == "physics") e.physics = (int)x;
                 else if (key == "rule") e.rule = (int)x;
                 else if (key == "dtype") e.dtype = (int)x;
@@ -142,10 +186,10 @@ static bool write_cache(const char* path, const std::vector<CacheEntry>& es) {
     for (size_t i = 0; i < es.size(); ++i) {
         const CacheEntry& e = es[i];
         std::fprintf(f,
-                     "  {\"arch\": \"%s\", \"dim\": %d, \"physics\": %d, \"rule\": %d, \"dtype\": %d, "
+                     "  {\"arch\": \"%s\", \"op\": %d, \"dim\": %d, \"physics\": %d, \"rule\": %d, \"dtype\": %d, "
                      "\"strategy\": %d, \"vec\": %d, \"waves_per_block\": %d, \"blocks_per_cu\": %d, "
                      "\"us\": %.3f}%s\n",
-                     e.arch.c_str(), e.dim, e.physics, e.rule, e.dtype, e.t.strategy, e.t.vec,
+                     e.arch.c_str(), e.op, e.dim, e.physics, e.rule, e.dtype, e.t.strategy, e.t.vec,
                      e.t.waves_per_block, e.t.blocks_per_cu, e.us, i + 1 < es.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
@@ -168,16 +212,17 @@ fem_status fem_load_tuning(const char* cache_path) {
     for (const CacheEntry& e : parse_cache(text)) {
         if (e.arch != arch) continue;
         fem_tuning t = e.t;
-        if (fem_set_tuning(e.dim, e.physics, e.rule, e.dtype, &t) == FEM_OK) ++used;
+        if (fem_set_tuning(e.op, e.dim, e.physics, e.rule, e.dtype, &t) == FEM_OK) ++used;
     }
     if (!used) { set_error("fem_load_tuning: no valid entry for %s in %s", arch.c_str(), cache_path); return FEM_ERR_NO_TUNING; }
     return FEM_OK;
 }
 
-fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_probe, const char* cache_path) {
+fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64_t n_probe, const char* cache_path) {
     fem_tuning current;
-    fem_status st = fem_get_tuning(dim, physics, rule, dtype, &current);
+    fem_status st = fem_get_tuning(op, dim, physics, rule, dtype, &current);
     if (st) return st;
+    if (op == FEM_OP_GEOMETRY) physics = FEM_LAPLACE, rule = FEM_RULE_CENTROID;
     if (n_probe < 4096 || n_probe > (int64_t)1 << 28) {
         set_error("fem_autotune: n_elem_probe must be in [4096, 2^28]");
         return FEM_ERR_INVALID_ARG;
@@ -188,42 +233,85 @@ fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_pro
     const int ncq = (physics == FEM_ELASTICITY ? 2 : 1) * nq;
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     const int64_t n = n_probe;
-    const size_t words_per_copy = (size_t)n * (dim * dim + 1 + 2 * nbt + ncq);
-    const size_t bytes_per_copy = words_per_copy * word;
-    int copies = (int)std::min<size_t>(8, std::max<size_t>(1, (size_t)(768u << 20) / bytes_per_copy + 1));
+    const bool mesh_op = op == FEM_OP_GEOMETRY || op == FEM_OP_RESIDUAL_MESH;
+    // probe mesh
+    const int per = dim == 2 ? 2 : 6;
+    int grid_n = 1;
+    while ((int64_t)per * (dim == 2 ? (int64_t)grid_n * grid_n : (int64_t)grid_n * grid_n * grid_n) < n) ++grid_n;
+    const int64_t n_vert = dim == 2 ? (int64_t)(grid_n + 1) * (grid_n + 1) : (int64_t)(grid_n + 1) * (grid_n + 1) * (grid_n + 1);
 
+    // one copy: geometry, u, coef, w, outputs, and for mesh ops the mesh
+    struct Copy { void *ij, *dj, *u, *cf, *w, *out, *du, *dc; double* X; int32_t* conn; };
+    const size_t rows_words = (size_t)n * (dim * dim + 1 + 4 * nbt + 2 * ncq);
+    const size_t bytes_per_copy = rows_words * word + (mesh_op ? (size_t)n * 4 * (dim + 1) + (size_t)n_vert * 8 * dim : 0);
+    const int copies = (int)std::min<size_t>(8, std::max<size_t>(2, (size_t)(768u << 20) / bytes_per_copy + 1));
     std::vector<void*> bufs;
-    auto cleanup = [&]() {
-        for (void* b : bufs) (void)hipFree(b);
+    auto cleanup = [&]() { for (void* b : bufs) (void)hipFree(b); };
+    auto alloc = [&](void** p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) bufs.push_back(*p);
+        return e;
     };
-    struct Copy { void *ij, *dj, *u, *cf, *out; };
-    std::vector<Copy> cs;
+    std::vector<Copy> cs(copies);
     hipError_t e = hipSuccess;
     for (int c = 0; c < copies && e == hipSuccess; ++c) {
-        Copy cp{};
-        void** slots[5] = {&cp.ij, &cp.dj, &cp.u, &cp.cf, &cp.out};
-        const size_t rows[5] = {(size_t)dim * dim, 1, (size_t)nbt, (size_t)ncq, (size_t)nbt};
-        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-            e = hipMalloc(slots[k], rows[k] * n * word);
-            if (e == hipSuccess) bufs.push_back(*slots[k]);
-        }
-        if (e != hipSuccess) break;
-        // geometry of a well-shaped element with mild variation, nodal values
-        // and coefficients in the benchmark ranges
+        Copy& cp = cs[c];
+        cp = Copy{};
+        if ((e = alloc(&cp.ij, (size_t)dim * dim * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.dj, (size_t)n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.u, (size_t)nbt * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.cf, (size_t)ncq * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.w, (size_t)nbt * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.out, (size_t)nbt * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.du, (size_t)nbt * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.dc, (size_t)ncq * n * word)) != hipSuccess) break;
+        // well-conditioned synthetic geometry, values in the benchmark ranges
         e = fill(dtype, cp.ij, (int64_t)dim * dim * n, 11 + c, -1.5, 1.5);
         if (e == hipSuccess) e = fill(dtype, cp.dj, n, 23 + c, 0.5, 2.0);
         if (e == hipSuccess) e = fill(dtype, cp.u, (int64_t)nbt * n, 37 + c, -1.0, 1.0);
         if (e == hipSuccess) e = fill(dtype, cp.cf, (int64_t)ncq * n, 41 + c, 0.5, 2.0);
-        cs.push_back(cp);
+        if (e == hipSuccess) e = fill(dtype, cp.w, (int64_t)nbt * n, 53 + c, -1.0, 1.0);
+        if (e == hipSuccess && mesh_op) {
+            void* px = nullptr;
+            void* pc = nullptr;
+            if ((e = alloc(&px, (size_t)n_vert * dim * 8)) != hipSuccess) break;
+            if ((e = alloc(&pc, (size_t)n * (dim + 1) * 4)) != hipSuccess) break;
+            cp.X = static_cast<double*>(px);
+            cp.conn = static_cast<int32_t*>(pc);
+            const int grid = (int)std::min<int64_t>((std::max(n, n_vert) + 255) / 256, 65536);
+            if (dim == 2)
+                hipLaunchKernelGGL(probe_mesh_kernel<2>, dim3(grid), dim3(256), 0, nullptr, n, grid_n, cp.conn, cp.X, n_vert);
+            else
+                hipLaunchKernelGGL(probe_mesh_kernel<3>, dim3(grid), dim3(256), 0, nullptr, n, grid_n, cp.conn, cp.X, n_vert);
+            e = hipGetLastError();
+        }
     }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "fem_autotune: probe buffers"); }
 
+    auto run = [&](const Copy& c) -> fem_status {
+        switch (op) {
+        case FEM_OP_RESIDUAL:
+            return fem_integrate_residual(dim, physics, rule, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);
+        case FEM_OP_BACKWARD:
+            return fem_integrate_residual_backward(dim, physics, rule, dtype, n, c.ij, c.dj, c.u, c.cf, c.w, c.du,
+                                                   c.dc, nullptr);
+        case FEM_OP_GEOMETRY:
+            return fem_geometry(dim, n, n_vert, c.X, c.conn, dtype, c.ij, c.dj, nullptr, nullptr);
+        default:
+            return fem_integrate_residual_mesh(dim, physics, rule, dtype, n, n_vert, c.X, c.conn, c.u, c.cf, c.out,
+                                               nullptr, nullptr, nullptr, nullptr);
+        }
+    };
+
     std::vector<fem_tuning> cands;
-    for (int v : {1, 2, 4})
+    const std::vector<int> vecs = op == FEM_OP_RESIDUAL_MESH ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    for (int v : vecs)
         for (int w : {1, 2, 4, 8})
             for (int b : {0, 2, 4, 8, 16}) cands.push_back(fem_tuning{FEM_STRATEGY_LANE, v, w, b});
-    for (int w : {1, 2, 4, 8})
-        for (int b : {0, 4, 8}) cands.push_back(fem_tuning{FEM_STRATEGY_TRANSPOSE, 1, w, b});
+    if (op == FEM_OP_RESIDUAL)
+        for (int w : {1, 2, 4, 8})
+            for (int b : {0, 4, 8}) cands.push_back(fem_tuning{FEM_STRATEGY_TRANSPOSE, 1, w, b});
 
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
@@ -232,19 +320,14 @@ fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_pro
     fem_tuning best = current;
     float best_ms = 1e30f;
     for (const fem_tuning& t : cands) {
-        if (fem_set_tuning(dim, physics, rule, dtype, &t) != FEM_OK) continue;
+        if (fem_set_tuning(op, dim, physics, rule, dtype, &t) != FEM_OK) continue;
         bool ok = true;
-        for (int r = 0; r < 2 && ok; ++r)
-            ok = fem_integrate_residual(dim, physics, rule, dtype, n, cs[r % copies].ij, cs[r % copies].dj,
-                                        cs[r % copies].u, cs[r % copies].cf, cs[r % copies].out, nullptr) == FEM_OK;
+        for (int r = 0; r < 2 && ok; ++r) ok = run(cs[r % copies]) == FEM_OK;
         if (!ok) continue;  // not available for this combination (e.g. LDS too large)
         (void)hipEventRecord(t0, nullptr);
-        for (int r = 0; r < reps; ++r) {
-            const Copy& cp = cs[r % copies];
-            fem_integrate_residual(dim, physics, rule, dtype, n, cp.ij, cp.dj, cp.u, cp.cf, cp.out, nullptr);
-        }
+        for (int r = 0; r < reps; ++r) (void)run(cs[r % copies]);
         (void)hipEventRecord(t1, nullptr);
-        if (hipEventSynchronize(t1) != hipSuccess) { ok = false; break; }
+        if (hipEventSynchronize(t1) != hipSuccess) break;
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, t0, t1);
         ms /= reps;
@@ -254,7 +337,7 @@ fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_pro
     (void)hipEventDestroy(t1);
     hipError_t sync = hipDeviceSynchronize();
     cleanup();
-    fem_set_tuning(dim, physics, rule, dtype, &best);
+    fem_set_tuning(op, dim, physics, rule, dtype, &best);
     if (sync != hipSuccess) return hip_fail(sync, "fem_autotune");
     if (best_ms >= 1e29f) { set_error("fem_autotune: no candidate ran"); return FEM_ERR_HIP; }
 
@@ -264,12 +347,13 @@ fem_status fem_autotune(int dim, int physics, int rule, int dtype, int64_t n_pro
         if (read_file(cache_path, text)) es = parse_cache(text);
         CacheEntry ne;
         ne.arch = device_arch();
-        ne.dim = dim; ne.physics = physics; ne.rule = rule; ne.dtype = dtype;
+        ne.op = op; ne.dim = dim; ne.physics = physics; ne.rule = rule; ne.dtype = dtype;
         ne.t = best;
         ne.us = best_ms * 1e3;
         bool replaced = false;
         for (CacheEntry& x : es)
-            if (x.arch == ne.arch && x.dim == dim && x.physics == physics && x.rule == rule && x.dtype == dtype) {
+            if (x.arch == ne.arch && x.op == op && x.dim == dim && x.physics == physics && x.rule == rule &&
+                x.dtype == dtype) {
                 x = ne;
                 replaced = true;
             }

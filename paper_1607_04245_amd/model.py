@@ -80,3 +80,13 @@ def geometry_bytes(dim: int, n_elem: int, n_vert: int, word: int) -> float:
     """Compulsory bytes per element of fem_geometry: connectivity, each vertex
     read once (amortised), invJ and detJ written."""
     return 4 * (dim + 1) + 8.0 * dim * n_vert / max(n_elem, 1) + word * (dim * dim + 1)
+
+
+def residual_mesh_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert: int, word: int,
+                        store_geometry: bool = False) -> float:
+    """Compulsory bytes per element of fem_integrate_residual_mesh:
+    connectivity, each vertex once (amortised), closure and coefficients in,
+    element vector out (and the geometry, if stored)."""
+    nbt = (dim + 1) * n_comp(dim, physics)
+    words = 2 * nbt + n_coef(physics) * n_qpts(dim, rule) + ((dim * dim + 1) if store_geometry else 0)
+    return 4 * (dim + 1) + 8.0 * dim * n_vert / max(n_elem, 1) + word * words

@@ -89,19 +89,33 @@ def test_stream_copy_validation(lib):
 
 
 def test_tuning_roundtrip(lib):
+    R = N.OP_RESIDUAL
     t = N.fem_tuning()
-    assert lib.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) == N.FEM_OK
+    assert lib.fem_get_tuning(R, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) == N.FEM_OK
     assert t.strategy == N.STRATEGY_LANE and t.vec in (1, 2, 4)
     new = N.fem_tuning(N.STRATEGY_LANE, 2, 8, 4)
-    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(new)) == N.FEM_OK
+    assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(new)) == N.FEM_OK
     got = N.fem_tuning()
-    lib.fem_get_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(got))
+    lib.fem_get_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(got))
     assert (got.strategy, got.vec, got.waves_per_block, got.blocks_per_cu) == (0, 2, 8, 4)
+    # other operations keep their own configuration
+    lib.fem_get_tuning(N.OP_BACKWARD, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(got))
+    assert (got.vec, got.waves_per_block, got.blocks_per_cu) != (2, 8, 4)
     bad = N.fem_tuning(N.STRATEGY_LANE, 3, 4, 0)
-    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
     bad = N.fem_tuning(N.STRATEGY_LANE, 4, 5, 0)
-    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
-    assert lib.fem_set_tuning(2, mg.MASS, mg.RULE_TET4, N.F64, ctypes.byref(new)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_TET4, N.F64, ctypes.byref(new)) == N.FEM_ERR_UNSUPPORTED
+    # the transposition strategy exists only for the residual; the fused kernel takes 1 or 2 elements per lane
+    tt = N.fem_tuning(N.STRATEGY_TRANSPOSE, 1, 4, 0)
+    assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(tt)) == N.FEM_OK
+    assert lib.fem_set_tuning(N.OP_BACKWARD, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(tt)) \
+        == N.FEM_ERR_INVALID_ARG
+    four = N.fem_tuning(N.STRATEGY_LANE, 4, 4, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) \
+        == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
+    assert lib.fem_set_tuning(7, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
 
 def test_batch_plan_validation(lib):
@@ -122,6 +136,21 @@ def test_batch_plan_validation(lib):
 
 
 def test_autotune_validation(lib):
-    assert lib.fem_autotune(2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
-    assert lib.fem_autotune(2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
+    R = N.OP_RESIDUAL
+    assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_autotune(9, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG
+
+
+def test_residual_mesh_validation(lib):
+    c = (3, mg.LAPLACE, mg.RULE_TET4, N.F32)
+    f = lib.fem_integrate_residual_mesh
+    assert f(*c, 0, 0, None, None, None, None, None, None, None, None, None) == N.FEM_OK
+    assert f(*c, -1, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(*c, 5, 0, _v(), _v(), _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(*c, 5, 5, _v(), None, _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    # geometry outputs: both or neither
+    assert f(*c, 5, 5, _v(), _v(), _v(), _v(), _v(), _v(), None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(3, mg.LAPLACE, mg.RULE_TRI3, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
+        == N.FEM_ERR_UNSUPPORTED

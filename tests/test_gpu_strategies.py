@@ -151,7 +151,7 @@ def test_autotune_picks_a_valid_configuration(tmp_path):
     assert t["strategy"] in (0, 1) and t["vec"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4, 8)
     data = json.loads(cache.read_text())
     (entry,) = data["entries"]
-    assert entry["arch"].startswith("gfx") and entry["dim"] == 3 and entry["us"] > 0
+    assert entry["arch"].startswith("gfx") and entry["op"] == 0 and entry["dim"] == 3 and entry["us"] > 0
     # a second entry is merged, the first kept
     api.fem_autotune(2, mg.ELASTICITY, mg.RULE_TRI3, torch.float64, 1 << 14, str(cache))
     assert len(json.loads(cache.read_text())["entries"]) == 2
@@ -168,3 +168,95 @@ def test_autotune_picks_a_valid_configuration(tmp_path):
                                    dev(wl.coef, torch.float32)).cpu().numpy()
     ref, ref_abs, _, _ = oracle_reference(wl, torch.float32)
     assert_close(R, ref, ref_abs, torch.float32, "tuned")
+
+
+# ------------------------------------------------ fused geometry + residual --
+
+def _restore_op(op, dim, phys, rule, dt):
+    return api.fem_get_tuning(dim, phys, rule, dt, op=op)
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n_elem", [1, 65, 4099, 20004])
+def test_residual_mesh_bitwise_equals_two_calls(dim, phys, dtype, n_elem):
+    wl = small_workload(dim, phys, n_elem, seed=21)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    u, cf = dev(wl.u, dtype), dev(wl.coef, dtype)
+    c_split = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ij, dj = api.fem_geometry(coords, conn, dtype, counts=c_split)
+    R = api.fem_integrate_residual(dim, phys, wl.rule, ij, dj, u, cf)
+    saved = _restore_op(N.OP_RESIDUAL_MESH, dim, phys, wl.rule, dtype)
+    try:
+        for ept in (1, 2):
+            for waves, bpc in ((1, 0), (4, 0), (2, 8)):
+                api.fem_set_tuning(dim, phys, wl.rule, dtype, vec=ept, waves_per_block=waves, blocks_per_cu=bpc,
+                                   op=N.OP_RESIDUAL_MESH)
+                c = torch.zeros(2, dtype=torch.int32, device="cuda")
+                Rm = api.fem_integrate_residual_mesh(dim, phys, wl.rule, coords, conn, u, cf, counts=c)
+                ij2, dj2 = torch.empty_like(ij), torch.empty_like(dj)
+                Rg = api.fem_integrate_residual_mesh(dim, phys, wl.rule, coords, conn, u, cf, inv_j=ij2, det_j=dj2)
+                torch.cuda.synchronize()
+                assert torch.equal(Rm, R) and torch.equal(Rg, R), f"fused != two calls (ept {ept})"
+                assert torch.equal(ij2, ij) and torch.equal(dj2, dj)
+                assert torch.equal(c, c_split)
+    finally:
+        api.fem_set_tuning(dim, phys, wl.rule, dtype, op=N.OP_RESIDUAL_MESH, **saved)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+    assert_close(Rm.cpu().numpy(), ref, ref_abs, dtype, "fused")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_geometry_launch_shapes_bitwise(dim, dtype):
+    wl = small_workload(dim, mg.LAPLACE, 30011, seed=31)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    saved = _restore_op(N.OP_GEOMETRY, dim, 0, 0, dtype)
+    first = None
+    try:
+        for ept in (1, 2, 4):
+            for waves, bpc in ((1, 0), (4, 0), (8, 2)):
+                api.fem_set_tuning(dim, 0, 0, dtype, vec=ept, waves_per_block=waves, blocks_per_cu=bpc,
+                                   op=N.OP_GEOMETRY)
+                ij, dj = api.fem_geometry(coords, conn, dtype)
+                if first is None:
+                    first = (ij, dj)
+                else:
+                    assert torch.equal(ij, first[0]) and torch.equal(dj, first[1])
+    finally:
+        api.fem_set_tuning(dim, 0, 0, dtype, op=N.OP_GEOMETRY, **saved)
+
+
+def test_residual_mesh_degenerate_elements():
+    coords = np.array([[0, 0], [1, 0], [2, 0], [0, 1], [1, 1e-5]], dtype=np.float64)
+    conn = np.array([[0, 1, 3], [0, 1, 2], [0, 2, 4], [0, 1, 7]], dtype=np.int32)
+    u = np.arange(12, dtype=np.float64).reshape(3, 4)
+    cf = np.ones((1, 3, 4))
+    c = torch.zeros(2, dtype=torch.int32, device="cuda")
+    R = api.fem_integrate_residual_mesh(2, mg.LAPLACE, mg.RULE_TRI3, dev(coords, torch.float64),
+                                        dev(conn, torch.int32), dev(u, torch.float64), dev(cf, torch.float64),
+                                        counts=c).cpu().numpy()
+    torch.cuda.synchronize()
+    assert c.tolist() == [2, 1]
+    assert np.isfinite(R[:, 0]).all() and np.isnan(R[:, 1]).all() and np.isnan(R[:, 3]).all()
+
+
+@pytest.mark.parametrize("cfg", [2, "3a", "3b"])
+def test_residual_mesh_full_workloads(cfg):
+    wl = mg.config(cfg)
+    for dtype in DTYPES:
+        R = api.fem_integrate_residual_mesh(wl.dim, wl.physics, wl.rule, dev(wl.coords, torch.float64),
+                                            dev(wl.conn, torch.int32), dev(wl.u, dtype), dev(wl.coef, dtype))
+        ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+        mx, agg = assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"fused config {cfg}")
+        print(f"fused config {cfg} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("op", [N.OP_GEOMETRY, N.OP_RESIDUAL_MESH, N.OP_BACKWARD])
+def test_autotune_other_operations(op):
+    saved = api.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, op=op)
+    try:
+        t = api.fem_autotune(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, 1 << 15, None, op=op)
+        assert t["strategy"] == N.STRATEGY_LANE and t["waves_per_block"] in (1, 2, 4, 8)
+    finally:
+        api.fem_set_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, op=op, **saved)
