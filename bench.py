@@ -12,10 +12,15 @@ timed region. They are replicated into several copies (> 512 MB in total) and
 the steps rotate through them, so the 256 MB last-level cache cannot serve a
 step from the data of the one before.
 
+The timed region is one replay of a HIP graph holding the `--steps` steps
+(captured with torch's graph capture on the stream the library launches on),
+bracketed by one pair of HIP events; launching through Python one call at a
+time would otherwise cost more host time than a step takes on the GPU.
+
 Prints ONE JSON line on stdout (progress goes to stderr). `value` is
-elements per second of the step. The roofline object is for the dominant
-kernel, timed with HIP events on the stream the library launches on, during
-the timed region. Extra sections (outside `value`): FP64, the elasticity
+elements per second of the step (wall clock around the replay). The roofline
+object is for the step's kernel, its duration being the events' elapsed time
+over the replay divided by the number of launches in it. Extra sections (outside `value`): FP64, the elasticity
 workloads, the adjoint, the batched launch against 64 separate launches, the
 achievable bandwidth of a plain copy kernel, and the FP64 CPU oracle.
 """
@@ -44,7 +49,7 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--quick", action="store_true", help="main step only (no extra sections, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -140,50 +145,52 @@ def main():
     def integrate(c):
         api.fem_integrate_residual(dim, phys, rule, c["inv_j"], c["det_j"], c["u"], c["coef"], out=c["R"])
 
-    def timed_fused(cs, steps, warmup):
-        """The timed region: `steps` fused steps, each bracketed by events."""
-        for i in range(warmup):
-            fused(cs[i % len(cs)])
+    def graph_of(fn, cs, steps):
+        """A HIP graph (torch's capture on the stream the library launches on)
+        holding `steps` calls of fn rotating through the input copies."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for i in range(3):          # eager warm-up on the capture stream
+                fn(cs[i % len(cs)])
+        torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
-        pairs = []
-        t = time.perf_counter()
-        for i in range(steps):
-            s = ev()
-            fused(cs[i % len(cs)])
-            pairs.append((s, ev()))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(steps):
+                fn(cs[i % len(cs)])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        return wall, sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
+        return g
 
-    def timed_split(cs, steps, warmup):
-        """The same step as two calls (geometry stored, then integration):
-        wall time with nothing bracketed, then a pass with each kernel
-        bracketed by events."""
-        for i in range(warmup):
-            geometry(cs[i % len(cs)])
-            integrate(cs[i % len(cs)])
+    def timed_graph(fn, cs, steps, warmup):
+        """The timed region: one replay of a graph of `steps` steps, bracketed
+        by a pair of events; returns (wall seconds, event ms per step)."""
+        g = graph_of(fn, cs, steps)
+        for _ in range(max(1, warmup // steps + 1)):
+            g.replay()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for i in range(steps):
-            geometry(cs[i % len(cs)])
-            integrate(cs[i % len(cs)])
+        s = ev()
+        g.replay()
+        e = ev()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        g, it = [], []
-        for r in range(20):
-            c = cs[r % len(cs)]
-            s = ev()
-            geometry(c)
-            m = ev()
-            integrate(c)
-            it.append((m, ev()))
-            g.append((s, m))
-        torch.cuda.synchronize()
-        return wall, sum(a.elapsed_time(b) for a, b in g) / 20, sum(a.elapsed_time(b) for a, b in it) / 20
+        return wall, s.elapsed_time(e) / steps
+
+    def split(c):
+        geometry(c)
+        integrate(c)
+
+    def breakdown(cs, reps=20):
+        """Untimed: graphs of geometry alone and of integration alone."""
+        _, g_ms = timed_graph(geometry, cs, reps, 1)
+        _, i_ms = timed_graph(integrate, cs, reps, 1)
+        return g_ms, i_ms
 
     cs = step_copies(torch.float32)
-    wall, fused_ms = timed_fused(cs, args.steps, args.warmup)
-    swall, geo_ms, int_ms = timed_split(cs, args.steps, args.warmup)
+    wall, fused_ms = timed_graph(fused, cs, args.steps, args.warmup)
+    swall, _ = timed_graph(split, cs, args.steps, args.warmup)
+    geo_ms, int_ms = breakdown(cs)
     del cs
     ms_per_step = 1e3 * wall / args.steps
     value = n * args.steps / wall
@@ -215,18 +222,9 @@ def main():
     def copy_gbs(nbytes, reps):
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         k = 1 if nbytes >= 2**30 else n_copies(2 * nbytes)
-        srcs = [src] + [src.clone() for _ in range(k - 1)]
-        dsts = [torch.empty_like(src) for _ in range(k)]
-        for i in range(3):
-            api.fem_stream_copy(srcs[i % k], dsts[i % k])
-        pairs = []
-        for i in range(reps):
-            s = ev()
-            api.fem_stream_copy(srcs[i % k], dsts[i % k])
-            pairs.append((s, ev()))
-        torch.cuda.synchronize()
-        t = sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
-        return 2 * nbytes / (t * 1e-3) / 1e9, t * 1e3
+        pairs = [(src if i == 0 else src.clone(), torch.empty_like(src)) for i in range(k)]
+        _, ms = timed_graph(lambda p: api.fem_stream_copy(p[0], p[1]), pairs, reps, 1)
+        return 2 * nbytes / (ms * 1e-3) / 1e9, ms * 1e3
 
     big_gbs, big_us = copy_gbs(2 << 30, 10)
     same_gbs, same_us = copy_gbs(int(dk["algorithmic_bytes"] // 2) // 16 * 16, 20)
@@ -267,8 +265,9 @@ def main():
         # ------------------------------------------------------ FP64 step --
         cs = step_copies(torch.float64)
         steps64 = max(10, args.steps // 2)
-        wall64, f64 = timed_fused(cs, steps64, 2)
-        swall64, g64, i64 = timed_split(cs, steps64, 2)
+        wall64, f64 = timed_graph(fused, cs, steps64, 2)
+        swall64, _ = timed_graph(split, cs, steps64, 2)
+        g64, i64 = breakdown(cs)
         del cs
         b64 = model.forward_bytes(dim, phys, rule, 8) * n
         fb64 = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 8) * n
@@ -297,15 +296,8 @@ def main():
             def go(c):
                 api.fem_integrate_residual(wlx.dim, wlx.physics, wlx.rule, c["ij"], c["dj"], c["u"], c["cf"],
                                            out=c["R"])
-            for k in range(3):
-                go(cps[k % len(cps)])
-            pairs = []
-            for k in range(reps):
-                s = ev()
-                go(cps[k % len(cps)])
-                pairs.append((s, ev()))
-            torch.cuda.synchronize()
-            us = 1e3 * sum(a.elapsed_time(b) for a, b in pairs) / reps
+            _, ms = timed_graph(go, cps, reps, 1)
+            us = ms * 1e3
             del cps
             f = model.model_flops(wlx.dim, wlx.physics, wlx.rule)
             return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
@@ -335,15 +327,8 @@ def main():
         def bwd(c):
             api.fem_integrate_residual_backward(3, mg.LAPLACE, wl5.rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
                                                 du=c["du"], dcoef=c["dc"])
-        for k in range(3):
-            bwd(cps[k % len(cps)])
-        pairs = []
-        for k in range(20):
-            s = ev()
-            bwd(cps[k % len(cps)])
-            pairs.append((s, ev()))
-        torch.cuda.synchronize()
-        us = 1e3 * sum(a.elapsed_time(b) for a, b in pairs) / 20
+        _, ms = timed_graph(bwd, cps, 20, 1)
+        us = ms * 1e3
         extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
                                                    elements_per_s=wl5.n_elem / (us * 1e-6),
                                                    frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
@@ -391,17 +376,20 @@ def main():
             plan.replay()
 
         sep_us = timeit(separate, 10)
+        _, sep_graph_ms = timed_graph(lambda _: separate(), [0], 5, 1)
         run_us = timeit(plan.run, 10)
         with torch.cuda.stream(side):
             rep_us = timeit(replay, 10)
         plan.close()
         extra["batched_64_meshes_f32"] = dict(
             n_mesh=len(meshes), n_elem=ntot, algorithmic_bytes=nbytes,
-            separate_launches_us=sep_us, persistent_launch_us=run_us, graph_replay_us=rep_us,
+            separate_launches_us=sep_us, separate_launches_in_a_graph_us=sep_graph_ms * 1e3,
+            persistent_launch_us=run_us, graph_replay_us=rep_us,
             graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
             speedup_vs_separate=sep_us / rep_us,
             note="the meshes total about 0.9 GB, above the last-level cache; medians of 10")
-        log(f"batched: 64 launches {sep_us:.1f} us, persistent {run_us:.1f} us, graph {rep_us:.1f} us "
+        log(f"batched: 64 launches {sep_us:.1f} us ({sep_graph_ms * 1e3:.1f} us as one graph), persistent "
+            f"{run_us:.1f} us, graph {rep_us:.1f} us "
             f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s)")
         del meshes
         result["extra"] = extra

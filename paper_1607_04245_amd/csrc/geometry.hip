@@ -21,10 +21,10 @@ namespace femq {
 // issued before the vertex gathers that depend on them, which gives each lane
 // EPT independent gather chains in flight. Workgroups own contiguous tile
 // ranges laid out XCD by XCD (block_tile_range).
-template <int DIM, typename Out, int EPT>
+template <int DIM, typename Out, int EPT, bool VEC>
 __global__ void __launch_bounds__(512)
 geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,
-                bool vec_conn, bool vec_coords, Out* __restrict__ inv_j, Out* __restrict__ det_j, int32_t* __restrict__ counts) {
+                Out* __restrict__ inv_j, Out* __restrict__ det_j, int32_t* __restrict__ counts) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
     const int64_t n_tiles = (n + 64 * EPT - 1) / (64 * EPT);
@@ -40,15 +40,12 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
             e[j] = tile * (64 * EPT) + j * 64 + lane;
             ok[j] = false;
             if (e[j] < n)
-                ok[j] = vec_conn ? load_conn<DIM, true>(conn, e[j], nv, v[j]) : load_conn<DIM, false>(conn, e[j], nv, v[j]);
+                ok[j] = load_conn<DIM, VEC>(conn, e[j], nv, v[j]);
         }
         double x[EPT][DIM + 1][DIM];
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
-            if (e[j] < n) {
-                if (vec_coords) gather_coords<DIM, true>(X, v[j], ok[j], x[j]);
-                else gather_coords<DIM, false>(X, v[j], ok[j], x[j]);
-            }
+            if (e[j] < n) gather_coords<DIM, VEC>(X, v[j], ok[j], x[j]);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             if (e[j] >= n) continue;
@@ -68,30 +65,39 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
     add_counts(counts, ndeg, npoor);
 }
 
-template <int DIM, typename Out>
-static hipError_t launch_d(int64_t n, int64_t nv, const double* X, const int32_t* conn, void* ij, void* dj,
+template <int DIM, typename Out, bool VEC>
+static hipError_t launch_e(int64_t n, int64_t nv, const double* X, const int32_t* conn, Out* ij, Out* dj,
                            int32_t* counts, const Launch& l) {
-    const bool vec = DIM == 3 && (reinterpret_cast<uintptr_t>(conn) % 16) == 0;
-    const bool vc = (reinterpret_cast<uintptr_t>(X) % 16) == 0;
-    Out* o_ij = static_cast<Out*>(ij);
-    Out* o_dj = static_cast<Out*>(dj);
     switch (l.vec) {
     case 1:
-        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 1>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
-                           vec, vc, o_ij, o_dj, counts);
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 1, VEC>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X,
+                           conn, ij, dj, counts);
         break;
     case 2:
-        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 2>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
-                           vec, vc, o_ij, o_dj, counts);
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 2, VEC>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X,
+                           conn, ij, dj, counts);
         break;
     case 4:
-        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 4>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X, conn,
-                           vec, vc, o_ij, o_dj, counts);
+        hipLaunchKernelGGL((geometry_kernel<DIM, Out, 4, VEC>), dim3(l.grid), dim3(l.block), 0, l.stream, n, nv, X,
+                           conn, ij, dj, counts);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// The wide-access variant needs 16-byte aligned coordinates (and, for
+// tetrahedra, connectivity); torch allocations always are.
+template <int DIM, typename Out>
+static hipError_t launch_d(int64_t n, int64_t nv, const double* X, const int32_t* conn, void* ij, void* dj,
+                           int32_t* counts, const Launch& l) {
+    const bool vec = (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
+                     (DIM == 2 || (reinterpret_cast<uintptr_t>(conn) % 16) == 0);
+    Out* o_ij = static_cast<Out*>(ij);
+    Out* o_dj = static_cast<Out*>(dj);
+    return vec ? launch_e<DIM, Out, true>(n, nv, X, conn, o_ij, o_dj, counts, l)
+               : launch_e<DIM, Out, false>(n, nv, X, conn, o_ij, o_dj, counts, l);
 }
 
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,

@@ -17,10 +17,10 @@
 
 namespace femq {
 
-template <int DIM, int PHYS, int RULE, typename Real, int EPT, bool STORE_GEOM>
+template <int DIM, int PHYS, int RULE, typename Real, int EPT, bool STORE_GEOM, bool VEC>
 __global__ void __launch_bounds__(512)
 residual_mesh_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,
-                     bool vec_conn, bool vec_coords, const Real* __restrict__ u, const Real* __restrict__ coef,
+                     const Real* __restrict__ u, const Real* __restrict__ coef,
                      Real* __restrict__ out, Real* __restrict__ inv_j, Real* __restrict__ det_j,
                      int32_t* __restrict__ counts) {
     using E = Elem<DIM, PHYS, RULE>;
@@ -40,7 +40,7 @@ residual_mesh_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const 
             e[j] = tile * (64 * EPT) + j * 64 + lane;
             ok[j] = false;
             if (e[j] < n)
-                ok[j] = vec_conn ? load_conn<DIM, true>(conn, e[j], nv, v[j]) : load_conn<DIM, false>(conn, e[j], nv, v[j]);
+                ok[j] = load_conn<DIM, VEC>(conn, e[j], nv, v[j]);
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -53,10 +53,7 @@ residual_mesh_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const 
         double x[EPT][DIM + 1][DIM];
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
-            if (e[j] < n) {
-                if (vec_coords) gather_coords<DIM, true>(X, v[j], ok[j], x[j]);
-                else gather_coords<DIM, false>(X, v[j], ok[j], x[j]);
-            }
+            if (e[j] < n) gather_coords<DIM, VEC>(X, v[j], ok[j], x[j]);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             if (e[j] >= n) continue;
@@ -84,29 +81,36 @@ residual_mesh_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const 
     add_counts(counts, ndeg, npoor);
 }
 
-template <int DIM, int PHYS, int RULE, typename Real, int EPT>
+template <int DIM, int PHYS, int RULE, typename Real, int EPT, bool VEC>
 static hipError_t launch_s(const MeshArgs& a, const Launch& l) {
-    const bool vec = DIM == 3 && (reinterpret_cast<uintptr_t>(a.conn) % 16) == 0;
-    const bool vc = (reinterpret_cast<uintptr_t>(a.coords) % 16) == 0;
     const Real* u = static_cast<const Real*>(a.u);
     const Real* cf = static_cast<const Real*>(a.coef);
     Real* out = static_cast<Real*>(a.out);
     Real* ij = static_cast<Real*>(a.inv_j);
     Real* dj = static_cast<Real*>(a.det_j);
     if (ij != nullptr)
-        hipLaunchKernelGGL((residual_mesh_kernel<DIM, PHYS, RULE, Real, EPT, true>), dim3(l.grid), dim3(l.block), 0,
-                           l.stream, a.n, a.n_vert, a.coords, a.conn, vec, vc, u, cf, out, ij, dj, a.counts);
+        hipLaunchKernelGGL((residual_mesh_kernel<DIM, PHYS, RULE, Real, EPT, true, VEC>), dim3(l.grid), dim3(l.block),
+                           0, l.stream, a.n, a.n_vert, a.coords, a.conn, u, cf, out, ij, dj, a.counts);
     else
-        hipLaunchKernelGGL((residual_mesh_kernel<DIM, PHYS, RULE, Real, EPT, false>), dim3(l.grid), dim3(l.block), 0,
-                           l.stream, a.n, a.n_vert, a.coords, a.conn, vec, vc, u, cf, out, ij, dj, a.counts);
+        hipLaunchKernelGGL((residual_mesh_kernel<DIM, PHYS, RULE, Real, EPT, false, VEC>), dim3(l.grid), dim3(l.block),
+                           0, l.stream, a.n, a.n_vert, a.coords, a.conn, u, cf, out, ij, dj, a.counts);
     return hipGetLastError();
+}
+
+// The wide-access variant needs 16-byte aligned coordinates (and, for
+// tetrahedra, connectivity); torch allocations always are.
+template <int DIM, int PHYS, int RULE, typename Real, int EPT>
+static hipError_t launch_a(const MeshArgs& a, const Launch& l) {
+    const bool vec = (reinterpret_cast<uintptr_t>(a.coords) % 16) == 0 &&
+                     (DIM == 2 || (reinterpret_cast<uintptr_t>(a.conn) % 16) == 0);
+    return vec ? launch_s<DIM, PHYS, RULE, Real, EPT, true>(a, l) : launch_s<DIM, PHYS, RULE, Real, EPT, false>(a, l);
 }
 
 template <int DIM, int PHYS, int RULE, typename Real>
 static hipError_t launch_v(const MeshArgs& a, const Launch& l) {
     switch (l.vec) {
-    case 1: return launch_s<DIM, PHYS, RULE, Real, 1>(a, l);
-    case 2: return launch_s<DIM, PHYS, RULE, Real, 2>(a, l);
+    case 1: return launch_a<DIM, PHYS, RULE, Real, 1>(a, l);
+    case 2: return launch_a<DIM, PHYS, RULE, Real, 2>(a, l);
     default: return hipErrorInvalidValue;
     }
 }
