@@ -106,7 +106,8 @@ enum fem_op {
  *     counts[0] += elements with det J == 0, non-finite, or a vertex index
  *                  outside [0, n_vert) (these get NaN geometry, and no
  *                  out-of-range coordinate is read);
- *     counts[1] += poorly shaped elements, |det J| < 1e-3 prod_k |J[:,k]|.
+ *     counts[1] += poorly shaped elements, |det J| < 1e-3 prod_k |J[:,k]|
+ *                  (evaluated as det^2 < 1e-6 prod_k |J[:,k]|^2).
  * Errors: FEM_ERR_INVALID_ARG (dim not 2/3, negative sizes, NULL arrays with
  * n_elem > 0, n_vert == 0 with n_elem > 0), FEM_ERR_UNSUPPORTED (dtype),
  * FEM_ERR_HIP. */
@@ -181,7 +182,7 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
                                  fem_batch_plan** out);
 /* Launch shape of the persistent kernel: waves per workgroup (1, 2, 4, 8;
  * one element per lane, so a tile is 64*waves_per_block elements) and
- * workgroups per compute unit (0 = one workgroup per tile). Defaults 4 and 8.
+ * workgroups per compute unit (0 = one workgroup per tile). Defaults 8 and 0.
  * Drops a recorded graph (capture again). Synchronizes the device. */
 fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, int blocks_per_cu);
 /* One persistent launch covering every mesh, on `stream`. */

@@ -231,7 +231,7 @@ class BatchPlan:
         N.check(N.lib().fem_batch_plan_create(descs, len(meshes), _DT[dtype], ctypes.byref(self._plan)),
                 "fem_batch_plan_create")
 
-    def set_launch(self, waves_per_block=4, blocks_per_cu=8):
+    def set_launch(self, waves_per_block=8, blocks_per_cu=0):
         N.check(N.lib().fem_batch_plan_set_launch(self._plan, waves_per_block, blocks_per_cu),
                 "fem_batch_plan_set_launch")
 

@@ -2,13 +2,13 @@
 // persistent launch, optionally recorded into a HIP graph.
 //
 // The plan concatenates the meshes' element ranges into one list of tiles
-// (one tile = one workgroup's worth of elements, one element per lane).
-// Persistent workgroups walk that list with a fixed stride, so there is no
-// work counter to reset between launches and the assignment is the same on
-// every replay. For each tile the workgroup finds its mesh by binary search
-// over the tiles' starting offsets (wave-uniform, read-only descriptor loads)
-// and branches, uniformly, into the element code of that mesh's
-// (dim, physics, rule). Each element runs exactly the arithmetic of the
+// (one tile = one workgroup's worth of elements, one element per lane) and
+// stores, per tile, the index of its mesh. Each persistent workgroup takes a
+// fixed contiguous run of tiles, so there is no work counter to reset between
+// launches and the assignment is the same on every replay. The workgroup
+// reads the descriptor of its first tile's mesh (wave-uniform loads), keeps
+// it while its tiles stay in that mesh, and branches, uniformly, into the
+// element code of the mesh's (dim, physics, rule). Each element runs exactly the arithmetic of the
 // single-mesh lane kernel, so batched and single-mesh results are bitwise
 // equal. This plays the role of the paper's assignment of cell chunks to
 // thread blocks (Section 3), across meshes instead of within one.
@@ -48,45 +48,55 @@ __device__ __forceinline__ void batch_element(const BatchMesh& M, int64_t e) {
 }
 
 template <typename Real>
-__global__ void __launch_bounds__(512)
-batch_kernel(const BatchMesh* __restrict__ meshes, int n_mesh, int64_t n_tiles) {
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        int lo = 0, hi = n_mesh - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (meshes[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
-        }
-        const BatchMesh M = meshes[lo];
-        const int64_t e = (t - M.tile_begin) * blockDim.x + threadIdx.x;
-        if (e >= M.n_elem) continue;
-        switch (M.type) {
+__device__ __forceinline__ void batch_tile(const BatchMesh& M, int64_t t) {
+    const int64_t e = (t - M.tile_begin) * blockDim.x + threadIdx.x;
+    if (e >= M.n_elem) return;
+    switch (M.type) {
 #define FEMQ_CASE(D, P, RU) \
     case type_code(D, P, RU): batch_element<D, P, RU, Real>(M, e); break;
-            FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_TRI3)
-            FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_TET4)
-            FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_TRI3)
-            FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_TET4)
-            FEMQ_CASE(2, FEM_MASS, FEM_RULE_TRI3)
-            FEMQ_CASE(3, FEM_MASS, FEM_RULE_TET4)
-            FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_CENTROID)
-            FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_CENTROID)
-            FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_CENTROID)
-            FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_CENTROID)
-            FEMQ_CASE(2, FEM_MASS, FEM_RULE_CENTROID)
-            FEMQ_CASE(3, FEM_MASS, FEM_RULE_CENTROID)
+        FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_TRI3)
+        FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_TET4)
+        FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_TRI3)
+        FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_TET4)
+        FEMQ_CASE(2, FEM_MASS, FEM_RULE_TRI3)
+        FEMQ_CASE(3, FEM_MASS, FEM_RULE_TET4)
+        FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_CENTROID)
+        FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_CENTROID)
+        FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_CENTROID)
+        FEMQ_CASE(3, FEM_ELASTICITY, FEM_RULE_CENTROID)
+        FEMQ_CASE(2, FEM_MASS, FEM_RULE_CENTROID)
+        FEMQ_CASE(3, FEM_MASS, FEM_RULE_CENTROID)
 #undef FEMQ_CASE
-        default: break;
-        }
+    default: break;
     }
 }
 
-hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, int64_t n_tiles, int tile_elems,
-                        const Launch& l) {
+// Each workgroup owns a contiguous run of tiles, which mostly lies in one
+// mesh: the descriptor is read once and kept until the run crosses into the
+// next mesh (tiles of a mesh are consecutive).
+template <typename Real>
+__global__ void __launch_bounds__(512)
+batch_kernel(const BatchMesh* __restrict__ meshes, const int32_t* __restrict__ tile_mesh, int64_t n_tiles) {
+    const int64_t t_begin = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t_end = ((int64_t)blockIdx.x + 1) * n_tiles / gridDim.x;
+    if (t_begin >= t_end) return;
+    int m = tile_mesh[t_begin];
+    BatchMesh M = meshes[m];
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        while (t >= M.tile_end) M = meshes[++m];
+        batch_tile<Real>(M, t);
+    }
+}
+
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, const int32_t* d_tile_mesh, int64_t n_tiles,
+                        int tile_elems, const Launch& l) {
     if (tile_elems != l.block) return hipErrorInvalidValue;
     if (dtype == FEM_F32)
-        hipLaunchKernelGGL(batch_kernel<float>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh, n_tiles);
+        hipLaunchKernelGGL(batch_kernel<float>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, d_tile_mesh,
+                           n_tiles);
     else
-        hipLaunchKernelGGL(batch_kernel<double>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh, n_tiles);
+        hipLaunchKernelGGL(batch_kernel<double>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, d_tile_mesh,
+                           n_tiles);
     return hipGetLastError();
 }
 
@@ -100,9 +110,11 @@ struct fem_batch_plan {
     int n_mesh = 0;              // non-empty meshes in the device table
     int64_t n_tiles = 0;
     int64_t n_elem_total = 0;
-    int waves_per_block = 4;
-    int blocks_per_cu = 8;
+    int waves_per_block = 8;   // measured on MI355X: one 512-element tile per
+    int blocks_per_cu = 0;     // workgroup beats persistent grids
     BatchMesh* d_meshes = nullptr;
+    int32_t* d_tile_mesh = nullptr;   // mesh index of every tile
+    int64_t tile_mesh_cap = 0;        // elements allocated in d_tile_mesh
     std::vector<BatchMesh> h_meshes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -119,7 +131,7 @@ static fem_status plan_launch(fem_batch_plan* p, hipStream_t s) {
     if (p->blocks_per_cu == 0 || grid > p->n_tiles) grid = p->n_tiles;
     if (grid > (1 << 22)) grid = 1 << 22;
     l.grid = (int)grid;
-    hipError_t e = launch_batch(p->dtype, p->d_meshes, p->n_mesh, p->n_tiles, l.block, l);
+    hipError_t e = launch_batch(p->dtype, p->d_meshes, p->d_tile_mesh, p->n_tiles, l.block, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch launch");
 }
 
@@ -129,12 +141,29 @@ static fem_status plan_build_table(fem_batch_plan* p) {
     for (auto& m : p->h_meshes) {
         m.tile_begin = t;
         t += (m.n_elem + tile - 1) / tile;
+        m.tile_end = t;
     }
     p->n_tiles = t;
     if (p->h_meshes.empty()) return FEM_OK;
     hipError_t e = hipMemcpy(p->d_meshes, p->h_meshes.data(), p->h_meshes.size() * sizeof(BatchMesh),
                              hipMemcpyHostToDevice);
-    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch descriptor upload");
+    if (e != hipSuccess) return hip_fail(e, "fem_batch descriptor upload");
+    std::vector<int32_t> tm((size_t)t);
+    for (size_t m = 0; m < p->h_meshes.size(); ++m) {
+        const int64_t b = p->h_meshes[m].tile_begin;
+        const int64_t end = m + 1 < p->h_meshes.size() ? p->h_meshes[m + 1].tile_begin : t;
+        for (int64_t k = b; k < end; ++k) tm[(size_t)k] = (int32_t)m;
+    }
+    if (t > p->tile_mesh_cap) {
+        if (p->d_tile_mesh) (void)hipFree(p->d_tile_mesh);
+        p->d_tile_mesh = nullptr;
+        p->tile_mesh_cap = 0;
+        e = hipMalloc(&p->d_tile_mesh, (size_t)t * sizeof(int32_t));
+        if (e != hipSuccess) return hip_fail(e, "fem_batch tile table");
+        p->tile_mesh_cap = t;
+    }
+    e = hipMemcpy(p->d_tile_mesh, tm.data(), (size_t)t * sizeof(int32_t), hipMemcpyHostToDevice);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch tile table upload");
 }
 
 static void plan_drop_graph(fem_batch_plan* p) {
@@ -247,6 +276,7 @@ void fem_batch_plan_destroy(fem_batch_plan* plan) {
     if (!plan) return;
     plan_drop_graph(plan);
     if (plan->d_meshes) (void)hipFree(plan->d_meshes);
+    if (plan->d_tile_mesh) (void)hipFree(plan->d_tile_mesh);
     delete plan;
 }
 

@@ -89,7 +89,11 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
     if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
-    if (op == FEM_OP_RESIDUAL_MESH) return f32 ? fem_tuning{FEM_STRATEGY_LANE, 1, 2, 8} : fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
+    if (op == FEM_OP_RESIDUAL_MESH) {
+        if (phys == FEM_LAPLACE && f32) return fem_tuning{FEM_STRATEGY_LANE, 1, 1, 8};
+        if (phys == FEM_ELASTICITY && f32) return fem_tuning{FEM_STRATEGY_LANE, 2, 2, 0};
+        return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
+    }
     const bool deg2 = rule != FEM_RULE_CENTROID;
     if (deg2 && phys == FEM_LAPLACE && dim == 3) t = f32 ? fem_tuning{0, 1, 2, 16} : fem_tuning{0, 1, 1, 0};
     if (deg2 && phys == FEM_ELASTICITY && dim == 2) t = f32 ? fem_tuning{0, 1, 4, 4} : fem_tuning{0, 1, 4, 0};

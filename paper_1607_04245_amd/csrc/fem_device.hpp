@@ -276,12 +276,13 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
 // inv[k][i] = (J^{-1})[k][i] = d xi_k / d x_i. Shared by the geometry kernel
 // and the fused mesh kernel, so both produce the same bits.
 
-// Poor shape: |det J| below this fraction of the product of edge lengths.
-constexpr double kPoorShape = 1e-3;
+// Poor shape: |det J| below this fraction of the product of edge lengths,
+// tested on squares (det^2 < 1e-6 prod |J[:,k]|^2) so no square root is taken.
+constexpr double kPoorShape2 = 1e-6;
 
 template <int DIM>
 __device__ __forceinline__ double element_geometry(const double (&x)[DIM + 1][DIM], double (&inv)[DIM][DIM],
-                                                   double& edge_product) {
+                                                   double& edge_product2) {
     double J[DIM][DIM];
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
@@ -314,23 +315,25 @@ __device__ __forceinline__ double element_geometry(const double (&x)[DIM + 1][DI
 #pragma unroll
             for (int i = 0; i < 3; ++i) inv[k][i] = C[i][k] * r;
     }
-    double len = 1.0;
+    double len2 = 1.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) s += J[i][k] * J[i][k];
-        len *= sqrt(s);
+        len2 *= s;
     }
-    edge_product = len;
+    edge_product2 = len2;
     return det;
 }
 
-// Loads the dim+1 vertex indices of element e (16-byte load for tets when the
-// array is 16-byte aligned) and reports whether all are in [0, nv).
+// Loads the dim+1 vertex indices of element e (one 16-byte load for
+// tetrahedra when the array is 16-byte aligned). Validation is a separate
+// step (conn_ok) so that a caller can issue further loads before it needs
+// the indices: testing them right after the load would make the wave wait
+// for every load it has in flight.
 template <int DIM, bool VEC_CONN>
-__device__ __forceinline__ bool load_conn(const int32_t* __restrict__ conn, int64_t e, int64_t nv,
-                                          int32_t (&v)[DIM + 1]) {
+__device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int64_t e, int32_t (&v)[DIM + 1]) {
     if constexpr (VEC_CONN && DIM == 3) {
         typedef int32_t I4 __attribute__((ext_vector_type(4)));
         const I4 c = __builtin_nontemporal_load(reinterpret_cast<const I4*>(conn + e * 4));
@@ -339,49 +342,38 @@ __device__ __forceinline__ bool load_conn(const int32_t* __restrict__ conn, int6
 #pragma unroll
         for (int b = 0; b <= DIM; ++b) v[b] = __builtin_nontemporal_load(conn + e * (DIM + 1) + b);
     }
+}
+
+// Whether all vertex indices lie in [0, nv).
+template <int DIM>
+__device__ __forceinline__ bool conn_ok(const int32_t (&v)[DIM + 1], int64_t nv) {
     bool ok = true;
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) ok = ok && v[b] >= 0 && (int64_t)v[b] < nv;
     return ok;
 }
 
-// Gathers the vertex coordinates; an element with a bad index reads vertex 0
-// (never outside the array) and is flagged degenerate by the caller.
-// With VEC (coordinate array 16-byte aligned) each vertex takes two loads
-// instead of dim: in 2D one 16-byte load; in 3D the 24-byte vertex is read as
-// an aligned 16-byte pair plus one 8-byte word, whose positions depend on the
-// parity of the vertex index (even: (x, y) then z; odd: x then (y, z)), chosen
-// without branching. Fewer, wider gathers cut the address-processing work of
-// the scattered loads.
-template <int DIM, bool VEC>
-__device__ __forceinline__ void gather_coords(const double* __restrict__ X, const int32_t (&v)[DIM + 1], bool ok,
+// Gathers the vertex coordinates. Indices are clamped into [0, nv), so an
+// element with a bad index (flagged degenerate by the caller) never reads
+// outside the array; the clamp is branch-free, which keeps all the gathers of
+// an element together in the instruction stream. (Wider loads, e.g. a
+// 16-byte pair plus one word per FP64 vertex, measured no faster.)
+template <int DIM>
+__device__ __forceinline__ void gather_coords(const double* __restrict__ X, const int32_t (&v)[DIM + 1], int64_t nv,
                                               double (&x)[DIM + 1][DIM]) {
-    typedef double D2 __attribute__((ext_vector_type(2)));
+    const int32_t hi = (int32_t)(nv - 1);
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) {
-        const int64_t vi = ok ? (int64_t)v[b] : 0;
-        if constexpr (!VEC) {
+        const int64_t vi = (int64_t)min(max(v[b], 0), hi);
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) x[b][i] = X[vi * DIM + i];
-        } else if constexpr (DIM == 2) {
-            const D2 p = *reinterpret_cast<const D2*>(X + vi * 2);
-            x[b][0] = p[0];
-            x[b][1] = p[1];
-        } else {
-            const int64_t odd = vi & 1;
-            const D2 p = *reinterpret_cast<const D2*>(X + vi * 3 + odd);   // 16-byte aligned pair
-            const double s = X[vi * 3 + (odd ? 0 : 2)];                     // the remaining word
-            x[b][0] = odd ? s : p[0];
-            x[b][1] = odd ? p[0] : p[1];
-            x[b][2] = odd ? p[1] : s;
-        }
+        for (int i = 0; i < DIM; ++i) x[b][i] = X[vi * DIM + i];
     }
 }
 
 // Classifies the element and replaces the geometry of a degenerate one by NaN.
 // Returns 1 for degenerate, 2 for poorly shaped, 0 otherwise.
 template <int DIM>
-__device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&inv)[DIM][DIM], double edge_product) {
+__device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&inv)[DIM][DIM], double edge_product2) {
     const bool degenerate = !ok || det == 0.0 || !isfinite(det);
     if (degenerate) {
         const double nan = __builtin_nan("");
@@ -392,7 +384,7 @@ __device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&in
             for (int i = 0; i < DIM; ++i) inv[k][i] = nan;
         return 1;
     }
-    return fabs(det) < kPoorShape * edge_product ? 2 : 0;
+    return det * det < kPoorShape2 * edge_product2 ? 2 : 0;
 }
 
 // XCD-aware work split for kernels that gather vertices. Workgroups are

@@ -68,6 +68,7 @@ struct BatchMesh {              // device-side descriptor, one per mesh
     int32_t pad;
     int64_t n_elem;
     int64_t tile_begin;         // first global tile of this mesh
+    int64_t tile_end;           // one past its last tile
     const void* inv_j;
     const void* det_j;
     const void* u;
@@ -75,7 +76,7 @@ struct BatchMesh {              // device-side descriptor, one per mesh
     void* out;
 };
 
-hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, int64_t n_tiles,
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, const int32_t* d_tile_mesh, int64_t n_tiles,
                         int tile_elems, const Launch& l);
 
 // Threads the transpose kernel needs per workgroup for a given tuning, or 0 if

@@ -17,10 +17,32 @@ namespace femq {
 
 // Each wave owns tiles of 64*EPT consecutive elements; lane l handles
 // elements l, l+64, ..., so every load and store instruction of the wave
-// covers 64 consecutive elements. All connectivity loads of a tile are
-// issued before the vertex gathers that depend on them, which gives each lane
-// EPT independent gather chains in flight. Workgroups own contiguous tile
-// ranges laid out XCD by XCD (block_tile_range).
+// covers 64 consecutive elements. Workgroups own contiguous tile ranges laid
+// out XCD by XCD (block_tile_range). Connectivity loads are unconditional
+// (indices past the end are clamped, their results ignored) and validated
+// only after the next loads are issued, so the wave never waits for more
+// than it needs. EPT = 1 is software-pipelined: the next tile's connectivity
+// is in flight while the current tile's vertices are gathered and processed.
+// EPT > 1 gives each lane EPT independent gather chains instead.
+template <int DIM, typename Out>
+__device__ __forceinline__ void geometry_finish(bool valid, int64_t e, int64_t n, bool ok,
+                                                const double (&x)[DIM + 1][DIM], Out* __restrict__ inv_j,
+                                                Out* __restrict__ det_j, int& ndeg, int& npoor) {
+    double inv[DIM][DIM], ep2;
+    double det = element_geometry<DIM>(x, inv, ep2);
+    const int flag = finish_geometry<DIM>(ok, det, inv, ep2);
+    ndeg += valid && flag == 1;
+    npoor += valid && flag == 2;
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+                __builtin_nontemporal_store(static_cast<Out>(inv[k][i]), inv_j + (int64_t)(k * DIM + i) * n + e);
+        __builtin_nontemporal_store(static_cast<Out>(det), det_j + e);
+    }
+}
+
 template <int DIM, typename Out, int EPT, bool VEC>
 __global__ void __launch_bounds__(512)
 geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,
@@ -31,35 +53,54 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
     int64_t t_begin, t_end;
     block_tile_range(n_tiles, t_begin, t_end);
     int ndeg = 0, npoor = 0;
-    for (int64_t tile = t_begin + wave; tile < t_end; tile += waves) {
-        int64_t e[EPT];
-        bool ok[EPT];
-        int32_t v[EPT][DIM + 1];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            e[j] = tile * (64 * EPT) + j * 64 + lane;
-            ok[j] = false;
-            if (e[j] < n)
-                ok[j] = load_conn<DIM, VEC>(conn, e[j], nv, v[j]);
+    int64_t tile = t_begin + wave;
+    auto clamp = [&](int64_t e) { return e < n ? e : n - 1; };
+    if constexpr (EPT == 1) {
+        int32_t va[DIM + 1], vb[DIM + 1];
+        load_conn<DIM, VEC>(conn, clamp(tile < t_end ? tile * 64 + lane : n), va);
+        while (tile < t_end) {
+            {
+                const int64_t e = tile * 64 + lane;
+                double x[DIM + 1][DIM];
+                gather_coords<DIM>(X, va, nv, x);
+                const bool ok = e < n && conn_ok<DIM>(va, nv);
+                __asm__ volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                const int64_t next = tile + waves;
+                load_conn<DIM, VEC>(conn, clamp(next < t_end ? next * 64 + lane : n), vb);
+                geometry_finish<DIM, Out>(e < n, e, n, ok, x, inv_j, det_j, ndeg, npoor);
+                tile = next;
+            }
+            if (tile >= t_end) break;
+            {
+                const int64_t e = tile * 64 + lane;
+                double x[DIM + 1][DIM];
+                gather_coords<DIM>(X, vb, nv, x);
+                const bool ok = e < n && conn_ok<DIM>(vb, nv);
+                __asm__ volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                const int64_t next = tile + waves;
+                load_conn<DIM, VEC>(conn, clamp(next < t_end ? next * 64 + lane : n), va);
+                geometry_finish<DIM, Out>(e < n, e, n, ok, x, inv_j, det_j, ndeg, npoor);
+                tile = next;
+            }
         }
-        double x[EPT][DIM + 1][DIM];
+    } else {
+        for (; tile < t_end; tile += waves) {
+            int64_t e[EPT];
+            int32_t v[EPT][DIM + 1];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (e[j] < n) gather_coords<DIM, VEC>(X, v[j], ok[j], x[j]);
+            for (int j = 0; j < EPT; ++j) {
+                e[j] = tile * (64 * EPT) + j * 64 + lane;
+                load_conn<DIM, VEC>(conn, clamp(e[j]), v[j]);
+            }
+            double x[EPT][DIM + 1][DIM];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (e[j] >= n) continue;
-            double inv[DIM][DIM], ep;
-            double det = element_geometry<DIM>(x[j], inv, ep);
-            const int flag = finish_geometry<DIM>(ok[j], det, inv, ep);
-            ndeg += flag == 1;
-            npoor += flag == 2;
+            for (int j = 0; j < EPT; ++j) gather_coords<DIM>(X, v[j], nv, x[j]);
 #pragma unroll
-            for (int k = 0; k < DIM; ++k)
-#pragma unroll
-                for (int i = 0; i < DIM; ++i)
-                    __builtin_nontemporal_store(static_cast<Out>(inv[k][i]), inv_j + (int64_t)(k * DIM + i) * n + e[j]);
-            __builtin_nontemporal_store(static_cast<Out>(det), det_j + e[j]);
+            for (int j = 0; j < EPT; ++j)
+                geometry_finish<DIM, Out>(e[j] < n, e[j], n, e[j] < n && conn_ok<DIM>(v[j], nv), x[j], inv_j, det_j,
+                                          ndeg, npoor);
         }
     }
     add_counts(counts, ndeg, npoor);
@@ -87,13 +128,12 @@ static hipError_t launch_e(int64_t n, int64_t nv, const double* X, const int32_t
     return hipGetLastError();
 }
 
-// The wide-access variant needs 16-byte aligned coordinates (and, for
-// tetrahedra, connectivity); torch allocations always are.
+// The wide-access variant (one 16-byte connectivity load per tetrahedron)
+// needs 16-byte aligned connectivity; torch allocations always are.
 template <int DIM, typename Out>
 static hipError_t launch_d(int64_t n, int64_t nv, const double* X, const int32_t* conn, void* ij, void* dj,
                            int32_t* counts, const Launch& l) {
-    const bool vec = (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
-                     (DIM == 2 || (reinterpret_cast<uintptr_t>(conn) % 16) == 0);
+    const bool vec = DIM == 3 && (reinterpret_cast<uintptr_t>(conn) % 16) == 0;
     Out* o_ij = static_cast<Out*>(ij);
     Out* o_dj = static_cast<Out*>(dj);
     return vec ? launch_e<DIM, Out, true>(n, nv, X, conn, o_ij, o_dj, counts, l)

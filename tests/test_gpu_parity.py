@@ -275,3 +275,38 @@ def test_adjoint_workload_full_fp32():
     mx1, _ = assert_close(du.cpu().numpy(), rdu, du_abs, dt, "du")
     mx2, _ = assert_close(dc.cpu().numpy()[0], rdc[0], dc_abs[0], dt, "dkappa")
     print(f"adjoint full: du {mx1:.2e} dkappa {mx2:.2e}", flush=True)
+
+
+# ------------------------------------------------------------- maximum sizes --
+
+def test_row_offsets_beyond_2_pow_31():
+    """3D elasticity with 2^28 elements: 12 rows of 2^28 words put row offsets
+    far beyond 2^31. The elements are 4096 distinct ones repeated, so every
+    copy must equal the small computation bitwise (lane and fused kernels)."""
+    dtype = torch.float32
+    base = small_workload(3, mg.ELASTICITY, 4096, seed=77)
+    reps = 1 << 16
+    n = base.n_elem * reps
+    coords = dev(base.coords, torch.float64)
+    conn_s = dev(base.conn, torch.int32)
+    ij_s, dj_s = api.fem_geometry(coords, conn_s, dtype)
+    u_s, cf_s = dev(base.u, dtype), dev(base.coef, dtype)
+    R_s = api.fem_integrate_residual(3, mg.ELASTICITY, base.rule, ij_s, dj_s, u_s, cf_s)
+    u = u_s.repeat(1, reps)
+    cf = cf_s.repeat(1, 1, reps)
+    ij = ij_s.repeat(1, reps)
+    dj = dj_s.repeat(reps)
+    R = api.fem_integrate_residual(3, mg.ELASTICITY, base.rule, ij, dj, u, cf)
+    del ij, dj
+    torch.cuda.synchronize()
+    assert R.shape == (12, n) and R.shape[0] * R.shape[1] > 2 ** 31
+    for blk in (0, 1, reps // 2, reps - 1):
+        sl = slice(blk * base.n_elem, (blk + 1) * base.n_elem)
+        assert torch.equal(R[:, sl], R_s), f"lane kernel block {blk}"
+    Rm = api.fem_integrate_residual_mesh(3, mg.ELASTICITY, base.rule, coords, conn_s.repeat(reps, 1), u, cf)
+    torch.cuda.synchronize()
+    for blk in (0, 7, reps // 3, reps - 1):
+        sl = slice(blk * base.n_elem, (blk + 1) * base.n_elem)
+        assert torch.equal(Rm[:, sl], R_s), f"fused kernel block {blk}"
+    ref, ref_abs, _, _ = oracle_reference(base, dtype)
+    assert_close(R_s.cpu().numpy(), ref, ref_abs, dtype, "base block")
