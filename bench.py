@@ -303,12 +303,38 @@ def main():
             return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
                         model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
+        def fused_only(wlx, dt, reps=20):
+            word = 4 if dt == torch.float32 else 8
+            nb = model.residual_mesh_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert, word) * wlx.n_elem
+            base = dict(X=to_dev(wlx.coords, torch.float64), conn=to_dev(wlx.conn, torch.int32), u=to_dev(wlx.u, dt),
+                        cf=to_dev(wlx.coef, dt))
+            cps = []
+            for _ in range(n_copies(nb)):
+                c = {k: v.clone() for k, v in base.items()}
+                c["R"] = torch.empty_like(c["u"])
+                cps.append(c)
+            del base
+
+            def go(c):
+                api.fem_integrate_residual_mesh(wlx.dim, wlx.physics, wlx.rule, c["X"], c["conn"], c["u"], c["cf"],
+                                                out=c["R"])
+            _, ms = timed_graph(go, cps, reps, 1)
+            us = ms * 1e3
+            del cps
+            f = model.model_flops(wlx.dim, wlx.physics, wlx.rule)
+            return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
+                        model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+
         for cfg in ("3a", "3b"):
             wlx = mg.config(cfg)
             for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
                 r = integrate_only(wlx, dt)
-                extra[f"{wlx.name}_{tag}"] = r
-                log(f"{wlx.name} {tag}: {r['us']:.1f} us, {r['gbs']:.0f} GB/s, {r['model_gflops']:.0f} model GF/s")
+                extra[f"{wlx.name}_{tag}_integrate"] = r
+                log(f"{wlx.name} {tag} integrate: {r['us']:.1f} us, {r['gbs']:.0f} GB/s, {r['model_gflops']:.0f} model GF/s")
+                r = fused_only(wlx, dt)
+                extra[f"{wlx.name}_{tag}_from_mesh"] = r
+                log(f"{wlx.name} {tag} from mesh: {r['us']:.1f} us ({r['elements_per_s']:.3e} elem/s), "
+                    f"{r['gbs']:.0f} GB/s")
             del wlx
 
         # --------------------------------------------------------- adjoint --
