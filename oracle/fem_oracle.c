@@ -34,8 +34,10 @@
  *    linear elasticity f1 = lambda tr(eps) I + 2 mu eps, eps the symmetric
  *    gradient (the paper's Lame function in Section 6 is lambda = 0,
  *    mu = 1/2); mass/reaction f0 = kappa u, f1 = 0;
- *  - coefficients live on quadrature points (Section 5 allows this on the
- *    CPU side).
+ *  - coefficients (Section 5, "Variable Coefficients") live on quadrature
+ *    points, or in the P1 space of u (nodal values, evaluated at point q
+ *    with the same tabulation as u), or in P0 (one value per cell); they
+ *    are evaluated at every quadrature point before the physics.
  *
  * Adjoint: L = sum_e w_e . R_e is linear in u for fixed coefficients and
  * linear in the coefficients for fixed u, so dL/du_j = w . R(u = unit_j) and
@@ -50,7 +52,7 @@
  *   coords [n_vert][dim], conn [n_elem][dim+1] (0-based),
  *   inv_j [dim*dim][n] (row k*dim+i), det_j [n],
  *   u, w, elem_vec [N_b*N_comp][n] (row b*N_comp+c),
- *   coef [N_coef][N_q][n].
+ *   coef [N_coef][N_w][n], N_w = N_q (points), N_b (P1) or 1 (P0).
  */
 #include <math.h>
 #include <stddef.h>
@@ -65,6 +67,7 @@
 
 enum { OR_LAPLACE = 0, OR_ELASTICITY = 1, OR_MASS = 2 };
 enum { OR_RULE_TRI3 = 0, OR_RULE_TET4 = 1, OR_RULE_CENTROID = 2 };
+enum { OR_COEF_QUAD = 0, OR_COEF_P1 = 1, OR_COEF_P0 = 2 };
 
 int fem_oracle_n_qpts(int dim, int rule)
 {
@@ -139,6 +142,34 @@ static int or_ncoef(int physics) { return physics == OR_ELASTICITY ? 2 : 1; }
 static int or_physics_ok(int physics)
 {
     return physics == OR_LAPLACE || physics == OR_ELASTICITY || physics == OR_MASS;
+}
+
+/* Words of one coefficient field per element, or -1 for an unknown space. */
+static int or_coef_words(int space, int nb, int nq)
+{
+    if (space == OR_COEF_QUAD) return nq;
+    if (space == OR_COEF_P1) return nb;
+    if (space == OR_COEF_P0) return 1;
+    return -1;
+}
+
+/* Coefficient values at the quadrature points, cq[m][q], from the element's
+ * coefficient words a[m][k] in their space. */
+static void or_coef_at_points(const or_tab *t, int space, int ncoef, double a[OR_MAXCOEF][OR_MAXB + OR_MAXQ],
+                              double cq[OR_MAXCOEF][OR_MAXQ], int absmode)
+{
+    for (int m = 0; m < ncoef; ++m)
+        for (int q = 0; q < t->nq; ++q) {
+            if (space == OR_COEF_QUAD) {
+                cq[m][q] = a[m][q];
+            } else if (space == OR_COEF_P1) {
+                double v = 0.0;
+                for (int b = 0; b < t->nb; ++b) v += (absmode ? fabs(t->B[q][b]) : t->B[q][b]) * a[m][b];
+                cq[m][q] = v;
+            } else {
+                cq[m][q] = a[m][0];
+            }
+        }
 }
 
 /* Pointwise physics at one quadrature point.
@@ -275,16 +306,19 @@ int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const doubl
 
 /* Element residuals from precomputed geometry. Returns 0, or -1 on bad
  * arguments. absmode != 0 gives the absolute-value bound described above. */
-int fem_oracle_integrate(int dim, int physics, int rule, int64_t n_elem, const double *inv_j,
+int fem_oracle_integrate(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
                          const double *det_j, const double *u, const double *coef,
                          double *elem_vec, int absmode)
 {
     or_tab t;
     if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
-    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nw = or_coef_words(space, t.nb, t.nq);
+    if (nw < 0) return -1;
     int64_t n = n_elem;
     for (int64_t e = 0; e < n; ++e) {
         double ij[OR_MAXD][OR_MAXD], ub[OR_MAXB][OR_MAXC], cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        double a[OR_MAXCOEF][OR_MAXB + OR_MAXQ];
         for (int k = 0; k < dim; ++k)
             for (int i = 0; i < dim; ++i) {
                 double v = inv_j[(int64_t)(k * dim + i) * n + e];
@@ -296,10 +330,11 @@ int fem_oracle_integrate(int dim, int physics, int rule, int64_t n_elem, const d
                 ub[b][c] = absmode ? fabs(v) : v;
             }
         for (int m = 0; m < ncoef; ++m)
-            for (int q = 0; q < nq; ++q) {
-                double v = coef[(int64_t)(m * nq + q) * n + e];
-                cf[m][q] = absmode ? fabs(v) : v;
+            for (int k = 0; k < nw; ++k) {
+                double v = coef[(int64_t)(m * nw + k) * n + e];
+                a[m][k] = absmode ? fabs(v) : v;
             }
+        or_coef_at_points(&t, space, ncoef, a, cf, absmode);
         or_element(&t, physics, ij, fabs(det_j[e]), ub, cf, R, absmode);
         for (int b = 0; b < nb; ++b)
             for (int c = 0; c < nc; ++c) elem_vec[(int64_t)(b * nc + c) * n + e] = R[b][c];
@@ -310,18 +345,21 @@ int fem_oracle_integrate(int dim, int physics, int rule, int64_t n_elem, const d
 /* Coordinates and connectivity to element residuals, one element at a time
  * (geometry, then integration). Returns the number of degenerate elements,
  * or -1 on bad arguments. */
-int64_t fem_oracle_residual(int dim, int physics, int rule, int64_t n_elem, int64_t n_vert,
+int64_t fem_oracle_residual(int dim, int physics, int rule, int space, int64_t n_elem, int64_t n_vert,
                             const double *coords, const int32_t *conn, const double *u,
                             const double *coef, double *elem_vec)
 {
     or_tab t;
     if (!or_physics_ok(physics) || n_elem < 0 || n_vert < 0 || or_tabulate(dim, rule, &t) < 0)
         return -1;
-    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nw = or_coef_words(space, t.nb, t.nq);
+    if (nw < 0) return -1;
     int64_t n = n_elem, ndeg = 0;
     for (int64_t e = 0; e < n; ++e) {
         double x[OR_MAXB][OR_MAXD], ij[OR_MAXD][OR_MAXD];
         double ub[OR_MAXB][OR_MAXC], cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        double a[OR_MAXCOEF][OR_MAXB + OR_MAXQ];
         for (int b = 0; b < nb; ++b) {
             int64_t v = conn[e * nb + b];
             if (v < 0 || v >= n_vert) return -1;
@@ -332,7 +370,8 @@ int64_t fem_oracle_residual(int dim, int physics, int rule, int64_t n_elem, int6
         for (int b = 0; b < nb; ++b)
             for (int c = 0; c < nc; ++c) ub[b][c] = u[(int64_t)(b * nc + c) * n + e];
         for (int m = 0; m < ncoef; ++m)
-            for (int q = 0; q < nq; ++q) cf[m][q] = coef[(int64_t)(m * nq + q) * n + e];
+            for (int k = 0; k < nw; ++k) a[m][k] = coef[(int64_t)(m * nw + k) * n + e];
+        or_coef_at_points(&t, space, ncoef, a, cf, 0);
         or_element(&t, physics, ij, fabs(det), ub, cf, R, 0);
         for (int b = 0; b < nb; ++b)
             for (int c = 0; c < nc; ++c) elem_vec[(int64_t)(b * nc + c) * n + e] = R[b][c];
@@ -342,17 +381,20 @@ int64_t fem_oracle_residual(int dim, int physics, int rule, int64_t n_elem, int6
 
 /* Adjoint of L = sum_e w_e . R_e. du [N_bt][n] and dcoef [N_coef][N_q][n]
  * may each be NULL. Returns 0, or -1 on bad arguments. */
-int fem_oracle_backward(int dim, int physics, int rule, int64_t n_elem, const double *inv_j,
+int fem_oracle_backward(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
                         const double *det_j, const double *u, const double *coef,
                         const double *w, double *du, double *dcoef)
 {
     or_tab t;
     if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
-    int nb = t.nb, nq = t.nq, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
+    int nw = or_coef_words(space, t.nb, t.nq);
+    if (nw < 0) return -1;
     int64_t n = n_elem;
     for (int64_t e = 0; e < n; ++e) {
         double ij[OR_MAXD][OR_MAXD], ub[OR_MAXB][OR_MAXC], wb[OR_MAXB][OR_MAXC];
         double cf[OR_MAXCOEF][OR_MAXQ], R[OR_MAXB][OR_MAXC];
+        double a[OR_MAXCOEF][OR_MAXB + OR_MAXQ];
         for (int k = 0; k < dim; ++k)
             for (int i = 0; i < dim; ++i) ij[k][i] = inv_j[(int64_t)(k * dim + i) * n + e];
         for (int b = 0; b < nb; ++b)
@@ -361,7 +403,8 @@ int fem_oracle_backward(int dim, int physics, int rule, int64_t n_elem, const do
                 wb[b][c] = w[(int64_t)(b * nc + c) * n + e];
             }
         for (int m = 0; m < ncoef; ++m)
-            for (int q = 0; q < nq; ++q) cf[m][q] = coef[(int64_t)(m * nq + q) * n + e];
+            for (int k = 0; k < nw; ++k) a[m][k] = coef[(int64_t)(m * nw + k) * n + e];
+        or_coef_at_points(&t, space, ncoef, a, cf, 0);
         double sdet = fabs(det_j[e]);
         if (du) {
             /* dL/du_j = w . R(unit_j): R is linear in u */
@@ -377,17 +420,19 @@ int fem_oracle_backward(int dim, int physics, int rule, int64_t n_elem, const do
             }
         }
         if (dcoef) {
-            /* dL/dcoef_{m,q} = w . R(coef = unit_{m,q}): R is linear in the coefficients */
+            /* dL/dcoef_{m,k} = w . R(coef = unit_{m,k}): R is linear in the
+             * coefficient words, whatever their space */
             for (int m = 0; m < ncoef; ++m)
-                for (int q = 0; q < nq; ++q) {
-                    double unit[OR_MAXCOEF][OR_MAXQ];
+                for (int k = 0; k < nw; ++k) {
+                    double unit[OR_MAXCOEF][OR_MAXB + OR_MAXQ], uq[OR_MAXCOEF][OR_MAXQ];
                     for (int mm = 0; mm < ncoef; ++mm)
-                        for (int qq = 0; qq < nq; ++qq) unit[mm][qq] = (mm == m && qq == q) ? 1.0 : 0.0;
-                    or_element(&t, physics, ij, sdet, ub, unit, R, 0);
+                        for (int kk = 0; kk < nw; ++kk) unit[mm][kk] = (mm == m && kk == k) ? 1.0 : 0.0;
+                    or_coef_at_points(&t, space, ncoef, unit, uq, 0);
+                    or_element(&t, physics, ij, sdet, ub, uq, R, 0);
                     double s = 0.0;
                     for (int b = 0; b < nb; ++b)
                         for (int c = 0; c < nc; ++c) s += wb[b][c] * R[b][c];
-                    dcoef[(int64_t)(m * nq + q) * n + e] = s;
+                    dcoef[(int64_t)(m * nw + k) * n + e] = s;
                 }
         }
     }

@@ -32,14 +32,14 @@ def load():
         lib.fem_oracle_rule.restype = ctypes.c_int
         lib.fem_oracle_geometry.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _dp, _ip, _dp, _dp]
         lib.fem_oracle_geometry.restype = ctypes.c_int64
-        lib.fem_oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
-                                             _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.fem_oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         lib.fem_oracle_integrate.restype = ctypes.c_int
-        lib.fem_oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
-                                            ctypes.c_int64, _dp, _ip, _dp, _dp, _dp]
+        lib.fem_oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int64, ctypes.c_int64, _dp, _ip, _dp, _dp, _dp]
         lib.fem_oracle_residual.restype = ctypes.c_int64
-        lib.fem_oracle_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
-                                            _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.fem_oracle_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.fem_oracle_backward.restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -63,6 +63,11 @@ def _ncomp(dim, physics):
 
 def _ncoef(physics):
     return 2 if physics == 1 else 1
+
+
+def coef_words(dim, rule_id, space):
+    """Words of one coefficient field per element: N_q, N_b or 1."""
+    return {0: n_qpts(dim, rule_id), 1: dim + 1, 2: 1}[space]
 
 
 def n_qpts(dim: int, rule: int) -> int:
@@ -94,48 +99,49 @@ def geometry(coords, conn):
     return inv_j, det_j, int(r)
 
 
-def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode):
+def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode, space):
     inv_j, det_j, u, coef = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef)
     n = det_j.shape[0]
     nb = dim + 1
     R = np.zeros((nb * _ncomp(dim, physics), n))
-    r = load().fem_oracle_integrate(dim, physics, rule_id, n, _p(inv_j), _p(det_j), _p(u), _p(coef),
+    r = load().fem_oracle_integrate(dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u), _p(coef),
                                     _p(R), int(absmode))
     if r != 0:
         raise ValueError("oracle integrate: bad arguments")
     return R
 
 
-def integrate(dim, physics, rule_id, inv_j, det_j, u, coef):
-    """Element residuals R[N_bt, n] from precomputed geometry (Eq. (2) bracket)."""
-    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False)
+def integrate(dim, physics, rule_id, inv_j, det_j, u, coef, space=0):
+    """Element residuals R[N_bt, n] from precomputed geometry (Eq. (2) bracket).
+    ``space``: 0 coefficients on quadrature points, 1 P1 nodal, 2 P0."""
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False, space)
 
 
-def integrate_abs(dim, physics, rule_id, inv_j, det_j, u, coef):
+def integrate_abs(dim, physics, rule_id, inv_j, det_j, u, coef, space=0):
     """Same sums with |.| on every factor: the scale of the rounding measure."""
-    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, True)
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, True, space)
 
 
-def residual(dim, physics, rule_id, coords, conn, u, coef):
+def residual(dim, physics, rule_id, coords, conn, u, coef, space=0):
     """Coordinates/connectivity to residuals R[N_bt, n]; returns (R, n_degenerate)."""
     coords, conn, u, coef = _f64(coords), _i32(conn), _f64(u), _f64(coef)
     n = conn.shape[0]
     R = np.zeros(((dim + 1) * _ncomp(dim, physics), n))
-    r = load().fem_oracle_residual(dim, physics, rule_id, n, coords.shape[0], _p(coords), _p(conn, _ip),
+    r = load().fem_oracle_residual(dim, physics, rule_id, space, n, coords.shape[0], _p(coords), _p(conn, _ip),
                                    _p(u), _p(coef), _p(R))
     if r < 0:
         raise ValueError("oracle residual: bad arguments")
     return R, int(r)
 
 
-def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want_dcoef=True):
-    """Adjoint of L = sum w.R: (du[N_bt, n] or None, dcoef[N_coef, N_q, n] or None)."""
+def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want_dcoef=True, space=0):
+    """Adjoint of L = sum w.R: (du[N_bt, n] or None, dcoef[N_coef, N_w, n] or None)."""
     inv_j, det_j, u, coef, w = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef), _f64(w)
     n = det_j.shape[0]
-    nq = n_qpts(dim, rule_id)
+    nw = coef_words(dim, rule_id, space)
     du = np.zeros(((dim + 1) * _ncomp(dim, physics), n)) if want_du else None
-    dcoef = np.zeros((_ncoef(physics), nq, n)) if want_dcoef else None
-    r = load().fem_oracle_backward(dim, physics, rule_id, n, _p(inv_j), _p(det_j), _p(u), _p(coef), _p(w),
+    dcoef = np.zeros((_ncoef(physics), nw, n)) if want_dcoef else None
+    r = load().fem_oracle_backward(dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u), _p(coef), _p(w),
                                    _p(du), _p(dcoef))
     if r != 0:
         raise ValueError("oracle backward: bad arguments")
