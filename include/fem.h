@@ -23,9 +23,18 @@
  *      inv_j   [dim*dim][n]  row k*dim+i holds d xi_k / d x_i (J^{-1}, row-major)
  *      det_j   [n]           det J, signed; the measure factor is |det J|
  *      u, w, elem_vec, du    [N_b*N_comp][n], row b*N_comp + c
- *      coef, dcoef           [N_coef][N_q][n]
+ *      coef, dcoef           [N_coef][N_w][n]
  *    with N_b = dim+1, N_comp = 1 (Laplacian, mass) or dim (elasticity),
- *    N_coef = 1 (kappa) or 2 (lambda, mu), N_q from the rule.
+ *    N_coef = 1 (kappa) or 2 (lambda, mu), N_q from the rule, and N_w the
+ *    words of one coefficient field per element in its space (below).
+ *  - Coefficient spaces (paper Section 5, "Variable Coefficients": an
+ *    auxiliary field may live on quadrature points, in the space of u, or be
+ *    constant per cell):
+ *      FEM_COEF_QUAD  values at the quadrature points, N_w = N_q
+ *      FEM_COEF_P1    nodal values of a P1 field, element closure in vertex
+ *                     order, N_w = N_b; evaluated at point q as
+ *                     sum_b phi_b(xi_q) a_b
+ *      FEM_COEF_P0    one value per element, N_w = 1
  *    Real arrays are float (FEM_F32) or double (FEM_F64) as selected.
  *  - Reference element: unit simplex, phi_0 = 1 - sum xi, phi_k = xi_k.
  *    Rules: FEM_RULE_TRI3 (dim 2; barycentric (2/3,1/6,1/6), point q has 2/3
@@ -75,6 +84,8 @@ enum fem_physics { FEM_LAPLACE = 0, FEM_ELASTICITY = 1, FEM_MASS = 2 };
 
 enum fem_rule { FEM_RULE_TRI3 = 0, FEM_RULE_TET4 = 1, FEM_RULE_CENTROID = 2 };
 
+enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
+
 /* Kernel strategies (see fem_tuning).
  *  FEM_STRATEGY_LANE       each lane owns whole elements; the quadrature and
  *                          basis phases run in registers.
@@ -121,11 +132,11 @@ fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* c
 
 /* elem_vec = per-element residual R_e as defined at the top of this file.
  * Errors: FEM_ERR_INVALID_ARG (negative n_elem, NULL arrays with
- * n_elem > 0), FEM_ERR_UNSUPPORTED (dim/physics/rule/dtype combination),
- * FEM_ERR_HIP. */
-fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int64_t n_elem,
-                                  const void* inv_j, const void* det_j, const void* u,
-                                  const void* coef, void* elem_vec, void* stream);
+ * n_elem > 0), FEM_ERR_UNSUPPORTED (dim/physics/rule/coef_space/dtype
+ * combination), FEM_ERR_HIP. */
+fem_status fem_integrate_residual(int dim, int physics, int rule, int coef_space, int dtype,
+                                  int64_t n_elem, const void* inv_j, const void* det_j,
+                                  const void* u, const void* coef, void* elem_vec, void* stream);
 
 /* Residual straight from the mesh: geometry and integration fused in one
  * pass over the elements, with no round trip of J^{-1} and det J through
@@ -137,24 +148,27 @@ fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int
  * (may be NULL). Layouts as above; coords [n_vert][dim] double, conn
  * [n_elem][dim+1] int32.
  * Errors: as fem_integrate_residual and fem_geometry. */
-fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int dtype, int64_t n_elem,
-                                       int64_t n_vert, const double* coords, const int32_t* conn,
-                                       const void* u, const void* coef, void* elem_vec,
-                                       void* inv_j, void* det_j, int32_t* counts, void* stream);
+fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_space, int dtype,
+                                       int64_t n_elem, int64_t n_vert, const double* coords,
+                                       const int32_t* conn, const void* u, const void* coef,
+                                       void* elem_vec, void* inv_j, void* det_j, int32_t* counts,
+                                       void* stream);
 
 /* Adjoint of L = sum_e w_e . R_e (not in the paper; the gradient of the
  * residual for automatic differentiation):
  *   du    = dL/du     [N_bt][n]           (may be NULL: not computed)
- *   dcoef = dL/dcoef  [N_coef][N_q][n]    (may be NULL: not computed)
+ *   dcoef = dL/dcoef  [N_coef][N_w][n]    (may be NULL: not computed), in the
+ *                                         coefficient's own space
  * All three physics are symmetric bilinear forms in (u, test function), so
  * du_e = R_e evaluated with u replaced by w_e; dcoef at point q is the
  * weighted pointwise derivative, e.g. w_q |det J| grad u . grad w for the
- * Laplacian. u is not read when dcoef is NULL.
+ * Laplacian (for P1 and P0 coefficients, summed back onto the nodal or cell
+ * value by the chain rule). u is not read when dcoef is NULL.
  * Errors as fem_integrate_residual. */
-fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int dtype,
-                                           int64_t n_elem, const void* inv_j, const void* det_j,
-                                           const void* u, const void* coef, const void* w,
-                                           void* du, void* dcoef, void* stream);
+fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int coef_space,
+                                           int dtype, int64_t n_elem, const void* inv_j,
+                                           const void* det_j, const void* u, const void* coef,
+                                           const void* w, void* du, void* dcoef, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Batched persistent launch over many meshes (not in the paper; its   */
@@ -163,7 +177,7 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int d
 /* ------------------------------------------------------------------ */
 
 typedef struct fem_mesh_desc {
-    int dim, physics, rule;
+    int dim, physics, rule, coef_space;
     int64_t n_elem;
     const void* inv_j;
     const void* det_j;
@@ -211,16 +225,18 @@ typedef struct fem_tuning {
     int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */
 } fem_tuning;
 
-/* The configuration used for (op, dim, physics, rule, dtype): the last one
- * set or tuned in this process, else a built-in default. */
+/* The configuration used for (op, dim, physics, rule, dtype), for every
+ * coefficient space: the last one set or tuned in this process, else a
+ * built-in default. */
 fem_status fem_get_tuning(int op, int dim, int physics, int rule, int dtype, fem_tuning* out);
 /* Override the configuration for (op, dim, physics, rule, dtype) in this process. */
 fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, const fem_tuning* t);
 /* Sweep launch configurations of `op` on synthetic device data of
  * n_elem_probe elements (a structured mesh for the mesh operations;
  * allocated and freed here, on the current device), time each with HIP
- * events, keep the fastest for this process, and, if cache_path is not NULL,
- * merge it into that JSON cache file. Synchronizes the device. */
+ * events (coefficients on quadrature points), keep the fastest for this
+ * process, and, if cache_path is not NULL, merge it into that JSON cache
+ * file. Synchronizes the device. */
 fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64_t n_elem_probe,
                         const char* cache_path);
 /* Load tuned configurations from a JSON cache written by fem_autotune.

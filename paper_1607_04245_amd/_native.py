@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "FEM_OK", -1: "FEM_ERR_INVALID_ARG", -2: "FEM_ERR_UNSUPPORTED
 F32, F64 = 0, 1
 STRATEGY_LANE, STRATEGY_TRANSPOSE = 0, 1
 OP_RESIDUAL, OP_RESIDUAL_MESH, OP_GEOMETRY, OP_BACKWARD = 0, 1, 2, 3
+COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
 
 
 class FemError(RuntimeError):
@@ -42,7 +43,7 @@ class fem_tuning(ctypes.Structure):
 
 class fem_mesh_desc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("physics", ctypes.c_int), ("rule", ctypes.c_int),
-                ("n_elem", ctypes.c_int64),
+                ("coef_space", ctypes.c_int), ("n_elem", ctypes.c_int64),
                 ("inv_j", ctypes.c_void_p), ("det_j", ctypes.c_void_p), ("u", ctypes.c_void_p),
                 ("coef", ctypes.c_void_p), ("elem_vec", ctypes.c_void_p)]
 
@@ -54,9 +55,10 @@ _i64 = ctypes.c_int64
 
 SIGNATURES = {
     "fem_geometry": (_i, [_i, _i64, _i64, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
-    "fem_integrate_residual": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "fem_integrate_residual_mesh": (_i, [_i, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual_mesh": (_i, [_i, _i, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _vp]),
+    "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),
     "fem_batch_run": (_i, [_vp, _vp]),

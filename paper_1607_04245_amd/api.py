@@ -30,6 +30,18 @@ def n_qpts(dim: int, rule: int) -> int:
     return 1 if rule == 2 else dim + 1
 
 
+def n_coef_words(dim: int, rule: int, coef_space: int = N.COEF_QUAD) -> int:
+    """Words per coefficient and element: N_q values at the points, the
+    N_b = d+1 vertex values of a P1 field, or one cell value (Section 5)."""
+    if coef_space == N.COEF_QUAD:
+        return n_qpts(dim, rule)
+    if coef_space == N.COEF_P1:
+        return dim + 1
+    if coef_space == N.COEF_P0:
+        return 1
+    raise ValueError(f"unknown coefficient space {coef_space}")
+
+
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
@@ -78,18 +90,21 @@ def fem_geometry(coords: torch.Tensor, conn: torch.Tensor, dtype=torch.float32, 
     return inv_j, det_j
 
 
-def _shapes(dim, physics, rule, n):
+def _shapes(dim, physics, rule, n, coef_space=N.COEF_QUAD):
     nbt = (dim + 1) * n_comp(dim, physics)
-    return (dim * dim, n), (n,), (nbt, n), (n_coef(physics), n_qpts(dim, rule), n)
+    return (dim * dim, n), (n,), (nbt, n), (n_coef(physics), n_coef_words(dim, rule, coef_space), n)
 
 
-def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, out=None):
-    """Element residuals R [N_bt, n] (paper Eq. (2), before assembly)."""
+def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, out=None, *,
+                           coef_space=N.COEF_QUAD):
+    """Element residuals R [N_bt, n] (paper Eq. (2), before assembly).
+
+    coef is [N_coef, N_w, n] with N_w given by ``coef_space`` (n_coef_words)."""
     dtype = det_j.dtype
     if dtype not in _DT:
         raise TypeError("geometry must be float32 or float64")
     n = det_j.shape[0]
-    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space)
     _need(inv_j, "inv_j", dtype, sij)
     _need(det_j, "det_j", dtype, sdj)
     _need(u, "u", dtype, su)
@@ -97,13 +112,13 @@ def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, c
     if out is None:
         out = torch.empty(su, dtype=dtype, device=u.device)
     _need(out, "out", dtype, su)
-    N.check(N.lib().fem_integrate_residual(dim, physics, rule, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u),
+    N.check(N.lib().fem_integrate_residual(dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u),
                                            _ptr(coef), _ptr(out), _stream()), "fem_integrate_residual")
     return out
 
 
 def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn, u, coef, out=None,
-                                inv_j=None, det_j=None, counts=None):
+                                inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD):
     """Element residuals straight from coordinates and connectivity (geometry
     fused into the integration; bitwise equal to fem_geometry followed by
     fem_integrate_residual). Pass inv_j and det_j to also receive the geometry."""
@@ -115,7 +130,7 @@ def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn,
     if coords.dim() != 2 or coords.shape[1] != dim or conn.dim() != 2 or conn.shape[1] != dim + 1:
         raise ValueError(f"coords must be [n_vert, {dim}] and conn [n_elem, {dim + 1}]")
     n = conn.shape[0]
-    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space)
     _need(u, "u", dtype, su)
     _need(coef, "coef", dtype, scf)
     if out is None:
@@ -128,7 +143,7 @@ def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn,
         _need(det_j, "det_j", dtype, sdj)
     if counts is not None:
         _need(counts, "counts", torch.int32, (2,))
-    N.check(N.lib().fem_integrate_residual_mesh(dim, physics, rule, _DT[dtype], n, coords.shape[0], _ptr(coords),
+    N.check(N.lib().fem_integrate_residual_mesh(dim, physics, rule, coef_space, _DT[dtype], n, coords.shape[0], _ptr(coords),
                                                 _ptr(conn), _ptr(u), _ptr(coef), _ptr(out), _ptr(inv_j),
                                                 _ptr(det_j), _ptr(counts), _stream()),
             "fem_integrate_residual_mesh")
@@ -136,11 +151,11 @@ def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn,
 
 
 def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
-                                    want_du=True, want_dcoef=True, du=None, dcoef=None):
-    """(du [N_bt, n] or None, dcoef [N_coef, N_q, n] or None) for L = sum w . R."""
+                                    want_du=True, want_dcoef=True, du=None, dcoef=None, *, coef_space=N.COEF_QUAD):
+    """(du [N_bt, n] or None, dcoef [N_coef, N_w, n] or None) for L = sum w . R."""
     dtype = det_j.dtype
     n = det_j.shape[0]
-    sij, sdj, su, scf = _shapes(dim, physics, rule, n)
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space)
     _need(inv_j, "inv_j", dtype, sij)
     _need(det_j, "det_j", dtype, sdj)
     _need(w, "w", dtype, su)
@@ -159,7 +174,7 @@ def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, de
     else:
         dcoef = None
     N.check(N.lib().fem_integrate_residual_backward(
-        dim, physics, rule, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
+        dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
         _ptr(coef) if want_du else None, _ptr(w), _ptr(du), _ptr(dcoef), _stream()),
         "fem_integrate_residual_backward")
     return du, dcoef
@@ -205,8 +220,9 @@ class BatchPlan:
     """Many meshes (mixed dim/physics) integrated by one persistent launch.
 
     ``meshes`` is a list of dicts with keys dim, physics, rule, inv_j, det_j,
-    u, coef and out (torch tensors, one dtype for all). The tensors must stay
-    alive while the plan is used.
+    u, coef and out (torch tensors, one dtype for all), and optionally
+    coef_space (default: values at the points). The tensors must stay alive
+    while the plan is used.
     """
 
     def __init__(self, meshes: list[dict]):
@@ -217,13 +233,14 @@ class BatchPlan:
         self._keep = []
         for i, m in enumerate(meshes):
             n = m["det_j"].shape[0]
-            sij, sdj, su, scf = _shapes(m["dim"], m["physics"], m["rule"], n)
+            space = m.get("coef_space", N.COEF_QUAD)
+            sij, sdj, su, scf = _shapes(m["dim"], m["physics"], m["rule"], n, space)
             _need(m["inv_j"], "inv_j", dtype, sij)
             _need(m["det_j"], "det_j", dtype, sdj)
             _need(m["u"], "u", dtype, su)
             _need(m["coef"], "coef", dtype, scf)
             _need(m["out"], "out", dtype, su)
-            descs[i] = N.fem_mesh_desc(m["dim"], m["physics"], m["rule"], n, m["inv_j"].data_ptr(),
+            descs[i] = N.fem_mesh_desc(m["dim"], m["physics"], m["rule"], space, n, m["inv_j"].data_ptr(),
                                        m["det_j"].data_ptr(), m["u"].data_ptr(), m["coef"].data_ptr(),
                                        m["out"].data_ptr())
             self._keep.append(m)
@@ -263,21 +280,22 @@ class IntegrateResidual(torch.autograd.Function):
     kernel. Geometry is treated as a constant."""
 
     @staticmethod
-    def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef):
+    def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef, coef_space):
         ctx.save_for_backward(inv_j, det_j, u, coef)
-        ctx.meta = (dim, physics, rule)
-        return fem_integrate_residual(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous())
+        ctx.meta = (dim, physics, rule, coef_space)
+        return fem_integrate_residual(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(),
+                                      coef_space=coef_space)
 
     @staticmethod
     def backward(ctx, grad_r):
         inv_j, det_j, u, coef = ctx.saved_tensors
-        dim, physics, rule = ctx.meta
+        dim, physics, rule, coef_space = ctx.meta
         du, dcoef = fem_integrate_residual_backward(
             dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), grad_r.contiguous(),
-            want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6])
-        return None, None, None, None, None, du, dcoef
+            want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6], coef_space=coef_space)
+        return None, None, None, None, None, du, dcoef, None
 
 
-def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef):
+def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef, coef_space=N.COEF_QUAD):
     """Differentiable element residuals (see IntegrateResidual)."""
-    return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef)
+    return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef, coef_space)

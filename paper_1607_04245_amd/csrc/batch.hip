@@ -8,7 +8,7 @@
 // launches and the assignment is the same on every replay. The workgroup
 // reads the descriptor of its first tile's mesh (wave-uniform loads), keeps
 // it while its tiles stay in that mesh, and branches, uniformly, into the
-// element code of the mesh's (dim, physics, rule). Each element runs exactly the arithmetic of the
+// element code of the mesh's (dim, physics, rule, coefficient space). Each element runs exactly the arithmetic of the
 // single-mesh lane kernel, so batched and single-mesh results are bitwise
 // equal. This plays the role of the paper's assignment of cell chunks to
 // thread blocks (Section 3), across meshes instead of within one.
@@ -23,7 +23,7 @@
 
 namespace femq {
 
-constexpr int type_code(int dim, int phys, int rule) { return dim * 16 + phys * 4 + rule; }
+constexpr int type_code(int dim, int phys, int rule, int space) { return dim * 64 + space * 16 + phys * 4 + rule; }
 
 template <int DIM, int PHYS, int RULE, typename Real>
 __device__ __forceinline__ void batch_element(const BatchMesh& M, int64_t e) {
@@ -52,8 +52,12 @@ __device__ __forceinline__ void batch_tile(const BatchMesh& M, int64_t t) {
     const int64_t e = (t - M.tile_begin) * blockDim.x + threadIdx.x;
     if (e >= M.n_elem) return;
     switch (M.type) {
-#define FEMQ_CASE(D, P, RU) \
-    case type_code(D, P, RU): batch_element<D, P, RU, Real>(M, e); break;
+#define FEMQ_CASE_S(D, P, RU, SP) \
+    case type_code(D, P, RU, SP): batch_element<D, P, scheme(RU, SP), Real>(M, e); break;
+#define FEMQ_CASE(D, P, RU)                \
+    FEMQ_CASE_S(D, P, RU, FEM_COEF_QUAD)   \
+    FEMQ_CASE_S(D, P, RU, FEM_COEF_P1)     \
+    FEMQ_CASE_S(D, P, RU, FEM_COEF_P0)
         FEMQ_CASE(2, FEM_LAPLACE, FEM_RULE_TRI3)
         FEMQ_CASE(3, FEM_LAPLACE, FEM_RULE_TET4)
         FEMQ_CASE(2, FEM_ELASTICITY, FEM_RULE_TRI3)
@@ -67,6 +71,7 @@ __device__ __forceinline__ void batch_tile(const BatchMesh& M, int64_t t) {
         FEMQ_CASE(2, FEM_MASS, FEM_RULE_CENTROID)
         FEMQ_CASE(3, FEM_MASS, FEM_RULE_CENTROID)
 #undef FEMQ_CASE
+#undef FEMQ_CASE_S
     default: break;
     }
 }
@@ -188,8 +193,10 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
         const bool phys_ok = d.physics == FEM_LAPLACE || d.physics == FEM_ELASTICITY || d.physics == FEM_MASS;
         const bool rule_ok = d.rule == FEM_RULE_CENTROID || (d.dim == 2 && d.rule == FEM_RULE_TRI3) ||
                              (d.dim == 3 && d.rule == FEM_RULE_TET4);
-        if (!dim_ok || !phys_ok || !rule_ok) {
-            set_error("fem_batch_plan_create: mesh %d has an unsupported (dim, physics, rule)", i);
+        const bool space_ok = d.coef_space == FEM_COEF_QUAD || d.coef_space == FEM_COEF_P1 ||
+                              d.coef_space == FEM_COEF_P0;
+        if (!dim_ok || !phys_ok || !rule_ok || !space_ok) {
+            set_error("fem_batch_plan_create: mesh %d has an unsupported (dim, physics, rule, coef_space)", i);
             return FEM_ERR_UNSUPPORTED;
         }
         if (d.n_elem < 0) { set_error("fem_batch_plan_create: mesh %d has negative n_elem", i); return FEM_ERR_INVALID_ARG; }
@@ -200,7 +207,7 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
         }
         BatchMesh m;
         std::memset(&m, 0, sizeof m);
-        m.type = type_code(d.dim, d.physics, d.rule);
+        m.type = type_code(d.dim, d.physics, d.rule, d.coef_space);
         m.n_elem = d.n_elem;
         m.inv_j = d.inv_j;
         m.det_j = d.det_j;

@@ -57,6 +57,13 @@ static bool valid_rule(int dim, int rule) {
     return rule == FEM_RULE_CENTROID || (dim == 2 && rule == FEM_RULE_TRI3) || (dim == 3 && rule == FEM_RULE_TET4);
 }
 
+static bool valid_space(int sp) { return sp == FEM_COEF_QUAD || sp == FEM_COEF_P1 || sp == FEM_COEF_P0; }
+
+static fem_status check_space(const char* fn, int space) {
+    if (!valid_space(space)) { set_error("%s: unknown coefficient space %d", fn, space); return FEM_ERR_UNSUPPORTED; }
+    return FEM_OK;
+}
+
 static fem_status check_combo(const char* fn, int dim, int phys, int rule, int dtype) {
     if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
     if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
@@ -208,10 +215,11 @@ fem_status fem_geometry(int dim, int64_t n_elem, int64_t n_vert, const double* c
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_geometry launch");
 }
 
-fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int64_t n_elem, const void* inv_j,
-                                  const void* det_j, const void* u, const void* coef, void* elem_vec,
+fem_status fem_integrate_residual(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
+                                  const void* inv_j, const void* det_j, const void* u, const void* coef, void* elem_vec,
                                   void* stream) {
     fem_status st = check_combo("fem_integrate_residual", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual", coef_space);
     if (st) return st;
     if (n_elem < 0) { set_error("fem_integrate_residual: negative n_elem"); return FEM_ERR_INVALID_ARG; }
     if (n_elem == 0) return FEM_OK;
@@ -224,24 +232,26 @@ fem_status fem_integrate_residual(int dim, int physics, int rule, int dtype, int
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     hipError_t e;
     if (t.strategy == FEM_STRATEGY_TRANSPOSE) {
-        int threads = transpose_block_threads(dim, physics, rule, dtype, t.waves_per_block);
+        int threads = transpose_block_threads(dim, physics, rule, coef_space, dtype, t.waves_per_block);
         if (threads == 0) { set_error("fem_integrate_residual: transpose strategy unavailable"); return FEM_ERR_UNSUPPORTED; }
         Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
         l.block = threads;
-        e = launch_residual_transpose(dim, physics, rule, dtype, a, l);
+        e = launch_residual_transpose(dim, physics, rule, coef_space, dtype, a, l);
     } else {
         const void* ptrs[5] = {inv_j, det_j, u, coef, elem_vec};
         int vec = usable_vec(t.vec, n_elem, word, ptrs, 5);
         Launch l = make_launch(t, n_elem / vec, vec, static_cast<hipStream_t>(stream));
-        e = launch_residual_lane(dim, physics, rule, dtype, a, l);
+        e = launch_residual_lane(dim, physics, rule, coef_space, dtype, a, l);
     }
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual launch");
 }
 
-fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int dtype, int64_t n_elem, int64_t n_vert,
+fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
+                                       int64_t n_vert,
                                        const double* coords, const int32_t* conn, const void* u, const void* coef,
                                        void* elem_vec, void* inv_j, void* det_j, int32_t* counts, void* stream) {
     fem_status st = check_combo("fem_integrate_residual_mesh", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_mesh", coef_space);
     if (st) return st;
     if (n_elem < 0 || n_vert < 0) { set_error("fem_integrate_residual_mesh: negative size"); return FEM_ERR_INVALID_ARG; }
     if (n_elem == 0) return FEM_OK;
@@ -253,14 +263,15 @@ fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int dtype
     const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_MESH, dim, physics, rule, dtype);
     MeshArgs a{n_elem, n_vert, coords, conn, u, coef, elem_vec, inv_j, det_j, counts};
     Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
-    hipError_t e = launch_residual_mesh(dim, physics, rule, dtype, a, l);
+    hipError_t e = launch_residual_mesh(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_mesh launch");
 }
 
-fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int dtype, int64_t n_elem,
+fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
                                            const void* inv_j, const void* det_j, const void* u, const void* coef,
                                            const void* w, void* du, void* dcoef, void* stream) {
     fem_status st = check_combo("fem_integrate_residual_backward", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_backward", coef_space);
     if (st) return st;
     if (n_elem < 0) { set_error("fem_integrate_residual_backward: negative n_elem"); return FEM_ERR_INVALID_ARG; }
     if (n_elem == 0 || (!du && !dcoef)) return FEM_OK;
@@ -274,7 +285,7 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int d
     int vec = usable_vec(t.vec, n_elem, word, ptrs, 7);
     BackwardArgs a{n_elem, inv_j, det_j, u, coef, w, du, dcoef};
     Launch l = make_launch(t, n_elem / vec, vec, static_cast<hipStream_t>(stream));
-    hipError_t e = launch_backward_lane(dim, physics, rule, dtype, a, l);
+    hipError_t e = launch_backward_lane(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_backward launch");
 }
 

@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include "fem.h"
+#include "fem_scheme.hpp"
 
 namespace femq {
 
@@ -22,6 +23,7 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 
 // ---------------------------------------------------------------- traits --
 
+// RULE is a scheme (fem_scheme.hpp): quadrature rule and coefficient space.
 template <int DIM, int PHYS, int RULE>
 struct Elem {
     static_assert(DIM == 2 || DIM == 3, "dim");
@@ -29,9 +31,11 @@ struct Elem {
     static constexpr int NB = DIM + 1;                              // P1 basis functions
     static constexpr int NC = (PHYS == FEM_ELASTICITY) ? DIM : 1;   // field components
     static constexpr int NBT = NB * NC;                             // closure / element-vector length
-    static constexpr int NQ = (RULE == FEM_RULE_CENTROID) ? 1 : DIM + 1;
+    static constexpr int NQ = (rule_of(RULE) == FEM_RULE_CENTROID) ? 1 : DIM + 1;
+    static constexpr int SPACE = space_of(RULE);                    // coefficient space
+    static constexpr int NW = SPACE == FEM_COEF_QUAD ? NQ : SPACE == FEM_COEF_P1 ? NB : 1;
     static constexpr int NCOEF = (PHYS == FEM_ELASTICITY) ? 2 : 1;
-    static constexpr int NCQ = NCOEF * NQ;                          // coefficient words per element
+    static constexpr int NCQ = NCOEF * NW;                          // coefficient words per element
     static constexpr int NG = DIM * DIM;                            // inverse-Jacobian words
 };
 
@@ -39,21 +43,22 @@ struct Elem {
 // Points are given by barycentric coordinates; point q has the large weight
 // at vertex q. Both degree-2 rules have equal weights, which sum to 1/dim!.
 
-template <int DIM, int RULE>
+template <int DIM, int SCHEME>
 struct Rule {
-    static constexpr int NQ = (RULE == FEM_RULE_CENTROID) ? 1 : DIM + 1;
+    static constexpr int R = rule_of(SCHEME);
+    static constexpr int NQ = (R == FEM_RULE_CENTROID) ? 1 : DIM + 1;
     // weight of every point
-    static constexpr double W = (RULE == FEM_RULE_TRI3)   ? 1.0 / 6.0
-                              : (RULE == FEM_RULE_TET4)   ? 1.0 / 24.0
-                              : (DIM == 2)                ? 0.5
-                                                          : 1.0 / 6.0;
+    static constexpr double W = (R == FEM_RULE_TRI3)   ? 1.0 / 6.0
+                              : (R == FEM_RULE_TET4)   ? 1.0 / 24.0
+                              : (DIM == 2)             ? 0.5
+                                                       : 1.0 / 6.0;
     // barycentric value of point q at its own vertex, and at the others
-    static constexpr double LA = (RULE == FEM_RULE_TRI3)  ? 2.0 / 3.0
-                               : (RULE == FEM_RULE_TET4)  ? 0.58541019662496845446137605030969143531609
-                                                          : 1.0 / (DIM + 1);
-    static constexpr double LB = (RULE == FEM_RULE_TRI3)  ? 1.0 / 6.0
-                               : (RULE == FEM_RULE_TET4)  ? 0.13819660112501051517954131656343618822797
-                                                          : 1.0 / (DIM + 1);
+    static constexpr double LA = (R == FEM_RULE_TRI3)  ? 2.0 / 3.0
+                               : (R == FEM_RULE_TET4)  ? 0.58541019662496845446137605030969143531609
+                                                       : 1.0 / (DIM + 1);
+    static constexpr double LB = (R == FEM_RULE_TRI3)  ? 1.0 / 6.0
+                               : (R == FEM_RULE_TET4)  ? 0.13819660112501051517954131656343618822797
+                                                       : 1.0 / (DIM + 1);
     // B[q][b] = phi_b(xi_q): for P1 the basis functions are the barycentric coordinates
     __host__ __device__ static constexpr double B(int q, int b) { return q == b ? LA : LB; }
 };
@@ -123,6 +128,25 @@ template <> struct Physics<FEM_MASS> {
 // and F is pulled back to reference coordinates once (Fh = J^{-1} F) before
 // the D^T contraction. f0/f1 are still evaluated at every quadrature point.
 
+// Coefficient m at quadrature point q from the element's coefficient words
+// cf[m*NW + k] in their space: the value at the point, the P1 interpolant
+// sum_b phi_b(xi_q) a_b, or the cell value.
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ Real coef_at(const Real* cf, int m, int q) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using Q = Rule<DIM, RULE>;
+    if constexpr (E::SPACE == FEM_COEF_QUAD) {
+        return cf[m * E::NW + q];
+    } else if constexpr (E::SPACE == FEM_COEF_P1) {
+        Real v = Real(Q::B(q, 0)) * cf[m * E::NW];
+#pragma unroll
+        for (int b = 1; b < E::NB; ++b) v = fmadd(Real(Q::B(q, b)), cf[m * E::NW + b], v);
+        return v;
+    } else {
+        return cf[m];
+    }
+}
+
 template <int DIM, int NC, typename Real>
 __device__ __forceinline__ void physical_gradient(const Real* ij, const Real* u, Real (&g)[NC][DIM]) {
     // reference gradient gh[c][k] = u_{k+1,c} - u_{0,c}; then g = J^{-T} gh
@@ -176,7 +200,7 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
         }
         Real a[E::NCOEF];
 #pragma unroll
-        for (int m = 0; m < E::NCOEF; ++m) a[m] = cf[m * NQ + q];
+        for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cf, m, q);
         Real f0[NC], f1[NC][DIM];
         P::template point<DIM, Real>(uq, g, a, f0, f1);
         if constexpr (P::HAS_F1) {
@@ -214,9 +238,12 @@ __device__ __forceinline__ void element_residual(const Real* ij, Real dj, const 
     }
 }
 
-// Adjoint of L = w . R for one element. du = R(w) (symmetric forms);
-// dcoef[m*NQ+q] = w_q |J| [ w^q . f0(e_m) + grad w : f1(e_m) ] with f0/f1
-// evaluated at unit coefficient e_m (the forms are linear in coefficients).
+// Adjoint of L = w . R for one element. du = R(w) (symmetric forms); the
+// derivative with respect to coefficient m at point q is
+// w_q |J| [ w^q . f0(e_m) + grad w : f1(e_m) ] with f0/f1 evaluated at unit
+// coefficient e_m (the forms are linear in coefficients); it is stored as is
+// (points), or summed onto the nodal values with weights phi_b(xi_q) (P1),
+// or onto the cell value (P0), by the chain rule.
 template <int DIM, int PHYS, int RULE, typename Real>
 __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Real* u,
                                               const Real* w, Real* dcf) {
@@ -231,6 +258,8 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
         physical_gradient<DIM, NC>(ij, w, gw);
     }
     const Real s = Real(Q::W) * fabs(dj);
+#pragma unroll
+    for (int k = 0; k < E::NCQ; ++k) dcf[k] = Real(0);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         Real uq[NC], wq[NC];
@@ -266,7 +295,15 @@ __device__ __forceinline__ void element_dcoef(const Real* ij, Real dj, const Rea
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) acc = fmadd(gw[c][i], f1[c][i], acc);
             }
-            dcf[m * NQ + q] = s * acc;
+            const Real dq = s * acc;
+            if constexpr (E::SPACE == FEM_COEF_QUAD) {
+                dcf[m * E::NW + q] = dq;
+            } else if constexpr (E::SPACE == FEM_COEF_P1) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) dcf[m * E::NW + b] = fmadd(Real(Q::B(q, b)), dq, dcf[m * E::NW + b]);
+            } else {
+                dcf[m] += dq;
+            }
         }
     }
 }

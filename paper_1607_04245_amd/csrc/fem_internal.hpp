@@ -49,13 +49,15 @@ struct Launch {
     hipStream_t stream;
 };
 
-// Each returns hipErrorInvalidValue when the combination has no kernel.
-hipError_t launch_residual_lane(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
+// Each returns hipErrorInvalidValue when the combination has no kernel;
+// `space` is the coefficient space (fem_coef_space).
+hipError_t launch_residual_lane(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                                 const Launch& l);
-hipError_t launch_residual_transpose(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
+hipError_t launch_residual_transpose(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                                      const Launch& l);
-hipError_t launch_residual_mesh(int dim, int phys, int rule, int dtype, const MeshArgs& a, const Launch& l);
-hipError_t launch_backward_lane(int dim, int phys, int rule, int dtype, const BackwardArgs& a,
+hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
+                                const Launch& l);
+hipError_t launch_backward_lane(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                                 const Launch& l);
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,
                            const int32_t* conn, void* inv_j, void* det_j, int32_t* counts,
@@ -64,7 +66,7 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t n_bytes, const
 
 // Batched persistent kernel (batch.hip).
 struct BatchMesh {              // device-side descriptor, one per mesh
-    int32_t type;               // dim*16 + physics*4 + rule
+    int32_t type;               // dim*64 + coef_space*16 + physics*4 + rule
     int32_t pad;
     int64_t n_elem;
     int64_t tile_begin;         // first global tile of this mesh
@@ -81,7 +83,7 @@ hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, const int32_t* d_t
 
 // Threads the transpose kernel needs per workgroup for a given tuning, or 0 if
 // the combination is not supported by that strategy.
-int transpose_block_threads(int dim, int phys, int rule, int dtype, int waves_per_block);
+int transpose_block_threads(int dim, int phys, int rule, int space, int dtype, int waves_per_block);
 
 }  // namespace femq
 

@@ -80,32 +80,18 @@ static hipError_t launch_t(int dtype, const ResidualArgs& a, const Launch& l) {
     return dtype == FEM_F32 ? launch_v<DIM, PHYS, RULE, float>(a, l) : launch_v<DIM, PHYS, RULE, double>(a, l);
 }
 
-template <int DIM, int PHYS>
-static hipError_t launch_r(int rule, int dtype, const ResidualArgs& a, const Launch& l) {
-    if (rule == FEM_RULE_CENTROID) return launch_t<DIM, PHYS, FEM_RULE_CENTROID>(dtype, a, l);
-    if constexpr (DIM == 2) {
-        if (rule == FEM_RULE_TRI3) return launch_t<DIM, PHYS, FEM_RULE_TRI3>(dtype, a, l);
-    } else {
-        if (rule == FEM_RULE_TET4) return launch_t<DIM, PHYS, FEM_RULE_TET4>(dtype, a, l);
-    }
-    return hipErrorInvalidValue;
-}
+struct LaneDispatch {
+    int dtype;
+    const ResidualArgs& a;
+    const Launch& l;
+    template <int D, int P, int S>
+    hipError_t operator()() const { return launch_t<D, P, S>(dtype, a, l); }
+};
 
-template <int DIM>
-static hipError_t launch_p(int phys, int rule, int dtype, const ResidualArgs& a, const Launch& l) {
-    switch (phys) {
-    case FEM_LAPLACE: return launch_r<DIM, FEM_LAPLACE>(rule, dtype, a, l);
-    case FEM_ELASTICITY: return launch_r<DIM, FEM_ELASTICITY>(rule, dtype, a, l);
-    case FEM_MASS: return launch_r<DIM, FEM_MASS>(rule, dtype, a, l);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_residual_lane(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
-                                const Launch& l) {
-    if (dim == 2) return launch_p<2>(phys, rule, dtype, a, l);
-    if (dim == 3) return launch_p<3>(phys, rule, dtype, a, l);
-    return hipErrorInvalidValue;
+hipError_t launch_residual_lane(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
+                               const Launch& l) {
+    const LaneDispatch f{dtype, a, l};
+    return dispatch_element(dim, phys, rule, space, f, hipErrorInvalidValue);
 }
 
 }  // namespace femq

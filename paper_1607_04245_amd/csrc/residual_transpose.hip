@@ -89,8 +89,11 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
             const Real dj = in_s[L::OFF_DJ * T + el];
 #pragma unroll
             for (int f = 0; f < E::NBT; ++f) uu[f] = in_s[(L::OFF_U + f) * T + el];
+            Real cfl[E::NCQ];
 #pragma unroll
-            for (int m = 0; m < E::NCOEF; ++m) a[m] = in_s[(L::OFF_CF + m * NQ + q) * T + el];
+            for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
+#pragma unroll
+            for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
             Real g[NC][DIM];
             physical_gradient<DIM, NC>(ij, uu, g);
             Real uq[NC];
@@ -178,36 +181,22 @@ static hipError_t launch_tt(const ResidualArgs& a, const Launch& l) {
     return hipGetLastError();
 }
 
-// Dispatch helper: calls f.template operator()<DIM, PHYS, RULE, Real>() for a
+// Dispatch helper: calls f.template operator()<DIM, PHYS, SCHEME, Real>() for a
 // runtime combination; returns fallback for an unknown one.
 template <typename F, typename R>
-static R tt_dispatch(int dim, int phys, int rule, int dtype, F&& f, R fallback) {
-    auto by_rule = [&](auto dim_c, auto phys_c) -> R {
-        constexpr int D = decltype(dim_c)::value, P = decltype(phys_c)::value;
-        auto by_type = [&](auto rule_c) -> R {
-            constexpr int RU = decltype(rule_c)::value;
-            return dtype == FEM_F32 ? f.template operator()<D, P, RU, float>()
-                                    : f.template operator()<D, P, RU, double>();
-        };
-        if (rule == FEM_RULE_CENTROID) return by_type(std::integral_constant<int, FEM_RULE_CENTROID>());
-        if constexpr (D == 2) {
-            if (rule == FEM_RULE_TRI3) return by_type(std::integral_constant<int, FEM_RULE_TRI3>());
-        } else {
-            if (rule == FEM_RULE_TET4) return by_type(std::integral_constant<int, FEM_RULE_TET4>());
-        }
-        return fallback;
-    };
-    auto by_phys = [&](auto dim_c) -> R {
-        switch (phys) {
-        case FEM_LAPLACE: return by_rule(dim_c, std::integral_constant<int, FEM_LAPLACE>());
-        case FEM_ELASTICITY: return by_rule(dim_c, std::integral_constant<int, FEM_ELASTICITY>());
-        case FEM_MASS: return by_rule(dim_c, std::integral_constant<int, FEM_MASS>());
-        default: return fallback;
-        }
-    };
-    if (dim == 2) return by_phys(std::integral_constant<int, 2>());
-    if (dim == 3) return by_phys(std::integral_constant<int, 3>());
-    return fallback;
+struct TTByType {
+    const F& f;
+    int dtype;
+    template <int D, int P, int S>
+    R operator()() const {
+        return dtype == FEM_F32 ? f.template operator()<D, P, S, float>() : f.template operator()<D, P, S, double>();
+    }
+};
+
+template <typename F, typename R>
+static R tt_dispatch(int dim, int phys, int rule, int space, int dtype, const F& f, R fallback) {
+    const TTByType<F, R> g{f, dtype};
+    return dispatch_element(dim, phys, rule, space, g, fallback);
 }
 
 struct TTLaunch {
@@ -222,13 +211,13 @@ struct TTBytes {
     size_t operator()() const { return tt_bytes_per_wave<D, P, RU, Real>(); }
 };
 
-hipError_t launch_residual_transpose(int dim, int phys, int rule, int dtype, const ResidualArgs& a,
+hipError_t launch_residual_transpose(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                                      const Launch& l) {
-    return tt_dispatch(dim, phys, rule, dtype, TTLaunch{a, l}, hipErrorInvalidValue);
+    return tt_dispatch(dim, phys, rule, space, dtype, TTLaunch{a, l}, hipErrorInvalidValue);
 }
 
-int transpose_block_threads(int dim, int phys, int rule, int dtype, int waves_per_block) {
-    const size_t per_wave = tt_dispatch(dim, phys, rule, dtype, TTBytes{}, (size_t)0);
+int transpose_block_threads(int dim, int phys, int rule, int space, int dtype, int waves_per_block) {
+    const size_t per_wave = tt_dispatch(dim, phys, rule, space, dtype, TTBytes{}, (size_t)0);
     if (per_wave == 0) return 0;
     int w = waves_per_block;
     while (w > 1 && (size_t)w * per_wave > kMaxLdsPerBlock) w >>= 1;

@@ -292,14 +292,14 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     auto run = [&](const Copy& c) -> fem_status {
         switch (op) {
         case FEM_OP_RESIDUAL:
-            return fem_integrate_residual(dim, physics, rule, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);
+            return fem_integrate_residual(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);
         case FEM_OP_BACKWARD:
-            return fem_integrate_residual_backward(dim, physics, rule, dtype, n, c.ij, c.dj, c.u, c.cf, c.w, c.du,
+            return fem_integrate_residual_backward(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.w, c.du,
                                                    c.dc, nullptr);
         case FEM_OP_GEOMETRY:
             return fem_geometry(dim, n, n_vert, c.X, c.conn, dtype, c.ij, c.dj, nullptr, nullptr);
         default:
-            return fem_integrate_residual_mesh(dim, physics, rule, dtype, n, n_vert, c.X, c.conn, c.u, c.cf, c.out,
+            return fem_integrate_residual_mesh(dim, physics, rule, FEM_COEF_QUAD, dtype, n, n_vert, c.X, c.conn, c.u, c.cf, c.out,
                                                nullptr, nullptr, nullptr, nullptr);
         }
     };

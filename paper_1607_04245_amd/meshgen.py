@@ -23,9 +23,10 @@ import numpy as np
 
 BASE_SEED = 160704245
 
-# Physics / rule codes; the numeric values match include/fem.h.
+# Physics / rule / coefficient-space codes; the numeric values match include/fem.h.
 LAPLACE, ELASTICITY, MASS = 0, 1, 2
 RULE_TRI3, RULE_TET4, RULE_CENTROID = 0, 1, 2
+COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
 
 PHYSICS_NAMES = {LAPLACE: "laplace", ELASTICITY: "elasticity", MASS: "mass"}
 
@@ -221,6 +222,32 @@ def _draw_fields(dim, physics, rule, conn, n_vert, rngs):
         u_vertex = r_u.uniform(-1.0, 1.0, size=(n_vert, nc))
     w = r_w.uniform(-1.0, 1.0, size=((dim + 1) * nc, ne))
     return np.ascontiguousarray(coef), u_vertex, np.ascontiguousarray(w)
+
+
+def _coef_draw(physics, rng, shape):
+    if physics == ELASTICITY:
+        return np.stack([rng.uniform(1.0, 10.0, size=shape), rng.uniform(0.5, 5.0, size=shape)], axis=0)
+    return rng.uniform(0.5, 2.0, size=(1,) + shape)
+
+
+def space_coefficients(wl: "Workload", space: int, seed: int) -> np.ndarray:
+    """Coefficients of ``wl`` in another space, [N_coef, N_w, N_e] float64.
+
+    COEF_QUAD returns the workload's own values at the points. COEF_P1 draws a
+    vertex field (one value per mesh vertex and coefficient, the distribution
+    of the point values) and gathers its closure, so neighbouring elements
+    share vertex values as an auxiliary P1 field does. COEF_P0 draws one value
+    per cell.
+    """
+    if space == COEF_QUAD:
+        return wl.coef
+    rng = np.random.default_rng(seed)
+    if space == COEF_P1:
+        vert = _coef_draw(wl.physics, rng, (wl.n_vert,))          # [N_coef, N_v]
+        return np.ascontiguousarray(np.stack([closure(wl.conn, v[:, None]) for v in vert]))
+    if space == COEF_P0:
+        return np.ascontiguousarray(_coef_draw(wl.physics, rng, (1, wl.n_elem)))
+    raise ValueError(f"unknown coefficient space {space}")
 
 
 def make_workload(name: str, dim: int, physics: int, grid_n: int, n_elem: int | None,

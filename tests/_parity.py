@@ -45,26 +45,26 @@ def assert_close(got, ref, ref_abs, dtype, what=""):
     return mx, agg
 
 
-def oracle_reference(wl, dtype, u=None, coef=None):
+def oracle_reference(wl, dtype, u=None, coef=None, space=0):
     """(R, R_abs, inv_j, det_j) of the oracle on the rounded inputs."""
     u = wl.u if u is None else u
     coef = wl.coef if coef is None else coef
     ij, dj, nd = oracle.geometry(wl.coords, wl.conn)
     assert nd == 0
     ur, cr = rounded(u, dtype), rounded(coef, dtype)
-    R = oracle.integrate(wl.dim, wl.physics, wl.rule, ij, dj, ur, cr)
-    Ra = oracle.integrate_abs(wl.dim, wl.physics, wl.rule, ij, dj, ur, cr)
+    R = oracle.integrate(wl.dim, wl.physics, wl.rule, ij, dj, ur, cr, space=space)
+    Ra = oracle.integrate_abs(wl.dim, wl.physics, wl.rule, ij, dj, ur, cr, space=space)
     return R, Ra, ij, dj
 
 
-def dcoef_abs(dim, physics, rule, inv_j, det_j, u, w, n_coef, n_q):
+def dcoef_abs(dim, physics, rule, inv_j, det_j, u, w, n_coef, n_w, space=0):
     """Scale of the coefficient adjoint: |w| . R_abs(u; unit coefficient)."""
     n = det_j.shape[0]
-    out = np.zeros((n_coef, n_q, n))
+    out = np.zeros((n_coef, n_w, n))
     for m in range(n_coef):
-        for q in range(n_q):
-            unit = np.zeros((n_coef, n_q, n))
-            unit[m, q] = 1.0
-            Ra = oracle.integrate_abs(dim, physics, rule, inv_j, det_j, u, unit)
-            out[m, q] = np.sum(np.abs(w) * Ra, axis=0)
+        for k in range(n_w):
+            unit = np.zeros((n_coef, n_w, n))
+            unit[m, k] = 1.0
+            Ra = oracle.integrate_abs(dim, physics, rule, inv_j, det_j, u, unit, space=space)
+            out[m, k] = np.sum(np.abs(w) * Ra, axis=0)
     return out

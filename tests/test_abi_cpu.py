@@ -55,12 +55,14 @@ def test_geometry_null_arrays(lib):
 
 
 @pytest.mark.parametrize("combo,status", [
-    ((2, mg.LAPLACE, mg.RULE_TET4, N.F32), N.FEM_ERR_UNSUPPORTED),   # tet rule in 2D
-    ((3, mg.LAPLACE, mg.RULE_TRI3, N.F32), N.FEM_ERR_UNSUPPORTED),   # triangle rule in 3D
-    ((1, mg.LAPLACE, mg.RULE_CENTROID, N.F32), N.FEM_ERR_UNSUPPORTED),
-    ((2, 9, mg.RULE_TRI3, N.F32), N.FEM_ERR_UNSUPPORTED),
-    ((2, mg.LAPLACE, 9, N.F32), N.FEM_ERR_UNSUPPORTED),
-    ((2, mg.LAPLACE, mg.RULE_TRI3, 5), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, N.F32), N.FEM_ERR_UNSUPPORTED),   # tet rule in 2D
+    ((3, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, N.F32), N.FEM_ERR_UNSUPPORTED),   # triangle rule in 3D
+    ((1, mg.LAPLACE, mg.RULE_CENTROID, N.COEF_QUAD, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, 9, mg.RULE_TRI3, N.COEF_QUAD, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, 9, N.COEF_QUAD, N.F32), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, 5), N.FEM_ERR_UNSUPPORTED),
+    ((2, mg.LAPLACE, mg.RULE_TRI3, 3, N.F32), N.FEM_ERR_UNSUPPORTED),            # unknown coefficient space
+    ((3, mg.ELASTICITY, mg.RULE_TET4, -1, N.F64), N.FEM_ERR_UNSUPPORTED),
 ])
 def test_residual_combo_validation(lib, combo, status):
     st = lib.fem_integrate_residual(*combo, 10, _v(), _v(), _v(), _v(), _v(), None)
@@ -70,7 +72,7 @@ def test_residual_combo_validation(lib, combo, status):
 
 
 def test_residual_sizes_and_nulls(lib):
-    c = (3, mg.ELASTICITY, mg.RULE_TET4, N.F64)
+    c = (3, mg.ELASTICITY, mg.RULE_TET4, N.COEF_P1, N.F64)
     assert lib.fem_integrate_residual(*c, -5, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_integrate_residual(*c, 0, None, None, None, None, None, None) == N.FEM_OK
     assert lib.fem_integrate_residual(*c, 5, _v(), None, _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
@@ -123,11 +125,13 @@ def test_batch_plan_validation(lib):
     assert lib.fem_batch_plan_create(None, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_batch_plan_create(None, 0, 9, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
     d = (N.fem_mesh_desc * 1)()
-    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TET4, 10, 1, 1, 1, 1, 1)
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, 10, 1, 1, 1, 1, 1)
     assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
-    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, -1, 1, 1, 1, 1, 1)
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, 5, 10, 1, 1, 1, 1, 1)
+    assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, -1, 1, 1, 1, 1, 1)
     assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
-    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, 10, 1, None, 1, 1, 1)
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_P0, 10, 1, None, 1, 1, 1)
     assert lib.fem_batch_plan_create(d, 1, N.F32, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_batch_run(None, None) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_batch_replay(None, None) == N.FEM_ERR_INVALID_ARG
@@ -144,7 +148,7 @@ def test_autotune_validation(lib):
 
 
 def test_residual_mesh_validation(lib):
-    c = (3, mg.LAPLACE, mg.RULE_TET4, N.F32)
+    c = (3, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, N.F32)
     f = lib.fem_integrate_residual_mesh
     assert f(*c, 0, 0, None, None, None, None, None, None, None, None, None) == N.FEM_OK
     assert f(*c, -1, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
@@ -152,5 +156,7 @@ def test_residual_mesh_validation(lib):
     assert f(*c, 5, 5, _v(), None, _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
     # geometry outputs: both or neither
     assert f(*c, 5, 5, _v(), _v(), _v(), _v(), _v(), _v(), None, None, None) == N.FEM_ERR_INVALID_ARG
-    assert f(3, mg.LAPLACE, mg.RULE_TRI3, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
+    assert f(3, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None,
+             None) == N.FEM_ERR_UNSUPPORTED
+    assert f(3, mg.LAPLACE, mg.RULE_TET4, 7, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
         == N.FEM_ERR_UNSUPPORTED

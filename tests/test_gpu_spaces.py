@@ -1,0 +1,247 @@
+"""GPU parity of the coefficient spaces (paper Section 5: an auxiliary field
+given at the quadrature points, in the P1 space of u, or constant per cell).
+
+Every kernel kind (lane, thread transposition, fused from-mesh, batched
+persistent, adjoint) runs P1 and P0 coefficients through the C ABI and is
+compared with the FP64 oracle (same bars as the other parity tests) or,
+between kernels that share the element arithmetic, bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1607_04245_amd import api, meshgen as mg
+from paper_1607_04245_amd import _native as N
+
+from _parity import assert_close, dcoef_abs, dev, oracle_reference, rounded
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+KINDS = [(2, mg.LAPLACE), (3, mg.LAPLACE), (2, mg.ELASTICITY), (3, mg.ELASTICITY), (2, mg.MASS), (3, mg.MASS)]
+SPACES = [mg.COEF_P1, mg.COEF_P0]
+OPS = [N.OP_RESIDUAL, N.OP_RESIDUAL_MESH, N.OP_BACKWARD]
+
+
+def small_workload(dim, phys, n_elem, rule=None, seed=11):
+    grid = mg.smallest_grid(dim, max(n_elem, 1))
+    return mg.make_workload(f"s{dim}{phys}", dim, phys, grid, n_elem, mg.BASE_SEED + seed, rule=rule)
+
+
+def coefficients(wl, space, seed=3):
+    return mg.space_coefficients(wl, space, mg.BASE_SEED + 1000 + seed)
+
+
+def gpu_geometry(wl, dtype):
+    ij, dj = api.fem_geometry(dev(wl.coords, torch.float64), dev(wl.conn, torch.int32), dtype)
+    return ij, dj
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    saved = {}
+    for dim, phys in KINDS:
+        for rule in (mg.default_rule(dim), mg.RULE_CENTROID):
+            for dt in DTYPES:
+                for op in OPS:
+                    saved[(dim, phys, rule, dt, op)] = api.fem_get_tuning(dim, phys, rule, dt, op=op)
+    yield
+    for (dim, phys, rule, dt, op), t in saved.items():
+        api.fem_set_tuning(dim, phys, rule, dt, op=op, **t)
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("rule_kind", ["default", "centroid"])
+def test_forward_matches_oracle(dim, phys, space, dtype, rule_kind):
+    rule = mg.default_rule(dim) if rule_kind == "default" else mg.RULE_CENTROID
+    wl = small_workload(dim, phys, 3001, rule=rule)
+    cf = coefficients(wl, space)
+    ij, dj = gpu_geometry(wl, dtype)
+    R = api.fem_integrate_residual(dim, phys, rule, ij, dj, dev(wl.u, dtype), dev(cf, dtype), coef_space=space)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+    assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"{dim}D phys {phys} space {space}")
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_every_lane_shape_bitwise(dim, phys, space, dtype):
+    """Lane kernel at each elements-per-lane and workgroup shape: same bits;
+    the fused from-mesh kernel at each of its shapes: the same bits again."""
+    wl = small_workload(dim, phys, 4099)
+    cf = coefficients(wl, space)
+    ij, dj = gpu_geometry(wl, dtype)
+    u, c = dev(wl.u, dtype), dev(cf, dtype)
+    first = None
+    for vec, waves, bpc in [(1, 2, 0), (2, 4, 4), (4, 1, 0), (1, 8, 16)]:
+        api.fem_set_tuning(dim, phys, wl.rule, dtype, strategy=N.STRATEGY_LANE, vec=vec, waves_per_block=waves,
+                           blocks_per_cu=bpc)
+        R = api.fem_integrate_residual(dim, phys, wl.rule, ij, dj, u, c, coef_space=space)
+        if first is None:
+            first = R.clone()
+        assert torch.equal(R, first), f"lane shape {(vec, waves, bpc)}"
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    for ept, waves, bpc in [(1, 1, 8), (2, 2, 0), (1, 4, 2)]:
+        api.fem_set_tuning(dim, phys, wl.rule, dtype, strategy=N.STRATEGY_LANE, vec=ept, waves_per_block=waves,
+                           blocks_per_cu=bpc, op=N.OP_RESIDUAL_MESH)
+        ij2 = torch.full_like(ij, float("nan"))
+        dj2 = torch.full_like(dj, float("nan"))
+        R = api.fem_integrate_residual_mesh(dim, phys, wl.rule, coords, conn, u, c, inv_j=ij2, det_j=dj2,
+                                            coef_space=space)
+        assert torch.equal(R, first), f"fused shape {(ept, waves, bpc)}"
+        assert torch.equal(ij2, ij) and torch.equal(dj2, dj)
+
+
+@pytest.mark.parametrize("dim,phys", [(2, mg.LAPLACE), (3, mg.ELASTICITY), (3, mg.MASS)])
+@pytest.mark.parametrize("space", SPACES)
+def test_transpose_strategy(dim, phys, space):
+    dtype = torch.float32
+    wl = small_workload(dim, phys, 2050)
+    cf = coefficients(wl, space)
+    ij, dj = gpu_geometry(wl, dtype)
+    api.fem_set_tuning(dim, phys, wl.rule, dtype, strategy=N.STRATEGY_TRANSPOSE, vec=1, waves_per_block=4)
+    R = api.fem_integrate_residual(dim, phys, wl.rule, ij, dj, dev(wl.u, dtype), dev(cf, dtype), coef_space=space)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+    assert_close(R.cpu().numpy(), ref, ref_abs, dtype, "transpose")
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_backward_matches_oracle(dim, phys, space, dtype):
+    wl = small_workload(dim, phys, 1025)
+    cf = coefficients(wl, space)
+    ij, dj = gpu_geometry(wl, dtype)
+    du, dc = api.fem_integrate_residual_backward(dim, phys, wl.rule, ij, dj, dev(wl.u, dtype), dev(cf, dtype),
+                                                 dev(wl.w, dtype), coef_space=space)
+    rij, rdj, _ = oracle.geometry(wl.coords, wl.conn)
+    ur, cr, wr = rounded(wl.u, dtype), rounded(cf, dtype), rounded(wl.w, dtype)
+    rdu, rdc = oracle.backward(dim, phys, wl.rule, rij, rdj, ur, cr, wr, space=space)
+    du_abs = oracle.integrate_abs(dim, phys, wl.rule, rij, rdj, wr, cr, space=space)
+    dc_abs = dcoef_abs(dim, phys, wl.rule, rij, rdj, ur, wr, rdc.shape[0], rdc.shape[1], space=space)
+    assert_close(du.cpu().numpy(), rdu, du_abs, dtype, "du")
+    nw = rdc.shape[0] * rdc.shape[1]
+    assert dc.shape == rdc.shape
+    assert_close(dc.cpu().numpy().reshape(nw, -1), rdc.reshape(nw, -1), dc_abs.reshape(nw, -1), dtype, "dcoef")
+    # du is the forward residual of w with the same coefficients, bit for bit
+    R_w = api.fem_integrate_residual(dim, phys, wl.rule, ij, dj, dev(wl.w, dtype), dev(cf, dtype),
+                                     coef_space=space)
+    assert torch.equal(du, R_w)
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_autograd_coefficient_gradient_fd(space):
+    """d/dcoef of L = sum w.R through the autograd wrapper against central
+    differences of the GPU forward (FP64, 256 elements)."""
+    dt = torch.float64
+    wl = small_workload(3, mg.ELASTICITY, 256)
+    cf0 = coefficients(wl, space)
+    ij, dj = gpu_geometry(wl, dt)
+    u = dev(wl.u, dt)
+    w = dev(wl.w, dt)
+    cf = dev(cf0, dt).requires_grad_(True)
+    L = (api.integrate_residual(3, mg.ELASTICITY, wl.rule, ij, dj, u, cf, coef_space=space) * w).sum()
+    L.backward()
+    g = cf.grad.cpu().numpy()
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        m = int(rng.integers(cf0.shape[0]))
+        k = int(rng.integers(cf0.shape[1]))
+        e = int(rng.integers(cf0.shape[2]))
+        h = 1e-4 * max(1.0, abs(cf0[m, k, e]))
+        vals = []
+        for sgn in (1, -1):
+            c = cf0.copy()
+            c[m, k, e] += sgn * h
+            R = api.fem_integrate_residual(3, mg.ELASTICITY, wl.rule, ij, dj, u, dev(c, dt), coef_space=space)
+            vals.append(float((R * w).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[m, k, e]) <= 1e-7 * max(1.0, abs(g).max()), (m, k, e, fd, g[m, k, e])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_mixed_spaces_bitwise(dtype):
+    """One persistent launch over meshes whose coefficients live in different
+    spaces: each mesh bit for bit equal to its single-mesh lane result."""
+    sizes = [1000, 65, 4097, 0, 3001, 1, 2000, 513]
+    meshes, wls = [], []
+    for m, ne in enumerate(sizes):
+        dim, phys = KINDS[m % len(KINDS)]
+        space = [mg.COEF_QUAD, mg.COEF_P1, mg.COEF_P0][m % 3]
+        rule = mg.default_rule(dim) if m % 4 else mg.RULE_CENTROID
+        wl = small_workload(dim, phys, ne, rule=rule, seed=200 + m)
+        cf = coefficients(wl, space, seed=m)
+        ij, dj = gpu_geometry(wl, dtype)
+        meshes.append(dict(dim=dim, physics=phys, rule=rule, coef_space=space, inv_j=ij, det_j=dj,
+                           u=dev(wl.u, dtype), coef=dev(cf, dtype),
+                           out=torch.full(wl.u.shape, float("nan"), dtype=dtype, device="cuda")))
+        wls.append((wl, cf, space))
+    for m in meshes:
+        api.fem_set_tuning(m["dim"], m["physics"], m["rule"], dtype, strategy=N.STRATEGY_LANE, vec=1)
+    singles = [api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                          m["coef"], coef_space=m["coef_space"]) for m in meshes]
+    plan = api.BatchPlan(meshes)
+    for waves, bpc in [(8, 0), (2, 3)]:
+        for m in meshes:
+            m["out"].fill_(float("nan"))
+        plan.set_launch(waves, bpc)
+        plan.run()
+        torch.cuda.synchronize()
+        for m, s, (wl, _, space) in zip(meshes, singles, wls):
+            assert torch.equal(m["out"], s), f"batched != single for {wl.name} space {space}"
+    for m, (wl, cf, space) in zip(meshes, wls):
+        if wl.n_elem == 0:
+            continue
+        ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+        assert_close(m["out"].cpu().numpy(), ref, ref_abs, dtype, f"{wl.name} space {space}")
+    plan.close()
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_laplace3d_full_size_fused(space, dtype):
+    """The 2^20-tetrahedron Laplace workload with P1 / P0 coefficients through
+    the fused from-mesh entry point in its default launch configuration."""
+    wl = mg.config(2)
+    cf = coefficients(wl, space, seed=20)
+    R = api.fem_integrate_residual_mesh(3, mg.LAPLACE, wl.rule, dev(wl.coords, torch.float64),
+                                        dev(wl.conn, torch.int32), dev(wl.u, dtype), dev(cf, dtype),
+                                        coef_space=space)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+    mx, agg = assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"laplace3d space {space}")
+    print(f"laplace3d 2^20 space {space} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
+
+
+def test_linear_coefficient_p1_equals_points():
+    """A coefficient linear in x: its P1 nodal values and its values at the
+    points describe the same field, so the GPU results agree to rounding."""
+    dt = torch.float64
+    wl = small_workload(3, mg.ELASTICITY, 2000)
+    a = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.3]])
+    c0 = np.array([4.0, 2.0])
+    vert = wl.coords @ a.T + c0                                     # [N_v, 2]
+    c1 = np.stack([mg.closure(wl.conn, vert[:, m:m + 1]) for m in range(2)])  # [2, 4, n]
+    xi, _ = oracle.rule(3, wl.rule)
+    lam = np.concatenate([1 - xi.sum(1, keepdims=True), xi], axis=1)          # [q, b]
+    xq = np.einsum("qb,nbi->nqi", lam, wl.coords[wl.conn])                   # [n, q, 3]
+    cq = np.ascontiguousarray(np.stack([(xq @ a[m] + c0[m]).T for m in range(2)]))
+    ij, dj = gpu_geometry(wl, dt)
+    u = dev(wl.u, dt)
+    R1 = api.fem_integrate_residual(3, mg.ELASTICITY, wl.rule, ij, dj, u, dev(c1, dt), coef_space=mg.COEF_P1)
+    Rq = api.fem_integrate_residual(3, mg.ELASTICITY, wl.rule, ij, dj, u, dev(cq, dt))
+    _, ref_abs, _, _ = oracle_reference(wl, dt, coef=cq)
+    assert_close(R1.cpu().numpy(), Rq.cpu().numpy(), ref_abs, dt, "P1 vs points")
+
+
+def test_wrong_coefficient_shape_rejected():
+    wl = small_workload(2, mg.LAPLACE, 10)
+    ij, dj = gpu_geometry(wl, torch.float32)
+    with pytest.raises(ValueError):
+        api.fem_integrate_residual(2, mg.LAPLACE, wl.rule, ij, dj, dev(wl.u, torch.float32),
+                                   dev(wl.coef, torch.float32), coef_space=mg.COEF_P0)
+    with pytest.raises(ValueError):
+        api.fem_integrate_residual(2, mg.LAPLACE, wl.rule, ij, dj, dev(wl.u, torch.float32),
+                                   dev(wl.coef, torch.float32), coef_space=7)
