@@ -281,11 +281,11 @@ def main():
             f" GB/s); integrate alone {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
 
         # --------------------------------------------------- other physics --
-        def integrate_only(wlx, dt, reps=20):
+        def integrate_only(wlx, dt, reps=20, space=mg.COEF_QUAD, coef=None):
             word = 4 if dt == torch.float32 else 8
-            nb = model.forward_bytes(wlx.dim, wlx.physics, wlx.rule, word) * wlx.n_elem
+            nb = model.forward_bytes(wlx.dim, wlx.physics, wlx.rule, word, coef_space=space) * wlx.n_elem
             ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
-            base = dict(ij=ij, dj=dj, u=to_dev(wlx.u, dt), cf=to_dev(wlx.coef, dt))
+            base = dict(ij=ij, dj=dj, u=to_dev(wlx.u, dt), cf=to_dev(wlx.coef if coef is None else coef, dt))
             cps = []
             for _ in range(n_copies(nb)):
                 c = {k: v.clone() for k, v in base.items()}
@@ -295,7 +295,7 @@ def main():
 
             def go(c):
                 api.fem_integrate_residual(wlx.dim, wlx.physics, wlx.rule, c["ij"], c["dj"], c["u"], c["cf"],
-                                           out=c["R"])
+                                           out=c["R"], coef_space=space)
             _, ms = timed_graph(go, cps, reps, 1)
             us = ms * 1e3
             del cps
@@ -303,11 +303,12 @@ def main():
             return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
                         model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
-        def fused_only(wlx, dt, reps=20):
+        def fused_only(wlx, dt, reps=20, space=mg.COEF_QUAD, coef=None):
             word = 4 if dt == torch.float32 else 8
-            nb = model.residual_mesh_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert, word) * wlx.n_elem
+            nb = model.residual_mesh_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert, word,
+                                           coef_space=space) * wlx.n_elem
             base = dict(X=to_dev(wlx.coords, torch.float64), conn=to_dev(wlx.conn, torch.int32), u=to_dev(wlx.u, dt),
-                        cf=to_dev(wlx.coef, dt))
+                        cf=to_dev(wlx.coef if coef is None else coef, dt))
             cps = []
             for _ in range(n_copies(nb)):
                 c = {k: v.clone() for k, v in base.items()}
@@ -317,7 +318,7 @@ def main():
 
             def go(c):
                 api.fem_integrate_residual_mesh(wlx.dim, wlx.physics, wlx.rule, c["X"], c["conn"], c["u"], c["cf"],
-                                                out=c["R"])
+                                                out=c["R"], coef_space=space)
             _, ms = timed_graph(go, cps, reps, 1)
             us = ms * 1e3
             del cps
@@ -335,6 +336,61 @@ def main():
                 extra[f"{wlx.name}_{tag}_from_mesh"] = r
                 log(f"{wlx.name} {tag} from mesh: {r['us']:.1f} us ({r['elements_per_s']:.3e} elem/s), "
                     f"{r['gbs']:.0f} GB/s")
+            del wlx
+
+        # ---------------------------------------------- coefficient spaces --
+        # The paper's GPU runs take the coefficient as a P1 field or per cell
+        # (Section 5); P1 coefficients are the closure of a vertex field.
+        for cfg in (2, "3a"):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            for space, sname in ((mg.COEF_P1, "p1"), (mg.COEF_P0, "p0")):
+                cf = mg.space_coefficients(wlx, space, mg.BASE_SEED + 1000)
+                r = integrate_only(wlx, torch.float32, space=space, coef=cf)
+                extra[f"{wlx.name}_f32_coef_{sname}_integrate"] = r
+                r2 = fused_only(wlx, torch.float32, space=space, coef=cf)
+                extra[f"{wlx.name}_f32_coef_{sname}_from_mesh"] = r2
+                log(f"{wlx.name} f32 coefficient {sname}: integrate {r['us']:.1f} us ({r['gbs']:.0f} GB/s), "
+                    f"from mesh {r2['us']:.1f} us ({r2['elements_per_s']:.3e} elem/s, {r2['gbs']:.0f} GB/s)")
+                del cf
+            del wlx
+
+        # ------------------------------------------------------ gather form --
+        # u per vertex (and a P1 coefficient per vertex), gathered in the kernel.
+        def gather_only(wlx, dt, space, reps=20):
+            word = 4 if dt == torch.float32 else 8
+            nb = model.residual_gather_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert, word,
+                                             coef_space=space) * wlx.n_elem
+            s = mg.BASE_SEED + 1000
+            cg = mg.vertex_coefficients(wlx, s) if space == mg.COEF_P1 else mg.space_coefficients(wlx, space, s)
+            base = dict(X=to_dev(wlx.coords, torch.float64), conn=to_dev(wlx.conn, torch.int32),
+                        u=to_dev(wlx.u_vertex, dt), cf=to_dev(cg, dt))
+            nbt = wlx.u.shape[0]
+            cps = []
+            for _ in range(n_copies(nb)):
+                c = {k: v.clone() for k, v in base.items()}
+                c["R"] = torch.empty((nbt, wlx.n_elem), dtype=dt, device=dev)
+                cps.append(c)
+            del base
+
+            def go(c):
+                api.fem_integrate_residual_gather(wlx.dim, wlx.physics, wlx.rule, c["X"], c["conn"], c["u"], c["cf"],
+                                                  out=c["R"], coef_space=space)
+            _, ms = timed_graph(go, cps, reps, 1)
+            us = ms * 1e3
+            del cps
+            f = model.model_flops(wlx.dim, wlx.physics, wlx.rule)
+            return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
+                        model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, bytes_per_elem=nb / wlx.n_elem,
+                        frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+
+        for cfg in (2, "3b"):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            for space, sname in ((mg.COEF_QUAD, "quad"), (mg.COEF_P1, "p1")):
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    r = gather_only(wlx, dt, space)
+                    extra[f"{wlx.name}_{tag}_coef_{sname}_gather"] = r
+                    log(f"{wlx.name} {tag} gather, coefficient {sname}: {r['us']:.1f} us "
+                        f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
             del wlx
 
         # --------------------------------------------------------- adjoint --

@@ -101,7 +101,8 @@ enum fem_op {
     FEM_OP_RESIDUAL = 0,       /* fem_integrate_residual */
     FEM_OP_RESIDUAL_MESH = 1,  /* fem_integrate_residual_mesh */
     FEM_OP_GEOMETRY = 2,       /* fem_geometry (physics and rule ignored) */
-    FEM_OP_BACKWARD = 3        /* fem_integrate_residual_backward */
+    FEM_OP_BACKWARD = 3,       /* fem_integrate_residual_backward */
+    FEM_OP_RESIDUAL_GATHER = 4 /* fem_integrate_residual_gather */
 };
 
 /* ------------------------------------------------------------------ */
@@ -153,6 +154,29 @@ fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_
                                        const int32_t* conn, const void* u, const void* coef,
                                        void* elem_vec, void* inv_j, void* det_j, int32_t* counts,
                                        void* stream);
+
+/* Residual from the mesh with u given per vertex: the element restriction
+ * (the closure u_e = E_e u of Section 2, gathered through the connectivity)
+ * is applied inside the kernel instead of being read as [N_bt][n] rows, so
+ * u costs N_comp words per vertex instead of N_bt words per element.
+ *   u_vertex [n_vert][N_comp]  dtype, component c of vertex v at v*N_comp + c
+ *   coef     FEM_COEF_P1: [n_vert][N_coef] vertex values (coefficient m of
+ *            vertex v at v*N_coef + m), gathered the same way (the paper's
+ *            auxiliary field in the space of u, Section 5);
+ *            FEM_COEF_QUAD, FEM_COEF_P0: per element as for
+ *            fem_integrate_residual.
+ * Everything else (geometry outputs, counts, layouts, bitwise agreement
+ * with the two-call path) as fem_integrate_residual_mesh: elem_vec is
+ * bitwise equal to fem_integrate_residual_mesh called with the gathered
+ * closure (and, for P1, the gathered coefficient closure). Vertex indices
+ * outside [0, n_vert) make the element degenerate (counted; its geometry
+ * and vector are NaN); nothing outside the arrays is read.
+ * Errors: as fem_integrate_residual_mesh. */
+fem_status fem_integrate_residual_gather(int dim, int physics, int rule, int coef_space, int dtype,
+                                         int64_t n_elem, int64_t n_vert, const double* coords,
+                                         const int32_t* conn, const void* u_vertex, const void* coef,
+                                         void* elem_vec, void* inv_j, void* det_j, int32_t* counts,
+                                         void* stream);
 
 /* Adjoint of L = sum_e w_e . R_e (not in the paper; the gradient of the
  * residual for automatic differentiation):
@@ -219,7 +243,7 @@ typedef struct fem_tuning {
     int strategy;        /* enum fem_strategy; FEM_STRATEGY_TRANSPOSE only for FEM_OP_RESIDUAL */
     int vec;             /* elements per lane: RESIDUAL and BACKWARD read 1, 2 or 4
                           * consecutive elements per vector access; GEOMETRY (1, 2, 4)
-                          * and RESIDUAL_MESH (1, 2) give each lane that many elements
+                          * and RESIDUAL_MESH / RESIDUAL_GATHER (1, 2) give each lane that many elements
                           * 64 apart, to overlap their dependent vertex gathers */
     int waves_per_block; /* 1, 2, 4 or 8 (wave64) */
     int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */

@@ -150,6 +150,41 @@ def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn,
     return out
 
 
+def fem_integrate_residual_gather(dim: int, physics: int, rule: int, coords, conn, u_vertex, coef, out=None,
+                                  inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD):
+    """Element residuals from the mesh with u given per vertex, u_vertex
+    [n_vert, N_comp]; the closure is gathered in the kernel. A P1 coefficient
+    is given per vertex too, [n_vert, N_coef]; point and cell coefficients
+    per element as for fem_integrate_residual. Bitwise equal to
+    fem_integrate_residual_mesh on the gathered closures."""
+    dtype = u_vertex.dtype
+    if dtype not in _DT:
+        raise TypeError("u_vertex must be float32 or float64")
+    _need(coords, "coords", torch.float64)
+    _need(conn, "conn", torch.int32)
+    if coords.dim() != 2 or coords.shape[1] != dim or conn.dim() != 2 or conn.shape[1] != dim + 1:
+        raise ValueError(f"coords must be [n_vert, {dim}] and conn [n_elem, {dim + 1}]")
+    n, nv = conn.shape[0], coords.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space)
+    _need(u_vertex, "u_vertex", dtype, (nv, n_comp(dim, physics)))
+    _need(coef, "coef", dtype, (nv, n_coef(physics)) if coef_space == N.COEF_P1 else scf)
+    if out is None:
+        out = torch.empty(su, dtype=dtype, device=u_vertex.device)
+    _need(out, "out", dtype, su)
+    if (inv_j is None) != (det_j is None):
+        raise ValueError("pass both inv_j and det_j, or neither")
+    if inv_j is not None:
+        _need(inv_j, "inv_j", dtype, sij)
+        _need(det_j, "det_j", dtype, sdj)
+    if counts is not None:
+        _need(counts, "counts", torch.int32, (2,))
+    N.check(N.lib().fem_integrate_residual_gather(dim, physics, rule, coef_space, _DT[dtype], n, nv, _ptr(coords),
+                                                  _ptr(conn), _ptr(u_vertex), _ptr(coef), _ptr(out), _ptr(inv_j),
+                                                  _ptr(det_j), _ptr(counts), _stream()),
+            "fem_integrate_residual_gather")
+    return out
+
+
 def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
                                     want_du=True, want_dcoef=True, du=None, dcoef=None, *, coef_space=N.COEF_QUAD):
     """(du [N_bt, n] or None, dcoef [N_coef, N_w, n] or None) for L = sum w . R."""

@@ -79,7 +79,8 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, fem_tuning> g_tune;
 
 static bool valid_op(int op) {
-    return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD;
+    return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
+           op == FEM_OP_RESIDUAL_GATHER;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -96,7 +97,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
     if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
-    if (op == FEM_OP_RESIDUAL_MESH) {
+    if (op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER) {
         if (phys == FEM_LAPLACE && f32) return fem_tuning{FEM_STRATEGY_LANE, 1, 1, 8};
         if (phys == FEM_ELASTICITY && f32) return fem_tuning{FEM_STRATEGY_LANE, 2, 2, 0};
         return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
@@ -111,8 +112,8 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
 static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
-    const bool vec_ok = op == FEM_OP_RESIDUAL_MESH ? (t.vec == 1 || t.vec == 2)
-                                                   : (t.vec == 1 || t.vec == 2 || t.vec == 4);
+    const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
+    const bool vec_ok = two ? (t.vec == 1 || t.vec == 2) : (t.vec == 1 || t.vec == 2 || t.vec == 4);
     return strategy_ok && vec_ok &&
            (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
             t.waves_per_block == 8) &&
@@ -265,6 +266,27 @@ fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_
     Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
     hipError_t e = launch_residual_mesh(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_mesh launch");
+}
+
+fem_status fem_integrate_residual_gather(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
+                                         int64_t n_vert, const double* coords, const int32_t* conn,
+                                         const void* u_vertex, const void* coef, void* elem_vec, void* inv_j,
+                                         void* det_j, int32_t* counts, void* stream) {
+    fem_status st = check_combo("fem_integrate_residual_gather", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_gather", coef_space);
+    if (st) return st;
+    if (n_elem < 0 || n_vert < 0) { set_error("fem_integrate_residual_gather: negative size"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (n_vert == 0) { set_error("fem_integrate_residual_gather: elements without vertices"); return FEM_ERR_INVALID_ARG; }
+    if (!coords || !conn || !u_vertex || !coef || !elem_vec || (!inv_j) != (!det_j)) {
+        set_error("fem_integrate_residual_gather: NULL array (inv_j and det_j must both be set or both NULL)");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_GATHER, dim, physics, rule, dtype);
+    MeshArgs a{n_elem, n_vert, coords, conn, u_vertex, coef, elem_vec, inv_j, det_j, counts};
+    Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_residual_gather(dim, physics, rule, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_gather launch");
 }
 
 fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,

@@ -395,10 +395,16 @@ __device__ __forceinline__ bool conn_ok(const int32_t (&v)[DIM + 1], int64_t nv)
 // outside the array; the clamp is branch-free, which keeps all the gathers of
 // an element together in the instruction stream. (Wider loads, e.g. a
 // 16-byte pair plus one word per FP64 vertex, measured no faster.)
+// Largest valid vertex index as an int32 (connectivity indices are int32, so
+// vertices past INT32_MAX are unreachable anyway).
+__device__ __forceinline__ int32_t vertex_hi(int64_t nv) {
+    return nv - 1 > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)(nv - 1);
+}
+
 template <int DIM>
 __device__ __forceinline__ void gather_coords(const double* __restrict__ X, const int32_t (&v)[DIM + 1], int64_t nv,
                                               double (&x)[DIM + 1][DIM]) {
-    const int32_t hi = (int32_t)(nv - 1);
+    const int32_t hi = vertex_hi(nv);
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) {
         const int64_t vi = (int64_t)min(max(v[b], 0), hi);

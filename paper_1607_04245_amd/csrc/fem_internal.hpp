@@ -57,6 +57,9 @@ hipError_t launch_residual_transpose(int dim, int phys, int rule, int space, int
                                      const Launch& l);
 hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                 const Launch& l);
+// u and a P1 coefficient per vertex (MeshArgs.u, MeshArgs.coef), gathered.
+hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
+                                  const Launch& l);
 hipError_t launch_backward_lane(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                                 const Launch& l);
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,

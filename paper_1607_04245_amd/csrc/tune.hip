@@ -233,13 +233,17 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     const int ncq = (physics == FEM_ELASTICITY ? 2 : 1) * nq;
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     const int64_t n = n_probe;
-    const bool mesh_op = op == FEM_OP_GEOMETRY || op == FEM_OP_RESIDUAL_MESH;
+    const bool mesh_op = op == FEM_OP_GEOMETRY || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
     // probe mesh
     const int per = dim == 2 ? 2 : 6;
     int grid_n = 1;
     while ((int64_t)per * (dim == 2 ? (int64_t)grid_n * grid_n : (int64_t)grid_n * grid_n * grid_n) < n) ++grid_n;
     const int64_t n_vert = dim == 2 ? (int64_t)(grid_n + 1) * (grid_n + 1) : (int64_t)(grid_n + 1) * (grid_n + 1) * (grid_n + 1);
 
+    if (n_vert * nc > (int64_t)nbt * n) {  // the gather probe reads vertex values from the closure buffer
+        set_error("fem_autotune: probe mesh too coarse");
+        return FEM_ERR_INVALID_ARG;
+    }
     // one copy: geometry, u, coef, w, outputs, and for mesh ops the mesh
     struct Copy { void *ij, *dj, *u, *cf, *w, *out, *du, *dc; double* X; int32_t* conn; };
     const size_t rows_words = (size_t)n * (dim * dim + 1 + 4 * nbt + 2 * ncq);
@@ -298,6 +302,9 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
                                                    c.dc, nullptr);
         case FEM_OP_GEOMETRY:
             return fem_geometry(dim, n, n_vert, c.X, c.conn, dtype, c.ij, c.dj, nullptr, nullptr);
+        case FEM_OP_RESIDUAL_GATHER:  // the closure buffer holds at least n_vert * N_comp vertex values
+            return fem_integrate_residual_gather(dim, physics, rule, FEM_COEF_QUAD, dtype, n, n_vert, c.X, c.conn, c.u,
+                                                 c.cf, c.out, nullptr, nullptr, nullptr, nullptr);
         default:
             return fem_integrate_residual_mesh(dim, physics, rule, FEM_COEF_QUAD, dtype, n, n_vert, c.X, c.conn, c.u, c.cf, c.out,
                                                nullptr, nullptr, nullptr, nullptr);
@@ -305,7 +312,8 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     };
 
     std::vector<fem_tuning> cands;
-    const std::vector<int> vecs = op == FEM_OP_RESIDUAL_MESH ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
+    const std::vector<int> vecs = two ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
     for (int v : vecs)
         for (int w : {1, 2, 4, 8})
             for (int b : {0, 2, 4, 8, 16}) cands.push_back(fem_tuning{FEM_STRATEGY_LANE, v, w, b});

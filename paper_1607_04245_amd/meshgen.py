@@ -230,6 +230,13 @@ def _coef_draw(physics, rng, shape):
     return rng.uniform(0.5, 2.0, size=(1,) + shape)
 
 
+def vertex_coefficients(wl: "Workload", seed: int) -> np.ndarray:
+    """The vertex field behind space_coefficients(wl, COEF_P1, seed):
+    [N_v, N_coef] float64, coefficient m of vertex v at [v, m]."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(_coef_draw(wl.physics, rng, (wl.n_vert,)).T)
+
+
 def space_coefficients(wl: "Workload", space: int, seed: int) -> np.ndarray:
     """Coefficients of ``wl`` in another space, [N_coef, N_w, N_e] float64.
 
@@ -241,10 +248,10 @@ def space_coefficients(wl: "Workload", space: int, seed: int) -> np.ndarray:
     """
     if space == COEF_QUAD:
         return wl.coef
-    rng = np.random.default_rng(seed)
     if space == COEF_P1:
-        vert = _coef_draw(wl.physics, rng, (wl.n_vert,))          # [N_coef, N_v]
-        return np.ascontiguousarray(np.stack([closure(wl.conn, v[:, None]) for v in vert]))
+        vert = vertex_coefficients(wl, seed)                       # [N_v, N_coef]
+        return np.ascontiguousarray(np.stack([closure(wl.conn, vert[:, m:m + 1]) for m in range(vert.shape[1])]))
+    rng = np.random.default_rng(seed)
     if space == COEF_P0:
         return np.ascontiguousarray(_coef_draw(wl.physics, rng, (1, wl.n_elem)))
     raise ValueError(f"unknown coefficient space {space}")

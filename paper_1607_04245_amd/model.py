@@ -48,26 +48,33 @@ def n_qpts(dim: int, rule: int) -> int:
     return 1 if rule == 2 else dim + 1
 
 
+def n_coef_words(dim: int, rule: int, coef_space: int = 0) -> int:
+    """Words per coefficient and element: values at the N_q points (0), the
+    d+1 vertex values of a P1 field (1), or one cell value (2)."""
+    return {0: n_qpts(dim, rule), 1: dim + 1, 2: 1}[coef_space]
+
+
 def model_flops(dim: int, physics: int, rule: int) -> int:
     """Paper-model flops per element for a (dim, physics, rule) of this library."""
     return paper_flops_per_cell(dim, dim + 1, n_comp(dim, physics), n_qpts(dim, rule))
 
 
-def forward_words(dim: int, physics: int, rule: int) -> int:
+def forward_words(dim: int, physics: int, rule: int, coef_space: int = 0) -> int:
     """Words moved by one element of fem_integrate_residual: invJ, detJ,
     closure u, coefficients in; element vector out."""
     nbt = (dim + 1) * n_comp(dim, physics)
-    return (dim * dim + 1) + 2 * nbt + n_coef(physics) * n_qpts(dim, rule)
+    return (dim * dim + 1) + 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space)
 
 
-def forward_bytes(dim: int, physics: int, rule: int, word: int) -> int:
-    return word * forward_words(dim, physics, rule)
+def forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
+    return word * forward_words(dim, physics, rule, coef_space)
 
 
-def backward_bytes(dim: int, physics: int, rule: int, word: int, want_du=True, want_dcoef=True) -> int:
+def backward_bytes(dim: int, physics: int, rule: int, word: int, want_du=True, want_dcoef=True,
+                   coef_space: int = 0) -> int:
     """Compulsory bytes per element of fem_integrate_residual_backward."""
     nbt = (dim + 1) * n_comp(dim, physics)
-    ncq = n_coef(physics) * n_qpts(dim, rule)
+    ncq = n_coef(physics) * n_coef_words(dim, rule, coef_space)
     words = (dim * dim + 1) + nbt   # geometry and w in
     if want_du:
         words += ncq + nbt           # coefficients in, du out
@@ -83,10 +90,23 @@ def geometry_bytes(dim: int, n_elem: int, n_vert: int, word: int) -> float:
 
 
 def residual_mesh_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert: int, word: int,
-                        store_geometry: bool = False) -> float:
+                        store_geometry: bool = False, coef_space: int = 0) -> float:
     """Compulsory bytes per element of fem_integrate_residual_mesh:
     connectivity, each vertex once (amortised), closure and coefficients in,
     element vector out (and the geometry, if stored)."""
     nbt = (dim + 1) * n_comp(dim, physics)
-    words = 2 * nbt + n_coef(physics) * n_qpts(dim, rule) + ((dim * dim + 1) if store_geometry else 0)
+    words = 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space) + \
+        ((dim * dim + 1) if store_geometry else 0)
     return 4 * (dim + 1) + 8.0 * dim * n_vert / max(n_elem, 1) + word * words
+
+
+def residual_gather_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert: int, word: int,
+                          coef_space: int = 0, store_geometry: bool = False) -> float:
+    """Compulsory bytes per element of fem_integrate_residual_gather:
+    connectivity; each vertex's coordinates, u (and P1 coefficient) once,
+    amortised; point or cell coefficients per element; element vector out."""
+    nbt = (dim + 1) * n_comp(dim, physics)
+    per_vertex = 8.0 * dim + word * n_comp(dim, physics) + (word * n_coef(physics) if coef_space == 1 else 0)
+    per_elem = word * (nbt + (0 if coef_space == 1 else n_coef(physics) * n_coef_words(dim, rule, coef_space)) +
+                       ((dim * dim + 1) if store_geometry else 0))
+    return 4 * (dim + 1) + per_vertex * n_vert / max(n_elem, 1) + per_elem

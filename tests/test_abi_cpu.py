@@ -160,3 +160,18 @@ def test_residual_mesh_validation(lib):
              None) == N.FEM_ERR_UNSUPPORTED
     assert f(3, mg.LAPLACE, mg.RULE_TET4, 7, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
         == N.FEM_ERR_UNSUPPORTED
+
+
+def test_residual_gather_validation(lib):
+    c = (3, mg.LAPLACE, mg.RULE_TET4, N.COEF_P1, N.F32)
+    f = lib.fem_integrate_residual_gather
+    assert f(*c, 0, 0, None, None, None, None, None, None, None, None, None) == N.FEM_OK
+    assert f(*c, -1, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(*c, 5, 0, _v(), _v(), _v(), _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(*c, 5, 5, _v(), _v(), None, _v(), _v(), None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(*c, 5, 5, _v(), _v(), _v(), _v(), _v(), None, _v(), None, None) == N.FEM_ERR_INVALID_ARG
+    assert f(3, mg.LAPLACE, mg.RULE_TET4, 4, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
+        == N.FEM_ERR_UNSUPPORTED
+    four = N.fem_tuning(N.STRATEGY_LANE, 4, 4, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_GATHER, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) \
+        == N.FEM_ERR_INVALID_ARG
