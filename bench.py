@@ -65,8 +65,10 @@ def source_hash(files):
 
 CSRC = "paper_1607_04245_amd/csrc/"
 KERNEL_SOURCES = {
-    "fem_integrate_residual_mesh": [CSRC + "residual_mesh.hip", CSRC + "fem_device.hpp", CSRC + "fem_abi.hip"],
-    "fem_integrate_residual": [CSRC + "residual_lane.hip", CSRC + "fem_device.hpp", CSRC + "fem_abi.hip"],
+    "fem_integrate_residual_mesh": [CSRC + "residual_mesh.hip", CSRC + "mesh_kernel.hpp", CSRC + "fem_device.hpp",
+                                    CSRC + "fem_scheme.hpp", CSRC + "fem_abi.hip"],
+    "fem_integrate_residual": [CSRC + "residual_lane.hip", CSRC + "fem_device.hpp", CSRC + "fem_scheme.hpp",
+                               CSRC + "fem_abi.hip"],
     "fem_geometry": [CSRC + "geometry.hip", CSRC + "fem_abi.hip"],
 }
 
