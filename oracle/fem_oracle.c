@@ -48,6 +48,12 @@
  * result bounds every partial sum and is the scale of the rounding-error
  * measure used by the parity tests.
  *
+ * Assembly (Section 2: the global residual is the sum over elements of the
+ * element vectors mapped back through the element restriction E_e, the
+ * transpose of the closure): F[v][c] = sum over (e, b) with conn[e][b] = v of
+ * R_e[b*N_comp + c], summed element by element in increasing e, from zero.
+ * Its adjoint is the restriction itself: the closure of a vertex field.
+ *
  * Layouts (structure of arrays, n = n_elem):
  *   coords [n_vert][dim], conn [n_elem][dim+1] (0-based),
  *   inv_j [dim*dim][n] (row k*dim+i), det_j [n],
@@ -436,5 +442,44 @@ int fem_oracle_backward(int dim, int physics, int rule, int space, int64_t n_ele
                 }
         }
     }
+    return 0;
+}
+
+/* Global residual F [n_vert][n_comp] = sum_e E_e^T R_e from element vectors
+ * elem_vec [(dim+1)*n_comp][n_elem]. Elements are added in increasing order.
+ * Returns 0, or -1 on bad arguments or a vertex index out of range. */
+int fem_oracle_assemble(int dim, int n_comp, int64_t n_elem, int64_t n_vert, const int32_t *conn,
+                        const double *elem_vec, double *out)
+{
+    if ((dim != 2 && dim != 3) || n_comp < 1 || n_comp > OR_MAXC || n_elem < 0 || n_vert < 0) return -1;
+    int nb = dim + 1;
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int b = 0; b < nb; ++b) {
+            int32_t v = conn[e * nb + b];
+            if (v < 0 || v >= n_vert) return -1;
+        }
+    for (int64_t i = 0; i < n_vert * n_comp; ++i) out[i] = 0.0;
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int b = 0; b < nb; ++b) {
+            int64_t v = conn[e * nb + b];
+            for (int c = 0; c < n_comp; ++c) out[v * n_comp + c] += elem_vec[(int64_t)(b * n_comp + c) * n_elem + e];
+        }
+    return 0;
+}
+
+/* Element restriction (the closure): elem_vec[(b*n_comp + c)][e] =
+ * vert[conn[e][b]][c]. Returns 0, or -1 on bad arguments or a vertex index
+ * out of range. */
+int fem_oracle_restrict(int dim, int n_comp, int64_t n_elem, int64_t n_vert, const int32_t *conn,
+                        const double *vert, double *elem_vec)
+{
+    if ((dim != 2 && dim != 3) || n_comp < 1 || n_comp > OR_MAXC || n_elem < 0 || n_vert < 0) return -1;
+    int nb = dim + 1;
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int b = 0; b < nb; ++b) {
+            int64_t v = conn[e * nb + b];
+            if (v < 0 || v >= n_vert) return -1;
+            for (int c = 0; c < n_comp; ++c) elem_vec[(int64_t)(b * n_comp + c) * n_elem + e] = vert[v * n_comp + c];
+        }
     return 0;
 }

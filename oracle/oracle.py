@@ -41,6 +41,10 @@ def load():
         lib.fem_oracle_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.fem_oracle_backward.restype = ctypes.c_int
+        for name in ("fem_oracle_assemble", "fem_oracle_restrict"):
+            f = getattr(lib, name)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _ip, _dp, _dp]
+            f.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -146,3 +150,23 @@ def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want
     if r != 0:
         raise ValueError("oracle backward: bad arguments")
     return du, dcoef
+
+
+def assemble(dim, n_comp, n_vert, conn, elem_vec):
+    """Global residual F[n_vert, n_comp] = sum_e E_e^T R_e (Section 2)."""
+    conn, elem_vec = _i32(conn), _f64(elem_vec)
+    n = conn.shape[0]
+    F = np.zeros((n_vert, n_comp))
+    if load().fem_oracle_assemble(dim, n_comp, n, n_vert, _p(conn, _ip), _p(elem_vec), _p(F)) != 0:
+        raise ValueError("oracle assemble: bad arguments or vertex index out of range")
+    return F
+
+
+def restrict(dim, n_comp, conn, vert):
+    """Closure R[(d+1)*n_comp, n] of a vertex field vert[n_vert, n_comp]."""
+    conn, vert = _i32(conn), _f64(vert)
+    n = conn.shape[0]
+    out = np.zeros(((dim + 1) * n_comp, n))
+    if load().fem_oracle_restrict(dim, n_comp, n, vert.shape[0], _p(conn, _ip), _p(vert), _p(out)) != 0:
+        raise ValueError("oracle restrict: bad arguments or vertex index out of range")
+    return out
