@@ -395,6 +395,28 @@ def main():
                         f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
             del wlx
 
+        # --------------------------------------------------------- assembly --
+        # global residual: element vectors summed onto vertices (deterministic gather)
+        for cfg in (2, "3b"):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            nc = wlx.n_comp
+            conn_d = to_dev(wlx.conn, torch.int32)
+            plan = api.AssemblyPlan(conn_d, wlx.n_vert)
+            nb = model.assemble_bytes(wlx.dim, nc, wlx.n_elem, wlx.n_vert, 4) * wlx.n_elem
+            R0 = torch.randn(((wlx.dim + 1) * nc, wlx.n_elem), device=dev)
+            cps = [dict(R=R0.clone(), F=torch.empty((wlx.n_vert, nc), device=dev)) for _ in range(n_copies(nb))]
+            del R0
+
+            def go(c, plan=plan, nc=nc):
+                plan.assemble(c["R"], nc, out=c["F"])
+            _, ms = timed_graph(go, cps, 20, 1)
+            us = ms * 1e3
+            extra[f"{wlx.name}_f32_assemble"] = dict(n_elem=wlx.n_elem, n_vert=wlx.n_vert, us=us,
+                                                     gbs=nb / (us * 1e-6) / 1e9,
+                                                     elements_per_s=wlx.n_elem / (us * 1e-6))
+            log(f"{wlx.name} f32 assembly: {us:.1f} us ({nb / (us * 1e-6) / 1e9:.0f} GB/s)")
+            del cps, plan, conn_d, wlx
+
         # --------------------------------------------------------- adjoint --
         wl5 = mg.config(5)
         dt = torch.float32

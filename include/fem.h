@@ -269,6 +269,47 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
 fem_status fem_load_tuning(const char* cache_path);
 
 /* ------------------------------------------------------------------ */
+/* Assembly (Section 2: the global residual is the sum over elements of  */
+/* each element vector mapped back through the element restriction,    */
+/* F = sum_e E_e^T R_e) and the restriction itself (the closure).       */
+/* ------------------------------------------------------------------ */
+
+/* Vertex field layout: [n_vert][n_comp], component c of vertex v at
+ * v*n_comp + c, n_comp in {1, 2, 3}. */
+typedef struct fem_assembly_plan fem_assembly_plan;
+
+/* Builds, on the device, the transpose of the connectivity conn
+ * [n_elem][dim+1] (device, int32): for every vertex the (element, local
+ * vertex) slots that touch it, in increasing element order. The plan owns
+ * that index (about 4 (dim+1) n_elem + 4 n_vert bytes) and keeps no pointer
+ * to conn. Synchronizes `stream` (the index is validated before returning).
+ * Errors: FEM_ERR_INVALID_ARG (negative sizes, NULL, an index outside
+ * [0, n_vert)), FEM_ERR_UNSUPPORTED (dim, or n_elem*(dim+1) or n_vert not
+ * below 2^31), FEM_ERR_HIP. */
+fem_status fem_assembly_plan_create(int dim, int64_t n_elem, int64_t n_vert, const int32_t* conn,
+                                    void* stream, fem_assembly_plan** out);
+/* vertex_vec[v][c] = sum over the slots (e, b) of v, in increasing e, of
+ * elem_vec[b*n_comp + c][e], starting from zero, in `dtype` arithmetic: the
+ * same sum in the same order every call (no atomics). elem_vec is
+ * [(dim+1)*n_comp][n_elem] as written by the residual entry points.
+ * Errors: FEM_ERR_INVALID_ARG (NULL plan or array), FEM_ERR_UNSUPPORTED
+ * (n_comp, dtype), FEM_ERR_HIP. */
+fem_status fem_assemble(const fem_assembly_plan* plan, int n_comp, int dtype, const void* elem_vec,
+                        void* vertex_vec, void* stream);
+/* Sizes the plan was built for (any output may be NULL). */
+fem_status fem_assembly_plan_info(const fem_assembly_plan* plan, int* dim, int64_t* n_elem,
+                                  int64_t* n_vert);
+void fem_assembly_plan_destroy(fem_assembly_plan* plan);
+
+/* The element restriction (closure), the adjoint of fem_assemble:
+ * elem_vec[b*n_comp + c][e] = vertex_vec[conn[e][b]][c]. An index outside
+ * [0, n_vert) gives NaN entries for that element; nothing outside
+ * vertex_vec is read. Errors: as fem_assemble, plus FEM_ERR_INVALID_ARG for
+ * negative sizes and elements without vertices. */
+fem_status fem_restrict(int dim, int n_comp, int dtype, int64_t n_elem, int64_t n_vert, const int32_t* conn,
+                        const void* vertex_vec, void* elem_vec, void* stream);
+
+/* ------------------------------------------------------------------ */
 /* Measurement helpers                                                  */
 /* ------------------------------------------------------------------ */
 

@@ -67,6 +67,11 @@ SIGNATURES = {
     "fem_batch_capture": (_i, [_vp, _vp]),
     "fem_batch_replay": (_i, [_vp, _vp]),
     "fem_batch_plan_destroy": (None, [_vp]),
+    "fem_assembly_plan_create": (_i, [_i, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)]),
+    "fem_assemble": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "fem_assembly_plan_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "fem_assembly_plan_destroy": (None, [_vp]),
+    "fem_restrict": (_i, [_i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp]),
     "fem_get_tuning": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
     "fem_set_tuning": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(fem_tuning)]),
     "fem_autotune": (_i, [_i, _i, _i, _i, _i, _i64, ctypes.c_char_p]),

@@ -308,6 +308,104 @@ class BatchPlan:
             pass
 
 
+# ---------------------------------------------------------------- assembly --
+
+def fem_restrict(conn, vertex_vec, out=None):
+    """Closure of a vertex field: out[b*N_comp + c, e] = vertex_vec[conn[e, b], c]
+    (the element restriction, adjoint of assembly)."""
+    _need(conn, "conn", torch.int32)
+    dtype = vertex_vec.dtype
+    if dtype not in _DT:
+        raise TypeError("vertex_vec must be float32 or float64")
+    if conn.dim() != 2 or conn.shape[1] not in (3, 4) or vertex_vec.dim() != 2:
+        raise ValueError("conn must be [n_elem, dim+1] and vertex_vec [n_vert, n_comp]")
+    dim, n = conn.shape[1] - 1, conn.shape[0]
+    nv, nc = vertex_vec.shape
+    _need(vertex_vec, "vertex_vec", dtype)
+    if out is None:
+        out = torch.empty(((dim + 1) * nc, n), dtype=dtype, device=vertex_vec.device)
+    _need(out, "out", dtype, ((dim + 1) * nc, n))
+    N.check(N.lib().fem_restrict(dim, nc, _DT[dtype], n, nv, _ptr(conn), _ptr(vertex_vec), _ptr(out), _stream()),
+            "fem_restrict")
+    return out
+
+
+class AssemblyPlan:
+    """Vertex-to-slot index of a mesh for deterministic assembly
+    (fem_assembly_plan_create). Building it synchronizes the current stream."""
+
+    def __init__(self, conn: torch.Tensor, n_vert: int):
+        _need(conn, "conn", torch.int32)
+        if conn.dim() != 2 or conn.shape[1] not in (3, 4):
+            raise ValueError("conn must be [n_elem, dim+1]")
+        self.dim, self.n_elem, self.n_vert = conn.shape[1] - 1, conn.shape[0], int(n_vert)
+        self._plan = ctypes.c_void_p()
+        N.check(N.lib().fem_assembly_plan_create(self.dim, self.n_elem, self.n_vert, _ptr(conn), _stream(),
+                                                 ctypes.byref(self._plan)), "fem_assembly_plan_create")
+
+    def assemble(self, elem_vec: torch.Tensor, n_comp: int, out=None):
+        """Global residual [n_vert, n_comp] = sum_e E_e^T R_e (Section 2)."""
+        dtype = elem_vec.dtype
+        if dtype not in _DT:
+            raise TypeError("elem_vec must be float32 or float64")
+        _need(elem_vec, "elem_vec", dtype, ((self.dim + 1) * n_comp, self.n_elem))
+        if out is None:
+            out = torch.empty((self.n_vert, n_comp), dtype=dtype, device=elem_vec.device)
+        _need(out, "out", dtype, (self.n_vert, n_comp))
+        N.check(N.lib().fem_assemble(self._plan, n_comp, _DT[dtype], _ptr(elem_vec), _ptr(out), _stream()),
+                "fem_assemble")
+        return out
+
+    def close(self):
+        if self._plan:
+            N.lib().fem_assembly_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Assemble(torch.autograd.Function):
+    """F = sum_e E_e^T R_e; the gradient with respect to R is the closure of
+    the gradient with respect to F."""
+
+    @staticmethod
+    def forward(ctx, plan, conn, elem_vec, n_comp):
+        ctx.plan, ctx.conn = plan, conn
+        return plan.assemble(elem_vec.contiguous(), n_comp)
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        return None, None, fem_restrict(ctx.conn, grad_f.contiguous()), None
+
+
+class Restrict(torch.autograd.Function):
+    """Closure of a vertex field; the gradient is the assembly of the
+    gradient with respect to the closure."""
+
+    @staticmethod
+    def forward(ctx, plan, conn, vertex_vec):
+        ctx.plan, ctx.n_comp = plan, vertex_vec.shape[1]
+        return fem_restrict(conn, vertex_vec.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        return None, None, ctx.plan.assemble(grad_e.contiguous(), ctx.n_comp)
+
+
+def assemble(plan, conn, elem_vec, n_comp):
+    """Differentiable assembly (see Assemble)."""
+    return Assemble.apply(plan, conn, elem_vec, n_comp)
+
+
+def restrict(plan, conn, vertex_vec):
+    """Differentiable restriction (see Restrict)."""
+    return Restrict.apply(plan, conn, vertex_vec)
+
+
 # ---------------------------------------------------------------- autograd --
 
 class IntegrateResidual(torch.autograd.Function):

@@ -381,12 +381,13 @@ __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int6
     }
 }
 
-// Whether all vertex indices lie in [0, nv).
+// Whether all vertex indices lie in [0, nv). Bitwise, not short-circuit, so
+// that it compiles to compares and no branches.
 template <int DIM>
 __device__ __forceinline__ bool conn_ok(const int32_t (&v)[DIM + 1], int64_t nv) {
     bool ok = true;
 #pragma unroll
-    for (int b = 0; b <= DIM; ++b) ok = ok && v[b] >= 0 && (int64_t)v[b] < nv;
+    for (int b = 0; b <= DIM; ++b) ok &= (v[b] >= 0) & ((int64_t)v[b] < nv);
     return ok;
 }
 
@@ -416,18 +417,18 @@ __device__ __forceinline__ void gather_coords(const double* __restrict__ X, cons
 // Classifies the element and replaces the geometry of a degenerate one by NaN.
 // Returns 1 for degenerate, 2 for poorly shaped, 0 otherwise.
 template <int DIM>
+// Selects only (no branches), so a caller's arithmetic is never moved into a
+// conditional block.
 __device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&inv)[DIM][DIM], double edge_product2) {
-    const bool degenerate = !ok || det == 0.0 || !isfinite(det);
-    if (degenerate) {
-        const double nan = __builtin_nan("");
-        if (!ok) det = nan;
+    const bool degenerate = !ok | (det == 0.0) | !isfinite(det);
+    const double nan = __builtin_nan("");
+    det = ok ? det : nan;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k)
+    for (int k = 0; k < DIM; ++k)
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) inv[k][i] = nan;
-        return 1;
-    }
-    return det * det < kPoorShape2 * edge_product2 ? 2 : 0;
+        for (int i = 0; i < DIM; ++i) inv[k][i] = degenerate ? nan : inv[k][i];
+    const bool poor = det * det < kPoorShape2 * edge_product2;
+    return degenerate ? 1 : (poor ? 2 : 0);
 }
 
 // XCD-aware work split for kernels that gather vertices. Workgroups are

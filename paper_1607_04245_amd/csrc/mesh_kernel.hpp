@@ -90,7 +90,7 @@ __device__ __forceinline__ bool mesh_stage_gather(MeshStage<Elem<DIM, PHYS, RULE
             }
         }
     }
-    return e < n && conn_ok<DIM>(vv, nv);
+    return (e < n) & conn_ok<DIM>(vv, nv);
 }
 
 // Geometry, integration and stores of one element whose vertices are in x.
@@ -105,8 +105,8 @@ __device__ __forceinline__ void mesh_element_finish(bool valid, int64_t e, int64
     double inv[DIM][DIM], ep2;
     double det = element_geometry<DIM>(x, inv, ep2);
     const int flag = finish_geometry<DIM>(ok, det, inv, ep2);
-    ndeg += valid && flag == 1;
-    npoor += valid && flag == 2;
+    ndeg += (int)(valid & (flag == 1));
+    npoor += (int)(valid & (flag == 2));
     Real ij[E::NG], r[E::NBT];
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
@@ -128,7 +128,9 @@ __device__ __forceinline__ void mesh_element_finish(bool valid, int64_t e, int64
 // EPT = 1: software-pipelined. While the vertex gathers and the arithmetic of
 // tile k run, the connectivity, closure and coefficient loads of the wave's
 // next tile are already in flight, so a wave pays roughly one memory latency
-// per tile instead of two. EPT = 2: two elements per lane, no pipelining.
+// per tile instead of two. (A three-deep pipeline, with the gathers of tile
+// k+1 also in flight during the arithmetic of tile k, measured slower at
+// every launch shape.) EPT = 2: two elements per lane, no pipelining.
 // GATHER: u (and a P1 coefficient) are vertex arrays gathered through the
 // connectivity instead of per-element closure rows.
 template <int DIM, int PHYS, int RULE, typename Real, int EPT, bool STORE_GEOM, bool VEC, bool GATHER>
@@ -140,7 +142,8 @@ residual_mesh_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const 
     using E = Elem<DIM, PHYS, RULE>;
     using Stage = MeshStage<E::NBT, E::NCQ, Real>;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    // wave-uniform (readfirstlane): the tile loop is then scalar control flow
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), waves = blockDim.x >> 6;
     const int64_t n_tiles = (n + 64 * EPT - 1) / (64 * EPT);
     int64_t t_begin, t_end;
     block_tile_range(n_tiles, t_begin, t_end);

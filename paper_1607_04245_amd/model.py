@@ -110,3 +110,10 @@ def residual_gather_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert
     per_elem = word * (nbt + (0 if coef_space == 1 else n_coef(physics) * n_coef_words(dim, rule, coef_space)) +
                        ((dim * dim + 1) if store_geometry else 0))
     return 4 * (dim + 1) + per_vertex * n_vert / max(n_elem, 1) + per_elem
+
+
+def assemble_bytes(dim: int, n_comp_: int, n_elem: int, n_vert: int, word: int) -> float:
+    """Compulsory bytes per element of fem_assemble: the slot index and the
+    element vectors in, row offsets in and the vertex field out (amortised)."""
+    nb = dim + 1
+    return 4.0 * nb + word * nb * n_comp_ + (4.0 + word * n_comp_) * n_vert / max(n_elem, 1)

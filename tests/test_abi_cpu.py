@@ -175,3 +175,24 @@ def test_residual_gather_validation(lib):
     four = N.fem_tuning(N.STRATEGY_LANE, 4, 4, 0)
     assert lib.fem_set_tuning(N.OP_RESIDUAL_GATHER, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) \
         == N.FEM_ERR_INVALID_ARG
+
+
+def test_assembly_validation(lib):
+    plan = ctypes.c_void_p()
+    f = lib.fem_assembly_plan_create
+    assert f(2, 5, 5, _v(), None, None) == N.FEM_ERR_INVALID_ARG            # out is NULL
+    assert f(4, 5, 5, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
+    assert f(2, -1, 5, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert f(2, 5, 0, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert f(2, 5, 5, None, None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert f(3, 2 ** 30, 5, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED  # 4 * 2^30 slots
+    assert not plan.value
+    assert lib.fem_assemble(None, 1, N.F32, _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    r = lib.fem_restrict
+    assert r(2, 1, N.F32, 0, 0, None, None, None, None) == N.FEM_OK
+    assert r(2, 4, N.F32, 5, 5, _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED
+    assert r(2, 1, 9, 5, 5, _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED
+    assert r(5, 1, N.F32, 5, 5, _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED
+    assert r(2, 1, N.F32, 5, 0, _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    assert r(2, 1, N.F32, 5, 5, _v(), None, _v(), None) == N.FEM_ERR_INVALID_ARG
+    lib.fem_assembly_plan_destroy(None)
