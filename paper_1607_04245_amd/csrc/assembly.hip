@@ -54,22 +54,37 @@ assembly_count_kernel(int64_t m, int64_t n_vert, const int32_t* __restrict__ con
 }
 
 // One lane per vertex: vertex_vec[v][c] = sum over the vertex's slots, in
-// slot order, of elem_vec[b * NC + c][e].
+// slot order, of elem_vec[b * NC + c][e]. The row is walked in chunks of CH
+// slots whose loads are all issued before the first add (indices past the
+// row's end are clamped to its first slot and their adds skipped), so a lane
+// waits about once per chunk instead of once per slot; the adds stay in slot
+// order.
 template <int NB, int NC, typename Real>
 __global__ void __launch_bounds__(256)
 assemble_kernel(int64_t n_vert, int64_t n_elem, const int32_t* __restrict__ row_ptr,
                 const uint32_t* __restrict__ slots, const Real* __restrict__ R, Real* __restrict__ out) {
+    constexpr int CH = 8;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_vert; v += stride) {
         Real acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = Real(0);
-        const int32_t s1 = row_ptr[v + 1];
-        for (int32_t s = row_ptr[v]; s < s1; ++s) {
-            const uint32_t slot = slots[s];
-            const uint32_t e = slot / NB, b = slot - e * NB;
+        const int32_t s0 = row_ptr[v], s1 = row_ptr[v + 1];
+        for (int32_t s = s0; s < s1; s += CH) {
+            uint32_t sl[CH];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += R[(int64_t)(b * NC + c) * n_elem + e];
+            for (int j = 0; j < CH; ++j) sl[j] = slots[s + j < s1 ? s + j : s0];
+            Real r[CH][NC];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const uint32_t e = sl[j] / NB, b = sl[j] - e * NB;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) r[j][c] = R[(int64_t)(b * NC + c) * n_elem + e];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = s + j < s1 ? acc[c] + r[j][c] : acc[c];
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) out[v * NC + c] = acc[c];
