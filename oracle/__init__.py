@@ -6,5 +6,5 @@ Functions marked "parity unpinned" have no independent pin; at present every
 function here is pinned by tests/test_oracle_*.py.
 """
 from .oracle import (  # noqa: F401
-    rule, geometry, integrate, integrate_abs, residual, backward, load, n_qpts, assemble, restrict,
+    rule, geometry, integrate, integrate_abs, residual, backward, load, n_qpts, assemble, restrict, n_basis,
 )

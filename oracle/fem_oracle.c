@@ -29,7 +29,18 @@
  *    permutations (point q has 2/3 at vertex q), weights 1/6; tetrahedron,
  *    four points with barycentric (a, b, b, b), a = (5 + 3 sqrt 5)/20,
  *    b = (5 - sqrt 5)/20 (point q has a at vertex q), weights 1/24;
- *    centroid rule, one point, weight 1/d!;
+ *    centroid rule, one point, weight 1/d!; for second-order elements also
+ *    degree-4 rules: triangle, six points in two orbits (barycentric a at
+ *    one vertex and (1-a)/2 at the others, a = 0.1081030181680702... and
+ *    0.8168475729804585..., weights 0.2233815896780115/2 and
+ *    0.1099517436553219/2); tetrahedron, eleven points (the centroid with
+ *    weight -148/1875, (11/14, 1/14, 1/14, 1/14) with weight 343/7500,
+ *    (a, a, b, b) with a = (1 + sqrt(5/14))/4, b = (1 - sqrt(5/14))/4 and
+ *    weight 56/375, all times 1/6);
+ *  - element order 1 (P1) or 2 (P2: vertex functions lam (2 lam - 1), then
+ *    edge functions 4 lam_i lam_j, edges (i, j), i < j, lexicographic); the
+ *    geometry stays affine, and a P1 coefficient keeps the d+1 vertex values
+ *    and the P1 basis whatever the order of u;
  *  - physics: Laplacian f1 = kappa grad u (Section 2; f0 = 0);
  *    linear elasticity f1 = lambda tr(eps) I + 2 mu eps, eps the symmetric
  *    gradient (the paper's Lame function in Section 6 is lambda = 0,
@@ -66,13 +77,13 @@
 #include <string.h>
 
 #define OR_MAXD 3
-#define OR_MAXB 4
-#define OR_MAXQ 4
+#define OR_MAXB 10
+#define OR_MAXQ 11
 #define OR_MAXC 3
 #define OR_MAXCOEF 2
 
 enum { OR_LAPLACE = 0, OR_ELASTICITY = 1, OR_MASS = 2 };
-enum { OR_RULE_TRI3 = 0, OR_RULE_TET4 = 1, OR_RULE_CENTROID = 2 };
+enum { OR_RULE_TRI3 = 0, OR_RULE_TET4 = 1, OR_RULE_CENTROID = 2, OR_RULE_TRI6 = 3, OR_RULE_TET11 = 4 };
 enum { OR_COEF_QUAD = 0, OR_COEF_P1 = 1, OR_COEF_P0 = 2 };
 
 int fem_oracle_n_qpts(int dim, int rule)
@@ -81,6 +92,8 @@ int fem_oracle_n_qpts(int dim, int rule)
     if (rule == OR_RULE_TRI3) return dim == 2 ? 3 : -1;
     if (rule == OR_RULE_TET4) return dim == 3 ? 4 : -1;
     if (rule == OR_RULE_CENTROID) return 1;
+    if (rule == OR_RULE_TRI6) return dim == 2 ? 6 : -1;
+    if (rule == OR_RULE_TET11) return dim == 3 ? 11 : -1;
     return -1;
 }
 
@@ -91,7 +104,7 @@ int fem_oracle_rule(int dim, int rule, double *xi, double *wts)
     int nq = fem_oracle_n_qpts(dim, rule);
     if (nq < 0) return -1;
     double lam[OR_MAXQ][OR_MAXB];
-    double w = 0.0;
+    double wq[OR_MAXQ];
     for (int q = 0; q < nq; ++q) {
         for (int b = 0; b <= dim; ++b) {
             if (rule == OR_RULE_TRI3)
@@ -101,44 +114,112 @@ int fem_oracle_rule(int dim, int rule, double *xi, double *wts)
             else
                 lam[q][b] = 1.0 / (double)(dim + 1);
         }
+        if (rule == OR_RULE_TRI3) wq[q] = 1.0 / 6.0;
+        else if (rule == OR_RULE_TET4) wq[q] = 1.0 / 24.0;
+        else wq[q] = (dim == 2) ? 0.5 : 1.0 / 6.0;
     }
-    if (rule == OR_RULE_TRI3) w = 1.0 / 6.0;
-    else if (rule == OR_RULE_TET4) w = 1.0 / 24.0;
-    else w = (dim == 2) ? 0.5 : 1.0 / 6.0;
+    if (rule == OR_RULE_TRI6) {
+        /* degree 4, two orbits of three points; point q (and q + 3) carries
+         * the distinguished barycentric value at vertex q */
+        const double a1 = 0.108103018168070227363341492234, b1 = 0.5 * (1.0 - a1);
+        const double a2 = 0.816847572980458513080857073195, b2 = 0.5 * (1.0 - a2);
+        const double w1 = 0.5 * 0.223381589678011465944710768628, w2 = 0.5 * 0.109951743655321867388622564704;
+        for (int q = 0; q < 3; ++q)
+            for (int b = 0; b < 3; ++b) {
+                lam[q][b] = (b == q) ? a1 : b1;
+                lam[q + 3][b] = (b == q) ? a2 : b2;
+            }
+        for (int q = 0; q < 3; ++q) { wq[q] = w1; wq[q + 3] = w2; }
+    } else if (rule == OR_RULE_TET11) {
+        /* degree 4: the centroid (negative weight), four points with 11/14 at
+         * one vertex, six points with (1 + sqrt(5/14))/4 at the two vertices
+         * of an edge, edges in lexicographic order */
+        const double s = sqrt(5.0 / 14.0), a = 0.25 * (1.0 + s), b = 0.25 * (1.0 - s);
+        for (int v = 0; v < 4; ++v) lam[0][v] = 0.25;
+        wq[0] = -148.0 / 1875.0 / 6.0;
+        for (int q = 0; q < 4; ++q) {
+            for (int v = 0; v < 4; ++v) lam[q + 1][v] = (v == q) ? 11.0 / 14.0 : 1.0 / 14.0;
+            wq[q + 1] = 343.0 / 7500.0 / 6.0;
+        }
+        int q = 5;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j, ++q) {
+                for (int v = 0; v < 4; ++v) lam[q][v] = (v == i || v == j) ? a : b;
+                wq[q] = 56.0 / 375.0 / 6.0;
+            }
+    }
     for (int q = 0; q < nq; ++q) {
         /* reference coordinates are the barycentric weights of vertices 1..d */
         for (int k = 0; k < dim; ++k) xi[q * dim + k] = lam[q][k + 1];
-        wts[q] = w;
+        wts[q] = wq[q];
     }
     return nq;
 }
 
-/* Tabulation of the P1 basis at the quadrature points:
- * B[q][b] = phi_b(xi_q), D[q][b][k] = d phi_b / d xi_k (xi_q). */
+/* Lagrange basis of order 1 or 2 on the unit simplex, in barycentric
+ * coordinates lam_0 = 1 - sum xi, lam_k = xi_k (grad lam_0 = -1,
+ * grad lam_k = e_k). Order 1: phi_b = lam_b. Order 2: vertex functions
+ * lam_b (2 lam_b - 1), b = 0..d, then edge functions 4 lam_i lam_j for the
+ * edges (i, j), i < j, in lexicographic order. */
+static int or_nbasis(int dim, int order) { return order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2; }
+
+static void or_grad_lam(int dim, int v, double g[OR_MAXD])
+{
+    for (int k = 0; k < dim; ++k) g[k] = (v == 0) ? -1.0 : (v - 1 == k ? 1.0 : 0.0);
+}
+
+static void or_basis(int dim, int order, const double *xi, double *phi, double dphi[OR_MAXB][OR_MAXD])
+{
+    double lam[OR_MAXD + 1], gl[OR_MAXD + 1][OR_MAXD];
+    double s = 0.0;
+    for (int k = 0; k < dim; ++k) s += xi[k];
+    lam[0] = 1.0 - s;
+    for (int k = 0; k < dim; ++k) lam[k + 1] = xi[k];
+    for (int v = 0; v <= dim; ++v) or_grad_lam(dim, v, gl[v]);
+    if (order == 1) {
+        for (int b = 0; b <= dim; ++b) {
+            phi[b] = lam[b];
+            for (int k = 0; k < dim; ++k) dphi[b][k] = gl[b][k];
+        }
+        return;
+    }
+    for (int b = 0; b <= dim; ++b) {
+        phi[b] = lam[b] * (2.0 * lam[b] - 1.0);
+        for (int k = 0; k < dim; ++k) dphi[b][k] = (4.0 * lam[b] - 1.0) * gl[b][k];
+    }
+    int b = dim + 1;
+    for (int i = 0; i <= dim; ++i)
+        for (int j = i + 1; j <= dim; ++j, ++b) {
+            phi[b] = 4.0 * lam[i] * lam[j];
+            for (int k = 0; k < dim; ++k) dphi[b][k] = 4.0 * (lam[i] * gl[j][k] + lam[j] * gl[i][k]);
+        }
+}
+
+/* Tabulation at the quadrature points: B[q][b] = phi_b(xi_q),
+ * D[q][b][k] = d phi_b / d xi_k (xi_q) for the basis of u (order 1 or 2),
+ * and B1[q][b] = lam_b(xi_q), the P1 basis a P1 coefficient lives in. */
 typedef struct {
-    int dim, nb, nq;
+    int dim, order, nb, nq;
     double w[OR_MAXQ];
     double B[OR_MAXQ][OR_MAXB];
     double D[OR_MAXQ][OR_MAXB][OR_MAXD];
+    double B1[OR_MAXQ][OR_MAXD + 1];
 } or_tab;
 
-static int or_tabulate(int dim, int rule, or_tab *t)
+static int or_tabulate(int dim, int rule, int order, or_tab *t)
 {
     double xi[OR_MAXQ * OR_MAXD];
+    if (order != 1 && order != 2) return -1;
     int nq = fem_oracle_rule(dim, rule, xi, t->w);
     if (nq < 0) return -1;
     t->dim = dim;
-    t->nb = dim + 1;
+    t->order = order;
+    t->nb = or_nbasis(dim, order);
     t->nq = nq;
     for (int q = 0; q < nq; ++q) {
-        double s = 0.0;
-        for (int k = 0; k < dim; ++k) s += xi[q * dim + k];
-        t->B[q][0] = 1.0 - s;
-        for (int b = 1; b <= dim; ++b) t->B[q][b] = xi[q * dim + (b - 1)];
-        for (int k = 0; k < dim; ++k) {
-            t->D[q][0][k] = -1.0;
-            for (int b = 1; b <= dim; ++b) t->D[q][b][k] = (b - 1 == k) ? 1.0 : 0.0;
-        }
+        double d1[OR_MAXB][OR_MAXD];
+        or_basis(dim, order, xi + q * dim, t->B[q], t->D[q]);
+        or_basis(dim, 1, xi + q * dim, t->B1[q], d1);
     }
     return nq;
 }
@@ -150,11 +231,12 @@ static int or_physics_ok(int physics)
     return physics == OR_LAPLACE || physics == OR_ELASTICITY || physics == OR_MASS;
 }
 
-/* Words of one coefficient field per element, or -1 for an unknown space. */
-static int or_coef_words(int space, int nb, int nq)
+/* Words of one coefficient field per element, or -1 for an unknown space
+ * (a P1 coefficient has the d+1 vertex values whatever the order of u). */
+static int or_coef_words(int space, int dim, int nq)
 {
     if (space == OR_COEF_QUAD) return nq;
-    if (space == OR_COEF_P1) return nb;
+    if (space == OR_COEF_P1) return dim + 1;
     if (space == OR_COEF_P0) return 1;
     return -1;
 }
@@ -170,7 +252,7 @@ static void or_coef_at_points(const or_tab *t, int space, int ncoef, double a[OR
                 cq[m][q] = a[m][q];
             } else if (space == OR_COEF_P1) {
                 double v = 0.0;
-                for (int b = 0; b < t->nb; ++b) v += (absmode ? fabs(t->B[q][b]) : t->B[q][b]) * a[m][b];
+                for (int b = 0; b <= t->dim; ++b) v += (absmode ? fabs(t->B1[q][b]) : t->B1[q][b]) * a[m][b];
                 cq[m][q] = v;
             } else {
                 cq[m][q] = a[m][0];
@@ -243,7 +325,7 @@ static void or_element(const or_tab *t, int physics, double ij[OR_MAXD][OR_MAXD]
         for (int m = 0; m < ncoef; ++m) cq[m] = cf[m][q];
         double f0[OR_MAXC], f1[OR_MAXC][OR_MAXD];
         or_physics(dim, physics, uq, gu, cq, f0, f1);
-        double s = t->w[q] * sdet;
+        double s = (absmode ? fabs(t->w[q]) : t->w[q]) * sdet;
         for (int b = 0; b < nb; ++b)
             for (int c = 0; c < nc; ++c) {
                 double v = Bq[b] * f0[c];
@@ -310,16 +392,18 @@ int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const doubl
     return ndeg;
 }
 
-/* Element residuals from precomputed geometry. Returns 0, or -1 on bad
- * arguments. absmode != 0 gives the absolute-value bound described above. */
-int fem_oracle_integrate(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
-                         const double *det_j, const double *u, const double *coef,
-                         double *elem_vec, int absmode)
+/* Element residuals from precomputed geometry for Lagrange elements of the
+ * given order (1 or 2; closure rows b*N_comp + c with the node order of
+ * or_basis). Returns 0, or -1 on bad arguments. absmode != 0 gives the
+ * absolute-value bound described above. */
+int fem_oracle_integrate_p(int order, int dim, int physics, int rule, int space, int64_t n_elem,
+                           const double *inv_j, const double *det_j, const double *u, const double *coef,
+                           double *elem_vec, int absmode)
 {
     or_tab t;
-    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
+    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, order, &t) < 0) return -1;
     int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
-    int nw = or_coef_words(space, t.nb, t.nq);
+    int nw = or_coef_words(space, dim, t.nq);
     if (nw < 0) return -1;
     int64_t n = n_elem;
     for (int64_t e = 0; e < n; ++e) {
@@ -356,10 +440,10 @@ int64_t fem_oracle_residual(int dim, int physics, int rule, int space, int64_t n
                             const double *coef, double *elem_vec)
 {
     or_tab t;
-    if (!or_physics_ok(physics) || n_elem < 0 || n_vert < 0 || or_tabulate(dim, rule, &t) < 0)
+    if (!or_physics_ok(physics) || n_elem < 0 || n_vert < 0 || or_tabulate(dim, rule, 1, &t) < 0)
         return -1;
     int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
-    int nw = or_coef_words(space, t.nb, t.nq);
+    int nw = or_coef_words(space, dim, t.nq);
     if (nw < 0) return -1;
     int64_t n = n_elem, ndeg = 0;
     for (int64_t e = 0; e < n; ++e) {
@@ -387,14 +471,14 @@ int64_t fem_oracle_residual(int dim, int physics, int rule, int space, int64_t n
 
 /* Adjoint of L = sum_e w_e . R_e. du [N_bt][n] and dcoef [N_coef][N_q][n]
  * may each be NULL. Returns 0, or -1 on bad arguments. */
-int fem_oracle_backward(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
-                        const double *det_j, const double *u, const double *coef,
-                        const double *w, double *du, double *dcoef)
+int fem_oracle_backward_p(int order, int dim, int physics, int rule, int space, int64_t n_elem,
+                          const double *inv_j, const double *det_j, const double *u, const double *coef,
+                          const double *w, double *du, double *dcoef)
 {
     or_tab t;
-    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, &t) < 0) return -1;
+    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, order, &t) < 0) return -1;
     int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics);
-    int nw = or_coef_words(space, t.nb, t.nq);
+    int nw = or_coef_words(space, dim, t.nq);
     if (nw < 0) return -1;
     int64_t n = n_elem;
     for (int64_t e = 0; e < n; ++e) {
@@ -482,4 +566,19 @@ int fem_oracle_restrict(int dim, int n_comp, int64_t n_elem, int64_t n_vert, con
             for (int c = 0; c < n_comp; ++c) elem_vec[(int64_t)(b * n_comp + c) * n_elem + e] = vert[v * n_comp + c];
         }
     return 0;
+}
+
+/* Order-1 forms of the two routines above (P1 elements). */
+int fem_oracle_integrate(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
+                         const double *det_j, const double *u, const double *coef,
+                         double *elem_vec, int absmode)
+{
+    return fem_oracle_integrate_p(1, dim, physics, rule, space, n_elem, inv_j, det_j, u, coef, elem_vec, absmode);
+}
+
+int fem_oracle_backward(int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
+                        const double *det_j, const double *u, const double *coef,
+                        const double *w, double *du, double *dcoef)
+{
+    return fem_oracle_backward_p(1, dim, physics, rule, space, n_elem, inv_j, det_j, u, coef, w, du, dcoef);
 }

@@ -41,6 +41,10 @@ def load():
         lib.fem_oracle_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.fem_oracle_backward.restype = ctypes.c_int
+        lib.fem_oracle_integrate_p.argtypes = [ctypes.c_int] + lib.fem_oracle_integrate.argtypes
+        lib.fem_oracle_integrate_p.restype = ctypes.c_int
+        lib.fem_oracle_backward_p.argtypes = [ctypes.c_int] + lib.fem_oracle_backward.argtypes
+        lib.fem_oracle_backward_p.restype = ctypes.c_int
         for name in ("fem_oracle_assemble", "fem_oracle_restrict"):
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _ip, _dp, _dp]
@@ -70,8 +74,13 @@ def _ncoef(physics):
 
 
 def coef_words(dim, rule_id, space):
-    """Words of one coefficient field per element: N_q, N_b or 1."""
+    """Words of one coefficient field per element: N_q, d+1 (P1) or 1."""
     return {0: n_qpts(dim, rule_id), 1: dim + 1, 2: 1}[space]
+
+
+def n_basis(dim, order):
+    """Lagrange basis functions per element: d+1 (order 1), (d+1)(d+2)/2 (order 2)."""
+    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
 
 
 def n_qpts(dim: int, rule: int) -> int:
@@ -103,27 +112,28 @@ def geometry(coords, conn):
     return inv_j, det_j, int(r)
 
 
-def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode, space):
+def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode, space, order):
     inv_j, det_j, u, coef = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef)
     n = det_j.shape[0]
-    nb = dim + 1
+    nb = n_basis(dim, order)
     R = np.zeros((nb * _ncomp(dim, physics), n))
-    r = load().fem_oracle_integrate(dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u), _p(coef),
-                                    _p(R), int(absmode))
+    r = load().fem_oracle_integrate_p(order, dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u),
+                                      _p(coef), _p(R), int(absmode))
     if r != 0:
         raise ValueError("oracle integrate: bad arguments")
     return R
 
 
-def integrate(dim, physics, rule_id, inv_j, det_j, u, coef, space=0):
+def integrate(dim, physics, rule_id, inv_j, det_j, u, coef, space=0, order=1):
     """Element residuals R[N_bt, n] from precomputed geometry (Eq. (2) bracket).
-    ``space``: 0 coefficients on quadrature points, 1 P1 nodal, 2 P0."""
-    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False, space)
+    ``space``: 0 coefficients on quadrature points, 1 P1 nodal, 2 P0;
+    ``order``: 1 (P1) or 2 (P2, vertices then edges in lexicographic order)."""
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False, space, order)
 
 
-def integrate_abs(dim, physics, rule_id, inv_j, det_j, u, coef, space=0):
+def integrate_abs(dim, physics, rule_id, inv_j, det_j, u, coef, space=0, order=1):
     """Same sums with |.| on every factor: the scale of the rounding measure."""
-    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, True, space)
+    return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, True, space, order)
 
 
 def residual(dim, physics, rule_id, coords, conn, u, coef, space=0):
@@ -138,15 +148,15 @@ def residual(dim, physics, rule_id, coords, conn, u, coef, space=0):
     return R, int(r)
 
 
-def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want_dcoef=True, space=0):
+def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want_dcoef=True, space=0, order=1):
     """Adjoint of L = sum w.R: (du[N_bt, n] or None, dcoef[N_coef, N_w, n] or None)."""
     inv_j, det_j, u, coef, w = _f64(inv_j), _f64(det_j), _f64(u), _f64(coef), _f64(w)
     n = det_j.shape[0]
     nw = coef_words(dim, rule_id, space)
-    du = np.zeros(((dim + 1) * _ncomp(dim, physics), n)) if want_du else None
+    du = np.zeros((n_basis(dim, order) * _ncomp(dim, physics), n)) if want_du else None
     dcoef = np.zeros((_ncoef(physics), nw, n)) if want_dcoef else None
-    r = load().fem_oracle_backward(dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u), _p(coef), _p(w),
-                                   _p(du), _p(dcoef))
+    r = load().fem_oracle_backward_p(order, dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(u),
+                                     _p(coef), _p(w), _p(du), _p(dcoef))
     if r != 0:
         raise ValueError("oracle backward: bad arguments")
     return du, dcoef

@@ -25,7 +25,7 @@ BASE_SEED = 160704245
 
 # Physics / rule / coefficient-space codes; the numeric values match include/fem.h.
 LAPLACE, ELASTICITY, MASS = 0, 1, 2
-RULE_TRI3, RULE_TET4, RULE_CENTROID = 0, 1, 2
+RULE_TRI3, RULE_TET4, RULE_CENTROID, RULE_TRI6, RULE_TET11 = 0, 1, 2, 3, 4
 COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
 
 PHYSICS_NAMES = {LAPLACE: "laplace", ELASTICITY: "elasticity", MASS: "mass"}
@@ -42,6 +42,10 @@ def n_coef(physics: int) -> int:
 
 
 def n_qpts(dim: int, rule: int) -> int:
+    if rule == RULE_TRI6:
+        return 6
+    if rule == RULE_TET11:
+        return 11
     if rule == RULE_CENTROID:
         return 1
     return dim + 1
