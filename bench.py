@@ -395,6 +395,37 @@ def main():
                         f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
             del wlx
 
+        # ------------------------------------------------- second order (P2) --
+        for cfg, rule in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            p2 = mg.p2_inputs(wlx, rule, mg.BASE_SEED + 5000)
+            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                word = 4 if dt == torch.float32 else 8
+                nb = model.p2_forward_bytes(wlx.dim, wlx.physics, rule, word) * wlx.n_elem
+                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                base = dict(ij=ij, dj=dj, u=to_dev(p2.u, dt), cf=to_dev(p2.coef, dt))
+                cps = []
+                for _ in range(n_copies(nb)):
+                    c = {k: v.clone() for k, v in base.items()}
+                    c["R"] = torch.empty_like(c["u"])
+                    cps.append(c)
+                del base
+
+                def go(c, wlx=wlx, rule=rule):
+                    api.fem_integrate_residual_p2(wlx.dim, wlx.physics, rule, c["ij"], c["dj"], c["u"], c["cf"],
+                                                  out=c["R"])
+                _, ms = timed_graph(go, cps, 20, 1)
+                us = ms * 1e3
+                f = model.p2_model_flops(wlx.dim, wlx.physics, rule)
+                extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
+                    n_elem=wlx.n_elem, rule=rule, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                    elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
+                    bytes_per_elem=nb / wlx.n_elem)
+                log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)")
+                del cps, ij, dj
+            del p2, wlx
+
         # --------------------------------------------------------- assembly --
         # global residual: element vectors summed onto vertices (deterministic gather)
         for cfg in (2, "3b"):

@@ -82,7 +82,11 @@ enum fem_dtype { FEM_F32 = 0, FEM_F64 = 1 };
  *                                                                (N_comp 1, N_coef 1) */
 enum fem_physics { FEM_LAPLACE = 0, FEM_ELASTICITY = 1, FEM_MASS = 2 };
 
-enum fem_rule { FEM_RULE_TRI3 = 0, FEM_RULE_TET4 = 1, FEM_RULE_CENTROID = 2 };
+enum fem_rule {
+    FEM_RULE_TRI3 = 0, FEM_RULE_TET4 = 1, FEM_RULE_CENTROID = 2,
+    /* degree-4 rules, second-order elements only (see fem_integrate_residual_p2) */
+    FEM_RULE_TRI6 = 3, FEM_RULE_TET11 = 4
+};
 
 enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
 
@@ -102,7 +106,9 @@ enum fem_op {
     FEM_OP_RESIDUAL_MESH = 1,  /* fem_integrate_residual_mesh */
     FEM_OP_GEOMETRY = 2,       /* fem_geometry (physics and rule ignored) */
     FEM_OP_BACKWARD = 3,       /* fem_integrate_residual_backward */
-    FEM_OP_RESIDUAL_GATHER = 4 /* fem_integrate_residual_gather */
+    FEM_OP_RESIDUAL_GATHER = 4, /* fem_integrate_residual_gather */
+    FEM_OP_RESIDUAL_P2 = 5,     /* fem_integrate_residual_p2 */
+    FEM_OP_BACKWARD_P2 = 6      /* fem_integrate_residual_p2_backward */
 };
 
 /* ------------------------------------------------------------------ */
@@ -193,6 +199,38 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int c
                                            int dtype, int64_t n_elem, const void* inv_j,
                                            const void* det_j, const void* u, const void* coef,
                                            const void* w, void* du, void* dcoef, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Second-order (P2) Lagrange elements on affine simplices: the same    */
+/* quadrature discretization of Eq. (2) with the P2 basis.              */
+/* ------------------------------------------------------------------ */
+
+/* Element residuals of P2 elements from precomputed affine geometry
+ * (fem_geometry of the vertices). N_b = (dim+1)(dim+2)/2 nodes per element,
+ * in the order vertices 0..dim, then the edges (i, j), i < j, in
+ * lexicographic order; basis lam_v (2 lam_v - 1) at vertices and
+ * 4 lam_i lam_j on edges (lam the barycentric coordinates of the unit
+ * simplex). u and elem_vec are [N_b*N_comp][n] (row b*N_comp + c); a P1
+ * coefficient has N_w = dim+1 vertex values and is evaluated with the P1
+ * basis. Rules: FEM_RULE_TRI3 / FEM_RULE_TET4 (degree 2: exact for the
+ * stiffness of constant coefficients) and the degree-4 rules
+ * FEM_RULE_TRI6 (six points, two orbits: barycentric a at vertex q for
+ * point q and q+3, a = 0.108103018168070227 and 0.816847572980458513,
+ * weights 0.223381589678011466/2 and 0.109951743655321867/2) and
+ * FEM_RULE_TET11 (the centroid, weight -148/1875; (11/14, 1/14, 1/14,
+ * 1/14) per vertex, weight 343/7500; (a, a, b, b) per edge with
+ * a = (1 + sqrt(5/14))/4, b = (1 - sqrt(5/14))/4, weight 56/375; all
+ * weights times 1/6), which integrate the P2 mass matrix exactly.
+ * Errors as fem_integrate_residual (FEM_ERR_UNSUPPORTED for other rules). */
+fem_status fem_integrate_residual_p2(int dim, int physics, int rule, int coef_space, int dtype,
+                                     int64_t n_elem, const void* inv_j, const void* det_j,
+                                     const void* u, const void* coef, void* elem_vec, void* stream);
+/* Adjoint of L = sum_e w_e . R_e for P2 elements; arguments and meaning as
+ * fem_integrate_residual_backward with the P2 layouts above. */
+fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, int coef_space, int dtype,
+                                              int64_t n_elem, const void* inv_j, const void* det_j,
+                                              const void* u, const void* coef, const void* w, void* du,
+                                              void* dcoef, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Batched persistent launch over many meshes (not in the paper; its   */

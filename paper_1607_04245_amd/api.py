@@ -27,7 +27,12 @@ def n_coef(physics: int) -> int:
 
 
 def n_qpts(dim: int, rule: int) -> int:
-    return 1 if rule == 2 else dim + 1
+    return {2: 1, 3: 6, 4: 11}.get(rule, dim + 1)
+
+
+def n_basis(dim: int, order: int = 1) -> int:
+    """Lagrange nodes per element: d+1 (P1) or (d+1)(d+2)/2 (P2)."""
+    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
 
 
 def n_coef_words(dim: int, rule: int, coef_space: int = N.COEF_QUAD) -> int:
@@ -90,8 +95,8 @@ def fem_geometry(coords: torch.Tensor, conn: torch.Tensor, dtype=torch.float32, 
     return inv_j, det_j
 
 
-def _shapes(dim, physics, rule, n, coef_space=N.COEF_QUAD):
-    nbt = (dim + 1) * n_comp(dim, physics)
+def _shapes(dim, physics, rule, n, coef_space=N.COEF_QUAD, order=1):
+    nbt = n_basis(dim, order) * n_comp(dim, physics)
     return (dim * dim, n), (n,), (nbt, n), (n_coef(physics), n_coef_words(dim, rule, coef_space), n)
 
 
@@ -212,6 +217,56 @@ def fem_integrate_residual_backward(dim: int, physics: int, rule: int, inv_j, de
         dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
         _ptr(coef) if want_du else None, _ptr(w), _ptr(du), _ptr(dcoef), _stream()),
         "fem_integrate_residual_backward")
+    return du, dcoef
+
+
+def fem_integrate_residual_p2(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, out=None, *,
+                              coef_space=N.COEF_QUAD):
+    """Element residuals of second-order (P2) elements, R [N_b*N_comp, n] with
+    N_b = (d+1)(d+2)/2 (vertices, then edges in lexicographic order), from
+    precomputed affine geometry."""
+    dtype = det_j.dtype
+    if dtype not in _DT:
+        raise TypeError("geometry must be float32 or float64")
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space, order=2)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(u, "u", dtype, su)
+    _need(coef, "coef", dtype, scf)
+    if out is None:
+        out = torch.empty(su, dtype=dtype, device=u.device)
+    _need(out, "out", dtype, su)
+    N.check(N.lib().fem_integrate_residual_p2(dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j),
+                                              _ptr(u), _ptr(coef), _ptr(out), _stream()), "fem_integrate_residual_p2")
+    return out
+
+
+def fem_integrate_residual_p2_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
+                                       want_du=True, want_dcoef=True, du=None, dcoef=None, *, coef_space=N.COEF_QUAD):
+    """(du, dcoef) of L = sum w.R for P2 elements (see fem_integrate_residual_p2)."""
+    dtype = det_j.dtype
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space, order=2)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(w, "w", dtype, su)
+    if want_du:
+        _need(coef, "coef", dtype, scf)
+        du = torch.empty(su, dtype=dtype, device=w.device) if du is None else du
+        _need(du, "du", dtype, su)
+    else:
+        du = None
+    if want_dcoef:
+        _need(u, "u", dtype, su)
+        dcoef = torch.empty(scf, dtype=dtype, device=w.device) if dcoef is None else dcoef
+        _need(dcoef, "dcoef", dtype, scf)
+    else:
+        dcoef = None
+    N.check(N.lib().fem_integrate_residual_p2_backward(
+        dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
+        _ptr(coef) if want_du else None, _ptr(w), _ptr(du), _ptr(dcoef), _stream()),
+        "fem_integrate_residual_p2_backward")
     return du, dcoef
 
 
@@ -413,22 +468,24 @@ class IntegrateResidual(torch.autograd.Function):
     kernel. Geometry is treated as a constant."""
 
     @staticmethod
-    def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef, coef_space):
+    def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef, coef_space, order):
         ctx.save_for_backward(inv_j, det_j, u, coef)
-        ctx.meta = (dim, physics, rule, coef_space)
-        return fem_integrate_residual(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(),
-                                      coef_space=coef_space)
+        ctx.meta = (dim, physics, rule, coef_space, order)
+        fwd = fem_integrate_residual if order == 1 else fem_integrate_residual_p2
+        return fwd(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), coef_space=coef_space)
 
     @staticmethod
     def backward(ctx, grad_r):
         inv_j, det_j, u, coef = ctx.saved_tensors
-        dim, physics, rule, coef_space = ctx.meta
-        du, dcoef = fem_integrate_residual_backward(
-            dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), grad_r.contiguous(),
-            want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6], coef_space=coef_space)
-        return None, None, None, None, None, du, dcoef, None
+        dim, physics, rule, coef_space, order = ctx.meta
+        bwd = fem_integrate_residual_backward if order == 1 else fem_integrate_residual_p2_backward
+        du, dcoef = bwd(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), grad_r.contiguous(),
+                        want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6], coef_space=coef_space)
+        return None, None, None, None, None, du, dcoef, None, None
 
 
-def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef, coef_space=N.COEF_QUAD):
-    """Differentiable element residuals (see IntegrateResidual)."""
-    return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef, coef_space)
+def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef, coef_space=N.COEF_QUAD, order=1):
+    """Differentiable element residuals (see IntegrateResidual); order 1 (P1) or 2 (P2)."""
+    if order not in (1, 2):
+        raise ValueError("order must be 1 or 2")
+    return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef, coef_space, order)

@@ -64,6 +64,19 @@ static fem_status check_space(const char* fn, int space) {
     return FEM_OK;
 }
 
+// Rules of the second-order entry points: the degree-2 and degree-4 rules.
+static bool valid_rule_p2(int dim, int rule) {
+    return dim == 2 ? (rule == FEM_RULE_TRI3 || rule == FEM_RULE_TRI6) : (rule == FEM_RULE_TET4 || rule == FEM_RULE_TET11);
+}
+
+static fem_status check_combo_p2(const char* fn, int dim, int phys, int rule, int dtype) {
+    if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_rule_p2(dim, rule)) { set_error("%s: rule %d is not available for P2 in %dD", fn, rule, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+    return FEM_OK;
+}
+
 static fem_status check_combo(const char* fn, int dim, int phys, int rule, int dtype) {
     if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
     if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
@@ -80,7 +93,7 @@ static std::map<TuneKey, fem_tuning> g_tune;
 
 static bool valid_op(int op) {
     return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
-           op == FEM_OP_RESIDUAL_GATHER;
+           op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -97,6 +110,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
     if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
+    if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER) {
         if (phys == FEM_LAPLACE && f32) return fem_tuning{FEM_STRATEGY_LANE, 1, 1, 8};
         if (phys == FEM_ELASTICITY && f32) return fem_tuning{FEM_STRATEGY_LANE, 2, 2, 0};
@@ -113,10 +127,11 @@ static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
     const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
-    const bool vec_ok = two ? (t.vec == 1 || t.vec == 2) : (t.vec == 1 || t.vec == 2 || t.vec == 4);
-    return strategy_ok && vec_ok &&
-           (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
-            t.waves_per_block == 8) &&
+    const bool one = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
+    const bool vec_ok = one ? t.vec == 1 : two ? (t.vec == 1 || t.vec == 2) : (t.vec == 1 || t.vec == 2 || t.vec == 4);
+    const bool waves_ok = t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
+                          (t.waves_per_block == 8 && !one);
+    return strategy_ok && vec_ok && waves_ok &&
            t.blocks_per_cu >= 0 && t.blocks_per_cu <= 64;
 }
 
@@ -175,6 +190,7 @@ static fem_status check_tuning_args(const char* fn, int op, int dim, int physics
         if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
         return FEM_OK;
     }
+    if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return check_combo_p2(fn, dim, physics, rule, dtype);
     return check_combo(fn, dim, physics, rule, dtype);
 }
 
@@ -309,6 +325,44 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int c
     Launch l = make_launch(t, n_elem / vec, vec, static_cast<hipStream_t>(stream));
     hipError_t e = launch_backward_lane(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_backward launch");
+}
+
+fem_status fem_integrate_residual_p2(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
+                                     const void* inv_j, const void* det_j, const void* u, const void* coef,
+                                     void* elem_vec, void* stream) {
+    fem_status st = check_combo_p2("fem_integrate_residual_p2", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_p2", coef_space);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual_p2: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (!inv_j || !det_j || !u || !coef || !elem_vec) {
+        set_error("fem_integrate_residual_p2: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_P2, dim, physics, rule, dtype);
+    ResidualArgs a{n_elem, inv_j, det_j, u, coef, elem_vec};
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_residual_p2(dim, physics, rule, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p2 launch");
+}
+
+fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, int coef_space, int dtype,
+                                              int64_t n_elem, const void* inv_j, const void* det_j, const void* u,
+                                              const void* coef, const void* w, void* du, void* dcoef, void* stream) {
+    fem_status st = check_combo_p2("fem_integrate_residual_p2_backward", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_p2_backward", coef_space);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual_p2_backward: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0 || (!du && !dcoef)) return FEM_OK;
+    if (!inv_j || !det_j || !w || (du && !coef) || (dcoef && !u)) {
+        set_error("fem_integrate_residual_p2_backward: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_BACKWARD_P2, dim, physics, rule, dtype);
+    BackwardArgs a{n_elem, inv_j, det_j, u, coef, w, du, dcoef};
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_backward_p2(dim, physics, rule, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p2_backward launch");
 }
 
 fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream) {

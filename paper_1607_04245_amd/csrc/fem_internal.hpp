@@ -60,6 +60,11 @@ hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtyp
 // u and a P1 coefficient per vertex (MeshArgs.u, MeshArgs.coef), gathered.
 hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                   const Launch& l);
+// Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
+hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
+                              const Launch& l);
+hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
+                              const Launch& l);
 hipError_t launch_backward_lane(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                                 const Launch& l);
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,

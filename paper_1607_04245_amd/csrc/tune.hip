@@ -227,9 +227,10 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         set_error("fem_autotune: n_elem_probe must be in [4096, 2^28]");
         return FEM_ERR_INVALID_ARG;
     }
+    const bool p2 = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
     const int nc = physics == FEM_ELASTICITY ? dim : 1;
-    const int nbt = (dim + 1) * nc;
-    const int nq = rule == FEM_RULE_CENTROID ? 1 : dim + 1;
+    const int nbt = (p2 ? (dim + 1) * (dim + 2) / 2 : dim + 1) * nc;
+    const int nq = rule == FEM_RULE_CENTROID ? 1 : rule == FEM_RULE_TRI6 ? 6 : rule == FEM_RULE_TET11 ? 11 : dim + 1;
     const int ncq = (physics == FEM_ELASTICITY ? 2 : 1) * nq;
     const size_t word = dtype == FEM_F32 ? 4 : 8;
     const int64_t n = n_probe;
@@ -295,6 +296,12 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
 
     auto run = [&](const Copy& c) -> fem_status {
         switch (op) {
+        case FEM_OP_RESIDUAL_P2:
+            return fem_integrate_residual_p2(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out,
+                                             nullptr);
+        case FEM_OP_BACKWARD_P2:
+            return fem_integrate_residual_p2_backward(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf,
+                                                      c.w, c.du, c.dc, nullptr);
         case FEM_OP_RESIDUAL:
             return fem_integrate_residual(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);
         case FEM_OP_BACKWARD:
@@ -313,7 +320,7 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
 
     std::vector<fem_tuning> cands;
     const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
-    const std::vector<int> vecs = two ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    const std::vector<int> vecs = p2 ? std::vector<int>{1} : two ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
     for (int v : vecs)
         for (int w : {1, 2, 4, 8})
             for (int b : {0, 2, 4, 8, 16}) cands.push_back(fem_tuning{FEM_STRATEGY_LANE, v, w, b});

@@ -345,3 +345,57 @@ def batch_workloads(n_mesh: int = 64, lo: float = 3.0, hi: float = 6.0,
                             physics=phys, rule=rule, coords=coords, conn=conn,
                             u_vertex=u_vertex, u=closure(conn, u_vertex), coef=coef, w=w))
     return out
+
+
+# ------------------------------------------------------ second-order inputs --
+
+P2_EDGES = {2: [(0, 1), (0, 2), (1, 2)], 3: [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]}
+
+
+def p2_connectivity(conn: np.ndarray, n_vert: int):
+    """P2 node numbering of a simplex mesh: vertices keep their numbers, each
+    edge gets one node n_vert + k (k in order of the sorted vertex pair).
+    Returns (conn2 [N_e, N_b] int64 with vertices then lexicographic edges,
+    number of nodes)."""
+    dim = conn.shape[1] - 1
+    ei = np.array([i for i, _ in P2_EDGES[dim]])
+    ej = np.array([j for _, j in P2_EDGES[dim]])
+    a, b = conn[:, ei].astype(np.int64), conn[:, ej].astype(np.int64)
+    key = np.minimum(a, b) * n_vert + np.maximum(a, b)
+    uniq, inv = np.unique(key.ravel(), return_inverse=True)
+    conn2 = np.concatenate([conn.astype(np.int64), n_vert + inv.reshape(key.shape)], axis=1)
+    return conn2, n_vert + uniq.size
+
+
+@dataclasses.dataclass
+class P2Inputs:
+    """Second-order inputs on the mesh of a Workload (same vertices and
+    elements): node field, its closure, coefficients at the rule's points
+    and upstream weights.
+
+    conn2  [N_e, N_b] int64, N_b = (d+1)(d+2)/2
+    u_node [N_nodes, N_comp]
+    u, w   [N_b*N_comp, N_e]   closure rows b*N_comp + c
+    coef   [N_coef, N_q, N_e]
+    """
+    rule: int
+    conn2: np.ndarray
+    n_nodes: int
+    u_node: np.ndarray
+    u: np.ndarray
+    coef: np.ndarray
+    w: np.ndarray
+
+
+def p2_inputs(wl: "Workload", rule: int, seed: int) -> P2Inputs:
+    """P2 inputs with the per-physics distributions of the P1 workloads,
+    drawn from ``SeedSequence(seed).spawn(3)`` = [coef, u, w]."""
+    r_coef, r_u, r_w = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3)]
+    conn2, n_nodes = p2_connectivity(wl.conn, wl.n_vert)
+    nc, nq, ne = wl.n_comp, n_qpts(wl.dim, rule), wl.n_elem
+    coef = np.ascontiguousarray(_coef_draw(wl.physics, r_coef, (nq, ne)))
+    lo, hi = (-1e-2, 1e-2) if wl.physics == ELASTICITY else (-1.0, 1.0)
+    u_node = r_u.uniform(lo, hi, size=(n_nodes, nc))
+    u = closure(conn2, u_node)
+    w = np.ascontiguousarray(r_w.uniform(-1.0, 1.0, size=u.shape))
+    return P2Inputs(rule=rule, conn2=conn2, n_nodes=n_nodes, u_node=u_node, u=u, coef=coef, w=w)

@@ -45,7 +45,11 @@ def n_coef(physics: int) -> int:
 
 
 def n_qpts(dim: int, rule: int) -> int:
-    return 1 if rule == 2 else dim + 1
+    return {2: 1, 3: 6, 4: 11}.get(rule, dim + 1)
+
+
+def n_basis(dim: int, order: int = 1) -> int:
+    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
 
 
 def n_coef_words(dim: int, rule: int, coef_space: int = 0) -> int:
@@ -117,3 +121,14 @@ def assemble_bytes(dim: int, n_comp_: int, n_elem: int, n_vert: int, word: int) 
     element vectors in, row offsets in and the vertex field out (amortised)."""
     nb = dim + 1
     return 4.0 * nb + word * nb * n_comp_ + (4.0 + word * n_comp_) * n_vert / max(n_elem, 1)
+
+
+def p2_model_flops(dim: int, physics: int, rule: int) -> int:
+    """The paper's per-cell flop formula with the P2 basis (N_b = (d+1)(d+2)/2)."""
+    return paper_flops_per_cell(dim, n_basis(dim, 2), n_comp(dim, physics), n_qpts(dim, rule))
+
+
+def p2_forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
+    """Compulsory bytes per element of fem_integrate_residual_p2."""
+    nbt = n_basis(dim, 2) * n_comp(dim, physics)
+    return word * ((dim * dim + 1) + 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space))

@@ -196,3 +196,27 @@ def test_assembly_validation(lib):
     assert r(2, 1, N.F32, 5, 0, _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
     assert r(2, 1, N.F32, 5, 5, _v(), None, _v(), None) == N.FEM_ERR_INVALID_ARG
     lib.fem_assembly_plan_destroy(None)
+
+
+def test_p2_validation(lib):
+    f, b = lib.fem_integrate_residual_p2, lib.fem_integrate_residual_p2_backward
+    ok = (3, mg.ELASTICITY, mg.RULE_TET11, N.COEF_QUAD, N.F32)
+    assert f(*ok, 0, None, None, None, None, None, None) == N.FEM_OK
+    assert f(*ok, -1, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    assert f(*ok, 5, _v(), None, _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    for bad in [(3, mg.LAPLACE, mg.RULE_CENTROID, 0, N.F32), (2, mg.LAPLACE, mg.RULE_TET11, 0, N.F32),
+                (3, mg.LAPLACE, mg.RULE_TRI6, 0, N.F32), (3, 7, mg.RULE_TET4, 0, N.F32),
+                (3, mg.LAPLACE, mg.RULE_TET4, 5, N.F32), (3, mg.LAPLACE, mg.RULE_TET4, 0, 3)]:
+        assert f(*bad, 5, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+        assert b(*bad, 5, _v(), _v(), _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+    assert b(*ok, 5, _v(), _v(), None, None, _v(), None, None, None) == N.FEM_OK            # nothing wanted
+    assert b(*ok, 5, _v(), _v(), None, _v(), _v(), None, _v(), None) == N.FEM_ERR_INVALID_ARG  # dcoef needs u
+    # the degree-4 rules exist only for the second-order entry points
+    assert lib.fem_integrate_residual(2, mg.LAPLACE, mg.RULE_TRI6, 0, N.F32, 5, _v(), _v(), _v(), _v(), _v(),
+                                      None) == N.FEM_ERR_UNSUPPORTED
+    t = N.fem_tuning(N.STRATEGY_LANE, 1, 8, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_P2, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_INVALID_ARG
+    t = N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0)
+    assert lib.fem_set_tuning(N.OP_BACKWARD_P2, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_INVALID_ARG
