@@ -280,10 +280,11 @@ void fem_batch_plan_destroy(fem_batch_plan* plan);
 typedef struct fem_tuning {
     int strategy;        /* enum fem_strategy; FEM_STRATEGY_TRANSPOSE only for FEM_OP_RESIDUAL */
     int vec;             /* elements per lane: RESIDUAL and BACKWARD read 1, 2 or 4
-                          * consecutive elements per vector access; GEOMETRY (1, 2, 4)
-                          * and RESIDUAL_MESH / RESIDUAL_GATHER (1, 2) give each lane that many elements
-                          * 64 apart, to overlap their dependent vertex gathers */
-    int waves_per_block; /* 1, 2, 4 or 8 (wave64) */
+                          * consecutive elements per vector access; GEOMETRY,
+                          * RESIDUAL_MESH and RESIDUAL_GATHER (1, 2, 4) give each lane that
+                          * many elements 64 apart, to overlap their dependent vertex
+                          * gathers; the P2 ops take 1 */
+    int waves_per_block; /* 1, 2, 4 or 8 (wave64; at most 4 for the P2 ops) */
     int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */
 } fem_tuning;
 

@@ -109,9 +109,10 @@ static TuneKey tune_key(int op, int dim, int phys, int rule, int dtype) {
 static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype) {
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
-    if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
+    if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 4, 4, 0};
     if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
-    if (op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER) {
+    if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
+    if (op == FEM_OP_RESIDUAL_MESH) {
         if (phys == FEM_LAPLACE && f32) return fem_tuning{FEM_STRATEGY_LANE, 1, 1, 8};
         if (phys == FEM_ELASTICITY && f32) return fem_tuning{FEM_STRATEGY_LANE, 2, 2, 0};
         return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
@@ -126,9 +127,8 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
 static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
-    const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
     const bool one = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
-    const bool vec_ok = one ? t.vec == 1 : two ? (t.vec == 1 || t.vec == 2) : (t.vec == 1 || t.vec == 2 || t.vec == 4);
+    const bool vec_ok = one ? t.vec == 1 : (t.vec == 1 || t.vec == 2 || t.vec == 4);
     const bool waves_ok = t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
                           (t.waves_per_block == 8 && !one);
     return strategy_ok && vec_ok && waves_ok &&

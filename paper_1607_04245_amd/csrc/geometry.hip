@@ -31,8 +31,8 @@ __device__ __forceinline__ void geometry_finish(bool valid, int64_t e, int64_t n
     double inv[DIM][DIM], ep2;
     double det = element_geometry<DIM>(x, inv, ep2);
     const int flag = finish_geometry<DIM>(ok, det, inv, ep2);
-    ndeg += valid && flag == 1;
-    npoor += valid && flag == 2;
+    ndeg += (int)(valid & (flag == 1));
+    npoor += (int)(valid & (flag == 2));
     if (valid) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(512)
 geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,
                 Out* __restrict__ inv_j, Out* __restrict__ det_j, int32_t* __restrict__ counts) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    // wave-uniform (readfirstlane): the tile loop is then scalar control flow
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), waves = blockDim.x >> 6;
     const int64_t n_tiles = (n + 64 * EPT - 1) / (64 * EPT);
     int64_t t_begin, t_end;
     block_tile_range(n_tiles, t_begin, t_end);
@@ -63,7 +64,7 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
                 const int64_t e = tile * 64 + lane;
                 double x[DIM + 1][DIM];
                 gather_coords<DIM>(X, va, nv, x);
-                const bool ok = e < n && conn_ok<DIM>(va, nv);
+                const bool ok = (e < n) & conn_ok<DIM>(va, nv);
                 __asm__ volatile("" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
                 const int64_t next = tile + waves;
@@ -76,7 +77,7 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
                 const int64_t e = tile * 64 + lane;
                 double x[DIM + 1][DIM];
                 gather_coords<DIM>(X, vb, nv, x);
-                const bool ok = e < n && conn_ok<DIM>(vb, nv);
+                const bool ok = (e < n) & conn_ok<DIM>(vb, nv);
                 __asm__ volatile("" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
                 const int64_t next = tile + waves;
@@ -99,7 +100,7 @@ geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32
             for (int j = 0; j < EPT; ++j) gather_coords<DIM>(X, v[j], nv, x[j]);
 #pragma unroll
             for (int j = 0; j < EPT; ++j)
-                geometry_finish<DIM, Out>(e[j] < n, e[j], n, e[j] < n && conn_ok<DIM>(v[j], nv), x[j], inv_j, det_j,
+                geometry_finish<DIM, Out>(e[j] < n, e[j], n, (e[j] < n) & conn_ok<DIM>(v[j], nv), x[j], inv_j, det_j,
                                           ndeg, npoor);
         }
     }

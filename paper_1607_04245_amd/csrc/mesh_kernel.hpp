@@ -130,7 +130,8 @@ __device__ __forceinline__ void mesh_element_finish(bool valid, int64_t e, int64
 // next tile are already in flight, so a wave pays roughly one memory latency
 // per tile instead of two. (A three-deep pipeline, with the gathers of tile
 // k+1 also in flight during the arithmetic of tile k, measured slower at
-// every launch shape.) EPT = 2: two elements per lane, no pipelining.
+// every launch shape.) EPT = 2 or 4: that many elements per lane, no
+// pipelining.
 // GATHER: u (and a P1 coefficient) are vertex arrays gathered through the
 // connectivity instead of per-element closure rows.
 template <int DIM, int PHYS, int RULE, typename Real, int EPT, bool STORE_GEOM, bool VEC, bool GATHER>
@@ -236,6 +237,7 @@ static hipError_t launch_v(const MeshArgs& a, const Launch& l) {
     switch (l.vec) {
     case 1: return launch_a<DIM, PHYS, RULE, Real, 1, GATHER>(a, l);
     case 2: return launch_a<DIM, PHYS, RULE, Real, 2, GATHER>(a, l);
+    case 4: return launch_a<DIM, PHYS, RULE, Real, 4, GATHER>(a, l);
     default: return hipErrorInvalidValue;
     }
 }

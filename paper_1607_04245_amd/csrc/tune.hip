@@ -319,8 +319,7 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     };
 
     std::vector<fem_tuning> cands;
-    const bool two = op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_RESIDUAL_GATHER;
-    const std::vector<int> vecs = p2 ? std::vector<int>{1} : two ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    const std::vector<int> vecs = p2 ? std::vector<int>{1} : std::vector<int>{1, 2, 4};
     for (int v : vecs)
         for (int w : {1, 2, 4, 8})
             for (int b : {0, 2, 4, 8, 16}) cands.push_back(fem_tuning{FEM_STRATEGY_LANE, v, w, b});

@@ -108,14 +108,19 @@ def test_tuning_roundtrip(lib):
     bad = N.fem_tuning(N.STRATEGY_LANE, 4, 5, 0)
     assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(bad)) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_TET4, N.F64, ctypes.byref(new)) == N.FEM_ERR_UNSUPPORTED
-    # the transposition strategy exists only for the residual; the fused kernel takes 1 or 2 elements per lane
+    # the transposition strategy exists only for the residual; the fused kernel takes 1, 2 or 4 elements per lane
     tt = N.fem_tuning(N.STRATEGY_TRANSPOSE, 1, 4, 0)
     assert lib.fem_set_tuning(R, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(tt)) == N.FEM_OK
     assert lib.fem_set_tuning(N.OP_BACKWARD, 2, mg.MASS, mg.RULE_CENTROID, N.F64, ctypes.byref(tt)) \
         == N.FEM_ERR_INVALID_ARG
     four = N.fem_tuning(N.STRATEGY_LANE, 4, 4, 0)
-    assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) \
+    three = N.fem_tuning(N.STRATEGY_LANE, 3, 4, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(three)) \
         == N.FEM_ERR_INVALID_ARG
+    saved = N.fem_tuning()
+    lib.fem_get_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_OK
+    lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
     assert lib.fem_set_tuning(7, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
@@ -172,8 +177,8 @@ def test_residual_gather_validation(lib):
     assert f(*c, 5, 5, _v(), _v(), _v(), _v(), _v(), None, _v(), None, None) == N.FEM_ERR_INVALID_ARG
     assert f(3, mg.LAPLACE, mg.RULE_TET4, 4, N.F32, 5, 5, _v(), _v(), _v(), _v(), _v(), None, None, None, None) \
         == N.FEM_ERR_UNSUPPORTED
-    four = N.fem_tuning(N.STRATEGY_LANE, 4, 4, 0)
-    assert lib.fem_set_tuning(N.OP_RESIDUAL_GATHER, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) \
+    three = N.fem_tuning(N.STRATEGY_LANE, 3, 4, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_GATHER, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(three)) \
         == N.FEM_ERR_INVALID_ARG
 
 

@@ -79,7 +79,7 @@ def test_gather_bitwise_equals_closure_form(dim, phys, space, dtype):
                                           coef_space=space)
     ij, dj = api.fem_geometry(coords, conn, dtype)
     uv, cgd = dev(wl.u_vertex, dtype), dev(cg, dtype)
-    for ept, waves, bpc in [(1, 1, 8), (1, 2, 0), (2, 1, 0), (2, 4, 3), (1, 8, 1)]:
+    for ept, waves, bpc in [(1, 1, 8), (1, 2, 0), (2, 1, 0), (2, 4, 3), (1, 8, 1), (4, 4, 0), (4, 1, 3)]:
         api.fem_set_tuning(dim, phys, rule, dtype, strategy=N.STRATEGY_LANE, vec=ept, waves_per_block=waves,
                            blocks_per_cu=bpc, op=N.OP_RESIDUAL_GATHER)
         ij2, dj2 = torch.full_like(ij, float("nan")), torch.full_like(dj, float("nan"))
@@ -144,7 +144,7 @@ def test_full_size_workloads(cfg, space, dtype):
 
 def test_autotune_gather_op():
     t = api.fem_autotune(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, n_elem_probe=1 << 18, op=N.OP_RESIDUAL_GATHER)
-    assert t["vec"] in (1, 2) and t["waves_per_block"] in (1, 2, 4, 8)
+    assert t["vec"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4, 8)
     wl = small_workload(3, mg.LAPLACE, 2000)
     cf, cg = inputs(wl, mg.COEF_QUAD)
     R = gather(wl, torch.float32, cg, mg.COEF_QUAD)

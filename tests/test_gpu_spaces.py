@@ -84,7 +84,7 @@ def test_every_lane_shape_bitwise(dim, phys, space, dtype):
             first = R.clone()
         assert torch.equal(R, first), f"lane shape {(vec, waves, bpc)}"
     coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
-    for ept, waves, bpc in [(1, 1, 8), (2, 2, 0), (1, 4, 2)]:
+    for ept, waves, bpc in [(1, 1, 8), (2, 2, 0), (1, 4, 2), (4, 4, 0)]:
         api.fem_set_tuning(dim, phys, wl.rule, dtype, strategy=N.STRATEGY_LANE, vec=ept, waves_per_block=waves,
                            blocks_per_cu=bpc, op=N.OP_RESIDUAL_MESH)
         ij2 = torch.full_like(ij, float("nan"))

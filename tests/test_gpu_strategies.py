@@ -188,7 +188,7 @@ def test_residual_mesh_bitwise_equals_two_calls(dim, phys, dtype, n_elem):
     R = api.fem_integrate_residual(dim, phys, wl.rule, ij, dj, u, cf)
     saved = _restore_op(N.OP_RESIDUAL_MESH, dim, phys, wl.rule, dtype)
     try:
-        for ept in (1, 2):
+        for ept in (1, 2, 4):
             for waves, bpc in ((1, 0), (4, 0), (2, 8)):
                 api.fem_set_tuning(dim, phys, wl.rule, dtype, vec=ept, waves_per_block=waves, blocks_per_cu=bpc,
                                    op=N.OP_RESIDUAL_MESH)
@@ -297,3 +297,52 @@ def test_entry_points_under_graph_capture():
         torch.cuda.synchronize()
         for a, b in zip((ij, dj, R1, R2, du, dc), eager):
             assert torch.equal(a, b), f"graph replay {rep} differs"
+
+
+def test_newer_entry_points_under_graph_capture():
+    """Gather form, assembly, restriction and the P2 residual and adjoint in
+    one captured graph: every replay equals the eager results."""
+    dtype = torch.float32
+    wl = small_workload(3, mg.ELASTICITY, 30000, seed=43)
+    p2 = mg.p2_inputs(wl, mg.RULE_TET11, mg.BASE_SEED + 77)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    uv, cf = dev(wl.u_vertex, dtype), dev(wl.coef, dtype)
+    cv = dev(mg.vertex_coefficients(wl, 5), dtype)
+    ij, dj = api.fem_geometry(coords, conn, dtype)
+    u2, cf2, w2 = dev(p2.u, dtype), dev(p2.coef, dtype), dev(p2.w, dtype)
+    plan = api.AssemblyPlan(conn, wl.n_vert)
+    R = torch.empty((12, wl.n_elem), dtype=dtype, device="cuda")
+    Rp = torch.empty_like(R)
+    F = torch.empty((wl.n_vert, 3), dtype=dtype, device="cuda")
+    C = torch.empty_like(R)
+    R2 = torch.empty_like(u2)
+    d2, dc2 = torch.empty_like(u2), torch.empty_like(cf2)
+
+    def work():
+        api.fem_integrate_residual_gather(3, mg.ELASTICITY, wl.rule, coords, conn, uv, cf, out=R)
+        api.fem_integrate_residual_gather(3, mg.ELASTICITY, wl.rule, coords, conn, uv, cv, out=Rp,
+                                          coef_space=mg.COEF_P1)
+        plan.assemble(R, 3, out=F)
+        api.fem_restrict(conn, F, out=C)
+        api.fem_integrate_residual_p2(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u2, cf2, out=R2)
+        api.fem_integrate_residual_p2_backward(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u2, cf2, w2, du=d2, dcoef=dc2)
+
+    outs = (R, Rp, F, C, R2, d2, dc2)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        work()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(outs, eager)):
+            assert torch.equal(a, b), f"graph replay {rep} differs in output {i}"
