@@ -69,12 +69,30 @@ def _need(t: torch.Tensor, name: str, dtype=None, shape=None):
     return t
 
 
+def _checked_counts(counts, check, device):
+    """The counter array to pass: the caller's, or a zeroed one when checking."""
+    if counts is None and check:
+        counts = torch.zeros(2, dtype=torch.int32, device=device)
+    return counts
+
+
+def _raise_if_degenerate(counts, base, what):
+    """Synchronizes on the counters and raises for degenerate elements
+    counted by this call (``base``: the count before it)."""
+    nd = int(counts[0]) - base
+    if nd:
+        raise N.FemError(N.FEM_ERR_DEGENERATE, f"{what}: {nd} degenerate element(s) (det J = 0, non-finite, "
+                                               f"or a vertex index out of range)")
+
+
 def fem_geometry(coords: torch.Tensor, conn: torch.Tensor, dtype=torch.float32, inv_j=None, det_j=None,
-                 counts=None):
+                 counts=None, *, check=False):
     """(inv_j [d*d, n], det_j [n]) from coords [n_vert, d] float64 and conn [n, d+1] int32.
 
     ``counts`` (int32 [2] on the GPU, added to) receives the number of
-    degenerate and of poorly shaped elements.
+    degenerate and of poorly shaped elements. ``check=True`` synchronizes
+    after the launch and raises FemError(FEM_ERR_DEGENERATE) if any element
+    is degenerate (the unchecked call never synchronizes).
     """
     _need(coords, "coords", torch.float64)
     dim = coords.shape[1]
@@ -88,10 +106,14 @@ def fem_geometry(coords: torch.Tensor, conn: torch.Tensor, dtype=torch.float32, 
         det_j = torch.empty((n,), dtype=dtype, device=coords.device)
     _need(inv_j, "inv_j", dtype, (dim * dim, n))
     _need(det_j, "det_j", dtype, (n,))
+    base = int(counts[0]) if (check and counts is not None) else 0
+    counts = _checked_counts(counts, check, coords.device)
     if counts is not None:
         _need(counts, "counts", torch.int32, (2,))
     N.check(N.lib().fem_geometry(dim, n, coords.shape[0], _ptr(coords), _ptr(conn), _DT[dtype], _ptr(inv_j),
                                  _ptr(det_j), _ptr(counts), _stream()), "fem_geometry")
+    if check:
+        _raise_if_degenerate(counts, base, "fem_geometry")
     return inv_j, det_j
 
 
@@ -123,7 +145,7 @@ def fem_integrate_residual(dim: int, physics: int, rule: int, inv_j, det_j, u, c
 
 
 def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn, u, coef, out=None,
-                                inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD):
+                                inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD, check=False):
     """Element residuals straight from coordinates and connectivity (geometry
     fused into the integration; bitwise equal to fem_geometry followed by
     fem_integrate_residual). Pass inv_j and det_j to also receive the geometry."""
@@ -146,17 +168,21 @@ def fem_integrate_residual_mesh(dim: int, physics: int, rule: int, coords, conn,
     if inv_j is not None:
         _need(inv_j, "inv_j", dtype, sij)
         _need(det_j, "det_j", dtype, sdj)
+    base = int(counts[0]) if (check and counts is not None) else 0
+    counts = _checked_counts(counts, check, u.device)
     if counts is not None:
         _need(counts, "counts", torch.int32, (2,))
     N.check(N.lib().fem_integrate_residual_mesh(dim, physics, rule, coef_space, _DT[dtype], n, coords.shape[0], _ptr(coords),
                                                 _ptr(conn), _ptr(u), _ptr(coef), _ptr(out), _ptr(inv_j),
                                                 _ptr(det_j), _ptr(counts), _stream()),
             "fem_integrate_residual_mesh")
+    if check:
+        _raise_if_degenerate(counts, base, "fem_integrate_residual_mesh")
     return out
 
 
 def fem_integrate_residual_gather(dim: int, physics: int, rule: int, coords, conn, u_vertex, coef, out=None,
-                                  inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD):
+                                  inv_j=None, det_j=None, counts=None, *, coef_space=N.COEF_QUAD, check=False):
     """Element residuals from the mesh with u given per vertex, u_vertex
     [n_vert, N_comp]; the closure is gathered in the kernel. A P1 coefficient
     is given per vertex too, [n_vert, N_coef]; point and cell coefficients
@@ -181,12 +207,16 @@ def fem_integrate_residual_gather(dim: int, physics: int, rule: int, coords, con
     if inv_j is not None:
         _need(inv_j, "inv_j", dtype, sij)
         _need(det_j, "det_j", dtype, sdj)
+    base = int(counts[0]) if (check and counts is not None) else 0
+    counts = _checked_counts(counts, check, u_vertex.device)
     if counts is not None:
         _need(counts, "counts", torch.int32, (2,))
     N.check(N.lib().fem_integrate_residual_gather(dim, physics, rule, coef_space, _DT[dtype], n, nv, _ptr(coords),
                                                   _ptr(conn), _ptr(u_vertex), _ptr(coef), _ptr(out), _ptr(inv_j),
                                                   _ptr(det_j), _ptr(counts), _stream()),
             "fem_integrate_residual_gather")
+    if check:
+        _raise_if_degenerate(counts, base, "fem_integrate_residual_gather")
     return out
 
 

@@ -310,3 +310,29 @@ def test_row_offsets_beyond_2_pow_31():
         assert torch.equal(Rm[:, sl], R_s), f"fused kernel block {blk}"
     ref, ref_abs, _, _ = oracle_reference(base, dtype)
     assert_close(R_s.cpu().numpy(), ref, ref_abs, dtype, "base block")
+
+
+def test_checked_calls_raise_on_degenerate_elements():
+    """check=True synchronizes and raises FEM_ERR_DEGENERATE for a mesh with
+    a collapsed element; the same calls unchecked return NaN for it."""
+    wl = small_workload(3, mg.LAPLACE, 500)
+    coords = wl.coords.copy()
+    conn = wl.conn.copy()
+    conn[10, 3] = conn[10, 0]                      # repeated vertex: det J = 0
+    X, C = dev(coords, torch.float64), dev(conn, torch.int32)
+    u, cf = dev(wl.u, torch.float32), dev(wl.coef, torch.float32)
+    with pytest.raises(N.FemError) as ei:
+        api.fem_geometry(X, C, torch.float32, check=True)
+    assert ei.value.status == N.FEM_ERR_DEGENERATE
+    with pytest.raises(N.FemError):
+        api.fem_integrate_residual_mesh(3, mg.LAPLACE, wl.rule, X, C, u, cf, check=True)
+    with pytest.raises(N.FemError):
+        api.fem_integrate_residual_gather(3, mg.LAPLACE, wl.rule, X, C, dev(wl.u_vertex, torch.float32), cf,
+                                          check=True)
+    ij, dj = api.fem_geometry(X, C, torch.float32)
+    assert torch.isnan(ij[:, 10]).all() and not torch.isnan(ij[:, 11]).any()
+    # a caller's counter that already holds counts: only this call's are checked
+    counts = torch.tensor([5, 0], dtype=torch.int32, device="cuda")
+    api.fem_geometry(dev(wl.coords, torch.float64), dev(wl.conn, torch.int32), torch.float32, counts=counts,
+                     check=True)
+    assert int(counts[0]) == 5
