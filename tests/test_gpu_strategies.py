@@ -346,3 +346,36 @@ def test_newer_entry_points_under_graph_capture():
         torch.cuda.synchronize()
         for i, (a, b) in enumerate(zip(outs, eager)):
             assert torch.equal(a, b), f"graph replay {rep} differs in output {i}"
+
+
+def test_batched_workload_full():
+    """The 64-mesh benchmark workload (about 8.9 M elements) through one
+    graph-replayed persistent launch in the benchmark's default shape:
+    every mesh against the oracle, and bit for bit against its single-mesh
+    lane-kernel result."""
+    dtype = torch.float32
+    wls = mg.batch_workloads()
+    meshes = []
+    for w in wls:
+        ij, dj = api.fem_geometry(dev(w.coords, torch.float64), dev(w.conn, torch.int32), dtype)
+        meshes.append(dict(dim=w.dim, physics=w.physics, rule=w.rule, inv_j=ij, det_j=dj, u=dev(w.u, dtype),
+                           coef=dev(w.coef, dtype), out=torch.full(w.u.shape, float("nan"), dtype=dtype,
+                                                                   device="cuda")))
+    assert sum(w.n_elem for w in wls) > 5_000_000
+    plan = api.BatchPlan(meshes)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.capture()
+        plan.replay()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, w in zip(meshes, wls):
+        single = api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                            m["coef"])
+        assert torch.equal(m["out"], single), w.name
+        ref, ref_abs, _, _ = oracle_reference(w, dtype)
+        mx, _ = assert_close(m["out"].cpu().numpy(), ref, ref_abs, dtype, w.name)
+        worst = max(worst, mx)
+    plan.close()
+    print(f"batched 64 meshes: worst scaled error {worst:.2e}", flush=True)
