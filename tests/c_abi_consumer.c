@@ -1,0 +1,185 @@
+/*
+ * c_abi_consumer.c -- a plain C program that uses libfemq through include/fem.h
+ * only (device memory from the HIP runtime API, no C++ and no Python), and
+ * checks it against the FP64 oracle library (test infrastructure).
+ *
+ * On a jittered 3D Kuhn grid with a variable coefficient at the quadrature
+ * points it checks, in FP64:
+ *   - fem_geometry then fem_integrate_residual against fem_oracle_residual
+ *     (max |dR| relative to max |R| <= 1e-12);
+ *   - fem_integrate_residual_mesh bit for bit against the two calls;
+ *   - fem_assemble against the element-order sum of the oracle's element
+ *     vectors (bit for bit: same values, same order, FP64);
+ *   - the error paths of a few calls (status codes, fem_last_error).
+ * Exit status 0 on success; messages on stderr.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "fem.h"
+
+/* oracle (liboracle.so) */
+int64_t fem_oracle_residual(int dim, int physics, int rule, int space, int64_t n_elem, int64_t n_vert,
+                            const double *coords, const int32_t *conn, const double *u, const double *coef,
+                            double *elem_vec);
+int fem_oracle_assemble(int dim, int n_comp, int64_t n_elem, int64_t n_vert, const int32_t *conn,
+                        const double *elem_vec, double *out);
+
+static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
+static double uniform(double lo, double hi) {
+    rng_state = rng_state * 6364136223846793005ull + 1442695040888963407ull;
+    return lo + (hi - lo) * (double)(rng_state >> 11) * (1.0 / 9007199254740992.0);
+}
+
+#define CHECK_HIP(x)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (x);                                                          \
+        if (e_ != hipSuccess) {                                                       \
+            fprintf(stderr, "HIP error %d at %s:%d\n", (int)e_, __FILE__, __LINE__);  \
+            return 2;                                                                 \
+        }                                                                             \
+    } while (0)
+
+#define CHECK_FEM(x)                                                                            \
+    do {                                                                                        \
+        fem_status s_ = (x);                                                                    \
+        if (s_ != FEM_OK) {                                                                     \
+            fprintf(stderr, "fem error %d (%s) at %s:%d\n", s_, fem_last_error(), __FILE__, __LINE__); \
+            return 3;                                                                           \
+        }                                                                                       \
+    } while (0)
+
+int main(void) {
+    const int nc = 6, m = nc + 1;                 /* cells per side, vertices per side */
+    const int64_t n_vert = (int64_t)m * m * m, n_elem = 6LL * nc * nc * nc;
+    const double h = 1.0 / nc;
+    double *X = malloc(sizeof(double) * 3 * n_vert);
+    int32_t *conn = malloc(sizeof(int32_t) * 4 * n_elem);
+    double *u = malloc(sizeof(double) * 4 * n_elem), *coef = malloc(sizeof(double) * 4 * n_elem);
+    double *R_ref = malloc(sizeof(double) * 4 * n_elem), *R = malloc(sizeof(double) * 4 * n_elem);
+    double *R_mesh = malloc(sizeof(double) * 4 * n_elem);
+    double *F_ref = malloc(sizeof(double) * n_vert), *F = malloc(sizeof(double) * n_vert);
+    double *u_vert = malloc(sizeof(double) * n_vert);
+    if (!X || !conn || !u || !coef || !R_ref || !R || !R_mesh || !F_ref || !F || !u_vert) return 4;
+
+    /* vertices: grid points, interior ones jittered by at most 0.2 h */
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < m; ++k) {
+                const int64_t v = ((int64_t)i * m + j) * m + k;
+                const int idx[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d) {
+                    const int interior = idx[0] > 0 && idx[0] < nc && idx[1] > 0 && idx[1] < nc && idx[2] > 0 &&
+                                         idx[2] < nc;
+                    X[3 * v + d] = h * idx[d] + (interior ? uniform(-0.2 * h, 0.2 * h) : 0.0);
+                }
+                u_vert[v] = uniform(-1.0, 1.0);
+            }
+    /* six Kuhn tetrahedra per cell along v000 -> v111, positively oriented */
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int64_t e = 0;
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j)
+            for (int k = 0; k < nc; ++k)
+                for (int t = 0; t < 6; ++t, ++e) {
+                    int c[3] = {i, j, k};
+                    int32_t vv[4];
+                    vv[0] = (int32_t)(((int64_t)c[0] * m + c[1]) * m + c[2]);
+                    for (int s = 0; s < 3; ++s) {
+                        c[perm[t][s]] += 1;
+                        vv[s + 1] = (int32_t)(((int64_t)c[0] * m + c[1]) * m + c[2]);
+                    }
+                    /* odd permutations have negative orientation: swap the last two */
+                    const int odd = (t == 1 || t == 2 || t == 5);
+                    if (odd) { int32_t tmp = vv[2]; vv[2] = vv[3]; vv[3] = tmp; }
+                    for (int b = 0; b < 4; ++b) {
+                        conn[4 * e + b] = vv[b];
+                        u[(int64_t)b * n_elem + e] = u_vert[vv[b]];
+                        coef[(int64_t)b * n_elem + e] = uniform(0.5, 2.0);
+                    }
+                }
+
+    /* oracle */
+    if (fem_oracle_residual(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, n_elem, n_vert, X, conn, u, coef, R_ref) != 0) {
+        fprintf(stderr, "oracle: degenerate elements or bad arguments\n");
+        return 5;
+    }
+    if (fem_oracle_assemble(3, 1, n_elem, n_vert, conn, R_ref, F_ref) != 0) return 5;
+
+    /* device buffers */
+    double *dX, *du, *dcoef, *dij, *ddj, *dR, *dRm, *dF;
+    int32_t *dconn, *dcounts;
+    CHECK_HIP(hipMalloc((void**)&dX, sizeof(double) * 3 * n_vert));
+    CHECK_HIP(hipMalloc((void**)&dconn, sizeof(int32_t) * 4 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&du, sizeof(double) * 4 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dcoef, sizeof(double) * 4 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dij, sizeof(double) * 9 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&ddj, sizeof(double) * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dR, sizeof(double) * 4 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dRm, sizeof(double) * 4 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dF, sizeof(double) * n_vert));
+    CHECK_HIP(hipMalloc((void**)&dcounts, sizeof(int32_t) * 2));
+    CHECK_HIP(hipMemcpy(dX, X, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice));
+    CHECK_HIP(hipMemcpy(dconn, conn, sizeof(int32_t) * 4 * n_elem, hipMemcpyHostToDevice));
+    CHECK_HIP(hipMemcpy(du, u, sizeof(double) * 4 * n_elem, hipMemcpyHostToDevice));
+    CHECK_HIP(hipMemcpy(dcoef, coef, sizeof(double) * 4 * n_elem, hipMemcpyHostToDevice));
+    CHECK_HIP(hipMemset(dcounts, 0, sizeof(int32_t) * 2));
+
+    hipStream_t stream;
+    CHECK_HIP(hipStreamCreate(&stream));
+    CHECK_FEM(fem_geometry(3, n_elem, n_vert, dX, dconn, FEM_F64, dij, ddj, dcounts, stream));
+    CHECK_FEM(fem_integrate_residual(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, FEM_F64, n_elem, dij, ddj, du,
+                                     dcoef, dR, stream));
+    CHECK_FEM(fem_integrate_residual_mesh(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, FEM_F64, n_elem, n_vert, dX,
+                                          dconn, du, dcoef, dRm, NULL, NULL, NULL, stream));
+    fem_assembly_plan *plan = NULL;
+    CHECK_FEM(fem_assembly_plan_create(3, n_elem, n_vert, dconn, stream, &plan));
+    CHECK_FEM(fem_assemble(plan, 1, FEM_F64, dR, dF, stream));
+    CHECK_HIP(hipStreamSynchronize(stream));
+
+    int32_t counts[2];
+    CHECK_HIP(hipMemcpy(counts, dcounts, sizeof counts, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(R, dR, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(R_mesh, dRm, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(F, dF, sizeof(double) * n_vert, hipMemcpyDeviceToHost));
+
+    int fails = 0;
+    if (counts[0] != 0) { fprintf(stderr, "unexpected degenerate elements: %d\n", counts[0]); ++fails; }
+    double dmax = 0.0, rmax = 0.0;
+    for (int64_t i = 0; i < 4 * n_elem; ++i) {
+        dmax = fmax(dmax, fabs(R[i] - R_ref[i]));
+        rmax = fmax(rmax, fabs(R_ref[i]));
+    }
+    if (!(dmax <= 1e-12 * rmax)) { fprintf(stderr, "residual vs oracle: %.3e relative\n", dmax / rmax); ++fails; }
+    if (memcmp(R, R_mesh, sizeof(double) * 4 * n_elem) != 0) { fprintf(stderr, "fused != two calls\n"); ++fails; }
+    /* assembly of the GPU element vectors vs the oracle's assembly of the
+     * same values: sum the GPU vectors with the oracle's routine */
+    if (fem_oracle_assemble(3, 1, n_elem, n_vert, conn, R, F_ref) != 0) return 5;
+    if (memcmp(F, F_ref, sizeof(double) * n_vert) != 0) { fprintf(stderr, "assembly differs from element-order sum\n"); ++fails; }
+
+    /* error paths */
+    if (fem_integrate_residual(3, FEM_LAPLACE, FEM_RULE_TRI3, FEM_COEF_QUAD, FEM_F64, n_elem, dij, ddj, du, dcoef,
+                               dR, stream) != FEM_ERR_UNSUPPORTED || strlen(fem_last_error()) == 0) {
+        fprintf(stderr, "expected FEM_ERR_UNSUPPORTED for a triangle rule in 3D\n");
+        ++fails;
+    }
+    if (fem_geometry(3, -1, n_vert, dX, dconn, FEM_F64, dij, ddj, NULL, stream) != FEM_ERR_INVALID_ARG) {
+        fprintf(stderr, "expected FEM_ERR_INVALID_ARG for a negative size\n");
+        ++fails;
+    }
+
+    fem_assembly_plan_destroy(plan);
+    CHECK_HIP(hipStreamDestroy(stream));
+    hipFree(dX); hipFree(dconn); hipFree(du); hipFree(dcoef); hipFree(dij); hipFree(ddj);
+    hipFree(dR); hipFree(dRm); hipFree(dF); hipFree(dcounts);
+    free(X); free(conn); free(u); free(coef); free(R_ref); free(R); free(R_mesh); free(F_ref); free(F); free(u_vert);
+    if (fails) return 1;
+    printf("c_abi_consumer: %lld elements, residual rel. error %.2e, fused and assembly bitwise: ok\n",
+           (long long)n_elem, dmax / rmax);
+    return 0;
+}
