@@ -1,6 +1,7 @@
 """The C ABI library without a GPU: it loads, exports every function the
 header declares, and rejects bad arguments before touching a device."""
 import ctypes
+import pathlib
 
 import pytest
 
@@ -225,3 +226,18 @@ def test_p2_validation(lib):
     t = N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0)
     assert lib.fem_set_tuning(N.OP_BACKWARD_P2, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
         == N.FEM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("std", ["c99", "c11"])
+def test_header_is_plain_c(tmp_path, std):
+    """include/fem.h compiles as ISO C with warnings as errors (no C++, no HIP headers)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_fem.c"
+    src.write_text('#include "fem.h"\nint main(void) { fem_tuning t = {0, 1, 2, 0}; (void)t; return FEM_OK; }\n')
+    inc = pathlib.Path(__file__).resolve().parents[1] / "include"
+    r = subprocess.run(["gcc", f"-std={std}", "-Wall", "-Wextra", "-pedantic", "-Werror", f"-I{inc}", "-fsyntax-only",
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
