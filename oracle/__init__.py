@@ -7,4 +7,5 @@ function here is pinned by tests/test_oracle_*.py.
 """
 from .oracle import (  # noqa: F401
     rule, geometry, integrate, integrate_abs, residual, backward, load, n_qpts, assemble, restrict, n_basis,
+    jacobian, jacobian_abs,
 )

@@ -59,6 +59,20 @@
  * result bounds every partial sum and is the scale of the rounding-error
  * measure used by the parity tests.
  *
+ * Element matrices: K_e = dR_e / du_e, the Jacobian of the bracket of
+ * Eq. (2) with respect to the closure. Differentiating the bracket gives, per
+ * quadrature point, the derivatives of the pointwise functions sandwiched
+ * between the tabulated basis values and physical gradients:
+ *
+ *   K[(b,c)][(b',c')] = sum_q w_q |det J| ( B_qb g0[c][c'] B_qb'
+ *                        + sum_{i,j} G_b,i(q) g3[c][i][c'][j] G_b',j(q) )
+ *
+ * with g0 = d f0 / d u and g3 = d f1 / d grad u (the mixed derivatives are
+ * zero for the three forms here): Laplacian g3 = kappa delta_ij; elasticity
+ * g3 = lambda delta_ci delta_c'j + mu (delta_cc' delta_ij + delta_cj
+ * delta_ic'); mass g0 = kappa. The matrix is written from this definition,
+ * not from the residual routine.
+ *
  * Assembly (Section 2: the global residual is the sum over elements of the
  * element vectors mapped back through the element restriction E_e, the
  * transpose of the closure): F[v][c] = sum over (e, b) with conn[e][b] = v of
@@ -69,7 +83,9 @@
  *   coords [n_vert][dim], conn [n_elem][dim+1] (0-based),
  *   inv_j [dim*dim][n] (row k*dim+i), det_j [n],
  *   u, w, elem_vec [N_b*N_comp][n] (row b*N_comp+c),
- *   coef [N_coef][N_w][n], N_w = N_q (points), N_b (P1) or 1 (P0).
+ *   coef [N_coef][N_w][n], N_w = N_q (points), N_b (P1) or 1 (P0),
+ *   elem_mat [N_bt*N_bt][n] (row r*N_bt + s, r = b*N_comp + c the test
+ *   function, s = b'*N_comp + c' the trial function).
  */
 #include <math.h>
 #include <stddef.h>
@@ -525,6 +541,109 @@ int fem_oracle_backward_p(int order, int dim, int physics, int rule, int space, 
                     dcoef[(int64_t)(m * nw + k) * n + e] = s;
                 }
         }
+    }
+    return 0;
+}
+
+/* Pointwise derivatives of the physics at one quadrature point from the
+ * coefficients cq[m] there: g0[c][c'] = d f0_c / d u_c' and
+ * g3[c][i][c'][j] = d f1_{c,i} / d (d u_c' / d x_j). In absmode the
+ * coefficients are already >= 0 and every term is added with its sign
+ * dropped. */
+static void or_physics_jac(int dim, int physics, const double *cq, double g0[OR_MAXC][OR_MAXC],
+                           double g3[OR_MAXC][OR_MAXD][OR_MAXC][OR_MAXD])
+{
+    memset(g0, 0, sizeof(double) * OR_MAXC * OR_MAXC);
+    memset(g3, 0, sizeof(double) * OR_MAXC * OR_MAXD * OR_MAXC * OR_MAXD);
+    if (physics == OR_LAPLACE) {
+        for (int i = 0; i < dim; ++i) g3[0][i][0][i] = cq[0];
+    } else if (physics == OR_ELASTICITY) {
+        /* f1_ci = lambda tr(eps) delta_ci + 2 mu eps_ci, eps_ci = (du_c/dx_i + du_i/dx_c) / 2 */
+        for (int c = 0; c < dim; ++c)
+            for (int i = 0; i < dim; ++i)
+                for (int cp = 0; cp < dim; ++cp)
+                    for (int j = 0; j < dim; ++j) {
+                        double v = 0.0;
+                        if (c == i && cp == j) v += cq[0];
+                        if (c == cp && i == j) v += cq[1];
+                        if (c == j && i == cp) v += cq[1];
+                        g3[c][i][cp][j] = v;
+                    }
+    } else { /* OR_MASS: f0 = kappa u */
+        g0[0][0] = cq[0];
+    }
+}
+
+/* Element matrix of one element; ij[k][i] = invJ, sdet = |det J|,
+ * cf[m][q] coefficients at the points. K[r][s] is overwritten. */
+static void or_element_jac(const or_tab *t, int physics, double ij[OR_MAXD][OR_MAXD], double sdet,
+                           double cf[OR_MAXCOEF][OR_MAXQ], double K[OR_MAXB * OR_MAXC][OR_MAXB * OR_MAXC],
+                           int absmode)
+{
+    int dim = t->dim, nb = t->nb;
+    int nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics), nbt = nb * nc;
+    for (int r = 0; r < nbt; ++r)
+        for (int s = 0; s < nbt; ++s) K[r][s] = 0.0;
+    for (int q = 0; q < t->nq; ++q) {
+        double G[OR_MAXB][OR_MAXD], Bq[OR_MAXB];
+        for (int b = 0; b < nb; ++b) {
+            Bq[b] = absmode ? fabs(t->B[q][b]) : t->B[q][b];
+            for (int i = 0; i < dim; ++i) {
+                double g = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double d = absmode ? fabs(t->D[q][b][k]) : t->D[q][b][k];
+                    g += ij[k][i] * d;
+                }
+                G[b][i] = g;
+            }
+        }
+        double cq[OR_MAXCOEF] = {0.0, 0.0};
+        for (int m = 0; m < ncoef; ++m) cq[m] = cf[m][q];
+        double g0[OR_MAXC][OR_MAXC], g3[OR_MAXC][OR_MAXD][OR_MAXC][OR_MAXD];
+        or_physics_jac(dim, physics, cq, g0, g3);
+        double s = (absmode ? fabs(t->w[q]) : t->w[q]) * sdet;
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c)
+                for (int bp = 0; bp < nb; ++bp)
+                    for (int cp = 0; cp < nc; ++cp) {
+                        double v = Bq[b] * g0[c][cp] * Bq[bp];
+                        for (int i = 0; i < dim; ++i)
+                            for (int j = 0; j < dim; ++j) v += G[b][i] * g3[c][i][cp][j] * G[bp][j];
+                        K[b * nc + c][bp * nc + cp] += s * v;
+                    }
+    }
+}
+
+/* Element matrices elem_mat [N_bt*N_bt][n] from precomputed geometry for
+ * Lagrange elements of the given order (1 or 2). Returns 0, or -1 on bad
+ * arguments. absmode != 0 gives the absolute-value bound. */
+int fem_oracle_jacobian_p(int order, int dim, int physics, int rule, int space, int64_t n_elem,
+                          const double *inv_j, const double *det_j, const double *coef, double *elem_mat,
+                          int absmode)
+{
+    or_tab t;
+    if (!or_physics_ok(physics) || n_elem < 0 || or_tabulate(dim, rule, order, &t) < 0) return -1;
+    int nb = t.nb, nc = or_ncomp(dim, physics), ncoef = or_ncoef(physics), nbt = nb * nc;
+    int nw = or_coef_words(space, dim, t.nq);
+    if (nw < 0) return -1;
+    int64_t n = n_elem;
+    for (int64_t e = 0; e < n; ++e) {
+        double ij[OR_MAXD][OR_MAXD], cf[OR_MAXCOEF][OR_MAXQ], a[OR_MAXCOEF][OR_MAXB + OR_MAXQ];
+        double K[OR_MAXB * OR_MAXC][OR_MAXB * OR_MAXC];
+        for (int k = 0; k < dim; ++k)
+            for (int i = 0; i < dim; ++i) {
+                double v = inv_j[(int64_t)(k * dim + i) * n + e];
+                ij[k][i] = absmode ? fabs(v) : v;
+            }
+        for (int m = 0; m < ncoef; ++m)
+            for (int k = 0; k < nw; ++k) {
+                double v = coef[(int64_t)(m * nw + k) * n + e];
+                a[m][k] = absmode ? fabs(v) : v;
+            }
+        or_coef_at_points(&t, space, ncoef, a, cf, absmode);
+        or_element_jac(&t, physics, ij, fabs(det_j[e]), cf, K, absmode);
+        for (int r = 0; r < nbt; ++r)
+            for (int s = 0; s < nbt; ++s) elem_mat[(int64_t)(r * nbt + s) * n + e] = K[r][s];
     }
     return 0;
 }

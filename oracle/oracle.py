@@ -45,6 +45,9 @@ def load():
         lib.fem_oracle_integrate_p.restype = ctypes.c_int
         lib.fem_oracle_backward_p.argtypes = [ctypes.c_int] + lib.fem_oracle_backward.argtypes
         lib.fem_oracle_backward_p.restype = ctypes.c_int
+        lib.fem_oracle_jacobian_p.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.fem_oracle_jacobian_p.restype = ctypes.c_int
         for name in ("fem_oracle_assemble", "fem_oracle_restrict"):
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _ip, _dp, _dp]
@@ -160,6 +163,30 @@ def backward(dim, physics, rule_id, inv_j, det_j, u, coef, w, want_du=True, want
     if r != 0:
         raise ValueError("oracle backward: bad arguments")
     return du, dcoef
+
+
+def _jacobian(dim, physics, rule_id, inv_j, det_j, coef, absmode, space, order):
+    inv_j, det_j, coef = _f64(inv_j), _f64(det_j), _f64(coef)
+    n = det_j.shape[0]
+    nbt = n_basis(dim, order) * _ncomp(dim, physics)
+    K = np.zeros((nbt * nbt, n))
+    r = load().fem_oracle_jacobian_p(order, dim, physics, rule_id, space, n, _p(inv_j), _p(det_j), _p(coef),
+                                     _p(K), int(absmode))
+    if r != 0:
+        raise ValueError("oracle jacobian: bad arguments")
+    return K
+
+
+def jacobian(dim, physics, rule_id, inv_j, det_j, coef, space=0, order=1):
+    """Element matrices K[N_bt*N_bt, n] = dR_e/du_e (row r*N_bt + s: test
+    function r = b*N_comp + c, trial function s), from the pointwise
+    derivatives of f0 and f1 (Section 2, Eq. (2) differentiated)."""
+    return _jacobian(dim, physics, rule_id, inv_j, det_j, coef, False, space, order)
+
+
+def jacobian_abs(dim, physics, rule_id, inv_j, det_j, coef, space=0, order=1):
+    """Same sums with |.| on every factor: the scale of the rounding measure."""
+    return _jacobian(dim, physics, rule_id, inv_j, det_j, coef, True, space, order)
 
 
 def assemble(dim, n_comp, n_vert, conn, elem_vec):
