@@ -108,7 +108,9 @@ enum fem_op {
     FEM_OP_BACKWARD = 3,       /* fem_integrate_residual_backward */
     FEM_OP_RESIDUAL_GATHER = 4, /* fem_integrate_residual_gather */
     FEM_OP_RESIDUAL_P2 = 5,     /* fem_integrate_residual_p2 */
-    FEM_OP_BACKWARD_P2 = 6      /* fem_integrate_residual_p2_backward */
+    FEM_OP_BACKWARD_P2 = 6,     /* fem_integrate_residual_p2_backward */
+    FEM_OP_JACOBIAN = 7,        /* fem_integrate_jacobian, order 1 */
+    FEM_OP_JACOBIAN_P2 = 8      /* fem_integrate_jacobian, order 2 */
 };
 
 /* ------------------------------------------------------------------ */
@@ -233,6 +235,35 @@ fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, in
                                               void* dcoef, void* stream);
 
 /* ------------------------------------------------------------------ */
+/* Element matrices: the Jacobian of the element residual with respect */
+/* to the closure (Eq. (2) of Section 2 differentiated in u).          */
+/* ------------------------------------------------------------------ */
+
+/* K_e = dR_e / du_e for P1 (order 1) or P2 (order 2) elements from
+ * precomputed affine geometry: per quadrature point, the derivatives of the
+ * pointwise functions, g0 = d f0 / d u and g3 = d f1 / d grad u, between the
+ * basis values and physical gradients,
+ *   K[(b,c)][(b',c')] = sum_q w_q |det J| ( phi_b g0[c][c'] phi_b'
+ *                       + sum_{i,j} G_b,i g3[c][i][c'][j] G_b',j ),
+ * Laplacian g3 = kappa delta_ij; elasticity g3 = lambda delta_ci delta_c'j
+ * + mu (delta_cc' delta_ij + delta_cj delta_ic'); mass g0 = kappa. The three
+ * forms are linear in u, so K_e u_e = R_e(u_e): the matrix is what the
+ * residual entry points apply without forming it.
+ *   inv_j [dim*dim][n], det_j [n], coef [N_coef][N_w][n] as for the
+ *   residual of the same order; elem_mat [N_bt*N_bt][n], N_bt = N_b*N_comp,
+ *   row r*N_bt + s for test function r = b*N_comp + c and trial function
+ *   s = b'*N_comp + c' (node order as fem_integrate_residual_p2 for P2).
+ * The matrices are symmetric and written so exactly (each entry below the
+ * diagonal is a copy of its mirror). Rules: order 1 takes FEM_RULE_TRI3 /
+ * FEM_RULE_TET4 or FEM_RULE_CENTROID; order 2 takes the degree-2 rule or
+ * FEM_RULE_TRI6 / FEM_RULE_TET11. Arrays are device memory owned by the
+ * caller; elem_mat may not overlap the inputs. Errors as
+ * fem_integrate_residual (FEM_ERR_UNSUPPORTED for another order or rule). */
+fem_status fem_integrate_jacobian(int dim, int physics, int rule, int coef_space, int order, int dtype,
+                                  int64_t n_elem, const void* inv_j, const void* det_j, const void* coef,
+                                  void* elem_mat, void* stream);
+
+/* ------------------------------------------------------------------ */
 /* Batched persistent launch over many meshes (not in the paper; its   */
 /* nearest analog is the assignment of cell chunks to thread blocks,   */
 /* Section 3).                                                          */
@@ -283,8 +314,9 @@ typedef struct fem_tuning {
                           * consecutive elements per vector access; GEOMETRY,
                           * RESIDUAL_MESH and RESIDUAL_GATHER (1, 2, 4) give each lane that
                           * many elements 64 apart, to overlap their dependent vertex
-                          * gathers; the P2 ops take 1 */
-    int waves_per_block; /* 1, 2, 4 or 8 (wave64; at most 4 for the P2 ops) */
+                          * gathers; the P2 and element-matrix ops take 1 */
+    int waves_per_block; /* 1, 2, 4 or 8 (wave64; at most 4 for the P2 and
+                          * element-matrix ops) */
     int blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs; 0 = one pass, no grid stride */
 } fem_tuning;
 

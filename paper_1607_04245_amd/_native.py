@@ -28,6 +28,7 @@ F32, F64 = 0, 1
 STRATEGY_LANE, STRATEGY_TRANSPOSE = 0, 1
 OP_RESIDUAL, OP_RESIDUAL_MESH, OP_GEOMETRY, OP_BACKWARD, OP_RESIDUAL_GATHER = 0, 1, 2, 3, 4
 OP_RESIDUAL_P2, OP_BACKWARD_P2 = 5, 6
+OP_JACOBIAN, OP_JACOBIAN_P2 = 7, 8
 COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
 
 
@@ -63,6 +64,7 @@ SIGNATURES = {
                                            _vp]),
     "fem_integrate_residual_p2": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_p2_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_jacobian": (_i, [_i, _i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),

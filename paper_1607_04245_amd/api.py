@@ -272,6 +272,29 @@ def fem_integrate_residual_p2(dim: int, physics: int, rule: int, inv_j, det_j, u
     return out
 
 
+def fem_integrate_jacobian(dim: int, physics: int, rule: int, inv_j, det_j, coef, out=None, *,
+                           coef_space=N.COEF_QUAD, order=1):
+    """Element matrices K = dR_e/du_e [N_bt*N_bt, n] (row r*N_bt + s: test
+    function r = b*N_comp + c, trial function s), for P1 (order 1) or P2
+    (order 2) elements from precomputed affine geometry. For these linear
+    forms K_e u_e is the element residual."""
+    dtype = det_j.dtype
+    if dtype not in _DT:
+        raise TypeError("geometry must be float32 or float64")
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space, order=order)
+    smat = (su[0] * su[0], n)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(coef, "coef", dtype, scf)
+    if out is None:
+        out = torch.empty(smat, dtype=dtype, device=det_j.device)
+    _need(out, "out", dtype, smat)
+    N.check(N.lib().fem_integrate_jacobian(dim, physics, rule, coef_space, order, _DT[dtype], n, _ptr(inv_j),
+                                           _ptr(det_j), _ptr(coef), _ptr(out), _stream()), "fem_integrate_jacobian")
+    return out
+
+
 def fem_integrate_residual_p2_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
                                        want_du=True, want_dcoef=True, du=None, dcoef=None, *, coef_space=N.COEF_QUAD):
     """(du, dcoef) of L = sum w.R for P2 elements (see fem_integrate_residual_p2)."""

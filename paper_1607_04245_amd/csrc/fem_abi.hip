@@ -77,6 +77,24 @@ static fem_status check_combo_p2(const char* fn, int dim, int phys, int rule, in
     return FEM_OK;
 }
 
+// Rules of the element-matrix entry point for each order.
+static bool valid_rule_jac(int dim, int order, int rule) {
+    const int low = dim == 2 ? FEM_RULE_TRI3 : FEM_RULE_TET4, high = dim == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
+    return rule == low || (order == 1 && rule == FEM_RULE_CENTROID) || (order == 2 && rule == high);
+}
+
+static fem_status check_combo_jac(const char* fn, int dim, int phys, int order, int rule, int dtype) {
+    if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
+    if (order != 1 && order != 2) { set_error("%s: order must be 1 or 2 (got %d)", fn, order); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_rule_jac(dim, order, rule)) {
+        set_error("%s: rule %d is not available for order %d in %dD", fn, rule, order, dim);
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+    return FEM_OK;
+}
+
 static fem_status check_combo(const char* fn, int dim, int phys, int rule, int dtype) {
     if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
     if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
@@ -93,7 +111,14 @@ static std::map<TuneKey, fem_tuning> g_tune;
 
 static bool valid_op(int op) {
     return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
-           op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
+           op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 ||
+           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
+}
+
+// Ops whose kernels take one element per lane and at most four waves per
+// workgroup (register-heavy elements).
+static bool one_per_lane_op(int op) {
+    return op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -110,7 +135,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
     if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 4, 4, 0};
-    if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
+    if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
     if (op == FEM_OP_RESIDUAL_MESH) {
         if (phys == FEM_LAPLACE && f32) return fem_tuning{FEM_STRATEGY_LANE, 1, 1, 8};
@@ -127,7 +152,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
 static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
-    const bool one = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
+    const bool one = one_per_lane_op(op);
     const bool vec_ok = one ? t.vec == 1 : (t.vec == 1 || t.vec == 2 || t.vec == 4);
     const bool waves_ok = t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
                           (t.waves_per_block == 8 && !one);
@@ -191,6 +216,8 @@ static fem_status check_tuning_args(const char* fn, int op, int dim, int physics
         return FEM_OK;
     }
     if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return check_combo_p2(fn, dim, physics, rule, dtype);
+    if (op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2)
+        return check_combo_jac(fn, dim, physics, op == FEM_OP_JACOBIAN ? 1 : 2, rule, dtype);
     return check_combo(fn, dim, physics, rule, dtype);
 }
 
@@ -363,6 +390,25 @@ fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, in
     Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
     hipError_t e = launch_backward_p2(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p2_backward launch");
+}
+
+fem_status fem_integrate_jacobian(int dim, int physics, int rule, int coef_space, int order, int dtype,
+                                  int64_t n_elem, const void* inv_j, const void* det_j, const void* coef,
+                                  void* elem_mat, void* stream) {
+    fem_status st = check_combo_jac("fem_integrate_jacobian", dim, physics, order, rule, dtype);
+    if (!st) st = check_space("fem_integrate_jacobian", coef_space);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_jacobian: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (!inv_j || !det_j || !coef || !elem_mat) {
+        set_error("fem_integrate_jacobian: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(order == 1 ? FEM_OP_JACOBIAN : FEM_OP_JACOBIAN_P2, dim, physics, rule, dtype);
+    JacobianArgs a{n_elem, inv_j, det_j, coef, elem_mat};
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_jacobian(dim, physics, order, rule, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_jacobian launch");
 }
 
 fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream) {

@@ -29,6 +29,14 @@ struct BackwardArgs {
     void* dcoef;
 };
 
+struct JacobianArgs {
+    int64_t n;
+    const void* inv_j;
+    const void* det_j;
+    const void* coef;
+    void* out;
+};
+
 struct MeshArgs {
     int64_t n;
     int64_t n_vert;
@@ -65,6 +73,9 @@ hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype,
                               const Launch& l);
 hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                               const Launch& l);
+// Element matrices (jacobian.hip); order 1 or 2.
+hipError_t launch_jacobian(int dim, int phys, int order, int rule, int space, int dtype, const JacobianArgs& a,
+                           const Launch& l);
 hipError_t launch_backward_lane(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                                 const Launch& l);
 hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, const double* coords,

@@ -227,9 +227,12 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         set_error("fem_autotune: n_elem_probe must be in [4096, 2^28]");
         return FEM_ERR_INVALID_ARG;
     }
-    const bool p2 = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2;
+    const bool jac = op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
+    const bool p2 = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN_P2;
+    const bool one = p2 || jac;  // one element per lane
     const int nc = physics == FEM_ELASTICITY ? dim : 1;
     const int nbt = (p2 ? (dim + 1) * (dim + 2) / 2 : dim + 1) * nc;
+    const int out_rows = jac ? nbt * nbt : nbt;
     const int nq = rule == FEM_RULE_CENTROID ? 1 : rule == FEM_RULE_TRI6 ? 6 : rule == FEM_RULE_TET11 ? 11 : dim + 1;
     const int ncq = (physics == FEM_ELASTICITY ? 2 : 1) * nq;
     const size_t word = dtype == FEM_F32 ? 4 : 8;
@@ -247,7 +250,7 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     }
     // one copy: geometry, u, coef, w, outputs, and for mesh ops the mesh
     struct Copy { void *ij, *dj, *u, *cf, *w, *out, *du, *dc; double* X; int32_t* conn; };
-    const size_t rows_words = (size_t)n * (dim * dim + 1 + 4 * nbt + 2 * ncq);
+    const size_t rows_words = (size_t)n * (dim * dim + 1 + 3 * nbt + out_rows + 2 * ncq);
     const size_t bytes_per_copy = rows_words * word + (mesh_op ? (size_t)n * 4 * (dim + 1) + (size_t)n_vert * 8 * dim : 0);
     const int copies = (int)std::min<size_t>(8, std::max<size_t>(2, (size_t)(768u << 20) / bytes_per_copy + 1));
     std::vector<void*> bufs;
@@ -267,7 +270,7 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         if ((e = alloc(&cp.u, (size_t)nbt * n * word)) != hipSuccess) break;
         if ((e = alloc(&cp.cf, (size_t)ncq * n * word)) != hipSuccess) break;
         if ((e = alloc(&cp.w, (size_t)nbt * n * word)) != hipSuccess) break;
-        if ((e = alloc(&cp.out, (size_t)nbt * n * word)) != hipSuccess) break;
+        if ((e = alloc(&cp.out, (size_t)out_rows * n * word)) != hipSuccess) break;
         if ((e = alloc(&cp.du, (size_t)nbt * n * word)) != hipSuccess) break;
         if ((e = alloc(&cp.dc, (size_t)ncq * n * word)) != hipSuccess) break;
         // well-conditioned synthetic geometry, values in the benchmark ranges
@@ -302,6 +305,10 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         case FEM_OP_BACKWARD_P2:
             return fem_integrate_residual_p2_backward(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf,
                                                       c.w, c.du, c.dc, nullptr);
+        case FEM_OP_JACOBIAN:
+        case FEM_OP_JACOBIAN_P2:
+            return fem_integrate_jacobian(dim, physics, rule, FEM_COEF_QUAD, op == FEM_OP_JACOBIAN ? 1 : 2, dtype, n, c.ij,
+                                          c.dj, c.cf, c.out, nullptr);
         case FEM_OP_RESIDUAL:
             return fem_integrate_residual(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);
         case FEM_OP_BACKWARD:
@@ -319,7 +326,7 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     };
 
     std::vector<fem_tuning> cands;
-    const std::vector<int> vecs = p2 ? std::vector<int>{1} : std::vector<int>{1, 2, 4};
+    const std::vector<int> vecs = one ? std::vector<int>{1} : std::vector<int>{1, 2, 4};
     for (int v : vecs)
         for (int w : {1, 2, 4, 8})
             for (int b : {0, 2, 4, 8, 16}) cands.push_back(fem_tuning{FEM_STRATEGY_LANE, v, w, b});

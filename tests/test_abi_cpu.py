@@ -123,7 +123,7 @@ def test_tuning_roundtrip(lib):
     assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_OK
     lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
-    assert lib.fem_set_tuning(7, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(9, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
 
 def test_batch_plan_validation(lib):
@@ -226,6 +226,37 @@ def test_p2_validation(lib):
     t = N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0)
     assert lib.fem_set_tuning(N.OP_BACKWARD_P2, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
         == N.FEM_ERR_INVALID_ARG
+
+
+def test_jacobian_validation(lib):
+    f = lib.fem_integrate_jacobian
+    # (dim, physics, rule, coef_space, order, dtype)
+    ok1 = (3, mg.ELASTICITY, mg.RULE_CENTROID, N.COEF_P1, 1, N.F64)
+    ok2 = (2, mg.MASS, mg.RULE_TRI6, N.COEF_P0, 2, N.F32)
+    for ok in (ok1, ok2):
+        assert f(*ok, 0, None, None, None, None, None) == N.FEM_OK
+        assert f(*ok, -1, _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+        for k in range(4):
+            arrs = [_v(), _v(), _v(), _v()]
+            arrs[k] = None
+            assert f(*ok, 5, *arrs, None) == N.FEM_ERR_INVALID_ARG, k
+    for bad in [(2, mg.LAPLACE, mg.RULE_TRI6, 0, 1, N.F32),       # degree-4 rule with order 1
+                (3, mg.LAPLACE, mg.RULE_CENTROID, 0, 2, N.F32),   # centroid with order 2
+                (2, mg.LAPLACE, mg.RULE_TET4, 0, 1, N.F32),       # tet rule in 2D
+                (3, mg.LAPLACE, mg.RULE_TET4, 0, 3, N.F32),       # order 3
+                (3, 9, mg.RULE_TET4, 0, 1, N.F32), (3, mg.LAPLACE, mg.RULE_TET4, 4, 1, N.F32),
+                (3, mg.LAPLACE, mg.RULE_TET4, 0, 1, 2), (4, mg.LAPLACE, mg.RULE_TET4, 0, 1, N.F32)]:
+        assert f(*bad, 5, _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+        assert N.last_error()
+    t = N.fem_tuning(N.STRATEGY_LANE, 1, 4, 2)
+    for op, rule in ((N.OP_JACOBIAN, mg.RULE_CENTROID), (N.OP_JACOBIAN_P2, mg.RULE_TET11)):
+        assert lib.fem_set_tuning(op, 3, mg.LAPLACE, rule, N.F32, ctypes.byref(t)) == N.FEM_OK
+        for bad_t in (N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0), N.fem_tuning(N.STRATEGY_LANE, 1, 8, 0)):
+            assert lib.fem_set_tuning(op, 3, mg.LAPLACE, rule, N.F32, ctypes.byref(bad_t)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_set_tuning(N.OP_JACOBIAN, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(N.OP_JACOBIAN_P2, 3, mg.LAPLACE, mg.RULE_CENTROID, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("std", ["c99", "c11"])
