@@ -446,6 +446,39 @@ def main():
                 del cps, ij, dj
             del p2, wlx
 
+        # ------------------------------------------------- element matrices --
+        for cfg, order, rule, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
+                                      ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",))):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            cf0 = mg.p2_inputs(wlx, rule, mg.BASE_SEED + 5000).coef
+            nbt = model.n_basis(wlx.dim, order) * wlx.n_comp
+            for tag in dts:
+                dt = torch.float32 if tag == "f32" else torch.float64
+                word = 4 if dt == torch.float32 else 8
+                nb = model.jacobian_bytes(wlx.dim, wlx.physics, rule, word, order=order) * wlx.n_elem
+                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                base = dict(ij=ij, dj=dj, cf=to_dev(cf0, dt))
+                cps = []
+                for _ in range(n_copies(nb)):
+                    c = {k: v.clone() for k, v in base.items()}
+                    c["K"] = torch.empty((nbt * nbt, wlx.n_elem), dtype=dt, device=dev)
+                    cps.append(c)
+                del base, ij, dj
+
+                def go(c, wlx=wlx, rule=rule, order=order):
+                    api.fem_integrate_jacobian(wlx.dim, wlx.physics, rule, c["ij"], c["dj"], c["cf"], out=c["K"],
+                                               order=order)
+                _, ms = timed_graph(go, cps, 10, 1)
+                us = ms * 1e3
+                extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
+                    n_elem=wlx.n_elem, rule=rule, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                    elements_per_s=wlx.n_elem / (us * 1e-6), bytes_per_elem=nb / wlx.n_elem,
+                    frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                log(f"{wlx.name} element matrices P{order} {tag}: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                    f"{nb / wlx.n_elem:.0f} B/elem, {nb / (us * 1e-6) / 1e9:.0f} GB/s)")
+                del cps
+            del cf0, wlx
+
         # --------------------------------------------------------- assembly --
         # global residual: element vectors summed onto vertices (deterministic gather)
         for cfg in (2, "3b"):

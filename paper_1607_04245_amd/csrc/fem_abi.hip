@@ -135,6 +135,10 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     fem_tuning t{FEM_STRATEGY_LANE, 1, 2, 0};
     const bool f32 = dtype == FEM_F32;
     if (op == FEM_OP_GEOMETRY) return fem_tuning{FEM_STRATEGY_LANE, 4, 4, 0};
+    if (op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2) {  // store-bound: more waves for the large matrices
+        if (phys == FEM_ELASTICITY) return fem_tuning{FEM_STRATEGY_LANE, 1, 4, 16};
+        return op == FEM_OP_JACOBIAN_P2 ? fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0} : fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
+    }
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
     if (op == FEM_OP_RESIDUAL_MESH) {

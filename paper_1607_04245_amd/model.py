@@ -128,6 +128,15 @@ def p2_model_flops(dim: int, physics: int, rule: int) -> int:
     return paper_flops_per_cell(dim, n_basis(dim, 2), n_comp(dim, physics), n_qpts(dim, rule))
 
 
+def jacobian_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0, order: int = 1) -> int:
+    """Compulsory bytes per element of fem_integrate_jacobian: the geometry
+    (det J only for the mass form, which has no gradients), the coefficient
+    words, and the N_bt^2 matrix entries written."""
+    nbt = n_basis(dim, order) * n_comp(dim, physics)
+    geo = 1 if physics == 2 else dim * dim + 1
+    return word * (geo + n_coef(physics) * n_coef_words(dim, rule, coef_space) + nbt * nbt)
+
+
 def p2_forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
     """Compulsory bytes per element of fem_integrate_residual_p2."""
     nbt = n_basis(dim, 2) * n_comp(dim, physics)
