@@ -10,6 +10,8 @@
  *   - fem_integrate_residual_mesh bit for bit against the two calls;
  *   - fem_assemble against the element-order sum of the oracle's element
  *     vectors (bit for bit: same values, same order, FP64);
+ *   - fem_integrate_jacobian (element matrices) against the oracle's
+ *     (max |dK| relative to max |K| <= 1e-12), and K_e u_e against R_e;
  *   - the error paths of a few calls (status codes, fem_last_error).
  * Exit status 0 on success; messages on stderr.
  */
@@ -29,6 +31,10 @@ int64_t fem_oracle_residual(int dim, int physics, int rule, int space, int64_t n
                             double *elem_vec);
 int fem_oracle_assemble(int dim, int n_comp, int64_t n_elem, int64_t n_vert, const int32_t *conn,
                         const double *elem_vec, double *out);
+int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const double *coords, const int32_t *conn,
+                            double *inv_j, double *det_j);
+int fem_oracle_jacobian_p(int order, int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
+                          const double *det_j, const double *coef, double *elem_mat, int absmode);
 
 static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
 static double uniform(double lo, double hi) {
@@ -65,7 +71,11 @@ int main(void) {
     double *R_mesh = malloc(sizeof(double) * 4 * n_elem);
     double *F_ref = malloc(sizeof(double) * n_vert), *F = malloc(sizeof(double) * n_vert);
     double *u_vert = malloc(sizeof(double) * n_vert);
-    if (!X || !conn || !u || !coef || !R_ref || !R || !R_mesh || !F_ref || !F || !u_vert) return 4;
+    double *K = malloc(sizeof(double) * 16 * n_elem), *K_ref = malloc(sizeof(double) * 16 * n_elem);
+    double *ij_ref = malloc(sizeof(double) * 9 * n_elem), *dj_ref = malloc(sizeof(double) * n_elem);
+    if (!X || !conn || !u || !coef || !R_ref || !R || !R_mesh || !F_ref || !F || !u_vert || !K || !K_ref || !ij_ref ||
+        !dj_ref)
+        return 4;
 
     /* vertices: grid points, interior ones jittered by at most 0.2 h */
     for (int i = 0; i < m; ++i)
@@ -110,9 +120,13 @@ int main(void) {
         return 5;
     }
     if (fem_oracle_assemble(3, 1, n_elem, n_vert, conn, R_ref, F_ref) != 0) return 5;
+    if (fem_oracle_geometry(3, n_elem, n_vert, X, conn, ij_ref, dj_ref) != 0) return 5;
+    if (fem_oracle_jacobian_p(1, 3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, n_elem, ij_ref, dj_ref, coef, K_ref,
+                              0) != 0)
+        return 5;
 
     /* device buffers */
-    double *dX, *du, *dcoef, *dij, *ddj, *dR, *dRm, *dF;
+    double *dX, *du, *dcoef, *dij, *ddj, *dR, *dRm, *dF, *dK;
     int32_t *dconn, *dcounts;
     CHECK_HIP(hipMalloc((void**)&dX, sizeof(double) * 3 * n_vert));
     CHECK_HIP(hipMalloc((void**)&dconn, sizeof(int32_t) * 4 * n_elem));
@@ -123,6 +137,7 @@ int main(void) {
     CHECK_HIP(hipMalloc((void**)&dR, sizeof(double) * 4 * n_elem));
     CHECK_HIP(hipMalloc((void**)&dRm, sizeof(double) * 4 * n_elem));
     CHECK_HIP(hipMalloc((void**)&dF, sizeof(double) * n_vert));
+    CHECK_HIP(hipMalloc((void**)&dK, sizeof(double) * 16 * n_elem));
     CHECK_HIP(hipMalloc((void**)&dcounts, sizeof(int32_t) * 2));
     CHECK_HIP(hipMemcpy(dX, X, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice));
     CHECK_HIP(hipMemcpy(dconn, conn, sizeof(int32_t) * 4 * n_elem, hipMemcpyHostToDevice));
@@ -140,6 +155,8 @@ int main(void) {
     fem_assembly_plan *plan = NULL;
     CHECK_FEM(fem_assembly_plan_create(3, n_elem, n_vert, dconn, stream, &plan));
     CHECK_FEM(fem_assemble(plan, 1, FEM_F64, dR, dF, stream));
+    CHECK_FEM(fem_integrate_jacobian(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, 1, FEM_F64, n_elem, dij, ddj, dcoef,
+                                     dK, stream));
     CHECK_HIP(hipStreamSynchronize(stream));
 
     int32_t counts[2];
@@ -147,6 +164,7 @@ int main(void) {
     CHECK_HIP(hipMemcpy(R, dR, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(R_mesh, dRm, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(F, dF, sizeof(double) * n_vert, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(K, dK, sizeof(double) * 16 * n_elem, hipMemcpyDeviceToHost));
 
     int fails = 0;
     if (counts[0] != 0) { fprintf(stderr, "unexpected degenerate elements: %d\n", counts[0]); ++fails; }
@@ -161,6 +179,20 @@ int main(void) {
      * same values: sum the GPU vectors with the oracle's routine */
     if (fem_oracle_assemble(3, 1, n_elem, n_vert, conn, R, F_ref) != 0) return 5;
     if (memcmp(F, F_ref, sizeof(double) * n_vert) != 0) { fprintf(stderr, "assembly differs from element-order sum\n"); ++fails; }
+    /* element matrices: against the oracle, and K_e u_e against R_e */
+    double kmax = 0.0, kref = 0.0, kumax = 0.0;
+    for (int64_t i = 0; i < 16 * n_elem; ++i) {
+        kmax = fmax(kmax, fabs(K[i] - K_ref[i]));
+        kref = fmax(kref, fabs(K_ref[i]));
+    }
+    for (int64_t e2 = 0; e2 < n_elem; ++e2)
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 4; ++c) s += K[(int64_t)(r * 4 + c) * n_elem + e2] * u[(int64_t)c * n_elem + e2];
+            kumax = fmax(kumax, fabs(s - R[(int64_t)r * n_elem + e2]));
+        }
+    if (!(kmax <= 1e-12 * kref)) { fprintf(stderr, "element matrices vs oracle: %.3e relative\n", kmax / kref); ++fails; }
+    if (!(kumax <= 1e-12 * rmax)) { fprintf(stderr, "K u vs R: %.3e relative\n", kumax / rmax); ++fails; }
 
     /* error paths */
     if (fem_integrate_residual(3, FEM_LAPLACE, FEM_RULE_TRI3, FEM_COEF_QUAD, FEM_F64, n_elem, dij, ddj, du, dcoef,
@@ -176,10 +208,11 @@ int main(void) {
     fem_assembly_plan_destroy(plan);
     CHECK_HIP(hipStreamDestroy(stream));
     hipFree(dX); hipFree(dconn); hipFree(du); hipFree(dcoef); hipFree(dij); hipFree(ddj);
-    hipFree(dR); hipFree(dRm); hipFree(dF); hipFree(dcounts);
+    hipFree(dR); hipFree(dRm); hipFree(dF); hipFree(dcounts); hipFree(dK);
     free(X); free(conn); free(u); free(coef); free(R_ref); free(R); free(R_mesh); free(F_ref); free(F); free(u_vert);
+    free(K); free(K_ref); free(ij_ref); free(dj_ref);
     if (fails) return 1;
-    printf("c_abi_consumer: %lld elements, residual rel. error %.2e, fused and assembly bitwise: ok\n",
-           (long long)n_elem, dmax / rmax);
+    printf("c_abi_consumer: %lld elements, residual rel. error %.2e, element matrices %.2e, fused and assembly "
+           "bitwise: ok\n", (long long)n_elem, dmax / rmax, kmax / kref);
     return 0;
 }

@@ -252,14 +252,18 @@ def test_residual_mesh_full_workloads(cfg):
         print(f"fused config {cfg} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
 
 
-@pytest.mark.parametrize("op", [N.OP_GEOMETRY, N.OP_RESIDUAL_MESH, N.OP_BACKWARD])
-def test_autotune_other_operations(op):
-    saved = api.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, op=op)
+@pytest.mark.parametrize("op,rule", [(N.OP_GEOMETRY, mg.RULE_TET4), (N.OP_RESIDUAL_MESH, mg.RULE_TET4),
+                                     (N.OP_BACKWARD, mg.RULE_TET4), (N.OP_JACOBIAN, mg.RULE_TET4),
+                                     (N.OP_JACOBIAN_P2, mg.RULE_TET11)])
+def test_autotune_other_operations(op, rule):
+    saved = api.fem_get_tuning(3, mg.LAPLACE, rule, torch.float32, op=op)
     try:
-        t = api.fem_autotune(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, 1 << 15, None, op=op)
+        t = api.fem_autotune(3, mg.LAPLACE, rule, torch.float32, 1 << 15, None, op=op)
         assert t["strategy"] == N.STRATEGY_LANE and t["waves_per_block"] in (1, 2, 4, 8)
+        if op in (N.OP_JACOBIAN, N.OP_JACOBIAN_P2):
+            assert t["vec"] == 1 and t["waves_per_block"] <= 4
     finally:
-        api.fem_set_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, op=op, **saved)
+        api.fem_set_tuning(3, mg.LAPLACE, rule, torch.float32, op=op, **saved)
 
 
 def test_entry_points_under_graph_capture():
@@ -300,8 +304,9 @@ def test_entry_points_under_graph_capture():
 
 
 def test_newer_entry_points_under_graph_capture():
-    """Gather form, assembly, restriction and the P2 residual and adjoint in
-    one captured graph: every replay equals the eager results."""
+    """Gather form, assembly, restriction, the P2 residual and adjoint, and
+    the element matrices in one captured graph: every replay equals the eager
+    results."""
     dtype = torch.float32
     wl = small_workload(3, mg.ELASTICITY, 30000, seed=43)
     p2 = mg.p2_inputs(wl, mg.RULE_TET11, mg.BASE_SEED + 77)
@@ -317,6 +322,8 @@ def test_newer_entry_points_under_graph_capture():
     C = torch.empty_like(R)
     R2 = torch.empty_like(u2)
     d2, dc2 = torch.empty_like(u2), torch.empty_like(cf2)
+    K1 = torch.empty((144, wl.n_elem), dtype=dtype, device="cuda")
+    K2 = torch.empty((900, wl.n_elem), dtype=dtype, device="cuda")
 
     def work():
         api.fem_integrate_residual_gather(3, mg.ELASTICITY, wl.rule, coords, conn, uv, cf, out=R)
@@ -326,8 +333,10 @@ def test_newer_entry_points_under_graph_capture():
         api.fem_restrict(conn, F, out=C)
         api.fem_integrate_residual_p2(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u2, cf2, out=R2)
         api.fem_integrate_residual_p2_backward(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u2, cf2, w2, du=d2, dcoef=dc2)
+        api.fem_integrate_jacobian(3, mg.ELASTICITY, wl.rule, ij, dj, cf, out=K1)
+        api.fem_integrate_jacobian(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, cf2, out=K2, order=2)
 
-    outs = (R, Rp, F, C, R2, d2, dc2)
+    outs = (R, Rp, F, C, R2, d2, dc2, K1, K2)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
