@@ -11,7 +11,7 @@ import oracle
 from paper_1607_04245_amd import api, meshgen as mg
 from paper_1607_04245_amd import _native as N
 
-from _parity import TOL, assert_close, dcoef_abs, dev, oracle_reference, rounded
+from _parity import TOL, assert_close, dcoef_abs, dev, measure, oracle_reference, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -184,9 +184,18 @@ def test_benchmark_workloads_full(cfg, dtype):
     launch configuration the benchmark uses."""
     wl = mg.config(cfg)
     R = run_forward(wl, dtype)
-    ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+    ref, ref_abs, ij, dj = oracle_reference(wl, dtype)
     mx, agg = assert_close(R, ref, ref_abs, dtype, f"config {cfg}")
-    print(f"config {cfg} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
+    # reports without a bar: the plain per-element ratio |dR_e| / |R_e| (ill-
+    # conditioned where R_e is near zero) and the scaled measure against the
+    # oracle on the unrounded FP64 inputs (input rounding included)
+    d = np.linalg.norm(np.asarray(R, dtype=np.float64) - ref, axis=0)
+    plain = d / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+    exact = oracle.integrate(wl.dim, wl.physics, wl.rule, ij, dj, wl.u, wl.coef)
+    mx_in, agg_in = measure(R, exact, ref_abs)
+    print(f"config {cfg} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}; plain ratio median "
+          f"{np.median(plain):.2e} p99.9 {np.quantile(plain, 0.999):.2e} max {plain.max():.2e}; "
+          f"unrounded inputs: scaled max {mx_in:.2e} aggregate {agg_in:.2e}", flush=True)
 
 
 # ---------------------------------------------------------------- backward --

@@ -18,6 +18,10 @@ LAP, EL, MASS = mg.LAPLACE, mg.ELASTICITY, mg.MASS
 TRI3, TET4, CEN = mg.RULE_TRI3, mg.RULE_TET4, mg.RULE_CENTROID
 
 
+def default_rule(dim):
+    return TRI3 if dim == 2 else TET4
+
+
 # ---------------------------------------------------------------- helpers ---
 
 def random_simplices(dim, n, rng, scale=1.0):
@@ -410,6 +414,23 @@ def test_elasticity_rigid_motions(dim):
     S = np.eye(dim) * 0.1
     u2 = np.einsum("ij,nbj->nbi", S, x).reshape(n, -1).T
     assert np.abs(oracle.integrate(dim, EL, rule, ij, dj, u2, coef)).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim,phys", [(2, LAP), (3, LAP), (2, EL), (3, EL), (2, MASS), (3, MASS)])
+def test_uniform_scaling(dim, phys):
+    """Scaling an element by h (same nodal values and coefficients): the
+    stiffness forms scale like h^(d-2) (the 2D Laplacian is scale-invariant),
+    the mass form like h^d; translation changes nothing."""
+    rng = np.random.default_rng(40 + dim + 3 * phys)
+    x = random_simplices(dim, 25, rng)
+    ij, dj, u, coef = element_arrays(dim, phys, default_rule(dim), x, rng)
+    R = oracle.integrate(dim, phys, default_rule(dim), ij, dj, u, coef)
+    power = dim if phys == MASS else dim - 2
+    for h in (0.25, 3.0):
+        xs = x * h + rng.normal(size=dim)
+        ij2, dj2, _, _ = element_arrays(dim, phys, default_rule(dim), xs, rng, coef=coef, u=u)
+        R2 = oracle.integrate(dim, phys, default_rule(dim), ij2, dj2, u, coef)
+        assert np.allclose(R2, h ** power * R, rtol=1e-11, atol=1e-13 * np.abs(R).max() * max(1.0, h ** power))
 
 
 @pytest.mark.parametrize("dim,phys", [(2, LAP), (3, LAP), (2, EL), (3, EL), (2, MASS), (3, MASS)])
