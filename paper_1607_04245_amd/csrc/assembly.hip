@@ -14,6 +14,11 @@
 // atomics (which also finds indices outside [0, n_vert)), an exclusive scan
 // for the row offsets, and a stable radix sort of the slot numbers keyed by
 // vertex, which leaves every row in increasing slot, hence element, order.
+// The rows are then stored sliced: for each group of 64 consecutive vertices
+// (one wave), slot j of all 64 rows is contiguous, and every row of the group
+// is padded with an empty marker to the group's longest row. A wave's j-th
+// slot load is then one contiguous 256-byte access instead of 64 accesses
+// one row apart; each vertex still sees its own slots in element order.
 //
 // The restriction (closure) kernel is the adjoint: one lane per element
 // copies the vertex values of its d+1 vertices into the SoA closure rows.
@@ -30,11 +35,16 @@ struct fem_assembly_plan {
     int device = 0;
     int64_t n_elem = 0;
     int64_t n_vert = 0;
-    int32_t* row_ptr = nullptr;  // [n_vert + 1]
-    uint32_t* slots = nullptr;   // [n_elem * (dim + 1)], slot = e * (dim + 1) + b
+    int64_t n_groups = 0;          // ceil(n_vert / 64)
+    int64_t* grp_off = nullptr;    // [n_groups + 1], first entry of each group in `sell`
+    int32_t* grp_width = nullptr;  // [n_groups], slots per row in the group (its longest row)
+    uint32_t* sell = nullptr;      // [grp_off[n_groups]]: group g, slot j, lane l at grp_off[g] + 64 j + l;
+                                   // slot = e * (dim + 1) + b, or kNoSlot past the row's end
 };
 
 namespace femq {
+
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 // Slots per vertex, bad indices, and the identity slot numbering.
 __global__ void __launch_bounds__(256)
@@ -53,41 +63,81 @@ assembly_count_kernel(int64_t m, int64_t n_vert, const int32_t* __restrict__ con
     if (nbad) atomicAdd(bad, nbad);
 }
 
-// One lane per vertex: vertex_vec[v][c] = sum over the vertex's slots, in
-// slot order, of elem_vec[b * NC + c][e]. The row is walked in chunks of CH
-// slots whose loads are all issued before the first add (indices past the
-// row's end are clamped to its first slot and their adds skipped), so a lane
-// waits about once per chunk instead of once per slot; the adds stay in slot
-// order.
+// Group widths: the longest row among each group's 64 vertices (vertices
+// past n_vert count as empty rows), and the padded size of the group.
+__global__ void __launch_bounds__(256)
+assembly_width_kernel(int64_t n_groups, int64_t n_vert, const int32_t* __restrict__ row_ptr,
+                      int32_t* __restrict__ width, int64_t* __restrict__ size) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
+        const int64_t v0 = g * 64, v1 = v0 + 64 < n_vert ? v0 + 64 : n_vert;
+        int32_t w = 0;
+        for (int64_t v = v0; v < v1; ++v) w = max(w, row_ptr[v + 1] - row_ptr[v]);
+        width[g] = w;
+        size[g] = (int64_t)w * 64;
+    }
+}
+
+// Sliced storage: entry (g, j, l) = slot j of vertex 64 g + l, or kNoSlot.
+__global__ void __launch_bounds__(256)
+assembly_slice_kernel(int64_t n_groups, int64_t n_vert, const int32_t* __restrict__ row_ptr,
+                      const uint32_t* __restrict__ slots, const int32_t* __restrict__ width,
+                      const int64_t* __restrict__ off, uint32_t* __restrict__ sell) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_groups * 64; i += stride) {
+        const int64_t g = i / 64, v = i;
+        const int l = (int)(i % 64);
+        const int32_t s0 = v < n_vert ? row_ptr[v] : 0, len = v < n_vert ? row_ptr[v + 1] - s0 : 0;
+        const int32_t w = width[g];
+        uint32_t* dst = sell + off[g] + l;
+        for (int32_t j = 0; j < w; ++j) dst[(int64_t)j * 64] = j < len ? slots[s0 + j] : kNoSlot;
+    }
+}
+
+// One wave per group of 64 vertices, one lane per vertex: vertex_vec[v][c] =
+// sum over the vertex's slots, in slot order, of elem_vec[b * NC + c][e]. The
+// rows are walked in chunks of CH slots whose loads are all issued before the
+// first add (empty entries read a valid slot and their adds are skipped), so
+// a lane waits about once per chunk instead of once per slot; the adds stay
+// in slot order.
 template <int NB, int NC, typename Real>
 __global__ void __launch_bounds__(256)
-assemble_kernel(int64_t n_vert, int64_t n_elem, const int32_t* __restrict__ row_ptr,
-                const uint32_t* __restrict__ slots, const Real* __restrict__ R, Real* __restrict__ out) {
+assemble_kernel(int64_t n_vert, int64_t n_elem, int64_t n_groups, const int64_t* __restrict__ grp_off,
+                const int32_t* __restrict__ grp_width, const uint32_t* __restrict__ sell,
+                const Real* __restrict__ R, Real* __restrict__ out) {
     constexpr int CH = 8;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_vert; v += stride) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    for (int64_t g = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + (threadIdx.x >> 6))); g < n_groups;
+         g += n_waves) {
         Real acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = Real(0);
-        const int32_t s0 = row_ptr[v], s1 = row_ptr[v + 1];
-        for (int32_t s = s0; s < s1; s += CH) {
+        const uint32_t* row = sell + grp_off[g] + lane;
+        const int32_t w = grp_width[g];
+        for (int32_t s = 0; s < w; s += CH) {
             uint32_t sl[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) sl[j] = slots[s + j < s1 ? s + j : s0];
+            for (int j = 0; j < CH; ++j) sl[j] = s + j < w ? row[(int64_t)(s + j) * 64] : kNoSlot;
             Real r[CH][NC];
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
-                const uint32_t e = sl[j] / NB, b = sl[j] - e * NB;
+                const uint32_t sj = sl[j] != kNoSlot ? sl[j] : 0u;
+                const uint32_t e = sj / NB, b = sj - e * NB;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) r[j][c] = R[(int64_t)(b * NC + c) * n_elem + e];
             }
 #pragma unroll
             for (int j = 0; j < CH; ++j)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] = s + j < s1 ? acc[c] + r[j][c] : acc[c];
+                for (int c = 0; c < NC; ++c) acc[c] = sl[j] != kNoSlot ? acc[c] + r[j][c] : acc[c];
         }
+        const int64_t v = g * 64 + lane;
+        if (v < n_vert) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[v * NC + c] = acc[c];
+            for (int c = 0; c < NC; ++c) out[v * NC + c] = acc[c];
+        }
     }
 }
 
@@ -121,13 +171,13 @@ static int grid_for(int64_t items) {
 
 template <int NB, typename Real>
 static hipError_t launch_assemble_nc(int nc, const fem_assembly_plan* p, const void* R, void* out, hipStream_t s) {
-    const dim3 g(grid_for(p->n_vert)), b(256);
+    const dim3 g(grid_for(p->n_groups * 64)), b(256);
     const Real* r = static_cast<const Real*>(R);
     Real* o = static_cast<Real*>(out);
     switch (nc) {
-    case 1: hipLaunchKernelGGL((assemble_kernel<NB, 1, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->row_ptr, p->slots, r, o); break;
-    case 2: hipLaunchKernelGGL((assemble_kernel<NB, 2, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->row_ptr, p->slots, r, o); break;
-    case 3: hipLaunchKernelGGL((assemble_kernel<NB, 3, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->row_ptr, p->slots, r, o); break;
+    case 1: hipLaunchKernelGGL((assemble_kernel<NB, 1, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->n_groups, p->grp_off, p->grp_width, p->sell, r, o); break;
+    case 2: hipLaunchKernelGGL((assemble_kernel<NB, 2, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->n_groups, p->grp_off, p->grp_width, p->sell, r, o); break;
+    case 3: hipLaunchKernelGGL((assemble_kernel<NB, 3, Real>), g, b, 0, s, p->n_vert, p->n_elem, p->n_groups, p->grp_off, p->grp_width, p->sell, r, o); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -150,8 +200,9 @@ static hipError_t launch_restrict_nc(int nc, int64_t n_elem, int64_t n_vert, con
 
 static void plan_free(fem_assembly_plan* p) {
     if (!p) return;
-    if (p->row_ptr) (void)hipFree(p->row_ptr);
-    if (p->slots) (void)hipFree(p->slots);
+    if (p->grp_off) (void)hipFree(p->grp_off);
+    if (p->grp_width) (void)hipFree(p->grp_width);
+    if (p->sell) (void)hipFree(p->sell);
     delete p;
 }
 
@@ -182,40 +233,49 @@ fem_status fem_assembly_plan_create(int dim, int64_t n_elem, int64_t n_vert, con
     p->dim = dim;
     p->n_elem = n_elem;
     p->n_vert = n_vert;
+    p->n_groups = (n_vert + 63) / 64;
+    const int64_t ng = p->n_groups;
     hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess) e = hipMalloc(&p->row_ptr, (size_t)(n_vert + 1) * sizeof(int32_t));
-    if (e == hipSuccess && m > 0) e = hipMalloc(&p->slots, (size_t)m * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->grp_off, (size_t)(ng + 1) * sizeof(int64_t));
+    if (e == hipSuccess && ng > 0) e = hipMalloc(&p->grp_width, (size_t)ng * sizeof(int32_t));
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "fem_assembly_plan_create: hipMalloc"); }
-    if (m == 0) {
-        e = hipMemsetAsync(p->row_ptr, 0, (size_t)(n_vert + 1) * sizeof(int32_t), s);
+    if (m == 0) {  // no slots: every group has width 0
+        e = hipMemsetAsync(p->grp_off, 0, (size_t)(ng + 1) * sizeof(int64_t), s);
+        if (e == hipSuccess && ng > 0) e = hipMemsetAsync(p->grp_width, 0, (size_t)ng * sizeof(int32_t), s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { plan_free(p); return hip_fail(e, "fem_assembly_plan_create"); }
         *out = p;
         return FEM_OK;
     }
 
-    // scratch: counts (+ bad counter), identity slots, sorted keys, cub temp
+    // scratch: counts (+ bad counter), compressed rows, identity slots, sorted
+    // keys and slots, group sizes, cub temp
     int32_t* count = nullptr;
+    int32_t* row_ptr = nullptr;
     uint32_t* ids = nullptr;
     uint32_t* keys_out = nullptr;
+    uint32_t* slots = nullptr;
+    int64_t* gsize = nullptr;
     void* temp = nullptr;
-    size_t scan_bytes = 0, sort_bytes = 0;
+    size_t scan_bytes = 0, sort_bytes = 0, gscan_bytes = 0;
     int end_bit = 1;
     while (end_bit < 32 && ((int64_t)1 << end_bit) < n_vert) ++end_bit;
     const uint32_t* keys_in = reinterpret_cast<const uint32_t*>(conn);  // valid indices are non-negative
     auto cleanup = [&]() {
-        if (count) (void)hipFree(count);
-        if (ids) (void)hipFree(ids);
-        if (keys_out) (void)hipFree(keys_out);
-        if (temp) (void)hipFree(temp);
+        for (void* q : {(void*)count, (void*)row_ptr, (void*)ids, (void*)keys_out, (void*)slots, (void*)gsize, temp})
+            if (q) (void)hipFree(q);
     };
     e = hipMalloc(&count, (size_t)(n_vert + 2) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&row_ptr, (size_t)(n_vert + 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&ids, (size_t)m * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&keys_out, (size_t)m * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, count, p->row_ptr, (int)(n_vert + 1), s);
+    if (e == hipSuccess) e = hipMalloc(&slots, (size_t)m * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&gsize, (size_t)(ng + 1) * sizeof(int64_t));
+    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, count, row_ptr, (int)(n_vert + 1), s);
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys_in, keys_out, ids, p->slots, (int)m, 0, end_bit, s);
-    if (e == hipSuccess) e = hipMalloc(&temp, std::max(scan_bytes, sort_bytes) + 16);
+        e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys_in, keys_out, ids, slots, (int)m, 0, end_bit, s);
+    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, gscan_bytes, gsize, p->grp_off, (int)(ng + 1), s);
+    if (e == hipSuccess) e = hipMalloc(&temp, std::max(std::max(scan_bytes, sort_bytes), gscan_bytes) + 16);
     if (e == hipSuccess) e = hipMemsetAsync(count, 0, (size_t)(n_vert + 2) * sizeof(int32_t), s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(assembly_count_kernel, dim3(grid_for(m)), dim3(256), 0, s, m, n_vert, conn, count, ids,
@@ -233,9 +293,26 @@ fem_status fem_assembly_plan_create(int dim, int64_t n_elem, int64_t n_vert, con
         return FEM_ERR_INVALID_ARG;
     }
     // count[n_vert] is zero, so row_ptr[n_vert] = m
-    e = hipcub::DeviceScan::ExclusiveSum(temp, scan_bytes, count, p->row_ptr, (int)(n_vert + 1), s);
+    e = hipcub::DeviceScan::ExclusiveSum(temp, scan_bytes, count, row_ptr, (int)(n_vert + 1), s);
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(temp, sort_bytes, keys_in, keys_out, ids, p->slots, (int)m, 0, end_bit, s);
+        e = hipcub::DeviceRadixSort::SortPairs(temp, sort_bytes, keys_in, keys_out, ids, slots, (int)m, 0, end_bit, s);
+    // group widths and offsets (gsize[ng] = 0, so grp_off[ng] is the total)
+    if (e == hipSuccess) e = hipMemsetAsync(gsize + ng, 0, sizeof(int64_t), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(assembly_width_kernel, dim3(grid_for(ng)), dim3(256), 0, s, ng, n_vert, row_ptr,
+                           p->grp_width, gsize);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(temp, gscan_bytes, gsize, p->grp_off, (int)(ng + 1), s);
+    int64_t total = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, p->grp_off + ng, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMalloc(&p->sell, (size_t)std::max<int64_t>(total, 1) * sizeof(uint32_t));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(assembly_slice_kernel, dim3(grid_for(ng * 64)), dim3(256), 0, s, ng, n_vert, row_ptr, slots,
+                           p->grp_width, p->grp_off, p->sell);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     cleanup();
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "fem_assembly_plan_create: index build"); }
