@@ -105,7 +105,9 @@ __global__ void __launch_bounds__(256)
 assemble_kernel(int64_t n_vert, int64_t n_elem, int64_t n_groups, const int64_t* __restrict__ grp_off,
                 const int32_t* __restrict__ grp_width, const uint32_t* __restrict__ sell,
                 const Real* __restrict__ R, Real* __restrict__ out) {
-    constexpr int CH = 8;
+    // chunk of slots in flight per lane: vertices of tetrahedral meshes lie in
+    // about 24 elements, of triangular meshes in about 6
+    constexpr int CH = NB == 4 ? 16 : 8;
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
