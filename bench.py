@@ -97,7 +97,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1607_04245_amd import api, meshgen as mg, model
+    from paper_1607_04245_amd import _native as N, api, meshgen as mg, model
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -376,6 +376,33 @@ def main():
                 f"{r2['elements_per_s']:.3e} el/s ({r2['paper_model_gflops']:.0f} GF/s)")
         del wlp, cfp
 
+        # ------------------------------------------ thread transposition --
+        # The paper's strategy (Section 3: quadrature-point-parallel work, an
+        # LDS transposition, basis-function-parallel work) against the default
+        # one-element-per-lane kernel, on the step mesh and the paper's 2D
+        # N_q = 1 case; best of the transposition's workgroup sizes.
+        wlq = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
+                               rule=mg.RULE_CENTROID)
+        for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
+            saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
+            lane = integrate_only(wlx, torch.float32)
+            best = None
+            for waves in (1, 2, 4, 8):
+                api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, strategy=N.STRATEGY_TRANSPOSE, vec=1,
+                                   waves_per_block=waves, blocks_per_cu=0)
+                try:
+                    r = integrate_only(wlx, torch.float32)
+                except N.FemError:  # workgroup too large for this element's LDS tile
+                    continue
+                if best is None or r["us"] < best[1]["us"]:
+                    best = (waves, r)
+            api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, **saved)
+            extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=best[1]["us"],
+                                              transpose_gbs=best[1]["gbs"], transpose_waves_per_block=best[0])
+            log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition "
+                f"{best[1]['us']:.1f} us ({best[1]['gbs']:.0f} GB/s, {best[0]} waves per workgroup)")
+        del wlq
+
         # ------------------------------------------------------ gather form --
         # u per vertex (and a P1 coefficient per vertex), gathered in the kernel.
         def gather_only(wlx, dt, space, reps=20):
@@ -437,12 +464,16 @@ def main():
                 _, ms = timed_graph(go, cps, 20, 1)
                 us = ms * 1e3
                 f = model.p2_model_flops(wlx.dim, wlx.physics, rule)
+                # a copy of the same bytes: how much of the kernel's time the
+                # stream itself needs, whatever unit does the arithmetic
+                cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 20)
                 extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
                     n_elem=wlx.n_elem, rule=rule, us=us, gbs=nb / (us * 1e-6) / 1e9,
                     elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
-                    bytes_per_elem=nb / wlx.n_elem)
+                    bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
                 log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
-                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)")
+                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
+                    f"copy of the same bytes {cp_us:.1f} us")
                 del cps, ij, dj
             del p2, wlx
 
