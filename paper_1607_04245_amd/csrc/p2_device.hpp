@@ -4,15 +4,19 @@
 //
 // Basis (node order: vertices v = 0..d, then edges (i, j), i < j,
 // lexicographic): phi_v = lam_v (2 lam_v - 1), phi_ij = 4 lam_i lam_j, with
-// lam_0 = 1 - sum xi, lam_k = xi_k, grad lam_0 = -1, grad lam_k = e_k. Hence
-// at a point
-//   grad_xi u = sum_v c_v grad lam_v,
-//   c_v = u_v (4 lam_v - 1) + 4 sum_{edges (v, j)} u_vj lam_j,
-// so the reference gradient is (c_1 - c_0, ..., c_d - c_0); and with
-// t_v = grad lam_v . fh (t_0 = -sum_k fh_k, t_k = fh_{k-1}) the basis phase
-// is r_v += (4 lam_v - 1) t_v, r_ij += 4 (lam_i t_j + lam_j t_i). No
-// multiplication by a tabulated zero is executed. The geometry is affine, as
-// for P1, and a P1 coefficient keeps its d+1 vertex values and the P1 basis.
+// lam_0 = 1 - sum xi, lam_k = xi_k. With g_v the physical gradients of the
+// barycentric coordinates (g_{k+1} = row k of J^{-1}, g_0 = -sum), the
+// gradient of a P2 field is affine in the barycentric coordinates:
+//   grad u(x) = sum_w lam_w(x) B_w,   B_w = sum_v (4 U_vw - u_v) g_v,
+// U_vv = u_v and U_vw = u on the edge (v, w); so B is formed once per element
+// and the gradient at a point costs d+1 multiply-adds per entry. The basis
+// phase is its transpose: with the weighted flux F_q = w_q |J| f1(x_q) and
+// its moments M_w = sum_q lam_w(x_q) F_q (and M = sum_w M_w = sum_q F_q),
+//   r_v = g_v . (4 M_v - M),   r_ij = 4 (g_i . M_j + g_j . M_i),
+// so each point only adds d+1 scaled copies of its flux. f0 and f1 are
+// still evaluated at every point; the f0 term is summed directly with the
+// basis values. The geometry is affine, as for P1, and a P1 coefficient
+// keeps its d+1 vertex values and the P1 basis.
 #pragma once
 
 #include "fem_device.hpp"
@@ -95,6 +99,12 @@ struct ElemP2 {
     __host__ __device__ static constexpr int ej(int k) {
         return DIM == 2 ? (k < 2 ? k + 1 : 2) : (k < 3 ? k + 1 : (k < 5 ? k - 1 : 3));
     }
+    // index of the edge joining vertices a != b
+    __host__ __device__ static constexpr int edge_of(int a, int b) {
+        return DIM == 2 ? ((a < b ? a : b) == 0 ? (a < b ? b : a) - 1 : 2)
+                        : ((a < b ? a : b) == 0 ? (a < b ? b : a) - 1
+                                                : ((a < b ? a : b) == 1 ? (a < b ? b : a) + 1 : 5));
+    }
 };
 
 // Coefficient m at point q from the element's words cf[m*NW + k].
@@ -114,94 +124,82 @@ __device__ __forceinline__ Real coef_at_p2(const Real* cf, int m, int q) {
     }
 }
 
-// Value and physical gradient of the field at point q: uq[c], g[c][i].
-template <int DIM, int PHYS, int RULE, int SPACE, typename Real>
-__device__ __forceinline__ void p2_field_at(int q, const Real* ij, const Real* u, Real (&uq)[ElemP2<DIM, PHYS, RULE, SPACE>::NC],
-                                            Real (&g)[ElemP2<DIM, PHYS, RULE, SPACE>::NC][DIM], bool need_value) {
-    using E = ElemP2<DIM, PHYS, RULE, SPACE>;
-    using Q = RuleP2<DIM, RULE>;
-    constexpr int NC = E::NC, NV = E::NV;
+// Physical gradients of the barycentric coordinates: g[k+1] = row k of
+// J^{-1}, g[0] = -(g[1] + ... + g[d]).
+template <int DIM, typename Real>
+__device__ __forceinline__ void p2_bary_grads(const Real* ij, Real (&g)[DIM + 1][DIM]) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        Real cv[NV];
+    for (int i = 0; i < DIM; ++i) {
+        Real s = ij[i];
+        g[1][i] = ij[i];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) cv[v] = Real(4.0 * Q::lam(q, v) - 1.0) * u[v * NC + c];
-#pragma unroll
-        for (int k = 0; k < E::NE; ++k) {
-            const Real ue = Real(4) * u[(NV + k) * NC + c];
-            const int i = E::ei(k), j = E::ej(k);
-            cv[i] = fmadd(Real(Q::lam(q, j)), ue, cv[i]);
-            cv[j] = fmadd(Real(Q::lam(q, i)), ue, cv[j]);
+        for (int k = 1; k < DIM; ++k) {
+            g[k + 1][i] = ij[k * DIM + i];
+            s += ij[k * DIM + i];
         }
-        Real gh[DIM];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) gh[k] = cv[k + 1] - cv[0];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-            Real s = gh[0] * ij[i];
-#pragma unroll
-            for (int k = 1; k < DIM; ++k) s = fmadd(gh[k], ij[k * DIM + i], s);
-            g[c][i] = s;
-        }
-        if (need_value) {
-            Real s = Real(Q::lam(q, 0) * (2.0 * Q::lam(q, 0) - 1.0)) * u[c];
-#pragma unroll
-            for (int v = 1; v < NV; ++v) s = fmadd(Real(Q::lam(q, v) * (2.0 * Q::lam(q, v) - 1.0)), u[v * NC + c], s);
-#pragma unroll
-            for (int k = 0; k < E::NE; ++k)
-                s = fmadd(Real(4.0 * Q::lam(q, E::ei(k)) * Q::lam(q, E::ej(k))), u[(NV + k) * NC + c], s);
-            uq[c] = s;
-        } else {
-            uq[c] = Real(0);
-        }
+        g[0][i] = -s;
     }
 }
 
-// Adds the weighted point contribution s*f0[c] phi_b + G_b . (s*f1[c]) to r.
+// Gradient coefficients of the field u[b*NC + c]: grad u_c(x) =
+// sum_w lam_w(x) B[c][w][i].
 template <int DIM, int PHYS, int RULE, int SPACE, typename Real>
-__device__ __forceinline__ void p2_basis_add(int q, const Real* ij, Real s, const Real (&f0)[ElemP2<DIM, PHYS, RULE, SPACE>::NC],
-                                             const Real (&f1)[ElemP2<DIM, PHYS, RULE, SPACE>::NC][DIM], bool has_f0,
-                                             bool has_f1, Real* r) {
+__device__ __forceinline__ void p2_grad_coeffs(const Real* u, const Real (&g)[DIM + 1][DIM],
+                                               Real (&B)[ElemP2<DIM, PHYS, RULE, SPACE>::NC][DIM + 1][DIM]) {
+    using E = ElemP2<DIM, PHYS, RULE, SPACE>;
+    constexpr int NC = E::NC, NV = E::NV;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+            Real d[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const Real U = v == w ? u[v * NC + c] : u[(NV + E::edge_of(v, w)) * NC + c];
+                d[v] = fmadd(Real(4), U, -u[v * NC + c]);
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                Real s = d[0] * g[0][i];
+#pragma unroll
+                for (int v = 1; v < NV; ++v) s = fmadd(d[v], g[v][i], s);
+                B[c][w][i] = s;
+            }
+        }
+}
+
+// Physical gradient at point q from the gradient coefficients.
+template <int DIM, int PHYS, int RULE, int SPACE, typename Real>
+__device__ __forceinline__ void p2_grad_at(int q, const Real (&B)[ElemP2<DIM, PHYS, RULE, SPACE>::NC][DIM + 1][DIM],
+                                           Real (&gq)[ElemP2<DIM, PHYS, RULE, SPACE>::NC][DIM]) {
+    using E = ElemP2<DIM, PHYS, RULE, SPACE>;
+    using Q = RuleP2<DIM, RULE>;
+#pragma unroll
+    for (int c = 0; c < E::NC; ++c)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            Real s = Real(Q::lam(q, 0)) * B[c][0][i];
+#pragma unroll
+            for (int w = 1; w < E::NV; ++w) s = fmadd(Real(Q::lam(q, w)), B[c][w][i], s);
+            gq[c][i] = s;
+        }
+}
+
+// Value of the field at point q: sum_b phi_b(x_q) u_b.
+template <int DIM, int PHYS, int RULE, int SPACE, typename Real>
+__device__ __forceinline__ void p2_value_at(int q, const Real* u, Real (&uq)[ElemP2<DIM, PHYS, RULE, SPACE>::NC]) {
     using E = ElemP2<DIM, PHYS, RULE, SPACE>;
     using Q = RuleP2<DIM, RULE>;
     constexpr int NC = E::NC, NV = E::NV;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (has_f1) {
-            // reference flux fh = J^{-1} (s f1)
-            Real fh[DIM];
+        Real s = Real(Q::lam(q, 0) * (2.0 * Q::lam(q, 0) - 1.0)) * u[c];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                Real t = ij[k * DIM] * f1[c][0];
+        for (int v = 1; v < NV; ++v) s = fmadd(Real(Q::lam(q, v) * (2.0 * Q::lam(q, v) - 1.0)), u[v * NC + c], s);
 #pragma unroll
-                for (int i = 1; i < DIM; ++i) t = fmadd(ij[k * DIM + i], f1[c][i], t);
-                fh[k] = s * t;
-            }
-            Real tv[NV];
-            Real sum = fh[0];
-#pragma unroll
-            for (int k = 1; k < DIM; ++k) sum += fh[k];
-            tv[0] = -sum;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) tv[k + 1] = fh[k];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) r[v * NC + c] = fmadd(Real(4.0 * Q::lam(q, v) - 1.0), tv[v], r[v * NC + c]);
-#pragma unroll
-            for (int k = 0; k < E::NE; ++k) {
-                const int i = E::ei(k), j = E::ej(k);
-                Real t = fmadd(Real(4.0 * Q::lam(q, i)), tv[j], r[(NV + k) * NC + c]);
-                r[(NV + k) * NC + c] = fmadd(Real(4.0 * Q::lam(q, j)), tv[i], t);
-            }
-        }
-        if (has_f0) {
-            const Real sf = s * f0[c];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                r[v * NC + c] = fmadd(Real(Q::lam(q, v) * (2.0 * Q::lam(q, v) - 1.0)), sf, r[v * NC + c]);
-#pragma unroll
-            for (int k = 0; k < E::NE; ++k)
-                r[(NV + k) * NC + c] = fmadd(Real(4.0 * Q::lam(q, E::ei(k)) * Q::lam(q, E::ej(k))), sf, r[(NV + k) * NC + c]);
-        }
+        for (int k = 0; k < E::NE; ++k)
+            s = fmadd(Real(4.0 * Q::lam(q, E::ei(k)) * Q::lam(q, E::ej(k))), u[(NV + k) * NC + c], s);
+        uq[c] = s;
     }
 }
 
@@ -212,20 +210,85 @@ __device__ __forceinline__ void element_residual_p2(const Real* ij, Real dj, con
     using E = ElemP2<DIM, PHYS, RULE, SPACE>;
     using Q = RuleP2<DIM, RULE>;
     using P = Physics<PHYS>;
-    constexpr int NC = E::NC;
+    constexpr int NC = E::NC, NV = E::NV;
 #pragma unroll
     for (int b = 0; b < E::NBT; ++b) r[b] = Real(0);
     const Real adj = fabs(dj);
+    Real g[NV][DIM];
+    p2_bary_grads<DIM, Real>(ij, g);
+    Real B[NC][NV][DIM];
+    if constexpr (P::HAS_F1) p2_grad_coeffs<DIM, PHYS, RULE, SPACE, Real>(u, g, B);
+    Real M[NC][NV][DIM];  // flux moments
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int w = 0; w < NV; ++w)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) M[c][w][i] = Real(0);
 #pragma unroll
     for (int q = 0; q < E::NQ; ++q) {
-        Real uq[NC], g[NC][DIM];
-        p2_field_at<DIM, PHYS, RULE, SPACE, Real>(q, ij, u, uq, g, P::NEEDS_U);
+        Real uq[NC], gq[NC][DIM];
+        if constexpr (P::NEEDS_U) p2_value_at<DIM, PHYS, RULE, SPACE, Real>(q, u, uq);
+        if constexpr (P::HAS_F1) p2_grad_at<DIM, PHYS, RULE, SPACE, Real>(q, B, gq);
         Real a[E::NCOEF];
 #pragma unroll
         for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at_p2<DIM, PHYS, RULE, SPACE, Real>(cf, m, q);
         Real f0[NC], f1[NC][DIM];
-        P::template point<DIM, Real>(uq, g, a, f0, f1);
-        p2_basis_add<DIM, PHYS, RULE, SPACE, Real>(q, ij, Real(Q::w(q)) * adj, f0, f1, P::HAS_F0, P::HAS_F1, r);
+        P::template point<DIM, Real>(uq, gq, a, f0, f1);
+        const Real s = Real(Q::w(q)) * adj;
+        if constexpr (P::HAS_F1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    const Real F = s * f1[c][i];
+#pragma unroll
+                    for (int w = 0; w < NV; ++w) M[c][w][i] = fmadd(Real(Q::lam(q, w)), F, M[c][w][i]);
+                }
+        }
+        if constexpr (P::HAS_F0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const Real sf = s * f0[c];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    r[v * NC + c] = fmadd(Real(Q::lam(q, v) * (2.0 * Q::lam(q, v) - 1.0)), sf, r[v * NC + c]);
+#pragma unroll
+                for (int k = 0; k < E::NE; ++k)
+                    r[(NV + k) * NC + c] =
+                        fmadd(Real(4.0 * Q::lam(q, E::ei(k)) * Q::lam(q, E::ej(k))), sf, r[(NV + k) * NC + c]);
+            }
+        }
+    }
+    if constexpr (P::HAS_F1) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Real Mt[DIM];  // sum over the points of the weighted flux
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                Real t = M[c][0][i];
+#pragma unroll
+                for (int w = 1; w < NV; ++w) t += M[c][w][i];
+                Mt[i] = t;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Real t = g[v][0] * fmadd(Real(4), M[c][v][0], -Mt[0]);
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) t = fmadd(g[v][i], fmadd(Real(4), M[c][v][i], -Mt[i]), t);
+                r[v * NC + c] += t;
+            }
+#pragma unroll
+            for (int k = 0; k < E::NE; ++k) {
+                const int a = E::ei(k), b = E::ej(k);
+                Real t = g[a][0] * M[c][b][0];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) t = fmadd(g[a][i], M[c][b][i], t);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) t = fmadd(g[b][i], M[c][a][i], t);
+                r[(NV + k) * NC + c] += Real(4) * t;
+            }
+        }
     }
 }
 
@@ -241,11 +304,23 @@ __device__ __forceinline__ void element_dcoef_p2(const Real* ij, Real dj, const 
 #pragma unroll
     for (int k = 0; k < E::NCQ; ++k) dcf[k] = Real(0);
     const Real adj = fabs(dj);
+    constexpr int NV = E::NV;
+    Real g[NV][DIM];
+    p2_bary_grads<DIM, Real>(ij, g);
+    Real Bu[NC][NV][DIM], Bw[NC][NV][DIM];
+    if constexpr (P::HAS_F1) {
+        p2_grad_coeffs<DIM, PHYS, RULE, SPACE, Real>(u, g, Bu);
+        p2_grad_coeffs<DIM, PHYS, RULE, SPACE, Real>(w, g, Bw);
+    }
 #pragma unroll
     for (int q = 0; q < E::NQ; ++q) {
         Real uq[NC], gu[NC][DIM], wq[NC], gw[NC][DIM];
-        p2_field_at<DIM, PHYS, RULE, SPACE, Real>(q, ij, u, uq, gu, P::NEEDS_U);
-        p2_field_at<DIM, PHYS, RULE, SPACE, Real>(q, ij, w, wq, gw, P::HAS_F0);
+        if constexpr (P::NEEDS_U) p2_value_at<DIM, PHYS, RULE, SPACE, Real>(q, u, uq);
+        if constexpr (P::HAS_F0) p2_value_at<DIM, PHYS, RULE, SPACE, Real>(q, w, wq);
+        if constexpr (P::HAS_F1) {
+            p2_grad_at<DIM, PHYS, RULE, SPACE, Real>(q, Bu, gu);
+            p2_grad_at<DIM, PHYS, RULE, SPACE, Real>(q, Bw, gw);
+        }
         const Real s = Real(Q::w(q)) * adj;
 #pragma unroll
         for (int m = 0; m < E::NCOEF; ++m) {
