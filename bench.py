@@ -443,12 +443,12 @@ def main():
             del wlx
 
         # ------------------------------------------------- second order (P2) --
-        for cfg, rule in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
+        for cfg, rule_p2 in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
             wlx = wl if cfg == 2 else mg.config(cfg)
-            p2 = mg.p2_inputs(wlx, rule, mg.BASE_SEED + 5000)
+            p2 = mg.p2_inputs(wlx, rule_p2, mg.BASE_SEED + 5000)
             for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
                 word = 4 if dt == torch.float32 else 8
-                nb = model.p2_forward_bytes(wlx.dim, wlx.physics, rule, word) * wlx.n_elem
+                nb = model.p2_forward_bytes(wlx.dim, wlx.physics, rule_p2, word) * wlx.n_elem
                 ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
                 base = dict(ij=ij, dj=dj, u=to_dev(p2.u, dt), cf=to_dev(p2.coef, dt))
                 cps = []
@@ -458,17 +458,17 @@ def main():
                     cps.append(c)
                 del base
 
-                def go(c, wlx=wlx, rule=rule):
-                    api.fem_integrate_residual_p2(wlx.dim, wlx.physics, rule, c["ij"], c["dj"], c["u"], c["cf"],
+                def go(c, wlx=wlx, rule_p2=rule_p2):
+                    api.fem_integrate_residual_p2(wlx.dim, wlx.physics, rule_p2, c["ij"], c["dj"], c["u"], c["cf"],
                                                   out=c["R"])
                 _, ms = timed_graph(go, cps, 20, 1)
                 us = ms * 1e3
-                f = model.p2_model_flops(wlx.dim, wlx.physics, rule)
+                f = model.p2_model_flops(wlx.dim, wlx.physics, rule_p2)
                 # a copy of the same bytes: how much of the kernel's time the
                 # stream itself needs, whatever unit does the arithmetic
                 cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 20)
                 extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
-                    n_elem=wlx.n_elem, rule=rule, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                    n_elem=wlx.n_elem, rule=rule_p2, us=us, gbs=nb / (us * 1e-6) / 1e9,
                     elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
                     bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
                 log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
@@ -478,15 +478,15 @@ def main():
             del p2, wlx
 
         # ------------------------------------------------- element matrices --
-        for cfg, order, rule, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
+        for cfg, order, rule_k, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
                                       ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",))):
             wlx = wl if cfg == 2 else mg.config(cfg)
-            cf0 = mg.p2_inputs(wlx, rule, mg.BASE_SEED + 5000).coef
+            cf0 = mg.p2_inputs(wlx, rule_k, mg.BASE_SEED + 5000).coef
             nbt = model.n_basis(wlx.dim, order) * wlx.n_comp
             for tag in dts:
                 dt = torch.float32 if tag == "f32" else torch.float64
                 word = 4 if dt == torch.float32 else 8
-                nb = model.jacobian_bytes(wlx.dim, wlx.physics, rule, word, order=order) * wlx.n_elem
+                nb = model.jacobian_bytes(wlx.dim, wlx.physics, rule_k, word, order=order) * wlx.n_elem
                 ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
                 base = dict(ij=ij, dj=dj, cf=to_dev(cf0, dt))
                 cps = []
@@ -496,13 +496,13 @@ def main():
                     cps.append(c)
                 del base, ij, dj
 
-                def go(c, wlx=wlx, rule=rule, order=order):
-                    api.fem_integrate_jacobian(wlx.dim, wlx.physics, rule, c["ij"], c["dj"], c["cf"], out=c["K"],
+                def go(c, wlx=wlx, rule_k=rule_k, order=order):
+                    api.fem_integrate_jacobian(wlx.dim, wlx.physics, rule_k, c["ij"], c["dj"], c["cf"], out=c["K"],
                                                order=order)
                 _, ms = timed_graph(go, cps, 10, 1)
                 us = ms * 1e3
                 extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
-                    n_elem=wlx.n_elem, rule=rule, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                    n_elem=wlx.n_elem, rule=rule_k, us=us, gbs=nb / (us * 1e-6) / 1e9,
                     elements_per_s=wlx.n_elem / (us * 1e-6), bytes_per_elem=nb / wlx.n_elem,
                     frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
                 log(f"{wlx.name} element matrices P{order} {tag}: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
@@ -531,6 +531,35 @@ def main():
                                                      elements_per_s=wlx.n_elem / (us * 1e-6))
             log(f"{wlx.name} f32 assembly: {us:.1f} us ({nb / (us * 1e-6) / 1e9:.0f} GB/s)")
             del cps, plan, conn_d, wlx
+
+        # ------------------------------------- forward and adjoint, one step --
+        # Every row of the path on the step workload: the fused residual
+        # (storing the geometry), then the adjoint (du and dcoef) of
+        # L = sum w . R from that geometry.
+        dt = torch.float32
+        nb_fb = (model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 4, store_geometry=True)
+                 + model.backward_bytes(dim, phys, rule, 4)) * n
+        base = dict(X=to_dev(wl.coords, torch.float64), conn=to_dev(wl.conn, torch.int32), u=to_dev(wl.u, dt),
+                    cf=to_dev(wl.coef, dt), w=to_dev(wl.w, dt))
+        cps = []
+        for _ in range(n_copies(nb_fb)):
+            c = {k: v.clone() for k, v in base.items()}
+            c["R"], c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["u"]), torch.empty_like(c["cf"])
+            c["ij"], c["dj"] = torch.empty((dim * dim, n), dtype=dt, device=dev), torch.empty(n, dtype=dt, device=dev)
+            cps.append(c)
+        del base
+
+        def fwd_bwd(c):
+            api.fem_integrate_residual_mesh(dim, phys, rule, c["X"], c["conn"], c["u"], c["cf"], out=c["R"],
+                                            inv_j=c["ij"], det_j=c["dj"])
+            api.fem_integrate_residual_backward(dim, phys, rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
+                                                du=c["du"], dcoef=c["dc"])
+        _, ms = timed_graph(fwd_bwd, cps, 20, 1)
+        extra["forward_and_adjoint_step_laplace3d_2p20_f32"] = dict(
+            us=ms * 1e3, elements_per_s=n / (ms * 1e-3), algorithmic_bytes=nb_fb, gbs=nb_fb / (ms * 1e-3) / 1e9)
+        log(f"forward (geometry stored) and adjoint, one step: {ms * 1e3:.1f} us ({n / (ms * 1e-3):.3e} elem/s, "
+            f"{nb_fb / (ms * 1e-3) / 1e9:.0f} GB/s)")
+        del cps
 
         # --------------------------------------------------------- adjoint --
         wl5 = mg.config(5)
