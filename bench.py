@@ -607,6 +607,7 @@ def main():
         plan = api.BatchPlan(meshes)
         side = torch.cuda.Stream()
         with torch.cuda.stream(side):
+            shape = plan.autotune()   # launch shape from the plan's own meshes
             plan.capture()
         torch.cuda.synchronize()
 
@@ -636,11 +637,11 @@ def main():
             separate_launches_us=sep_us, separate_launches_in_a_graph_us=sep_graph_ms * 1e3,
             persistent_launch_us=run_us, graph_replay_us=rep_us,
             graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
-            speedup_vs_separate=sep_us / rep_us,
+            speedup_vs_separate=sep_us / rep_us, autotuned_launch=shape,
             note="the meshes total about 0.9 GB, above the last-level cache; medians of 10")
         log(f"batched: 64 launches {sep_us:.1f} us ({sep_graph_ms * 1e3:.1f} us as one graph), persistent "
             f"{run_us:.1f} us, graph {rep_us:.1f} us "
-            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s)")
+            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s); autotuned launch {shape}")
         del meshes
         result["extra"] = extra
 

@@ -292,6 +292,13 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
  * workgroups per compute unit (0 = one workgroup per tile). Defaults 8 and 0.
  * Drops a recorded graph (capture again). Synchronizes the device. */
 fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, int blocks_per_cu);
+/* Sweep the launch shapes above (waves per workgroup 1, 2, 4, 8; workgroups
+ * per compute unit 0, 2, 4, 8, 16) on the plan's own meshes, timing a few
+ * launches of each with HIP events on `stream`, and keep the fastest (as
+ * fem_batch_plan_set_launch would; a recorded graph is dropped). The runs
+ * write every mesh's element vectors. The chosen shape is returned through
+ * the two pointers (either may be NULL). Synchronizes the device. */
+fem_status fem_batch_plan_autotune(fem_batch_plan* plan, void* stream, int* waves_per_block, int* blocks_per_cu);
 /* One persistent launch covering every mesh, on `stream`. */
 fem_status fem_batch_run(fem_batch_plan* plan, void* stream);
 /* Record the persistent launch into a HIP graph (captured on `stream`, which

@@ -68,6 +68,7 @@ SIGNATURES = {
     "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),
+    "fem_batch_plan_autotune": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "fem_batch_run": (_i, [_vp, _vp]),
     "fem_batch_capture": (_i, [_vp, _vp]),
     "fem_batch_replay": (_i, [_vp, _vp]),

@@ -395,6 +395,14 @@ class BatchPlan:
         N.check(N.lib().fem_batch_plan_set_launch(self._plan, waves_per_block, blocks_per_cu),
                 "fem_batch_plan_set_launch")
 
+    def autotune(self) -> dict:
+        """Time every launch shape on this plan's meshes (their element
+        vectors are written) and keep the fastest; returns it."""
+        w, b = ctypes.c_int(), ctypes.c_int()
+        N.check(N.lib().fem_batch_plan_autotune(self._plan, _stream(), ctypes.byref(w), ctypes.byref(b)),
+                "fem_batch_plan_autotune")
+        return dict(waves_per_block=w.value, blocks_per_cu=b.value)
+
     def run(self):
         N.check(N.lib().fem_batch_run(self._plan, _stream()), "fem_batch_run")
 

@@ -250,6 +250,50 @@ fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, 
     return plan_build_table(plan);
 }
 
+fem_status fem_batch_plan_autotune(fem_batch_plan* plan, void* stream, int* waves_out, int* bpc_out) {
+    if (!plan) { set_error("fem_batch_plan_autotune: NULL plan"); return FEM_ERR_INVALID_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return hip_fail(e, "fem_batch_plan_autotune: events");
+    }
+    int best_w = plan->waves_per_block, best_b = plan->blocks_per_cu;
+    float best_ms = 1e30f;
+    fem_status st = FEM_OK;
+    const int reps = 5;
+    for (int w : {1, 2, 4, 8}) {
+        for (int b : {0, 2, 4, 8, 16}) {
+            st = fem_batch_plan_set_launch(plan, w, b);
+            for (int r = 0; r < 2 && !st; ++r) st = plan_launch(plan, s);  // warm-up
+            if (!st) e = hipEventRecord(t0, s);
+            for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = plan_launch(plan, s);
+            if (!st && e == hipSuccess) e = hipEventRecord(t1, s);
+            if (!st && e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.0f;
+            if (!st && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (st || e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_w = w;
+                best_b = b;
+            }
+        }
+        if (st || e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "fem_batch_plan_autotune: timing");
+    if (st) return st;
+    st = fem_batch_plan_set_launch(plan, best_w, best_b);
+    if (st) return st;
+    if (waves_out) *waves_out = best_w;
+    if (bpc_out) *bpc_out = best_b;
+    return FEM_OK;
+}
+
 fem_status fem_batch_run(fem_batch_plan* plan, void* stream) {
     if (!plan) { set_error("fem_batch_run: NULL plan"); return FEM_ERR_INVALID_ARG; }
     return plan_launch(plan, static_cast<hipStream_t>(stream));

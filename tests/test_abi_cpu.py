@@ -228,6 +228,12 @@ def test_p2_validation(lib):
         == N.FEM_ERR_INVALID_ARG
 
 
+def test_batch_autotune_validation(lib):
+    w, b = ctypes.c_int(), ctypes.c_int()
+    assert lib.fem_batch_plan_autotune(None, None, ctypes.byref(w), ctypes.byref(b)) == N.FEM_ERR_INVALID_ARG
+    assert N.last_error()
+
+
 def test_jacobian_validation(lib):
     f = lib.fem_integrate_jacobian
     # (dim, physics, rule, coef_space, order, dtype)

@@ -133,6 +133,27 @@ def test_batch_graph_replays():
     plan.close()
 
 
+def test_batch_autotune_keeps_results():
+    """The batched plan's autotuner picks a valid launch shape; the results at
+    that shape equal the single-mesh calls bit for bit."""
+    dtype = torch.float32
+    meshes, wls = batch_meshes(dtype, [3000, 777, 12345, 64, 999, 40000])
+    for m in meshes:
+        api.fem_set_tuning(m["dim"], m["physics"], m["rule"], dtype, strategy=N.STRATEGY_LANE, vec=1)
+    singles = [api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                          m["coef"]) for m in meshes]
+    plan = api.BatchPlan(meshes)
+    t = plan.autotune()
+    assert t["waves_per_block"] in (1, 2, 4, 8) and t["blocks_per_cu"] in (0, 2, 4, 8, 16)
+    for m in meshes:
+        m["out"].fill_(float("nan"))
+    plan.run()
+    torch.cuda.synchronize()
+    for m, s in zip(meshes, singles):
+        assert torch.equal(m["out"], s)
+    plan.close()
+
+
 def test_batch_plan_argument_errors():
     dtype = torch.float32
     meshes, _ = batch_meshes(dtype, [100])
