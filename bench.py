@@ -442,6 +442,54 @@ def main():
                         f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
             del wlx
 
+        # ------------------------------------------------------- mesh plans --
+        # The from-mesh residual through a per-mesh plan of each tile's
+        # distinct vertices (built once, outside the timed region; its build
+        # time is reported), beside the unplanned fused and gather kernels.
+        for cfg in (2, "3a", "3b"):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            conn0 = to_dev(wlx.conn, torch.int32)
+            t0 = time.perf_counter()
+            plan0 = api.MeshPlan(conn0, wlx.n_vert)
+            build_s = time.perf_counter() - t0
+            info = plan0.info()
+            plan0.close()
+            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                word = 4 if dt == torch.float32 else 8
+                row = dict(n_elem=wlx.n_elem, plan_build_s=build_s, tile_vertices_per_elem=info["tile_vertices"] / wlx.n_elem)
+                for gather in (False, True):
+                    nb = model.planned_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert,
+                                             info["tile_vertices"], word, gather=gather) * wlx.n_elem
+                    base = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0,
+                                u=to_dev(wlx.u_vertex if gather else wlx.u, dt), cf=to_dev(wlx.coef, dt))
+                    cps = []
+                    for _ in range(n_copies(nb)):
+                        c = {k: v.clone() for k, v in base.items()}
+                        c["plan"] = api.MeshPlan(c["conn"], wlx.n_vert)
+                        c["R"] = torch.empty(wlx.u.shape, dtype=dt, device=dev)
+                        cps.append(c)
+                    del base
+
+                    def go(c, wlx=wlx, gather=gather):
+                        f = c["plan"].gather if gather else c["plan"].integrate
+                        f(wlx.physics, wlx.rule, c["X"], c["u"], c["cf"], out=c["R"])
+                    _, ms = timed_graph(go, cps, 20, 1)
+                    for c in cps:
+                        c["plan"].close()
+                    del cps
+                    unplanned = (gather_only(wlx, dt, mg.COEF_QUAD) if gather else fused_only(wlx, dt))["us"]
+                    form = "gather" if gather else "closure"
+                    row[f"{form}_us"] = ms * 1e3
+                    row[f"{form}_elements_per_s"] = wlx.n_elem / (ms * 1e-3)
+                    row[f"{form}_gbs"] = nb / (ms * 1e-3) / 1e9
+                    row[f"{form}_unplanned_us"] = unplanned
+                extra[f"{wlx.name}_{tag}_mesh_plan"] = row
+                log(f"{wlx.name} {tag} mesh plan (built in {build_s:.2f} s, "
+                    f"{row['tile_vertices_per_elem']:.2f} tile vertices per element): closure "
+                    f"{row['closure_us']:.1f} us (unplanned {row['closure_unplanned_us']:.1f}), gather "
+                    f"{row['gather_us']:.1f} us (unplanned {row['gather_unplanned_us']:.1f})")
+            del conn0, wlx
+
         # ------------------------------------------------- second order (P2) --
         for cfg, rule_p2 in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
             wlx = wl if cfg == 2 else mg.config(cfg)

@@ -235,6 +235,46 @@ fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, in
                                               void* dcoef, void* stream);
 
 /* ------------------------------------------------------------------ */
+/* Mesh plans: the fused from-mesh residual for meshes that are         */
+/* integrated many times (not in the paper; the paper's kernel reads    */
+/* precomputed geometry).                                               */
+/* ------------------------------------------------------------------ */
+
+/* A plan lists, for every tile of 64 consecutive elements, the tile's
+ * distinct vertices, and for every element the position of each of its
+ * vertices in that list (replacing the connectivity row). The planned
+ * entry points load each distinct vertex record of a tile once into LDS
+ * instead of once per element that uses it, and otherwise compute exactly
+ * what fem_integrate_residual_mesh / fem_integrate_residual_gather compute:
+ * the element vectors are bitwise equal to theirs.
+ *   conn [n_elem][dim+1] int32 device array; it is copied to the host once
+ *   (the plan is built there and uploaded) and not referenced afterwards.
+ * Every vertex index must lie in [0, n_vert) (else FEM_ERR_INVALID_ARG). The
+ * plan holds about 4 + 4 N_tile_vertices / 64 bytes per element of device
+ * memory and is bound to the device current at creation. Synchronizes
+ * `stream`. */
+typedef struct fem_mesh_plan fem_mesh_plan;
+fem_status fem_mesh_plan_create(int dim, int64_t n_elem, int64_t n_vert, const int32_t* conn, void* stream,
+                                fem_mesh_plan** out);
+/* Sizes of a plan; max_tile_vertices is the largest number of distinct
+ * vertices of one tile, tile_vertices their total over all tiles. Any
+ * pointer may be NULL. */
+fem_status fem_mesh_plan_info(const fem_mesh_plan* plan, int* dim, int64_t* n_elem, int64_t* n_vert,
+                              int* max_tile_vertices, int64_t* tile_vertices);
+void fem_mesh_plan_destroy(fem_mesh_plan* plan);
+/* fem_integrate_residual_mesh through a plan: coords [n_vert][dim] FP64, u
+ * and coef per element as there, elem_vec [N_bt][n_elem]; counts as there
+ * (may be NULL). The geometry is not written out. */
+fem_status fem_integrate_residual_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space,
+                                          int dtype, const double* coords, const void* u, const void* coef,
+                                          void* elem_vec, int32_t* counts, void* stream);
+/* fem_integrate_residual_gather through a plan: u_vertex [n_vert][N_comp],
+ * a P1 coefficient per vertex, point and cell coefficients per element. */
+fem_status fem_integrate_residual_gather_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space,
+                                                 int dtype, const double* coords, const void* u_vertex,
+                                                 const void* coef, void* elem_vec, int32_t* counts, void* stream);
+
+/* ------------------------------------------------------------------ */
 /* Element matrices: the Jacobian of the element residual with respect */
 /* to the closure (Eq. (2) of Section 2 differentiated in u).          */
 /* ------------------------------------------------------------------ */

@@ -446,6 +446,72 @@ def fem_restrict(conn, vertex_vec, out=None):
     return out
 
 
+class MeshPlan:
+    """Distinct vertices of every 64-element tile of a mesh
+    (fem_mesh_plan_create), for repeated from-mesh residuals. Building it
+    copies the connectivity to the host once and synchronizes the stream."""
+
+    def __init__(self, conn: torch.Tensor, n_vert: int):
+        _need(conn, "conn", torch.int32)
+        if conn.dim() != 2 or conn.shape[1] not in (3, 4):
+            raise ValueError("conn must be [n_elem, dim+1]")
+        self.dim, self.n_elem, self.n_vert = conn.shape[1] - 1, conn.shape[0], int(n_vert)
+        self._plan = ctypes.c_void_p()
+        N.check(N.lib().fem_mesh_plan_create(self.dim, self.n_elem, self.n_vert, _ptr(conn), _stream(),
+                                             ctypes.byref(self._plan)), "fem_mesh_plan_create")
+
+    def info(self) -> dict:
+        d, ne, nv, mx = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        tot = ctypes.c_int64()
+        N.check(N.lib().fem_mesh_plan_info(self._plan, ctypes.byref(d), ctypes.byref(ne), ctypes.byref(nv),
+                                           ctypes.byref(mx), ctypes.byref(tot)), "fem_mesh_plan_info")
+        return dict(dim=d.value, n_elem=ne.value, n_vert=nv.value, max_tile_vertices=mx.value,
+                    tile_vertices=tot.value)
+
+    def _run(self, fn, name, physics, rule, coords, u, coef, out, counts, coef_space, per_vertex):
+        dtype = u.dtype
+        if dtype not in _DT:
+            raise TypeError("u must be float32 or float64")
+        dim, n = self.dim, self.n_elem
+        _need(coords, "coords", torch.float64, (self.n_vert, dim))
+        sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space)
+        if per_vertex:
+            _need(u, "u_vertex", dtype, (self.n_vert, n_comp(dim, physics)))
+            _need(coef, "coef", dtype, (self.n_vert, n_coef(physics)) if coef_space == N.COEF_P1 else scf)
+        else:
+            _need(u, "u", dtype, su)
+            _need(coef, "coef", dtype, scf)
+        if out is None:
+            out = torch.empty(su, dtype=dtype, device=u.device)
+        _need(out, "out", dtype, su)
+        if counts is not None:
+            _need(counts, "counts", torch.int32, (2,))
+        N.check(fn(self._plan, physics, rule, coef_space, _DT[dtype], _ptr(coords), _ptr(u), _ptr(coef), _ptr(out),
+                   _ptr(counts), _stream()), name)
+        return out
+
+    def integrate(self, physics, rule, coords, u, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD):
+        """fem_integrate_residual_mesh through the plan (bitwise the same)."""
+        return self._run(N.lib().fem_integrate_residual_planned, "fem_integrate_residual_planned", physics, rule,
+                         coords, u, coef, out, counts, coef_space, False)
+
+    def gather(self, physics, rule, coords, u_vertex, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD):
+        """fem_integrate_residual_gather through the plan (bitwise the same)."""
+        return self._run(N.lib().fem_integrate_residual_gather_planned, "fem_integrate_residual_gather_planned",
+                         physics, rule, coords, u_vertex, coef, out, counts, coef_space, True)
+
+    def close(self):
+        if self._plan:
+            N.lib().fem_mesh_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class AssemblyPlan:
     """Vertex-to-slot index of a mesh for deterministic assembly
     (fem_assembly_plan_create). Building it synchronizes the current stream."""

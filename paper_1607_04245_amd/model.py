@@ -116,6 +116,17 @@ def residual_gather_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert
     return 4 * (dim + 1) + per_vertex * n_vert / max(n_elem, 1) + per_elem
 
 
+def planned_bytes(dim: int, physics: int, rule: int, n_elem: int, n_vert: int, tile_vertices: int, word: int,
+                  gather: bool = False, coef_space: int = 0) -> float:
+    """Compulsory bytes per element of the planned residuals: the packed
+    local indices (4 bytes) and the tiles' vertex lists in place of the
+    connectivity, otherwise as fem_integrate_residual_mesh (gather=False) or
+    fem_integrate_residual_gather (gather=True)."""
+    base = (residual_gather_bytes if gather else residual_mesh_bytes)(dim, physics, rule, n_elem, n_vert, word,
+                                                                        coef_space=coef_space)
+    return base - 4 * (dim + 1) + 4 + 4.0 * tile_vertices / max(n_elem, 1)
+
+
 def assemble_bytes(dim: int, n_comp_: int, n_elem: int, n_vert: int, word: int) -> float:
     """Compulsory bytes per element of fem_assemble: the slot index and the
     element vectors in, row offsets in and the vertex field out (amortised)."""

@@ -228,6 +228,20 @@ def test_p2_validation(lib):
         == N.FEM_ERR_INVALID_ARG
 
 
+def test_mesh_plan_validation(lib):
+    plan = ctypes.c_void_p()
+    assert lib.fem_mesh_plan_create(2, 10, 10, _v(), None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_mesh_plan_create(4, 10, 10, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_mesh_plan_create(3, -1, 10, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_mesh_plan_create(3, 10, 10, None, None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_mesh_plan_create(3, 10, 0, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
+    assert not plan.value
+    for f in (lib.fem_integrate_residual_planned, lib.fem_integrate_residual_gather_planned):
+        assert f(None, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, _v(), _v(), _v(), _v(), None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_mesh_plan_info(None, None, None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    lib.fem_mesh_plan_destroy(None)
+
+
 def test_batch_autotune_validation(lib):
     w, b = ctypes.c_int(), ctypes.c_int()
     assert lib.fem_batch_plan_autotune(None, None, ctypes.byref(w), ctypes.byref(b)) == N.FEM_ERR_INVALID_ARG

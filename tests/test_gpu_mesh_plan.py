@@ -1,0 +1,167 @@
+"""GPU tests of the mesh plan (fem_mesh_plan_*, the planned residuals): the
+planned kernels must give the element vectors of fem_integrate_residual_mesh
+and fem_integrate_residual_gather bit for bit, on structured, renumbered,
+disconnected and degenerate meshes, ragged tails and the full-size
+benchmark meshes; and the plan's sizes must match a count done here."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_04245_amd import api, meshgen as mg
+from paper_1607_04245_amd import _native as N
+
+from _parity import dev
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+KINDS = [(2, mg.LAPLACE), (3, mg.LAPLACE), (2, mg.ELASTICITY), (3, mg.ELASTICITY), (2, mg.MASS), (3, mg.MASS)]
+SPACES = [mg.COEF_QUAD, mg.COEF_P1, mg.COEF_P0]
+
+
+def workload(dim, phys, n_elem, rule=None, seed=81):
+    grid = mg.smallest_grid(dim, max(n_elem, 1))
+    return mg.make_workload(f"plan_{dim}{phys}", dim, phys, grid, n_elem, mg.BASE_SEED + seed, rule=rule)
+
+
+def same_bits(a, b):
+    """Bitwise equality, NaN payloads included."""
+    it = torch.int32 if a.dtype == torch.float32 else torch.int64
+    return a.shape == b.shape and torch.equal(a.view(it), b.view(it))
+
+
+def tile_counts(conn):
+    n = conn.shape[0]
+    return [np.unique(conn[t:t + 64]).size for t in range(0, n, 64)]
+
+
+def check_against_mesh(wl, conn, dtype, space, seed=3):
+    """Planned closure and gather forms against the unplanned ones."""
+    cf = mg.space_coefficients(wl, space, mg.BASE_SEED + 700 + seed)
+    cv = mg.vertex_coefficients(wl, mg.BASE_SEED + 700 + seed) if space == mg.COEF_P1 else cf
+    coords, conn_d = dev(wl.coords, torch.float64), dev(conn, torch.int32)
+    closure = mg.closure(conn, wl.u_vertex)
+    if space == mg.COEF_P1:
+        cf = np.ascontiguousarray(np.stack([mg.closure(conn, cv[:, m:m + 1]) for m in range(cv.shape[1])]))
+    u, c = dev(closure, dtype), dev(cf, dtype)
+    uv, cvd = dev(wl.u_vertex, dtype), dev(cv, dtype)
+    plan = api.MeshPlan(conn_d, wl.n_vert)
+    cnt_ref = torch.zeros(2, dtype=torch.int32, device="cuda")
+    cnt_pl = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ref = api.fem_integrate_residual_mesh(wl.dim, wl.physics, wl.rule, coords, conn_d, u, c, counts=cnt_ref,
+                                          coef_space=space)
+    got = plan.integrate(wl.physics, wl.rule, coords, u, c, counts=cnt_pl, coef_space=space)
+    assert same_bits(got, ref)
+    assert torch.equal(cnt_pl, cnt_ref)
+    ref_g = api.fem_integrate_residual_gather(wl.dim, wl.physics, wl.rule, coords, conn_d, uv, cvd, coef_space=space)
+    got_g = plan.gather(wl.physics, wl.rule, coords, uv, cvd, coef_space=space)
+    assert same_bits(got_g, ref_g)
+    info = plan.info()
+    counts = tile_counts(conn)
+    assert info["max_tile_vertices"] == max(counts) and info["tile_vertices"] == sum(counts)
+    plan.close()
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_planned_equals_unplanned(dim, phys, space, dtype):
+    rule = mg.default_rule(dim) if (dim + phys) % 2 else mg.RULE_CENTROID
+    wl = workload(dim, phys, 3001, rule=rule)
+    check_against_mesh(wl, wl.conn, dtype, space)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_renumbered_vertices(dim):
+    """Vertex numbers shuffled (an unstructured numbering): tiles touch
+    scattered vertices; results still equal the unplanned kernels."""
+    wl = workload(dim, mg.ELASTICITY, 5000, seed=83)
+    rng = np.random.default_rng(11)
+    perm = rng.permutation(wl.n_vert)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(wl.n_vert)
+    wl.coords = np.ascontiguousarray(wl.coords[perm])
+    wl.u_vertex = np.ascontiguousarray(wl.u_vertex[perm])
+    conn = np.ascontiguousarray(inv[wl.conn].astype(np.int32))
+    wl.conn = conn
+    check_against_mesh(wl, conn, torch.float32, mg.COEF_P1)
+
+
+def test_disconnected_elements_fill_the_tile():
+    """Every element with its own vertices: 256 distinct vertices per 3D tile,
+    the largest plan and LDS footprint."""
+    wl = workload(3, mg.ELASTICITY, 1000, seed=85)
+    x = wl.coords[wl.conn]                                 # [n, 4, 3]
+    wl.coords = np.ascontiguousarray(x.reshape(-1, 3))
+    wl.u_vertex = np.ascontiguousarray(wl.u_vertex[wl.conn].reshape(-1, 3))
+    wl.conn = np.arange(4 * wl.n_elem, dtype=np.int32).reshape(-1, 4)
+    for dt in DTYPES:
+        check_against_mesh(wl, wl.conn, dt, mg.COEF_P1)
+    plan = api.MeshPlan(dev(wl.conn, torch.int32), wl.n_vert)
+    assert plan.info()["max_tile_vertices"] == 256
+
+
+def test_degenerate_elements_counted_like_unplanned():
+    wl = workload(2, mg.LAPLACE, 700, seed=87)
+    conn = wl.conn.copy()
+    conn[[3, 500], 2] = conn[[3, 500], 1]                  # zero area
+    wl.conn = conn
+    check_against_mesh(wl, conn, torch.float64, mg.COEF_QUAD)
+
+
+def test_plan_errors_and_empty():
+    conn = torch.tensor([[0, 1, 2], [0, 2, 5]], dtype=torch.int32, device="cuda")
+    with pytest.raises(N.FemError) as ei:
+        api.MeshPlan(conn, 4)                              # index 5 out of range
+    assert ei.value.status == N.FEM_ERR_INVALID_ARG
+    plan = api.MeshPlan(torch.zeros((0, 4), dtype=torch.int32, device="cuda"), 0)
+    assert plan.info()["tile_vertices"] == 0
+    R = plan.integrate(mg.LAPLACE, mg.RULE_TET4, torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                       torch.zeros((4, 0), device="cuda"), torch.zeros((1, 4, 0), device="cuda"))
+    assert R.shape == (4, 0)
+    wl = workload(2, mg.LAPLACE, 10)
+    plan = api.MeshPlan(dev(wl.conn, torch.int32), wl.n_vert)
+    x, u = dev(wl.coords, torch.float64), dev(wl.u, torch.float32)
+    cf, out = torch.ones((1, 4, 10), device="cuda"), torch.empty_like(u)
+    for f in (N.lib().fem_integrate_residual_planned, N.lib().fem_integrate_residual_gather_planned):
+        # a tetrahedron rule on a triangle mesh's plan
+        assert f(plan._plan, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, x.data_ptr(), u.data_ptr(), cf.data_ptr(),
+                 out.data_ptr(), None, None) == N.FEM_ERR_UNSUPPORTED
+
+
+def test_planned_under_graph_capture():
+    dtype = torch.float32
+    wl = workload(3, mg.LAPLACE, 20000, seed=89)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    u, cf, uv = dev(wl.u, dtype), dev(wl.coef, dtype), dev(wl.u_vertex, dtype)
+    plan = api.MeshPlan(conn, wl.n_vert)
+    R1, R2 = torch.empty_like(u), torch.empty_like(u)
+
+    def work():
+        plan.integrate(wl.physics, wl.rule, coords, u, cf, out=R1)
+        plan.gather(wl.physics, wl.rule, coords, uv, cf, out=R2)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        work()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = [R1.clone(), R2.clone()]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    for rep in range(3):
+        R1.fill_(float("nan"))
+        R2.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(R1, eager[0]) and torch.equal(R2, eager[1]), rep
+
+
+@pytest.mark.parametrize("cfg", [2, "3a", "3b"])
+def test_full_size_meshes(cfg):
+    wl = mg.config(cfg)
+    for dt in DTYPES:
+        check_against_mesh(wl, wl.conn, dt, mg.COEF_QUAD)
