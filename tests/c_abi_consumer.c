@@ -7,7 +7,9 @@
  * points it checks, in FP64:
  *   - fem_geometry then fem_integrate_residual against fem_oracle_residual
  *     (max |dR| relative to max |R| <= 1e-12);
- *   - fem_integrate_residual_mesh bit for bit against the two calls;
+ *   - fem_integrate_residual_mesh bit for bit against the two calls, and
+ *     fem_integrate_residual_planned (through a mesh plan) bit for bit
+ *     against fem_integrate_residual_mesh;
  *   - fem_assemble against the element-order sum of the oracle's element
  *     vectors (bit for bit: same values, same order, FP64);
  *   - fem_integrate_jacobian (element matrices) against the oracle's
@@ -68,13 +70,13 @@ int main(void) {
     int32_t *conn = malloc(sizeof(int32_t) * 4 * n_elem);
     double *u = malloc(sizeof(double) * 4 * n_elem), *coef = malloc(sizeof(double) * 4 * n_elem);
     double *R_ref = malloc(sizeof(double) * 4 * n_elem), *R = malloc(sizeof(double) * 4 * n_elem);
-    double *R_mesh = malloc(sizeof(double) * 4 * n_elem);
+    double *R_mesh = malloc(sizeof(double) * 4 * n_elem), *R_plan = malloc(sizeof(double) * 4 * n_elem);
     double *F_ref = malloc(sizeof(double) * n_vert), *F = malloc(sizeof(double) * n_vert);
     double *u_vert = malloc(sizeof(double) * n_vert);
     double *K = malloc(sizeof(double) * 16 * n_elem), *K_ref = malloc(sizeof(double) * 16 * n_elem);
     double *ij_ref = malloc(sizeof(double) * 9 * n_elem), *dj_ref = malloc(sizeof(double) * n_elem);
-    if (!X || !conn || !u || !coef || !R_ref || !R || !R_mesh || !F_ref || !F || !u_vert || !K || !K_ref || !ij_ref ||
-        !dj_ref)
+    if (!X || !conn || !u || !coef || !R_ref || !R || !R_mesh || !R_plan || !F_ref || !F || !u_vert || !K || !K_ref ||
+        !ij_ref || !dj_ref)
         return 4;
 
     /* vertices: grid points, interior ones jittered by at most 0.2 h */
@@ -126,7 +128,7 @@ int main(void) {
         return 5;
 
     /* device buffers */
-    double *dX, *du, *dcoef, *dij, *ddj, *dR, *dRm, *dF, *dK;
+    double *dX, *du, *dcoef, *dij, *ddj, *dR, *dRm, *dF, *dK, *dRp;
     int32_t *dconn, *dcounts;
     CHECK_HIP(hipMalloc((void**)&dX, sizeof(double) * 3 * n_vert));
     CHECK_HIP(hipMalloc((void**)&dconn, sizeof(int32_t) * 4 * n_elem));
@@ -138,6 +140,7 @@ int main(void) {
     CHECK_HIP(hipMalloc((void**)&dRm, sizeof(double) * 4 * n_elem));
     CHECK_HIP(hipMalloc((void**)&dF, sizeof(double) * n_vert));
     CHECK_HIP(hipMalloc((void**)&dK, sizeof(double) * 16 * n_elem));
+    CHECK_HIP(hipMalloc((void**)&dRp, sizeof(double) * 4 * n_elem));
     CHECK_HIP(hipMalloc((void**)&dcounts, sizeof(int32_t) * 2));
     CHECK_HIP(hipMemcpy(dX, X, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice));
     CHECK_HIP(hipMemcpy(dconn, conn, sizeof(int32_t) * 4 * n_elem, hipMemcpyHostToDevice));
@@ -157,6 +160,10 @@ int main(void) {
     CHECK_FEM(fem_assemble(plan, 1, FEM_F64, dR, dF, stream));
     CHECK_FEM(fem_integrate_jacobian(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, 1, FEM_F64, n_elem, dij, ddj, dcoef,
                                      dK, stream));
+    fem_mesh_plan *mplan = NULL;
+    CHECK_FEM(fem_mesh_plan_create(3, n_elem, n_vert, dconn, stream, &mplan));
+    CHECK_FEM(fem_integrate_residual_planned(mplan, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, FEM_F64, dX, du, dcoef,
+                                             dRp, NULL, stream));
     CHECK_HIP(hipStreamSynchronize(stream));
 
     int32_t counts[2];
@@ -165,6 +172,7 @@ int main(void) {
     CHECK_HIP(hipMemcpy(R_mesh, dRm, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(F, dF, sizeof(double) * n_vert, hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(K, dK, sizeof(double) * 16 * n_elem, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(R_plan, dRp, sizeof(double) * 4 * n_elem, hipMemcpyDeviceToHost));
 
     int fails = 0;
     if (counts[0] != 0) { fprintf(stderr, "unexpected degenerate elements: %d\n", counts[0]); ++fails; }
@@ -175,6 +183,7 @@ int main(void) {
     }
     if (!(dmax <= 1e-12 * rmax)) { fprintf(stderr, "residual vs oracle: %.3e relative\n", dmax / rmax); ++fails; }
     if (memcmp(R, R_mesh, sizeof(double) * 4 * n_elem) != 0) { fprintf(stderr, "fused != two calls\n"); ++fails; }
+    if (memcmp(R_plan, R_mesh, sizeof(double) * 4 * n_elem) != 0) { fprintf(stderr, "planned != fused\n"); ++fails; }
     /* assembly of the GPU element vectors vs the oracle's assembly of the
      * same values: sum the GPU vectors with the oracle's routine */
     if (fem_oracle_assemble(3, 1, n_elem, n_vert, conn, R, F_ref) != 0) return 5;
@@ -206,11 +215,12 @@ int main(void) {
     }
 
     fem_assembly_plan_destroy(plan);
+    fem_mesh_plan_destroy(mplan);
     CHECK_HIP(hipStreamDestroy(stream));
     hipFree(dX); hipFree(dconn); hipFree(du); hipFree(dcoef); hipFree(dij); hipFree(ddj);
-    hipFree(dR); hipFree(dRm); hipFree(dF); hipFree(dcounts); hipFree(dK);
+    hipFree(dR); hipFree(dRm); hipFree(dF); hipFree(dcounts); hipFree(dK); hipFree(dRp);
     free(X); free(conn); free(u); free(coef); free(R_ref); free(R); free(R_mesh); free(F_ref); free(F); free(u_vert);
-    free(K); free(K_ref); free(ij_ref); free(dj_ref);
+    free(K); free(K_ref); free(ij_ref); free(dj_ref); free(R_plan);
     if (fails) return 1;
     printf("c_abi_consumer: %lld elements, residual rel. error %.2e, element matrices %.2e, fused and assembly "
            "bitwise: ok\n", (long long)n_elem, dmax / rmax, kmax / kref);
