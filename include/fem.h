@@ -263,16 +263,17 @@ fem_status fem_mesh_plan_info(const fem_mesh_plan* plan, int* dim, int64_t* n_el
                               int* max_tile_vertices, int64_t* tile_vertices);
 void fem_mesh_plan_destroy(fem_mesh_plan* plan);
 /* fem_integrate_residual_mesh through a plan: coords [n_vert][dim] FP64, u
- * and coef per element as there, elem_vec [N_bt][n_elem]; counts as there
- * (may be NULL). The geometry is not written out. */
+ * and coef per element as there, elem_vec [N_bt][n_elem]; inv_j/det_j
+ * (both or neither) and counts as there (may be NULL). */
 fem_status fem_integrate_residual_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space,
                                           int dtype, const double* coords, const void* u, const void* coef,
-                                          void* elem_vec, int32_t* counts, void* stream);
+                                          void* elem_vec, void* inv_j, void* det_j, int32_t* counts, void* stream);
 /* fem_integrate_residual_gather through a plan: u_vertex [n_vert][N_comp],
  * a P1 coefficient per vertex, point and cell coefficients per element. */
 fem_status fem_integrate_residual_gather_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space,
                                                  int dtype, const double* coords, const void* u_vertex,
-                                                 const void* coef, void* elem_vec, int32_t* counts, void* stream);
+                                                 const void* coef, void* elem_vec, void* inv_j, void* det_j,
+                                                 int32_t* counts, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Element matrices: the Jacobian of the element residual with respect */

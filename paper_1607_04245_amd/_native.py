@@ -70,8 +70,8 @@ SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int64)]),
     "fem_mesh_plan_destroy": (None, [_vp]),
-    "fem_integrate_residual_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "fem_integrate_residual_gather_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fem_integrate_residual_gather_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_batch_plan_create": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, ctypes.POINTER(_vp)]),
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),

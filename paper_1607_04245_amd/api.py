@@ -468,7 +468,7 @@ class MeshPlan:
         return dict(dim=d.value, n_elem=ne.value, n_vert=nv.value, max_tile_vertices=mx.value,
                     tile_vertices=tot.value)
 
-    def _run(self, fn, name, physics, rule, coords, u, coef, out, counts, coef_space, per_vertex):
+    def _run(self, fn, name, physics, rule, coords, u, coef, out, counts, coef_space, per_vertex, inv_j, det_j):
         dtype = u.dtype
         if dtype not in _DT:
             raise TypeError("u must be float32 or float64")
@@ -486,19 +486,26 @@ class MeshPlan:
         _need(out, "out", dtype, su)
         if counts is not None:
             _need(counts, "counts", torch.int32, (2,))
+        if (inv_j is None) != (det_j is None):
+            raise ValueError("pass both inv_j and det_j, or neither")
+        if inv_j is not None:
+            _need(inv_j, "inv_j", dtype, sij)
+            _need(det_j, "det_j", dtype, sdj)
         N.check(fn(self._plan, physics, rule, coef_space, _DT[dtype], _ptr(coords), _ptr(u), _ptr(coef), _ptr(out),
-                   _ptr(counts), _stream()), name)
+                   _ptr(inv_j), _ptr(det_j), _ptr(counts), _stream()), name)
         return out
 
-    def integrate(self, physics, rule, coords, u, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD):
+    def integrate(self, physics, rule, coords, u, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD,
+                  inv_j=None, det_j=None):
         """fem_integrate_residual_mesh through the plan (bitwise the same)."""
         return self._run(N.lib().fem_integrate_residual_planned, "fem_integrate_residual_planned", physics, rule,
-                         coords, u, coef, out, counts, coef_space, False)
+                         coords, u, coef, out, counts, coef_space, False, inv_j, det_j)
 
-    def gather(self, physics, rule, coords, u_vertex, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD):
+    def gather(self, physics, rule, coords, u_vertex, coef, out=None, counts=None, *, coef_space=N.COEF_QUAD,
+               inv_j=None, det_j=None):
         """fem_integrate_residual_gather through the plan (bitwise the same)."""
         return self._run(N.lib().fem_integrate_residual_gather_planned, "fem_integrate_residual_gather_planned",
-                         physics, rule, coords, u_vertex, coef, out, counts, coef_space, True)
+                         physics, rule, coords, u_vertex, coef, out, counts, coef_space, True, inv_j, det_j)
 
     def close(self):
         if self._plan:

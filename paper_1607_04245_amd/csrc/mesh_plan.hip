@@ -51,12 +51,13 @@ __device__ __forceinline__ void wave_sync() {
 // One wave (the whole workgroup) per tile. LDS holds the tile's vertex
 // records: maxc x DIM coordinates (FP64), then maxc x (NU + NK) values of u
 // and of a P1 coefficient (gather form).
-template <int DIM, int PHYS, int RULE, typename Real, bool GATHER>
+template <int DIM, int PHYS, int RULE, typename Real, bool GATHER, bool STORE_GEOM>
 __global__ void __launch_bounds__(64)
 residual_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ tile_off,
                         const int32_t* __restrict__ tile_verts, const uint32_t* __restrict__ lidx,
                         const double* __restrict__ X, const Real* __restrict__ u, const Real* __restrict__ coef,
-                        Real* __restrict__ out, int32_t* __restrict__ counts, int maxc) {
+                        Real* __restrict__ out, Real* __restrict__ inv_j, Real* __restrict__ det_j,
+                        int32_t* __restrict__ counts, int maxc) {
     using E = Elem<DIM, PHYS, RULE>;
     constexpr bool CV = coef_per_vertex<DIM, PHYS, RULE, GATHER>();
     constexpr int NU = GATHER ? E::NC : 0, NK = CV ? E::NCOEF : 0, NR = NU + NK;
@@ -112,8 +113,8 @@ residual_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ 
                 for (int m = 0; m < E::NCOEF; ++m) cf[m * E::NB + b] = vs[l * NR + NU + m];
             }
         }
-        mesh_element_finish<DIM, PHYS, RULE, Real, false>(e < n, e, n, true, x, uu, cf, out, nullptr, nullptr, ndeg,
-                                                          npoor);
+        mesh_element_finish<DIM, PHYS, RULE, Real, STORE_GEOM>(e < n, e, n, true, x, uu, cf, out, inv_j, det_j, ndeg,
+                                                               npoor);
         wave_sync();  // every lane has read the tile before the next one is staged
     }
     add_counts(counts, ndeg, npoor);
@@ -125,6 +126,8 @@ struct PlannedArgs {
     const void* u;
     const void* coef;
     void* out;
+    void* inv_j;
+    void* det_j;
     int32_t* counts;
     int dtype;
     hipStream_t stream;
@@ -138,10 +141,16 @@ static hipError_t launch_planned_t(const PlannedArgs& a) {
     const int maxc = std::max(a.p->max_tile, 1);
     const size_t lds = (size_t)maxc * (DIM * sizeof(double) + NR * sizeof(Real));
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(a.p->n_tiles, 1), (int64_t)1 << 30);
-    hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER>), dim3((unsigned)grid), dim3(64), lds,
-                       a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx, a.coords,
-                       static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out),
-                       a.counts, maxc);
+    if (a.inv_j != nullptr)
+        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, true>), dim3((unsigned)grid), dim3(64),
+                           lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx, a.coords,
+                           static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out),
+                           static_cast<Real*>(a.inv_j), static_cast<Real*>(a.det_j), a.counts, maxc);
+    else
+        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, false>), dim3((unsigned)grid), dim3(64),
+                           lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx, a.coords,
+                           static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out),
+                           nullptr, nullptr, a.counts, maxc);
     return hipGetLastError();
 }
 
@@ -164,7 +173,8 @@ static void mesh_plan_free(fem_mesh_plan* p) {
 }
 
 static fem_status planned_common(const char* fn, const fem_mesh_plan* plan, int physics, int rule, int coef_space,
-                                 int dtype, const double* coords, const void* u, const void* coef, void* out) {
+                                 int dtype, const double* coords, const void* u, const void* coef, void* out,
+                                 const void* inv_j, const void* det_j) {
     if (!plan) { set_error("%s: NULL plan", fn); return FEM_ERR_INVALID_ARG; }
     const int dim = plan->dim;
     if (physics != FEM_LAPLACE && physics != FEM_ELASTICITY && physics != FEM_MASS) {
@@ -179,7 +189,10 @@ static fem_status planned_common(const char* fn, const fem_mesh_plan* plan, int 
     }
     if (dtype != FEM_F32 && dtype != FEM_F64) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
     if (plan->n_elem == 0) return FEM_OK;
-    if (!coords || !u || !coef || !out) { set_error("%s: NULL array", fn); return FEM_ERR_INVALID_ARG; }
+    if (!coords || !u || !coef || !out || (!inv_j) != (!det_j)) {
+        set_error("%s: NULL array (inv_j and det_j must both be set or both NULL)", fn);
+        return FEM_ERR_INVALID_ARG;
+    }
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev != plan->device) {
         set_error("%s: the plan was built on device %d, current device is %d", fn, plan->device, dev);
@@ -296,11 +309,11 @@ void fem_mesh_plan_destroy(fem_mesh_plan* plan) { mesh_plan_free(plan); }
 
 fem_status fem_integrate_residual_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space, int dtype,
                                           const double* coords, const void* u, const void* coef, void* elem_vec,
-                                          int32_t* counts, void* stream) {
+                                          void* inv_j, void* det_j, int32_t* counts, void* stream) {
     fem_status st = planned_common("fem_integrate_residual_planned", plan, physics, rule, coef_space, dtype, coords, u,
-                                   coef, elem_vec);
+                                   coef, elem_vec, inv_j, det_j);
     if (st || plan->n_elem == 0) return st;
-    const PlannedArgs a{plan, coords, u, coef, elem_vec, counts, dtype, static_cast<hipStream_t>(stream)};
+    const PlannedArgs a{plan, coords, u, coef, elem_vec, inv_j, det_j, counts, dtype, static_cast<hipStream_t>(stream)};
     const PlannedDispatch<false> f{a};
     hipError_t e = dispatch_element(plan->dim, physics, rule, coef_space, f, hipErrorInvalidValue);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_planned launch");
@@ -308,11 +321,13 @@ fem_status fem_integrate_residual_planned(const fem_mesh_plan* plan, int physics
 
 fem_status fem_integrate_residual_gather_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space,
                                                  int dtype, const double* coords, const void* u_vertex,
-                                                 const void* coef, void* elem_vec, int32_t* counts, void* stream) {
+                                                 const void* coef, void* elem_vec, void* inv_j, void* det_j,
+                                                 int32_t* counts, void* stream) {
     fem_status st = planned_common("fem_integrate_residual_gather_planned", plan, physics, rule, coef_space, dtype,
-                                   coords, u_vertex, coef, elem_vec);
+                                   coords, u_vertex, coef, elem_vec, inv_j, det_j);
     if (st || plan->n_elem == 0) return st;
-    const PlannedArgs a{plan, coords, u_vertex, coef, elem_vec, counts, dtype, static_cast<hipStream_t>(stream)};
+    const PlannedArgs a{plan, coords, u_vertex, coef, elem_vec, inv_j, det_j, counts, dtype,
+                        static_cast<hipStream_t>(stream)};
     const PlannedDispatch<true> f{a};
     hipError_t e = dispatch_element(plan->dim, physics, rule, coef_space, f, hipErrorInvalidValue);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_gather_planned launch");

@@ -163,7 +163,7 @@ int main(void) {
     fem_mesh_plan *mplan = NULL;
     CHECK_FEM(fem_mesh_plan_create(3, n_elem, n_vert, dconn, stream, &mplan));
     CHECK_FEM(fem_integrate_residual_planned(mplan, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, FEM_F64, dX, du, dcoef,
-                                             dRp, NULL, stream));
+                                             dRp, NULL, NULL, NULL, stream));
     CHECK_HIP(hipStreamSynchronize(stream));
 
     int32_t counts[2];

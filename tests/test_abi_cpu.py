@@ -237,7 +237,8 @@ def test_mesh_plan_validation(lib):
     assert lib.fem_mesh_plan_create(3, 10, 0, _v(), None, ctypes.byref(plan)) == N.FEM_ERR_INVALID_ARG
     assert not plan.value
     for f in (lib.fem_integrate_residual_planned, lib.fem_integrate_residual_gather_planned):
-        assert f(None, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, _v(), _v(), _v(), _v(), None, None) == N.FEM_ERR_INVALID_ARG
+        assert f(None, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, _v(), _v(), _v(), _v(), None, None, None,
+                 None) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_mesh_plan_info(None, None, None, None, None, None) == N.FEM_ERR_INVALID_ARG
     lib.fem_mesh_plan_destroy(None)
 

@@ -126,7 +126,29 @@ def test_plan_errors_and_empty():
     for f in (N.lib().fem_integrate_residual_planned, N.lib().fem_integrate_residual_gather_planned):
         # a tetrahedron rule on a triangle mesh's plan
         assert f(plan._plan, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, x.data_ptr(), u.data_ptr(), cf.data_ptr(),
-                 out.data_ptr(), None, None) == N.FEM_ERR_UNSUPPORTED
+                 out.data_ptr(), None, None, None, None) == N.FEM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_planned_geometry_outputs(dtype):
+    """The planned forms also write J^{-1} and det J, equal to fem_geometry's."""
+    wl = workload(3, mg.ELASTICITY, 3333, seed=91)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    ij, dj = api.fem_geometry(coords, conn, dtype)
+    plan = api.MeshPlan(conn, wl.n_vert)
+    for gather in (False, True):
+        ij2, dj2 = torch.full_like(ij, float("nan")), torch.full_like(dj, float("nan"))
+        if gather:
+            R = plan.gather(wl.physics, wl.rule, coords, dev(wl.u_vertex, dtype), dev(wl.coef, dtype), inv_j=ij2,
+                            det_j=dj2)
+            ref = api.fem_integrate_residual_gather(3, wl.physics, wl.rule, coords, conn, dev(wl.u_vertex, dtype),
+                                                    dev(wl.coef, dtype))
+        else:
+            R = plan.integrate(wl.physics, wl.rule, coords, dev(wl.u, dtype), dev(wl.coef, dtype), inv_j=ij2,
+                               det_j=dj2)
+            ref = api.fem_integrate_residual_mesh(3, wl.physics, wl.rule, coords, conn, dev(wl.u, dtype),
+                                                  dev(wl.coef, dtype))
+        assert torch.equal(R, ref) and torch.equal(ij2, ij) and torch.equal(dj2, dj)
 
 
 def test_planned_under_graph_capture():
