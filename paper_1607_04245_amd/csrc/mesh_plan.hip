@@ -48,10 +48,13 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave (the whole workgroup) per tile. LDS holds the tile's vertex
-// records: maxc x DIM coordinates (FP64), then maxc x (NU + NK) values of u
-// and of a P1 coefficient (gather form).
-template <int DIM, int PHYS, int RULE, typename Real, bool GATHER, bool STORE_GEOM>
+// One wave (the whole workgroup) per TPW consecutive tiles, whose loads are
+// all issued before the first element is finished (two in the gather form on
+// triangles, one otherwise). LDS
+// holds, per tile, maxc x DIM coordinates (FP64), then, after all tiles'
+// coordinates, maxc x (NU + NK) values of u and of a P1 coefficient (gather
+// form).
+template <int DIM, int PHYS, int RULE, typename Real, bool GATHER, bool STORE_GEOM, int TPW>
 __global__ void __launch_bounds__(64)
 residual_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ tile_off,
                         const int32_t* __restrict__ tile_verts, const uint32_t* __restrict__ lidx,
@@ -63,59 +66,79 @@ residual_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ 
     constexpr int NU = GATHER ? E::NC : 0, NK = CV ? E::NCOEF : 0, NR = NU + NK;
     extern __shared__ double plan_lds[];
     double* xs = plan_lds;
-    Real* vs = reinterpret_cast<Real*>(plan_lds + (int64_t)maxc * DIM);
+    Real* vs = reinterpret_cast<Real*>(plan_lds + (int64_t)TPW * maxc * DIM);
     const int lane = threadIdx.x;
     int ndeg = 0, npoor = 0;
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int64_t off = tile_off[t];
-        const int cnt = (int)(tile_off[t + 1] - off);
-        // per-element streams, independent of the vertex records
-        const int64_t e = t * kPlanTile + lane, ec = e < n ? e : n - 1;
-        const uint32_t li = __builtin_nontemporal_load(lidx + ec);
-        Real uu[E::NBT], cf[E::NCQ];
-        if constexpr (!GATHER) {
+    for (int64_t t0 = (int64_t)blockIdx.x * TPW; t0 < n_tiles; t0 += (int64_t)gridDim.x * TPW) {
+        int64_t off[TPW], e[TPW];
+        int cnt[TPW];
+        uint32_t li[TPW];
+        Real uu[TPW][E::NBT], cf[TPW][E::NCQ];
 #pragma unroll
-            for (int f = 0; f < E::NBT; ++f) uu[f] = __builtin_nontemporal_load(u + f * n + ec);
-        }
-        if constexpr (!CV) {
+        for (int k = 0; k < TPW; ++k) {
+            // a tile past the end is skipped: no records, masked stores
+            const bool live = t0 + k < n_tiles;
+            const int64_t t = live ? t0 + k : n_tiles - 1;
+            off[k] = tile_off[t];
+            cnt[k] = live ? (int)(tile_off[t + 1] - off[k]) : 0;
+            // per-element streams, independent of the vertex records
+            e[k] = (t0 + k) * kPlanTile + lane;
+            const int64_t ec = e[k] < n ? e[k] : n - 1;
+            li[k] = __builtin_nontemporal_load(lidx + ec);
+            if constexpr (!GATHER) {
 #pragma unroll
-            for (int f = 0; f < E::NCQ; ++f) cf[f] = __builtin_nontemporal_load(coef + f * n + ec);
+                for (int f = 0; f < E::NBT; ++f) uu[k][f] = __builtin_nontemporal_load(u + f * n + ec);
+            }
+            if constexpr (!CV) {
+#pragma unroll
+                for (int f = 0; f < E::NCQ; ++f) cf[k][f] = __builtin_nontemporal_load(coef + f * n + ec);
+            }
         }
-        // the tile's distinct vertex records, once each (a version that
+        // the tiles' distinct vertex records, once each (a version that
         // issued all of a lane's record loads before its first LDS store
         // measured slower on tetrahedra and barely faster on triangles)
-        for (int j = lane; j < cnt; j += kPlanTile) {
-            const int64_t v = tile_verts[off + j];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) xs[j * DIM + i] = X[v * DIM + i];
-            if constexpr (GATHER) {
+        for (int k = 0; k < TPW; ++k) {
+            double* xk = xs + (int64_t)k * maxc * DIM;
+            Real* vk = vs + (int64_t)k * maxc * NR;
+            for (int j = lane; j < cnt[k]; j += kPlanTile) {
+                const int64_t v = tile_verts[off[k] + j];
 #pragma unroll
-                for (int c = 0; c < E::NC; ++c) vs[j * NR + c] = u[v * E::NC + c];
-            }
-            if constexpr (CV) {
+                for (int i = 0; i < DIM; ++i) xk[j * DIM + i] = X[v * DIM + i];
+                if constexpr (GATHER) {
 #pragma unroll
-                for (int m = 0; m < E::NCOEF; ++m) vs[j * NR + NU + m] = coef[v * E::NCOEF + m];
+                    for (int c = 0; c < E::NC; ++c) vk[j * NR + c] = u[v * E::NC + c];
+                }
+                if constexpr (CV) {
+#pragma unroll
+                    for (int m = 0; m < E::NCOEF; ++m) vk[j * NR + NU + m] = coef[v * E::NCOEF + m];
+                }
             }
         }
         wave_sync();
-        double x[DIM + 1][DIM];
 #pragma unroll
-        for (int b = 0; b <= DIM; ++b) {
-            const int l = (int)((li >> (8 * b)) & 255u);
+        for (int k = 0; k < TPW; ++k) {
+            const double* xk = xs + (int64_t)k * maxc * DIM;
+            const Real* vk = vs + (int64_t)k * maxc * NR;
+            double x[DIM + 1][DIM];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) x[b][i] = xs[l * DIM + i];
-            if constexpr (GATHER) {
+            for (int b = 0; b <= DIM; ++b) {
+                const int l = (int)((li[k] >> (8 * b)) & 255u);
 #pragma unroll
-                for (int c = 0; c < E::NC; ++c) uu[b * E::NC + c] = vs[l * NR + c];
+                for (int i = 0; i < DIM; ++i) x[b][i] = xk[l * DIM + i];
+                if constexpr (GATHER) {
+#pragma unroll
+                    for (int c = 0; c < E::NC; ++c) uu[k][b * E::NC + c] = vk[l * NR + c];
+                }
+                if constexpr (CV) {
+#pragma unroll
+                    for (int m = 0; m < E::NCOEF; ++m) cf[k][m * E::NB + b] = vk[l * NR + NU + m];
+                }
             }
-            if constexpr (CV) {
-#pragma unroll
-                for (int m = 0; m < E::NCOEF; ++m) cf[m * E::NB + b] = vs[l * NR + NU + m];
-            }
+            mesh_element_finish<DIM, PHYS, RULE, Real, STORE_GEOM>(e[k] < n, e[k], n, true, x, uu[k], cf[k], out,
+                                                                   inv_j, det_j, ndeg, npoor);
         }
-        mesh_element_finish<DIM, PHYS, RULE, Real, STORE_GEOM>(e < n, e, n, true, x, uu, cf, out, inv_j, det_j, ndeg,
-                                                               npoor);
-        wave_sync();  // every lane has read the tile before the next one is staged
+        wave_sync();  // every lane has read the tiles before the next ones are staged
     }
     add_counts(counts, ndeg, npoor);
 }
@@ -138,19 +161,23 @@ static hipError_t launch_planned_t(const PlannedArgs& a) {
     using E = Elem<DIM, PHYS, RULE>;
     constexpr bool CV = coef_per_vertex<DIM, PHYS, RULE, GATHER>();
     constexpr int NR = (GATHER ? E::NC : 0) + (CV ? E::NCOEF : 0);
+    // measured: two tiles per wave pay in the triangle gather form only
+    constexpr int TPW = (DIM == 2 && GATHER) ? 2 : 1;
     const int maxc = std::max(a.p->max_tile, 1);
-    const size_t lds = (size_t)maxc * (DIM * sizeof(double) + NR * sizeof(Real));
-    const int64_t grid = std::min<int64_t>(std::max<int64_t>(a.p->n_tiles, 1), (int64_t)1 << 30);
+    const size_t lds = (size_t)TPW * maxc * (DIM * sizeof(double) + NR * sizeof(Real));
+    const int64_t grid =
+        std::min<int64_t>(std::max<int64_t>((a.p->n_tiles + TPW - 1) / TPW, 1), (int64_t)1 << 30);
     if (a.inv_j != nullptr)
-        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, true>), dim3((unsigned)grid), dim3(64),
-                           lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx, a.coords,
-                           static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out),
-                           static_cast<Real*>(a.inv_j), static_cast<Real*>(a.det_j), a.counts, maxc);
+        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, true, TPW>), dim3((unsigned)grid),
+                           dim3(64), lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx,
+                           a.coords, static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef),
+                           static_cast<Real*>(a.out), static_cast<Real*>(a.inv_j), static_cast<Real*>(a.det_j),
+                           a.counts, maxc);
     else
-        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, false>), dim3((unsigned)grid), dim3(64),
-                           lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx, a.coords,
-                           static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out),
-                           nullptr, nullptr, a.counts, maxc);
+        hipLaunchKernelGGL((residual_planned_kernel<DIM, PHYS, RULE, Real, GATHER, false, TPW>), dim3((unsigned)grid),
+                           dim3(64), lds, a.stream, a.p->n_elem, a.p->n_tiles, a.p->tile_off, a.p->tile_verts, a.p->lidx,
+                           a.coords, static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef),
+                           static_cast<Real*>(a.out), nullptr, nullptr, a.counts, maxc);
     return hipGetLastError();
 }
 
