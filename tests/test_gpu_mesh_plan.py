@@ -71,6 +71,15 @@ def test_planned_equals_unplanned(dim, phys, space, dtype):
     check_against_mesh(wl, wl.conn, dtype, space)
 
 
+@pytest.mark.parametrize("n_elem", [1, 63, 64, 65, 129, 191])
+@pytest.mark.parametrize("dim,phys", [(2, mg.ELASTICITY), (3, mg.LAPLACE)])
+def test_small_and_ragged_sizes(n_elem, dim, phys):
+    """One partial tile, exact tiles, and odd tile counts (the two-tile
+    triangle gather form then has a tile past the end)."""
+    wl = workload(dim, phys, n_elem, seed=93)
+    check_against_mesh(wl, wl.conn, torch.float32, mg.COEF_P1)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_renumbered_vertices(dim):
     """Vertex numbers shuffled (an unstructured numbering): tiles touch
