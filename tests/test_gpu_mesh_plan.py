@@ -10,7 +10,7 @@ import torch
 from paper_1607_04245_amd import api, meshgen as mg
 from paper_1607_04245_amd import _native as N
 
-from _parity import dev
+from _parity import assert_close, dev, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,19 @@ def test_planned_equals_unplanned(dim, phys, space, dtype):
     rule = mg.default_rule(dim) if (dim + phys) % 2 else mg.RULE_CENTROID
     wl = workload(dim, phys, 3001, rule=rule)
     check_against_mesh(wl, wl.conn, dtype, space)
+
+
+@pytest.mark.parametrize("dim,phys", [(2, mg.LAPLACE), (3, mg.ELASTICITY)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_planned_matches_oracle(dim, phys, dtype):
+    """Directly against the FP64 oracle, with the bars of the other parity tests."""
+    wl = workload(dim, phys, 2500, seed=95)
+    plan = api.MeshPlan(dev(wl.conn, torch.int32), wl.n_vert)
+    R = plan.integrate(phys, wl.rule, dev(wl.coords, torch.float64), dev(wl.u, dtype), dev(wl.coef, dtype))
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+    assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"planned {dim}D phys {phys}")
+    Rg = plan.gather(phys, wl.rule, dev(wl.coords, torch.float64), dev(wl.u_vertex, dtype), dev(wl.coef, dtype))
+    assert_close(Rg.cpu().numpy(), ref, ref_abs, dtype, f"planned gather {dim}D phys {phys}")
 
 
 @pytest.mark.parametrize("n_elem", [1, 63, 64, 65, 129, 191])
