@@ -483,11 +483,34 @@ def main():
                     row[f"{form}_elements_per_s"] = wlx.n_elem / (ms * 1e-3)
                     row[f"{form}_gbs"] = nb / (ms * 1e-3) / 1e9
                     row[f"{form}_unplanned_us"] = unplanned
+                # the geometry alone, through the plan and through fem_geometry
+                nb = model.geometry_bytes(wlx.dim, wlx.n_elem, wlx.n_vert, word) * wlx.n_elem
+                cps = []
+                for _ in range(n_copies(nb)):
+                    c = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0.clone())
+                    c["plan"] = api.MeshPlan(c["conn"], wlx.n_vert)
+                    c["ij"] = torch.empty((wlx.dim * wlx.dim, wlx.n_elem), dtype=dt, device=dev)
+                    c["dj"] = torch.empty((wlx.n_elem,), dtype=dt, device=dev)
+                    cps.append(c)
+
+                def geo_plain(c, dt=dt):
+                    api.fem_geometry(c["X"], c["conn"], dt, inv_j=c["ij"], det_j=c["dj"])
+
+                def geo_planned(c, dt=dt):
+                    c["plan"].geometry(c["X"], dt, inv_j=c["ij"], det_j=c["dj"])
+                _, ms_g = timed_graph(geo_plain, cps, 20, 1)
+                _, ms_gp = timed_graph(geo_planned, cps, 20, 1)
+                for c in cps:
+                    c["plan"].close()
+                del cps
+                row.update(geometry_us=ms_gp * 1e3, geometry_unplanned_us=ms_g * 1e3,
+                           geometry_gbs=nb / (ms_gp * 1e-3) / 1e9)
                 extra[f"{wlx.name}_{tag}_mesh_plan"] = row
                 log(f"{wlx.name} {tag} mesh plan (built in {build_s:.2f} s, "
                     f"{row['tile_vertices_per_elem']:.2f} tile vertices per element): closure "
                     f"{row['closure_us']:.1f} us (unplanned {row['closure_unplanned_us']:.1f}), gather "
-                    f"{row['gather_us']:.1f} us (unplanned {row['gather_unplanned_us']:.1f})")
+                    f"{row['gather_us']:.1f} us (unplanned {row['gather_unplanned_us']:.1f}), geometry "
+                    f"{row['geometry_us']:.1f} us (unplanned {row['geometry_unplanned_us']:.1f})")
             del conn0, wlx
 
         # ------------------------------------------------- second order (P2) --

@@ -262,6 +262,10 @@ fem_status fem_mesh_plan_create(int dim, int64_t n_elem, int64_t n_vert, const i
 fem_status fem_mesh_plan_info(const fem_mesh_plan* plan, int* dim, int64_t* n_elem, int64_t* n_vert,
                               int* max_tile_vertices, int64_t* tile_vertices);
 void fem_mesh_plan_destroy(fem_mesh_plan* plan);
+/* fem_geometry through a plan: coords [n_vert][dim] FP64; inv_j, det_j and
+ * counts as fem_geometry (bitwise its outputs). */
+fem_status fem_geometry_planned(const fem_mesh_plan* plan, const double* coords, int out_dtype, void* inv_j,
+                               void* det_j, int32_t* counts, void* stream);
 /* fem_integrate_residual_mesh through a plan: coords [n_vert][dim] FP64, u
  * and coef per element as there, elem_vec [N_bt][n_elem]; inv_j/det_j
  * (both or neither) and counts as there (may be NULL). */

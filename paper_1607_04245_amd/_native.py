@@ -70,6 +70,7 @@ SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int64)]),
     "fem_mesh_plan_destroy": (None, [_vp]),
+    "fem_geometry_planned": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_gather_planned": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fem_integrate_residual_backward": (_i, [_i, _i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),

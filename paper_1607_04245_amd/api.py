@@ -468,6 +468,24 @@ class MeshPlan:
         return dict(dim=d.value, n_elem=ne.value, n_vert=nv.value, max_tile_vertices=mx.value,
                     tile_vertices=tot.value)
 
+    def geometry(self, coords, dtype=torch.float32, inv_j=None, det_j=None, counts=None):
+        """fem_geometry through the plan (bitwise the same): (inv_j, det_j)."""
+        if dtype not in _DT:
+            raise TypeError("dtype must be float32 or float64")
+        dim, n = self.dim, self.n_elem
+        _need(coords, "coords", torch.float64, (self.n_vert, dim))
+        if inv_j is None:
+            inv_j = torch.empty((dim * dim, n), dtype=dtype, device=coords.device)
+        if det_j is None:
+            det_j = torch.empty((n,), dtype=dtype, device=coords.device)
+        _need(inv_j, "inv_j", dtype, (dim * dim, n))
+        _need(det_j, "det_j", dtype, (n,))
+        if counts is not None:
+            _need(counts, "counts", torch.int32, (2,))
+        N.check(N.lib().fem_geometry_planned(self._plan, _ptr(coords), _DT[dtype], _ptr(inv_j), _ptr(det_j),
+                                             _ptr(counts), _stream()), "fem_geometry_planned")
+        return inv_j, det_j
+
     def _run(self, fn, name, physics, rule, coords, u, coef, out, counts, coef_space, per_vertex, inv_j, det_j):
         dtype = u.dtype
         if dtype not in _DT:

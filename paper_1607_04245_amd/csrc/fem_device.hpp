@@ -431,6 +431,28 @@ __device__ __forceinline__ int finish_geometry(bool ok, double& det, double (&in
     return degenerate ? 1 : (poor ? 2 : 0);
 }
 
+// Geometry of one element from its vertices, classified, and stored (rounded
+// once to the output type) when valid: the epilogue of every kernel that
+// writes the geometry alone.
+template <int DIM, typename Out>
+__device__ __forceinline__ void geometry_finish(bool valid, int64_t e, int64_t n, bool ok,
+                                                const double (&x)[DIM + 1][DIM], Out* __restrict__ inv_j,
+                                                Out* __restrict__ det_j, int& ndeg, int& npoor) {
+    double inv[DIM][DIM], ep2;
+    double det = element_geometry<DIM>(x, inv, ep2);
+    const int flag = finish_geometry<DIM>(ok, det, inv, ep2);
+    ndeg += (int)(valid & (flag == 1));
+    npoor += (int)(valid & (flag == 2));
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+                __builtin_nontemporal_store(static_cast<Out>(inv[k][i]), inv_j + (int64_t)(k * DIM + i) * n + e);
+        __builtin_nontemporal_store(static_cast<Out>(det), det_j + e);
+    }
+}
+
 // XCD-aware work split for kernels that gather vertices. Workgroups are
 // dispatched round-robin over the 8 XCDs, each with its own L2; numbering the
 // workgroups so that XCD k holds a contiguous run of logical indices, and

@@ -24,25 +24,6 @@ namespace femq {
 // than it needs. EPT = 1 is software-pipelined: the next tile's connectivity
 // is in flight while the current tile's vertices are gathered and processed.
 // EPT > 1 gives each lane EPT independent gather chains instead.
-template <int DIM, typename Out>
-__device__ __forceinline__ void geometry_finish(bool valid, int64_t e, int64_t n, bool ok,
-                                                const double (&x)[DIM + 1][DIM], Out* __restrict__ inv_j,
-                                                Out* __restrict__ det_j, int& ndeg, int& npoor) {
-    double inv[DIM][DIM], ep2;
-    double det = element_geometry<DIM>(x, inv, ep2);
-    const int flag = finish_geometry<DIM>(ok, det, inv, ep2);
-    ndeg += (int)(valid & (flag == 1));
-    npoor += (int)(valid & (flag == 2));
-    if (valid) {
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-#pragma unroll
-            for (int i = 0; i < DIM; ++i)
-                __builtin_nontemporal_store(static_cast<Out>(inv[k][i]), inv_j + (int64_t)(k * DIM + i) * n + e);
-        __builtin_nontemporal_store(static_cast<Out>(det), det_j + e);
-    }
-}
-
 template <int DIM, typename Out, int EPT, bool VEC>
 __global__ void __launch_bounds__(512)
 geometry_kernel(int64_t n, int64_t nv, const double* __restrict__ X, const int32_t* __restrict__ conn,

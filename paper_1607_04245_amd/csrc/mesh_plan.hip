@@ -143,6 +143,41 @@ residual_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ 
     add_counts(counts, ndeg, npoor);
 }
 
+// The geometry alone through the plan: coordinates staged as above, then
+// the epilogue of fem_geometry, so the outputs are bitwise its outputs.
+template <int DIM, typename Out>
+__global__ void __launch_bounds__(64)
+geometry_planned_kernel(int64_t n, int64_t n_tiles, const int64_t* __restrict__ tile_off,
+                        const int32_t* __restrict__ tile_verts, const uint32_t* __restrict__ lidx,
+                        const double* __restrict__ X, Out* __restrict__ inv_j, Out* __restrict__ det_j,
+                        int32_t* __restrict__ counts) {
+    extern __shared__ double plan_lds[];
+    const int lane = threadIdx.x;
+    int ndeg = 0, npoor = 0;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t off = tile_off[t];
+        const int cnt = (int)(tile_off[t + 1] - off);
+        const int64_t e = t * kPlanTile + lane, ec = e < n ? e : n - 1;
+        const uint32_t li = __builtin_nontemporal_load(lidx + ec);
+        for (int j = lane; j < cnt; j += kPlanTile) {
+            const int64_t v = tile_verts[off + j];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) plan_lds[j * DIM + i] = X[v * DIM + i];
+        }
+        wave_sync();
+        double x[DIM + 1][DIM];
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b) {
+            const int l = (int)((li >> (8 * b)) & 255u);
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[b][i] = plan_lds[l * DIM + i];
+        }
+        geometry_finish<DIM, Out>(e < n, e, n, true, x, inv_j, det_j, ndeg, npoor);
+        wave_sync();
+    }
+    add_counts(counts, ndeg, npoor);
+}
+
 struct PlannedArgs {
     const fem_mesh_plan* p;
     const double* coords;
@@ -333,6 +368,44 @@ fem_status fem_mesh_plan_info(const fem_mesh_plan* plan, int* dim, int64_t* n_el
 }
 
 void fem_mesh_plan_destroy(fem_mesh_plan* plan) { mesh_plan_free(plan); }
+
+fem_status fem_geometry_planned(const fem_mesh_plan* plan, const double* coords, int out_dtype, void* inv_j,
+                               void* det_j, int32_t* counts, void* stream) {
+    if (!plan) { set_error("fem_geometry_planned: NULL plan"); return FEM_ERR_INVALID_ARG; }
+    if (out_dtype != FEM_F32 && out_dtype != FEM_F64) {
+        set_error("fem_geometry_planned: unknown dtype %d", out_dtype);
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (plan->n_elem == 0) return FEM_OK;
+    if (!coords || !inv_j || !det_j) { set_error("fem_geometry_planned: NULL array"); return FEM_ERR_INVALID_ARG; }
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev != plan->device) {
+        set_error("fem_geometry_planned: the plan was built on device %d, current device is %d", plan->device, dev);
+        return FEM_ERR_INVALID_ARG;
+    }
+    const int maxc = std::max(plan->max_tile, 1);
+    const size_t lds = (size_t)maxc * plan->dim * sizeof(double);
+    const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(plan->n_tiles, 1), (int64_t)1 << 30);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto go = [&](auto dim_c, auto out_c) {
+        constexpr int D = decltype(dim_c)::value;
+        using Out = typename decltype(out_c)::type;
+        hipLaunchKernelGGL((geometry_planned_kernel<D, Out>), dim3(grid), dim3(64), lds, s, plan->n_elem,
+                           plan->n_tiles, plan->tile_off, plan->tile_verts, plan->lidx, coords,
+                           static_cast<Out*>(inv_j), static_cast<Out*>(det_j), counts);
+    };
+    struct F32 { using type = float; };
+    struct F64 { using type = double; };
+    if (plan->dim == 2) {
+        if (out_dtype == FEM_F32) go(std::integral_constant<int, 2>(), F32{});
+        else go(std::integral_constant<int, 2>(), F64{});
+    } else {
+        if (out_dtype == FEM_F32) go(std::integral_constant<int, 3>(), F32{});
+        else go(std::integral_constant<int, 3>(), F64{});
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_geometry_planned launch");
+}
 
 fem_status fem_integrate_residual_planned(const fem_mesh_plan* plan, int physics, int rule, int coef_space, int dtype,
                                           const double* coords, const void* u, const void* coef, void* elem_vec,

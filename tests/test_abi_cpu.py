@@ -240,6 +240,7 @@ def test_mesh_plan_validation(lib):
         assert f(None, mg.LAPLACE, mg.RULE_TET4, 0, N.F32, _v(), _v(), _v(), _v(), None, None, None,
                  None) == N.FEM_ERR_INVALID_ARG
     assert lib.fem_mesh_plan_info(None, None, None, None, None, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_geometry_planned(None, _v(), N.F32, _v(), _v(), None, None) == N.FEM_ERR_INVALID_ARG
     lib.fem_mesh_plan_destroy(None)
 
 

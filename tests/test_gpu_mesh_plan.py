@@ -173,6 +173,23 @@ def test_planned_geometry_outputs(dtype):
         assert torch.equal(R, ref) and torch.equal(ij2, ij) and torch.equal(dj2, dj)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_planned_geometry_equals_fem_geometry(dim, dtype):
+    """Including degenerate elements (NaN outputs) and the counters."""
+    wl = workload(dim, mg.LAPLACE, 4097, seed=97)
+    conn = wl.conn.copy()
+    conn[[5, 4000], dim] = conn[[5, 4000], 0]              # zero measure
+    coords, conn_d = dev(wl.coords, torch.float64), dev(conn, torch.int32)
+    c1 = torch.zeros(2, dtype=torch.int32, device="cuda")
+    c2 = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ij, dj = api.fem_geometry(coords, conn_d, dtype, counts=c1)
+    plan = api.MeshPlan(conn_d, wl.n_vert)
+    ij2, dj2 = plan.geometry(coords, dtype, counts=c2)
+    assert same_bits(ij2, ij) and same_bits(dj2, dj)
+    assert torch.equal(c1, c2) and int(c1[0]) == 2
+
+
 def test_planned_under_graph_capture():
     dtype = torch.float32
     wl = workload(3, mg.LAPLACE, 20000, seed=89)
