@@ -262,8 +262,13 @@ fem_status fem_mesh_plan_create(int dim, int64_t n_elem, int64_t n_vert, const i
 fem_status fem_mesh_plan_info(const fem_mesh_plan* plan, int* dim, int64_t* n_elem, int64_t* n_vert,
                               int* max_tile_vertices, int64_t* tile_vertices);
 void fem_mesh_plan_destroy(fem_mesh_plan* plan);
-/* fem_geometry through a plan: coords [n_vert][dim] FP64; inv_j, det_j and
- * counts as fem_geometry (bitwise its outputs). */
+/* fem_geometry through a plan (the affine element geometry of Section 3:
+ * J^{-1} and |det J| per element): coords [n_vert][dim] FP64 device array;
+ * out_dtype FEM_F32 or FEM_F64; inv_j [dim*dim][n_elem], det_j [n_elem] and
+ * counts (may be NULL) as fem_geometry, whose outputs these are bit for bit.
+ * Errors: NULL plan or array, a device other than the plan's ->
+ * FEM_ERR_INVALID_ARG; another dtype -> FEM_ERR_UNSUPPORTED. An empty plan
+ * returns FEM_OK at once. Asynchronous on `stream`. */
 fem_status fem_geometry_planned(const fem_mesh_plan* plan, const double* coords, int out_dtype, void* inv_j,
                                void* det_j, int32_t* counts, void* stream);
 /* fem_integrate_residual_mesh through a plan: coords [n_vert][dim] FP64, u
