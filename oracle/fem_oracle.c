@@ -37,10 +37,13 @@
  *    weight -148/1875, (11/14, 1/14, 1/14, 1/14) with weight 343/7500,
  *    (a, a, b, b) with a = (1 + sqrt(5/14))/4, b = (1 - sqrt(5/14))/4 and
  *    weight 56/375, all times 1/6);
- *  - element order 1 (P1) or 2 (P2: vertex functions lam (2 lam - 1), then
- *    edge functions 4 lam_i lam_j, edges (i, j), i < j, lexicographic); the
- *    geometry stays affine, and a P1 coefficient keeps the d+1 vertex values
- *    and the P1 basis whatever the order of u;
+ *  - element order 1 (P1), 2 (P2: vertex functions lam (2 lam - 1), then
+ *    edge functions 4 lam_i lam_j, edges (i, j), i < j, lexicographic) or 3
+ *    (P3: the Lagrange basis on the nodes of the cubic lattice: vertices,
+ *    two nodes per edge, the node nearer i first, then one node per face
+ *    (i, j, k), i < j < k, lexicographic); the geometry stays affine, and a
+ *    P1 coefficient keeps the d+1 vertex values and the P1 basis whatever
+ *    the order of u;
  *  - physics: Laplacian f1 = kappa grad u (Section 2; f0 = 0);
  *    linear elasticity f1 = lambda tr(eps) I + 2 mu eps, eps the symmetric
  *    gradient (the paper's Lame function in Section 6 is lambda = 0,
@@ -93,7 +96,7 @@
 #include <string.h>
 
 #define OR_MAXD 3
-#define OR_MAXB 10
+#define OR_MAXB 20
 #define OR_MAXQ 11
 #define OR_MAXC 3
 #define OR_MAXCOEF 2
@@ -172,12 +175,22 @@ int fem_oracle_rule(int dim, int rule, double *xi, double *wts)
     return nq;
 }
 
-/* Lagrange basis of order 1 or 2 on the unit simplex, in barycentric
+/* Lagrange basis of order 1, 2 or 3 on the unit simplex, in barycentric
  * coordinates lam_0 = 1 - sum xi, lam_k = xi_k (grad lam_0 = -1,
  * grad lam_k = e_k). Order 1: phi_b = lam_b. Order 2: vertex functions
  * lam_b (2 lam_b - 1), b = 0..d, then edge functions 4 lam_i lam_j for the
- * edges (i, j), i < j, in lexicographic order. */
-static int or_nbasis(int dim, int order) { return order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2; }
+ * edges (i, j), i < j, in lexicographic order. Order 3 (nodes at barycentric
+ * multiples of 1/3): vertex functions lam (3 lam - 1)(3 lam - 2) / 2; per
+ * edge (i, j), lexicographic, (9/2) lam_i lam_j (3 lam_i - 1) (the node at
+ * 2/3 lam_i) then (9/2) lam_i lam_j (3 lam_j - 1); per face (i, j, k),
+ * lexicographic, 27 lam_i lam_j lam_k. Gradients follow from the chain rule
+ * through the barycentric coordinates. */
+static int or_nbasis(int dim, int order)
+{
+    if (order == 1) return dim + 1;
+    if (order == 2) return (dim + 1) * (dim + 2) / 2;
+    return (dim + 1) * (dim + 2) * (dim + 3) / 6;
+}
 
 static void or_grad_lam(int dim, int v, double g[OR_MAXD])
 {
@@ -199,6 +212,42 @@ static void or_basis(int dim, int order, const double *xi, double *phi, double d
         }
         return;
     }
+    if (order == 3) {
+        /* derivative of each function with respect to each lam_v, then the
+         * chain rule */
+        double dl[OR_MAXB][OR_MAXD + 1];
+        for (int b = 0; b < OR_MAXB; ++b)
+            for (int v = 0; v <= dim; ++v) dl[b][v] = 0.0;
+        int b = 0;
+        for (int v = 0; v <= dim; ++v, ++b) {
+            const double l = lam[v];
+            phi[b] = 0.5 * l * (3.0 * l - 1.0) * (3.0 * l - 2.0);
+            dl[b][v] = 0.5 * (27.0 * l * l - 18.0 * l + 2.0);
+        }
+        for (int i = 0; i <= dim; ++i)
+            for (int j = i + 1; j <= dim; ++j)
+                for (int s = 0; s < 2; ++s, ++b) {
+                    const int a = s == 0 ? i : j, o = s == 0 ? j : i;  /* node nearer a */
+                    phi[b] = 4.5 * lam[a] * lam[o] * (3.0 * lam[a] - 1.0);
+                    dl[b][a] = 4.5 * lam[o] * (6.0 * lam[a] - 1.0);
+                    dl[b][o] = 4.5 * lam[a] * (3.0 * lam[a] - 1.0);
+                }
+        for (int i = 0; i <= dim; ++i)
+            for (int j = i + 1; j <= dim; ++j)
+                for (int k = j + 1; k <= dim; ++k, ++b) {
+                    phi[b] = 27.0 * lam[i] * lam[j] * lam[k];
+                    dl[b][i] = 27.0 * lam[j] * lam[k];
+                    dl[b][j] = 27.0 * lam[i] * lam[k];
+                    dl[b][k] = 27.0 * lam[i] * lam[j];
+                }
+        for (int c = 0; c < b; ++c)
+            for (int k = 0; k < dim; ++k) {
+                double g = 0.0;
+                for (int v = 0; v <= dim; ++v) g += dl[c][v] * gl[v][k];
+                dphi[c][k] = g;
+            }
+        return;
+    }
     for (int b = 0; b <= dim; ++b) {
         phi[b] = lam[b] * (2.0 * lam[b] - 1.0);
         for (int k = 0; k < dim; ++k) dphi[b][k] = (4.0 * lam[b] - 1.0) * gl[b][k];
@@ -212,7 +261,7 @@ static void or_basis(int dim, int order, const double *xi, double *phi, double d
 }
 
 /* Tabulation at the quadrature points: B[q][b] = phi_b(xi_q),
- * D[q][b][k] = d phi_b / d xi_k (xi_q) for the basis of u (order 1 or 2),
+ * D[q][b][k] = d phi_b / d xi_k (xi_q) for the basis of u (order 1 to 3),
  * and B1[q][b] = lam_b(xi_q), the P1 basis a P1 coefficient lives in. */
 typedef struct {
     int dim, order, nb, nq;
@@ -225,7 +274,7 @@ typedef struct {
 static int or_tabulate(int dim, int rule, int order, or_tab *t)
 {
     double xi[OR_MAXQ * OR_MAXD];
-    if (order != 1 && order != 2) return -1;
+    if (order < 1 || order > 3) return -1;
     int nq = fem_oracle_rule(dim, rule, xi, t->w);
     if (nq < 0) return -1;
     t->dim = dim;
@@ -409,7 +458,7 @@ int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const doubl
 }
 
 /* Element residuals from precomputed geometry for Lagrange elements of the
- * given order (1 or 2; closure rows b*N_comp + c with the node order of
+ * given order (1 to 3; closure rows b*N_comp + c with the node order of
  * or_basis). Returns 0, or -1 on bad arguments. absmode != 0 gives the
  * absolute-value bound described above. */
 int fem_oracle_integrate_p(int order, int dim, int physics, int rule, int space, int64_t n_elem,
@@ -615,7 +664,7 @@ static void or_element_jac(const or_tab *t, int physics, double ij[OR_MAXD][OR_M
 }
 
 /* Element matrices elem_mat [N_bt*N_bt][n] from precomputed geometry for
- * Lagrange elements of the given order (1 or 2). Returns 0, or -1 on bad
+ * Lagrange elements of the given order (1 to 3). Returns 0, or -1 on bad
  * arguments. absmode != 0 gives the absolute-value bound. */
 int fem_oracle_jacobian_p(int order, int dim, int physics, int rule, int space, int64_t n_elem,
                           const double *inv_j, const double *det_j, const double *coef, double *elem_mat,

@@ -7,6 +7,7 @@ coef [N_coef][N_q][n]; coords [n_vert][d] and conn [n][d+1].
 from __future__ import annotations
 
 import ctypes
+import math
 import pathlib
 
 import numpy as np
@@ -82,8 +83,11 @@ def coef_words(dim, rule_id, space):
 
 
 def n_basis(dim, order):
-    """Lagrange basis functions per element: d+1 (order 1), (d+1)(d+2)/2 (order 2)."""
-    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
+    """Lagrange basis functions per element: d+1 (order 1), (d+1)(d+2)/2
+    (order 2), (d+1)(d+2)(d+3)/6 (order 3)."""
+    if order not in (1, 2, 3):
+        raise ValueError(f"no Lagrange elements of order {order}")
+    return math.comb(dim + order, order)
 
 
 def n_qpts(dim: int, rule: int) -> int:
@@ -130,7 +134,9 @@ def _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, absmode, space, ord
 def integrate(dim, physics, rule_id, inv_j, det_j, u, coef, space=0, order=1):
     """Element residuals R[N_bt, n] from precomputed geometry (Eq. (2) bracket).
     ``space``: 0 coefficients on quadrature points, 1 P1 nodal, 2 P0;
-    ``order``: 1 (P1) or 2 (P2, vertices then edges in lexicographic order)."""
+    ``order``: 1 (P1), 2 (P2, vertices then edges in lexicographic order) or
+    3 (P3: vertices, two nodes per lexicographic edge (i, j), the one nearer
+    i first, then the faces (i, j, k) in lexicographic order)."""
     return _integrate(dim, physics, rule_id, inv_j, det_j, u, coef, False, space, order)
 
 

@@ -391,6 +391,6 @@ def test_order_and_rule_validation():
     x = random_simplices(2, 2, np.random.default_rng(1))
     ij, dj = geom(x)
     with pytest.raises(ValueError):
-        oracle.integrate(2, LAP, mg.RULE_TRI6, ij, dj, np.zeros((6, 2)), np.ones((1, 6, 2)), order=3)
+        oracle.integrate(2, LAP, mg.RULE_TRI6, ij, dj, np.zeros((6, 2)), np.ones((1, 6, 2)), order=4)
     with pytest.raises(ValueError):
         oracle.integrate(2, LAP, mg.RULE_TET11, ij, dj, np.zeros((6, 2)), np.ones((1, 11, 2)), order=2)
