@@ -295,7 +295,7 @@ def test_argument_validation():
     ij, dj = geom(random_simplices(2, 2, np.random.default_rng(0)))
     cf = np.ones((1, 3, 2))
     with pytest.raises(ValueError):
-        oracle.jacobian(2, LAP, mg.RULE_TRI3, ij, dj, cf, order=3)
+        oracle.jacobian(2, LAP, mg.RULE_TRI3, ij, dj, cf, order=4)
     with pytest.raises(ValueError):
         oracle.jacobian(2, 7, mg.RULE_TRI3, ij, dj, cf)
     with pytest.raises(ValueError):
