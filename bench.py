@@ -548,6 +548,40 @@ def main():
                 del cps, ij, dj
             del p2, wlx
 
+        # -------------------------------------------------- third order (P3) --
+        for cfg in (2, "3b", "3a"):
+            wlx = wl if cfg == 2 else mg.config(cfg)
+            rule_p3 = mg.RULE_TET11 if wlx.dim == 3 else mg.RULE_TRI6
+            p3 = mg.p3_inputs(wlx, rule_p3, mg.BASE_SEED + 7700)
+            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                word = 4 if dt == torch.float32 else 8
+                nb = model.p3_forward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
+                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                base = dict(ij=ij, dj=dj, u=to_dev(p3.u, dt), cf=to_dev(p3.coef, dt))
+                cps = []
+                for _ in range(n_copies(nb)):
+                    c = {k: v.clone() for k, v in base.items()}
+                    c["R"] = torch.empty_like(c["u"])
+                    cps.append(c)
+                del base
+
+                def go(c, wlx=wlx, rule_p3=rule_p3):
+                    api.fem_integrate_residual_p3(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"], c["cf"],
+                                                  out=c["R"])
+                _, ms = timed_graph(go, cps, 10, 1)
+                us = ms * 1e3
+                f = model.p3_model_flops(wlx.dim, wlx.physics, rule_p3)
+                cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 10)
+                extra[f"{wlx.name}_p3_{tag}_integrate"] = dict(
+                    n_elem=wlx.n_elem, rule=rule_p3, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                    elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
+                    bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
+                log(f"{wlx.name} P3 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
+                    f"copy of the same bytes {cp_us:.1f} us")
+                del cps, ij, dj
+            del p3, wlx
+
         # ------------------------------------------------- element matrices --
         for cfg, order, rule_k, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
                                       ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",))):

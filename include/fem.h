@@ -110,7 +110,8 @@ enum fem_op {
     FEM_OP_RESIDUAL_P2 = 5,     /* fem_integrate_residual_p2 */
     FEM_OP_BACKWARD_P2 = 6,     /* fem_integrate_residual_p2_backward */
     FEM_OP_JACOBIAN = 7,        /* fem_integrate_jacobian, order 1 */
-    FEM_OP_JACOBIAN_P2 = 8      /* fem_integrate_jacobian, order 2 */
+    FEM_OP_JACOBIAN_P2 = 8,     /* fem_integrate_jacobian, order 2 */
+    FEM_OP_RESIDUAL_P3 = 9      /* fem_integrate_residual_p3 */
 };
 
 /* ------------------------------------------------------------------ */
@@ -225,6 +226,21 @@ fem_status fem_integrate_residual_backward(int dim, int physics, int rule, int c
  * weights times 1/6), which integrate the P2 mass matrix exactly.
  * Errors as fem_integrate_residual (FEM_ERR_UNSUPPORTED for other rules). */
 fem_status fem_integrate_residual_p2(int dim, int physics, int rule, int coef_space, int dtype,
+                                     int64_t n_elem, const void* inv_j, const void* det_j,
+                                     const void* u, const void* coef, void* elem_vec, void* stream);
+/* Element residuals for third-order (P3) Lagrange elements: the bracket
+ * of Eq. (2) with the P3 basis tabulated at the points (Section 3 takes
+ * any basis; the paper evaluates P1). Node order: vertices 0..d; per edge
+ * (i, j), i < j, lexicographic, the node at (2/3, 1/3) of (i, j) then the
+ * one at (1/3, 2/3); per face (i, j, k), lexicographic, its centroid
+ * (N_b = 10 in 2D, 20 in 3D). rule must be FEM_RULE_TRI6 (2D) or
+ * FEM_RULE_TET11 (3D), the degree-4 rules. Layouts as
+ * fem_integrate_residual_p2: inv_j [d*d][n_elem], det_j [n_elem], u
+ * [N_b*N_comp][n_elem] (row b*N_comp + c), coef [N_coef*N_w][n_elem],
+ * elem_vec [N_b*N_comp][n_elem], all device arrays of dtype. Errors: an
+ * unsupported dim, physics, rule, space or dtype -> FEM_ERR_UNSUPPORTED;
+ * negative n_elem or a NULL array -> FEM_ERR_INVALID_ARG. Asynchronous. */
+fem_status fem_integrate_residual_p3(int dim, int physics, int rule, int coef_space, int dtype,
                                      int64_t n_elem, const void* inv_j, const void* det_j,
                                      const void* u, const void* coef, void* elem_vec, void* stream);
 /* Adjoint of L = sum_e w_e . R_e for P2 elements; arguments and meaning as

@@ -8,6 +8,7 @@ are allocated with torch (plumbing only).
 from __future__ import annotations
 
 import ctypes
+import math
 
 import torch
 
@@ -31,8 +32,11 @@ def n_qpts(dim: int, rule: int) -> int:
 
 
 def n_basis(dim: int, order: int = 1) -> int:
-    """Lagrange nodes per element: d+1 (P1) or (d+1)(d+2)/2 (P2)."""
-    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
+    """Lagrange nodes per element: d+1 (P1), (d+1)(d+2)/2 (P2) or
+    (d+1)(d+2)(d+3)/6 (P3)."""
+    if order not in (1, 2, 3):
+        raise ValueError(f"no Lagrange elements of order {order}")
+    return math.comb(dim + order, order)
 
 
 def n_coef_words(dim: int, rule: int, coef_space: int = N.COEF_QUAD) -> int:
@@ -269,6 +273,29 @@ def fem_integrate_residual_p2(dim: int, physics: int, rule: int, inv_j, det_j, u
     _need(out, "out", dtype, su)
     N.check(N.lib().fem_integrate_residual_p2(dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j),
                                               _ptr(u), _ptr(coef), _ptr(out), _stream()), "fem_integrate_residual_p2")
+    return out
+
+
+def fem_integrate_residual_p3(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, out=None, *,
+                              coef_space=N.COEF_QUAD):
+    """Element residuals of third-order (P3) elements, R [N_b*N_comp, n] with
+    N_b = 10 (2D) or 20 (3D): vertices, two nodes per lexicographic edge
+    (the one nearer its first vertex first), then the faces; rule is the
+    degree-4 rule of the dimension."""
+    dtype = det_j.dtype
+    if dtype not in _DT:
+        raise TypeError("geometry must be float32 or float64")
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space, order=3)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(u, "u", dtype, su)
+    _need(coef, "coef", dtype, scf)
+    if out is None:
+        out = torch.empty(su, dtype=dtype, device=u.device)
+    _need(out, "out", dtype, su)
+    N.check(N.lib().fem_integrate_residual_p3(dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j),
+                                              _ptr(u), _ptr(coef), _ptr(out), _stream()), "fem_integrate_residual_p3")
     return out
 
 

@@ -77,6 +77,19 @@ static fem_status check_combo_p2(const char* fn, int dim, int phys, int rule, in
     return FEM_OK;
 }
 
+// P3 elements take the degree-4 rule of their dimension, which integrates
+// a stiffness entry with a constant coefficient exactly.
+static fem_status check_combo_p3(const char* fn, int dim, int phys, int rule, int dtype) {
+    if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
+    if (rule != (dim == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11)) {
+        set_error("%s: P3 in %dD takes rule %d only (got %d)", fn, dim, dim == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11, rule);
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (!valid_dtype(dtype)) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+    return FEM_OK;
+}
+
 // Rules of the element-matrix entry point for each order.
 static bool valid_rule_jac(int dim, int order, int rule) {
     const int low = dim == 2 ? FEM_RULE_TRI3 : FEM_RULE_TET4, high = dim == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
@@ -112,13 +125,14 @@ static std::map<TuneKey, fem_tuning> g_tune;
 static bool valid_op(int op) {
     return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
            op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 ||
-           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
+           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_RESIDUAL_P3;
 }
 
 // Ops whose kernels take one element per lane and at most four waves per
 // workgroup (register-heavy elements).
 static bool one_per_lane_op(int op) {
-    return op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
+    return op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 ||
+           op == FEM_OP_RESIDUAL_P3;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -220,6 +234,7 @@ static fem_status check_tuning_args(const char* fn, int op, int dim, int physics
         return FEM_OK;
     }
     if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return check_combo_p2(fn, dim, physics, rule, dtype);
+    if (op == FEM_OP_RESIDUAL_P3) return check_combo_p3(fn, dim, physics, rule, dtype);
     if (op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2)
         return check_combo_jac(fn, dim, physics, op == FEM_OP_JACOBIAN ? 1 : 2, rule, dtype);
     return check_combo(fn, dim, physics, rule, dtype);
@@ -375,6 +390,25 @@ fem_status fem_integrate_residual_p2(int dim, int physics, int rule, int coef_sp
     Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
     hipError_t e = launch_residual_p2(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p2 launch");
+}
+
+fem_status fem_integrate_residual_p3(int dim, int physics, int rule, int coef_space, int dtype, int64_t n_elem,
+                                     const void* inv_j, const void* det_j, const void* u, const void* coef,
+                                     void* elem_vec, void* stream) {
+    fem_status st = check_combo_p3("fem_integrate_residual_p3", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_p3", coef_space);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual_p3: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0) return FEM_OK;
+    if (!inv_j || !det_j || !u || !coef || !elem_vec) {
+        set_error("fem_integrate_residual_p3: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_P3, dim, physics, rule, dtype);
+    ResidualArgs a{n_elem, inv_j, det_j, u, coef, elem_vec};
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_residual_p3(dim, physics, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p3 launch");
 }
 
 fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, int coef_space, int dtype,

@@ -69,6 +69,7 @@ hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtyp
 hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                   const Launch& l);
 // Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
+hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
 hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                               const Launch& l);
 hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,

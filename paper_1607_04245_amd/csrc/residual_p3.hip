@@ -1,0 +1,103 @@
+// residual_p3.hip -- element residuals of third-order (P3) Lagrange elements
+// from precomputed affine geometry.
+//
+// One lane per element, as the P1 and P2 lane kernels: every SoA row
+// (inverse Jacobian, det J, the N_b * N_comp closure rows, the coefficient
+// rows) is one coalesced access per wave, and the quadrature and basis
+// phases run in registers with the basis tabulated at compile time
+// (p3_device.hpp). Workgroups hold at most four waves, so the largest
+// elements (3D elasticity in FP64, 60 closure and 60 output words) may use
+// the accumulation registers too instead of spilling to memory.
+#include "fem_internal.hpp"
+#include "p3_device.hpp"
+
+namespace femq {
+
+// The coefficient words of element e turned into values at the points: the
+// space is a uniform run-time branch (one kernel per dimension, physics and
+// type), the arithmetic after it is the same for every space.
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void p3_coef_points(int space, const Real* __restrict__ coef, int64_t n, int64_t e,
+                                               Real (&aq)[ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>::NCQ]) {
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    using Q = RuleP2<DIM, RULE>;
+    if (space == FEM_COEF_QUAD) {
+#pragma unroll
+        for (int f = 0; f < E::NCQ; ++f) aq[f] = __builtin_nontemporal_load(coef + f * n + e);
+    } else if (space == FEM_COEF_P1) {
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            Real c[E::NV];
+#pragma unroll
+            for (int v = 0; v < E::NV; ++v) c[v] = __builtin_nontemporal_load(coef + (m * E::NV + v) * n + e);
+#pragma unroll
+            for (int q = 0; q < E::NQ; ++q) {
+                Real t = Real(Q::lam(q, 0)) * c[0];
+#pragma unroll
+                for (int v = 1; v < E::NV; ++v) t = fmadd(Real(Q::lam(q, v)), c[v], t);
+                aq[m * E::NQ + q] = t;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            const Real c = __builtin_nontemporal_load(coef + m * n + e);
+#pragma unroll
+            for (int q = 0; q < E::NQ; ++q) aq[m * E::NQ + q] = c;
+        }
+    }
+}
+
+template <int DIM, int PHYS, typename Real>
+__global__ void __launch_bounds__(256)
+residual_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
+                   const Real* __restrict__ u, const Real* __restrict__ coef, Real* __restrict__ out) {
+    constexpr int RULE = DIM == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        Real ij[E::NG], uu[E::NBT], aq[E::NCQ], r[E::NBT];
+#pragma unroll
+        for (int f = 0; f < E::NG; ++f) ij[f] = __builtin_nontemporal_load(inv_j + f * n + e);
+        const Real dj = __builtin_nontemporal_load(det_j + e);
+#pragma unroll
+        for (int f = 0; f < E::NBT; ++f) uu[f] = __builtin_nontemporal_load(u + f * n + e);
+        p3_coef_points<DIM, PHYS, RULE, Real>(space, coef, n, e, aq);
+        element_residual_p3<DIM, PHYS, RULE, Real>(ij, dj, uu, aq, r);
+#pragma unroll
+        for (int f = 0; f < E::NBT; ++f) __builtin_nontemporal_store(r[f], out + f * n + e);
+    }
+}
+
+template <int DIM, int PHYS, typename Real>
+static hipError_t launch_fwd(int space, const ResidualArgs& a, const Launch& l) {
+    hipLaunchKernelGGL((residual_p3_kernel<DIM, PHYS, Real>), dim3(l.grid), dim3(l.block), 0, l.stream, a.n, space,
+                       static_cast<const Real*>(a.inv_j), static_cast<const Real*>(a.det_j),
+                       static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out));
+    return hipGetLastError();
+}
+
+// Runtime (dim, physics, dtype) to a kernel instance; the rule is the
+// degree-4 rule of the dimension (checked by the caller), the space a
+// kernel argument.
+hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l) {
+    if (space != FEM_COEF_QUAD && space != FEM_COEF_P1 && space != FEM_COEF_P0) return hipErrorInvalidValue;
+    auto by_phys = [&](auto dim_c) -> hipError_t {
+        constexpr int D = decltype(dim_c)::value;
+        auto go = [&](auto phys_c) -> hipError_t {
+            constexpr int P = decltype(phys_c)::value;
+            return dtype == FEM_F32 ? launch_fwd<D, P, float>(space, a, l) : launch_fwd<D, P, double>(space, a, l);
+        };
+        switch (phys) {
+        case FEM_LAPLACE: return go(std::integral_constant<int, FEM_LAPLACE>());
+        case FEM_ELASTICITY: return go(std::integral_constant<int, FEM_ELASTICITY>());
+        case FEM_MASS: return go(std::integral_constant<int, FEM_MASS>());
+        default: return hipErrorInvalidValue;
+        }
+    };
+    if (dim == 2) return by_phys(std::integral_constant<int, 2>());
+    if (dim == 3) return by_phys(std::integral_constant<int, 3>());
+    return hipErrorInvalidValue;
+}
+
+}  // namespace femq

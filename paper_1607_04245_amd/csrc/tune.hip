@@ -229,9 +229,10 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     }
     const bool jac = op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
     const bool p2 = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN_P2;
-    const bool one = p2 || jac;  // one element per lane
+    const bool p3 = op == FEM_OP_RESIDUAL_P3;
+    const bool one = p2 || p3 || jac;  // one element per lane
     const int nc = physics == FEM_ELASTICITY ? dim : 1;
-    const int nbt = (p2 ? (dim + 1) * (dim + 2) / 2 : dim + 1) * nc;
+    const int nbt = (p3 ? (dim + 1) * (dim + 2) * (dim + 3) / 6 : p2 ? (dim + 1) * (dim + 2) / 2 : dim + 1) * nc;
     const int out_rows = jac ? nbt * nbt : nbt;
     const int nq = rule == FEM_RULE_CENTROID ? 1 : rule == FEM_RULE_TRI6 ? 6 : rule == FEM_RULE_TET11 ? 11 : dim + 1;
     const int ncq = (physics == FEM_ELASTICITY ? 2 : 1) * nq;
@@ -301,6 +302,9 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         switch (op) {
         case FEM_OP_RESIDUAL_P2:
             return fem_integrate_residual_p2(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out,
+                                             nullptr);
+        case FEM_OP_RESIDUAL_P3:
+            return fem_integrate_residual_p3(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out,
                                              nullptr);
         case FEM_OP_BACKWARD_P2:
             return fem_integrate_residual_p2_backward(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf,

@@ -399,3 +399,24 @@ def p2_inputs(wl: "Workload", rule: int, seed: int) -> P2Inputs:
     u = closure(conn2, u_node)
     w = np.ascontiguousarray(r_w.uniform(-1.0, 1.0, size=u.shape))
     return P2Inputs(rule=rule, conn2=conn2, n_nodes=n_nodes, u_node=u_node, u=u, coef=coef, w=w)
+
+
+@dataclasses.dataclass
+class P3Inputs:
+    rule: int
+    u: np.ndarray          # [N_b * N_comp, N_e] closure rows, N_b = 10 (2D) or 20 (3D)
+    coef: np.ndarray       # [N_coef, N_q, N_e] values at the rule's points
+
+
+def p3_inputs(wl: "Workload", rule: int, seed: int) -> P3Inputs:
+    """Third-order inputs with the per-physics distributions of the P1
+    workloads, drawn from ``SeedSequence(seed).spawn(2)`` = [coef, u]. The
+    closure rows are drawn per element (the integration reads closure rows;
+    continuity of the field across elements does not enter it)."""
+    r_coef, r_u = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(2)]
+    nb = (wl.dim + 1) * (wl.dim + 2) * (wl.dim + 3) // 6
+    nq, ne = n_qpts(wl.dim, rule), wl.n_elem
+    coef = np.ascontiguousarray(_coef_draw(wl.physics, r_coef, (nq, ne)))
+    lo, hi = (-1e-2, 1e-2) if wl.physics == ELASTICITY else (-1.0, 1.0)
+    u = np.ascontiguousarray(r_u.uniform(lo, hi, size=(nb * wl.n_comp, ne)))
+    return P3Inputs(rule=rule, u=u, coef=coef)

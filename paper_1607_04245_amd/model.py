@@ -13,6 +13,7 @@ input word is read once and every output word written once.
 """
 from __future__ import annotations
 
+import math
 from fractions import Fraction
 
 # MI355X published peaks used as roofline denominators.
@@ -49,7 +50,7 @@ def n_qpts(dim: int, rule: int) -> int:
 
 
 def n_basis(dim: int, order: int = 1) -> int:
-    return dim + 1 if order == 1 else (dim + 1) * (dim + 2) // 2
+    return math.comb(dim + order, order)
 
 
 def n_coef_words(dim: int, rule: int, coef_space: int = 0) -> int:
@@ -151,4 +152,15 @@ def jacobian_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int
 def p2_forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
     """Compulsory bytes per element of fem_integrate_residual_p2."""
     nbt = n_basis(dim, 2) * n_comp(dim, physics)
+    return word * ((dim * dim + 1) + 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space))
+
+
+def p3_model_flops(dim: int, physics: int, rule: int) -> int:
+    """The paper's per-cell flop formula with the P3 basis (N_b = (d+1)(d+2)(d+3)/6)."""
+    return paper_flops_per_cell(dim, n_basis(dim, 3), n_comp(dim, physics), n_qpts(dim, rule))
+
+
+def p3_forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
+    """Compulsory bytes per element of fem_integrate_residual_p3."""
+    nbt = n_basis(dim, 3) * n_comp(dim, physics)
     return word * ((dim * dim + 1) + 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space))

@@ -123,7 +123,7 @@ def test_tuning_roundtrip(lib):
     assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_OK
     lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
-    assert lib.fem_set_tuning(9, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(10, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
 
 def test_batch_plan_validation(lib):
@@ -149,7 +149,7 @@ def test_autotune_validation(lib):
     R = N.OP_RESIDUAL
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
-    assert lib.fem_autotune(9, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_autotune(10, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG
 
 
@@ -226,6 +226,25 @@ def test_p2_validation(lib):
     t = N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0)
     assert lib.fem_set_tuning(N.OP_BACKWARD_P2, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
         == N.FEM_ERR_INVALID_ARG
+
+
+def test_p3_validation(lib):
+    f = lib.fem_integrate_residual_p3
+    ok = (3, mg.ELASTICITY, mg.RULE_TET11, N.COEF_P1, N.F64)
+    assert f(*ok, 0, None, None, None, None, None, None) == N.FEM_OK
+    assert f(*ok, -1, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
+    assert f(*ok, 5, _v(), _v(), _v(), None, _v(), None) == N.FEM_ERR_INVALID_ARG
+    for bad in [(3, mg.LAPLACE, mg.RULE_TET4, 0, N.F32), (2, mg.LAPLACE, mg.RULE_TRI3, 0, N.F32),
+                (2, mg.LAPLACE, mg.RULE_TET11, 0, N.F32), (3, mg.LAPLACE, mg.RULE_CENTROID, 0, N.F32),
+                (3, 7, mg.RULE_TET11, 0, N.F32), (3, mg.LAPLACE, mg.RULE_TET11, 5, N.F32),
+                (3, mg.LAPLACE, mg.RULE_TET11, 0, 3), (4, mg.LAPLACE, mg.RULE_TET11, 0, N.F32)]:
+        assert f(*bad, 5, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+    t = N.fem_tuning(N.STRATEGY_LANE, 1, 8, 0)   # at most four waves per block
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_P3, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_INVALID_ARG
+    t = N.fem_tuning(N.STRATEGY_LANE, 1, 4, 0)
+    assert lib.fem_set_tuning(N.OP_RESIDUAL_P3, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) \
+        == N.FEM_ERR_UNSUPPORTED
 
 
 def test_mesh_plan_validation(lib):

@@ -1,0 +1,141 @@
+"""GPU parity of third-order (P3) elements through the C ABI against the
+FP64 oracle (order 3), with the bars of the P1 and P2 tests: scaled
+per-element error and aggregate error <= 1e-5 in FP32, <= 1e-12 in FP64.
+Also: launch-shape independence (bitwise), K_e u_e of the oracle's element
+matrices, empty input, rejected rules, and the full-size meshes (sampled
+elements against the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1607_04245_amd import api, meshgen as mg
+from paper_1607_04245_amd import _native as N
+
+from _parity import assert_close, dev, rounded
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+KINDS = [(2, mg.LAPLACE), (3, mg.LAPLACE), (2, mg.ELASTICITY), (3, mg.ELASTICITY), (2, mg.MASS), (3, mg.MASS)]
+RULE = {2: mg.RULE_TRI6, 3: mg.RULE_TET11}
+SPACES = [mg.COEF_QUAD, mg.COEF_P1, mg.COEF_P0]
+
+
+def workload(dim, phys, n_elem, seed=81):
+    grid = mg.smallest_grid(dim, max(n_elem, 1))
+    wl = mg.make_workload(f"p3_{dim}{phys}", dim, phys, grid, n_elem, mg.BASE_SEED + seed)
+    return wl, mg.p3_inputs(wl, RULE[dim], mg.BASE_SEED + 7000 + seed)
+
+
+def coefficients(wl, p3, space):
+    if space == mg.COEF_QUAD:
+        return p3.coef
+    return mg.space_coefficients(wl, space, mg.BASE_SEED + 7500)
+
+
+def geometry(wl, dtype):
+    return api.fem_geometry(dev(wl.coords, torch.float64), dev(wl.conn, torch.int32), dtype)
+
+
+def reference(wl, u, cf, space, dtype, cols=None):
+    ij, dj, nd = oracle.geometry(wl.coords, wl.conn)
+    assert nd == 0
+    ur, cr = rounded(u, dtype), rounded(cf, dtype)
+    if cols is not None:
+        ij, dj, ur, cr = ij[:, cols], dj[cols], ur[:, cols], cr[..., cols]
+    rule = RULE[wl.dim]
+    R = oracle.integrate(wl.dim, wl.physics, rule, ij, dj, ur, cr, space=space, order=3)
+    Ra = oracle.integrate_abs(wl.dim, wl.physics, rule, ij, dj, ur, cr, space=space, order=3)
+    return R, Ra
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    saved = {}
+    for dim, phys in KINDS:
+        for dt in DTYPES:
+            saved[(dim, phys, dt)] = api.fem_get_tuning(dim, phys, RULE[dim], dt, op=N.OP_RESIDUAL_P3)
+    yield
+    for (dim, phys, dt), t in saved.items():
+        api.fem_set_tuning(dim, phys, RULE[dim], dt, op=N.OP_RESIDUAL_P3, **t)
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("space", SPACES)
+def test_p3_forward_matches_oracle(dim, phys, dtype, space):
+    wl, p3 = workload(dim, phys, 1500)
+    cf = coefficients(wl, p3, space)
+    ij, dj = geometry(wl, dtype)
+    R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, dev(p3.u, dtype), dev(cf, dtype), coef_space=space)
+    ref, ref_abs = reference(wl, p3.u, cf, space, dtype)
+    assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"P3 {dim}D phys {phys} space {space}")
+
+
+@pytest.mark.parametrize("dim,phys", [(2, mg.LAPLACE), (3, mg.ELASTICITY)])
+def test_p3_matches_oracle_element_matrices(dim, phys):
+    """R_e = K_e u_e with K_e the oracle's P3 element matrix (FP64)."""
+    dt = torch.float64
+    wl, p3 = workload(dim, phys, 300, seed=83)
+    ij, dj = geometry(wl, dt)
+    R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, dev(p3.u, dt), dev(p3.coef, dt)).cpu().numpy()
+    rij, rdj, _ = oracle.geometry(wl.coords, wl.conn)
+    K = oracle.jacobian(dim, phys, RULE[dim], rij, rdj, p3.coef, order=3)
+    m = p3.u.shape[0]
+    Ku = np.einsum("rse,se->re", K.reshape(m, m, -1), p3.u)
+    Ra = oracle.integrate_abs(dim, phys, RULE[dim], rij, rdj, p3.u, p3.coef, order=3)
+    err = np.linalg.norm(R - Ku, axis=0) / np.linalg.norm(Ra, axis=0)
+    assert err.max() <= 1e-12, err.max()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dim,phys", [(3, mg.ELASTICITY), (2, mg.LAPLACE)])
+def test_p3_launch_shapes_bitwise(dtype, dim, phys):
+    wl, p3 = workload(dim, phys, 4099, seed=85)
+    ij, dj = geometry(wl, dtype)
+    u, cf = dev(p3.u, dtype), dev(p3.coef, dtype)
+    first = None
+    for waves, bpc in [(2, 0), (1, 4), (4, 0), (4, 2)]:
+        api.fem_set_tuning(dim, phys, RULE[dim], dtype, vec=1, waves_per_block=waves, blocks_per_cu=bpc,
+                           op=N.OP_RESIDUAL_P3)
+        R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, u, cf)
+        first = R.clone() if first is None else first
+        assert torch.equal(R, first), (waves, bpc)
+    with pytest.raises(N.FemError):
+        api.fem_set_tuning(dim, phys, RULE[dim], dtype, vec=1, waves_per_block=8, op=N.OP_RESIDUAL_P3)
+
+
+def test_p3_empty_and_rejected():
+    e = torch.empty((9, 0), device="cuda")
+    R = api.fem_integrate_residual_p3(3, mg.LAPLACE, mg.RULE_TET11, e, torch.empty(0, device="cuda"),
+                                      torch.empty((20, 0), device="cuda"), torch.empty((1, 11, 0), device="cuda"))
+    assert R.shape == (20, 0)
+    wl, p3 = workload(2, mg.LAPLACE, 10)
+    ij, dj = geometry(wl, torch.float32)
+    with pytest.raises(N.FemError) as ei:   # degree-2 rule: not offered for P3
+        api.fem_integrate_residual_p3(2, mg.LAPLACE, mg.RULE_TRI3, ij, dj, dev(p3.u, torch.float32),
+                                      torch.ones((1, 3, 10), device="cuda"))
+    assert ei.value.status == N.FEM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("cfg", [2, "3b", "3a"])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_p3_full_size_meshes(cfg, dtype):
+    """The benchmark meshes (2^20 tetrahedra, Laplacian; 2^21 tetrahedra and
+    2^22 triangles, elasticity) with P3 closures and the degree-4 rules:
+    every output finite; 4096 sampled elements (first and last included)
+    against the oracle."""
+    wl = mg.config(cfg)
+    p3 = mg.p3_inputs(wl, RULE[wl.dim], mg.BASE_SEED + 7700)
+    ij, dj = geometry(wl, dtype)
+    R = api.fem_integrate_residual_p3(wl.dim, wl.physics, RULE[wl.dim], ij, dj, dev(p3.u, dtype),
+                                      dev(p3.coef, dtype))
+    assert bool(torch.isfinite(R).all())
+    rng = np.random.default_rng(9)
+    cols = np.unique(np.concatenate([[0, wl.n_elem - 1], rng.integers(0, wl.n_elem, 4094)]))
+    got = R[:, torch.from_numpy(cols).to("cuda")].cpu().numpy()
+    del R
+    ref, ref_abs = reference(wl, p3.u, p3.coef, mg.COEF_QUAD, dtype, cols=cols)
+    mx, agg = assert_close(got, ref, ref_abs, dtype, f"P3 {wl.name}")
+    print(f"P3 {wl.name} {dtype}: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
