@@ -111,7 +111,8 @@ enum fem_op {
     FEM_OP_BACKWARD_P2 = 6,     /* fem_integrate_residual_p2_backward */
     FEM_OP_JACOBIAN = 7,        /* fem_integrate_jacobian, order 1 */
     FEM_OP_JACOBIAN_P2 = 8,     /* fem_integrate_jacobian, order 2 */
-    FEM_OP_RESIDUAL_P3 = 9      /* fem_integrate_residual_p3 */
+    FEM_OP_RESIDUAL_P3 = 9,     /* fem_integrate_residual_p3 */
+    FEM_OP_BACKWARD_P3 = 10     /* fem_integrate_residual_p3_backward */
 };
 
 /* ------------------------------------------------------------------ */
@@ -243,6 +244,14 @@ fem_status fem_integrate_residual_p2(int dim, int physics, int rule, int coef_sp
 fem_status fem_integrate_residual_p3(int dim, int physics, int rule, int coef_space, int dtype,
                                      int64_t n_elem, const void* inv_j, const void* det_j,
                                      const void* u, const void* coef, void* elem_vec, void* stream);
+/* Adjoint of L = sum_e w_e . R_e for P3 elements; arguments, NULL rules
+ * and meaning as fem_integrate_residual_backward with the P3 layouts of
+ * fem_integrate_residual_p3 (du = R(w), the forms being symmetric; dcoef in
+ * the coefficient's space). */
+fem_status fem_integrate_residual_p3_backward(int dim, int physics, int rule, int coef_space, int dtype,
+                                              int64_t n_elem, const void* inv_j, const void* det_j,
+                                              const void* u, const void* coef, const void* w, void* du,
+                                              void* dcoef, void* stream);
 /* Adjoint of L = sum_e w_e . R_e for P2 elements; arguments and meaning as
  * fem_integrate_residual_backward with the P2 layouts above. */
 fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, int coef_space, int dtype,

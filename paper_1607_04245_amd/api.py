@@ -299,6 +299,34 @@ def fem_integrate_residual_p3(dim: int, physics: int, rule: int, inv_j, det_j, u
     return out
 
 
+def fem_integrate_residual_p3_backward(dim: int, physics: int, rule: int, inv_j, det_j, u, coef, w,
+                                       want_du=True, want_dcoef=True, du=None, dcoef=None, *, coef_space=N.COEF_QUAD):
+    """(du, dcoef) of L = sum w.R for P3 elements (see fem_integrate_residual_p3)."""
+    dtype = det_j.dtype
+    n = det_j.shape[0]
+    sij, sdj, su, scf = _shapes(dim, physics, rule, n, coef_space, order=3)
+    _need(inv_j, "inv_j", dtype, sij)
+    _need(det_j, "det_j", dtype, sdj)
+    _need(w, "w", dtype, su)
+    if want_du:
+        _need(coef, "coef", dtype, scf)
+        du = torch.empty(su, dtype=dtype, device=w.device) if du is None else du
+        _need(du, "du", dtype, su)
+    else:
+        du = None
+    if want_dcoef:
+        _need(u, "u", dtype, su)
+        dcoef = torch.empty(scf, dtype=dtype, device=w.device) if dcoef is None else dcoef
+        _need(dcoef, "dcoef", dtype, scf)
+    else:
+        dcoef = None
+    N.check(N.lib().fem_integrate_residual_p3_backward(
+        dim, physics, rule, coef_space, _DT[dtype], n, _ptr(inv_j), _ptr(det_j), _ptr(u) if want_dcoef else None,
+        _ptr(coef) if want_du else None, _ptr(w), _ptr(du), _ptr(dcoef), _stream()),
+        "fem_integrate_residual_p3_backward")
+    return du, dcoef
+
+
 def fem_integrate_jacobian(dim: int, physics: int, rule: int, inv_j, det_j, coef, out=None, *,
                            coef_space=N.COEF_QUAD, order=1):
     """Element matrices K = dR_e/du_e [N_bt*N_bt, n] (row r*N_bt + s: test
@@ -650,21 +678,22 @@ class IntegrateResidual(torch.autograd.Function):
     def forward(ctx, dim, physics, rule, inv_j, det_j, u, coef, coef_space, order):
         ctx.save_for_backward(inv_j, det_j, u, coef)
         ctx.meta = (dim, physics, rule, coef_space, order)
-        fwd = fem_integrate_residual if order == 1 else fem_integrate_residual_p2
+        fwd = {1: fem_integrate_residual, 2: fem_integrate_residual_p2, 3: fem_integrate_residual_p3}[order]
         return fwd(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), coef_space=coef_space)
 
     @staticmethod
     def backward(ctx, grad_r):
         inv_j, det_j, u, coef = ctx.saved_tensors
         dim, physics, rule, coef_space, order = ctx.meta
-        bwd = fem_integrate_residual_backward if order == 1 else fem_integrate_residual_p2_backward
+        bwd = {1: fem_integrate_residual_backward, 2: fem_integrate_residual_p2_backward,
+               3: fem_integrate_residual_p3_backward}[order]
         du, dcoef = bwd(dim, physics, rule, inv_j, det_j, u.contiguous(), coef.contiguous(), grad_r.contiguous(),
                         want_du=ctx.needs_input_grad[5], want_dcoef=ctx.needs_input_grad[6], coef_space=coef_space)
         return None, None, None, None, None, du, dcoef, None, None
 
 
 def integrate_residual(dim, physics, rule, inv_j, det_j, u, coef, coef_space=N.COEF_QUAD, order=1):
-    """Differentiable element residuals (see IntegrateResidual); order 1 (P1) or 2 (P2)."""
-    if order not in (1, 2):
-        raise ValueError("order must be 1 or 2")
+    """Differentiable element residuals (see IntegrateResidual); order 1 (P1), 2 (P2) or 3 (P3)."""
+    if order not in (1, 2, 3):
+        raise ValueError("order must be 1, 2 or 3")
     return IntegrateResidual.apply(dim, physics, rule, inv_j, det_j, u, coef, coef_space, order)

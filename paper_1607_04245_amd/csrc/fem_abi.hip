@@ -125,14 +125,14 @@ static std::map<TuneKey, fem_tuning> g_tune;
 static bool valid_op(int op) {
     return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
            op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 ||
-           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_RESIDUAL_P3;
+           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3;
 }
 
 // Ops whose kernels take one element per lane and at most four waves per
 // workgroup (register-heavy elements).
 static bool one_per_lane_op(int op) {
     return op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 ||
-           op == FEM_OP_RESIDUAL_P3;
+           op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -155,7 +155,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     }
     // P3: the 3D elements hold 20-60 closure and output words per lane, and
     // single-wave workgroups measured fastest there; 2D streams better with four
-    if (op == FEM_OP_RESIDUAL_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
+    if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
     if (op == FEM_OP_RESIDUAL_MESH) {
@@ -237,7 +237,7 @@ static fem_status check_tuning_args(const char* fn, int op, int dim, int physics
         return FEM_OK;
     }
     if (op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2) return check_combo_p2(fn, dim, physics, rule, dtype);
-    if (op == FEM_OP_RESIDUAL_P3) return check_combo_p3(fn, dim, physics, rule, dtype);
+    if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return check_combo_p3(fn, dim, physics, rule, dtype);
     if (op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2)
         return check_combo_jac(fn, dim, physics, op == FEM_OP_JACOBIAN ? 1 : 2, rule, dtype);
     return check_combo(fn, dim, physics, rule, dtype);
@@ -431,6 +431,25 @@ fem_status fem_integrate_residual_p2_backward(int dim, int physics, int rule, in
     Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
     hipError_t e = launch_backward_p2(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p2_backward launch");
+}
+
+fem_status fem_integrate_residual_p3_backward(int dim, int physics, int rule, int coef_space, int dtype,
+                                              int64_t n_elem, const void* inv_j, const void* det_j, const void* u,
+                                              const void* coef, const void* w, void* du, void* dcoef, void* stream) {
+    fem_status st = check_combo_p3("fem_integrate_residual_p3_backward", dim, physics, rule, dtype);
+    if (!st) st = check_space("fem_integrate_residual_p3_backward", coef_space);
+    if (st) return st;
+    if (n_elem < 0) { set_error("fem_integrate_residual_p3_backward: negative n_elem"); return FEM_ERR_INVALID_ARG; }
+    if (n_elem == 0 || (!du && !dcoef)) return FEM_OK;
+    if (!inv_j || !det_j || !w || (du && !coef) || (dcoef && !u)) {
+        set_error("fem_integrate_residual_p3_backward: NULL array");
+        return FEM_ERR_INVALID_ARG;
+    }
+    const fem_tuning t = get_tuning(FEM_OP_BACKWARD_P3, dim, physics, rule, dtype);
+    BackwardArgs a{n_elem, inv_j, det_j, u, coef, w, du, dcoef};
+    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_backward_p3(dim, physics, coef_space, dtype, a, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p3_backward launch");
 }
 
 fem_status fem_integrate_jacobian(int dim, int physics, int rule, int coef_space, int order, int dtype,

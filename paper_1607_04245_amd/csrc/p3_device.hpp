@@ -181,4 +181,80 @@ __device__ __forceinline__ void element_residual_p3(const Real* ij, Real dj, con
     });
 }
 
+// Derivative of L = w . R with respect to the coefficient values at the
+// points (the forms are linear in the coefficients): dq[m*NQ + q] =
+// w_q |J| [w^q . f0(u; e_m) + grad w : f1(u; e_m)].
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void element_dcoef_points_p3(const Real* ij, Real dj, const Real* u, const Real* w,
+                                                        Real* dq) {
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    using Q = RuleP2<DIM, RULE>;
+    using T = P3Basis<DIM, RULE>;
+    using P = Physics<PHYS>;
+    constexpr int NC = E::NC, NV = E::NV, NB = E::NB;
+    const Real adj = fabs(dj);
+    Real g[NV][DIM];
+    p2_bary_grads<DIM, Real>(ij, g);
+    // value and physical gradient of a field at point q
+    auto field_at = [&](auto q_c, const Real* f, Real (&fq)[NC], Real (&gf)[NC][DIM]) {
+        constexpr int q = decltype(q_c)::value;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (P::HAS_F0) {
+                Real s = Real(0);
+                unroll_for<0, NB>([&](auto b_c) {
+                    constexpr int b = decltype(b_c)::value;
+                    s = fmadd(Real(T::phi(q, b)), f[b * NC + c], s);
+                });
+                fq[c] = s;
+            }
+            if constexpr (P::HAS_F1) {
+                Real U[NV];
+                unroll_for<0, NV>([&](auto v_c) {
+                    constexpr int v = decltype(v_c)::value;
+                    Real s = Real(0);
+                    unroll_for<0, NB>([&](auto b_c) {
+                        constexpr int b = decltype(b_c)::value;
+                        constexpr double d = T::dl(q, b, v);
+                        if constexpr (d != 0.0) s = fmadd(Real(d), f[b * NC + c], s);
+                    });
+                    U[v] = s;
+                });
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    Real s = U[0] * g[0][i];
+#pragma unroll
+                    for (int v = 1; v < NV; ++v) s = fmadd(U[v], g[v][i], s);
+                    gf[c][i] = s;
+                }
+            }
+        }
+    };
+    unroll_for<0, E::NQ>([&](auto q_c) {
+        constexpr int q = decltype(q_c)::value;
+        Real uq[NC], gu[NC][DIM], wq[NC], gw[NC][DIM];
+        field_at(q_c, u, uq, gu);
+        field_at(q_c, w, wq, gw);
+        const Real s = Real(Q::w(q)) * adj;
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            Real a[E::NCOEF];
+#pragma unroll
+            for (int mm = 0; mm < E::NCOEF; ++mm) a[mm] = Real(mm == m ? 1 : 0);
+            Real f0[NC], f1[NC][DIM];
+            P::template point<DIM, Real>(uq, gu, a, f0, f1);
+            Real acc = Real(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (P::HAS_F0) acc = fmadd(wq[c], f0[c], acc);
+                if constexpr (P::HAS_F1) {
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) acc = fmadd(gw[c][i], f1[c][i], acc);
+                }
+            }
+            dq[m * E::NQ + q] = s * acc;
+        }
+    });
+}
+
 }  // namespace femq

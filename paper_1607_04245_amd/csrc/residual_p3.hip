@@ -1,5 +1,5 @@
 // residual_p3.hip -- element residuals of third-order (P3) Lagrange elements
-// from precomputed affine geometry.
+// and their adjoint from precomputed affine geometry.
 //
 // One lane per element, as the P1 and P2 lane kernels: every SoA row
 // (inverse Jacobian, det J, the N_b * N_comp closure rows, the coefficient
@@ -69,6 +69,73 @@ residual_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const R
     }
 }
 
+// du = R(w) (the forms are symmetric) and dcoef, the derivative with respect
+// to the coefficient words: the point values mapped back onto the space
+// (the transpose of p3_coef_points). Either output may be skipped
+// (uniform flags); u is read only for dcoef.
+template <int DIM, int PHYS, typename Real>
+__global__ void __launch_bounds__(256)
+backward_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
+                   const Real* __restrict__ u, const Real* __restrict__ coef, const Real* __restrict__ w,
+                   Real* __restrict__ du, Real* __restrict__ dcoef) {
+    constexpr int RULE = DIM == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    using Q = RuleP2<DIM, RULE>;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        Real ij[E::NG], ww[E::NBT];
+#pragma unroll
+        for (int f = 0; f < E::NG; ++f) ij[f] = __builtin_nontemporal_load(inv_j + f * n + e);
+        const Real dj = __builtin_nontemporal_load(det_j + e);
+#pragma unroll
+        for (int f = 0; f < E::NBT; ++f) ww[f] = __builtin_nontemporal_load(w + f * n + e);
+        if (du != nullptr) {
+            Real aq[E::NCQ], r[E::NBT];
+            p3_coef_points<DIM, PHYS, RULE, Real>(space, coef, n, e, aq);
+            element_residual_p3<DIM, PHYS, RULE, Real>(ij, dj, ww, aq, r);
+#pragma unroll
+            for (int f = 0; f < E::NBT; ++f) __builtin_nontemporal_store(r[f], du + f * n + e);
+        }
+        if (dcoef != nullptr) {
+            Real uu[E::NBT], dq[E::NCQ];
+#pragma unroll
+            for (int f = 0; f < E::NBT; ++f) uu[f] = __builtin_nontemporal_load(u + f * n + e);
+            element_dcoef_points_p3<DIM, PHYS, RULE, Real>(ij, dj, uu, ww, dq);
+            if (space == FEM_COEF_QUAD) {
+#pragma unroll
+                for (int f = 0; f < E::NCQ; ++f) __builtin_nontemporal_store(dq[f], dcoef + f * n + e);
+            } else if (space == FEM_COEF_P1) {
+#pragma unroll
+                for (int m = 0; m < E::NCOEF; ++m)
+#pragma unroll
+                    for (int v = 0; v < E::NV; ++v) {
+                        Real t = Real(0);
+#pragma unroll
+                        for (int q = 0; q < E::NQ; ++q) t = fmadd(Real(Q::lam(q, v)), dq[m * E::NQ + q], t);
+                        __builtin_nontemporal_store(t, dcoef + (m * E::NV + v) * n + e);
+                    }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E::NCOEF; ++m) {
+                    Real t = Real(0);
+#pragma unroll
+                    for (int q = 0; q < E::NQ; ++q) t += dq[m * E::NQ + q];
+                    __builtin_nontemporal_store(t, dcoef + m * n + e);
+                }
+            }
+        }
+    }
+}
+
+template <int DIM, int PHYS, typename Real>
+static hipError_t launch_bwd(int space, const BackwardArgs& a, const Launch& l) {
+    hipLaunchKernelGGL((backward_p3_kernel<DIM, PHYS, Real>), dim3(l.grid), dim3(l.block), 0, l.stream, a.n, space,
+                       static_cast<const Real*>(a.inv_j), static_cast<const Real*>(a.det_j),
+                       static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<const Real*>(a.w),
+                       static_cast<Real*>(a.du), static_cast<Real*>(a.dcoef));
+    return hipGetLastError();
+}
+
 template <int DIM, int PHYS, typename Real>
 static hipError_t launch_fwd(int space, const ResidualArgs& a, const Launch& l) {
     hipLaunchKernelGGL((residual_p3_kernel<DIM, PHYS, Real>), dim3(l.grid), dim3(l.block), 0, l.stream, a.n, space,
@@ -80,13 +147,14 @@ static hipError_t launch_fwd(int space, const ResidualArgs& a, const Launch& l) 
 // Runtime (dim, physics, dtype) to a kernel instance; the rule is the
 // degree-4 rule of the dimension (checked by the caller), the space a
 // kernel argument.
-hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l) {
+template <typename F>
+static hipError_t p3_dispatch(int dim, int phys, int space, int dtype, const F& f) {
     if (space != FEM_COEF_QUAD && space != FEM_COEF_P1 && space != FEM_COEF_P0) return hipErrorInvalidValue;
     auto by_phys = [&](auto dim_c) -> hipError_t {
         constexpr int D = decltype(dim_c)::value;
         auto go = [&](auto phys_c) -> hipError_t {
             constexpr int P = decltype(phys_c)::value;
-            return dtype == FEM_F32 ? launch_fwd<D, P, float>(space, a, l) : launch_fwd<D, P, double>(space, a, l);
+            return dtype == FEM_F32 ? f.template operator()<D, P, float>() : f.template operator()<D, P, double>();
         };
         switch (phys) {
         case FEM_LAPLACE: return go(std::integral_constant<int, FEM_LAPLACE>());
@@ -98,6 +166,30 @@ hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const Res
     if (dim == 2) return by_phys(std::integral_constant<int, 2>());
     if (dim == 3) return by_phys(std::integral_constant<int, 3>());
     return hipErrorInvalidValue;
+}
+
+struct P3Fwd {
+    int space;
+    const ResidualArgs& a;
+    const Launch& l;
+    template <int D, int P, typename Real>
+    hipError_t operator()() const { return launch_fwd<D, P, Real>(space, a, l); }
+};
+
+struct P3Bwd {
+    int space;
+    const BackwardArgs& a;
+    const Launch& l;
+    template <int D, int P, typename Real>
+    hipError_t operator()() const { return launch_bwd<D, P, Real>(space, a, l); }
+};
+
+hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l) {
+    return p3_dispatch(dim, phys, space, dtype, P3Fwd{space, a, l});
+}
+
+hipError_t launch_backward_p3(int dim, int phys, int space, int dtype, const BackwardArgs& a, const Launch& l) {
+    return p3_dispatch(dim, phys, space, dtype, P3Bwd{space, a, l});
 }
 
 }  // namespace femq

@@ -123,7 +123,7 @@ def test_tuning_roundtrip(lib):
     assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_OK
     lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
-    assert lib.fem_set_tuning(10, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(11, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
 
 def test_batch_plan_validation(lib):
@@ -149,7 +149,7 @@ def test_autotune_validation(lib):
     R = N.OP_RESIDUAL
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
-    assert lib.fem_autotune(10, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_autotune(11, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG
 
 
@@ -239,9 +239,16 @@ def test_p3_validation(lib):
                 (3, 7, mg.RULE_TET11, 0, N.F32), (3, mg.LAPLACE, mg.RULE_TET11, 5, N.F32),
                 (3, mg.LAPLACE, mg.RULE_TET11, 0, 3), (4, mg.LAPLACE, mg.RULE_TET11, 0, N.F32)]:
         assert f(*bad, 5, _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+    b = lib.fem_integrate_residual_p3_backward
+    for bad in [(3, mg.LAPLACE, mg.RULE_TET4, 0, N.F32), (2, mg.LAPLACE, mg.RULE_TRI3, 0, N.F32),
+                (3, mg.LAPLACE, mg.RULE_TET11, 5, N.F32)]:
+        assert b(*bad, 5, _v(), _v(), _v(), _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
+    assert b(*ok, 5, _v(), _v(), None, None, _v(), None, None, None) == N.FEM_OK            # nothing wanted
+    assert b(*ok, 5, _v(), _v(), None, _v(), _v(), None, _v(), None) == N.FEM_ERR_INVALID_ARG  # dcoef needs u
+    assert b(*ok, 5, _v(), _v(), _v(), None, _v(), _v(), None, None) == N.FEM_ERR_INVALID_ARG  # du needs coef
     t = N.fem_tuning(N.STRATEGY_LANE, 1, 8, 0)   # at most four waves per block
-    assert lib.fem_set_tuning(N.OP_RESIDUAL_P3, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) \
-        == N.FEM_ERR_INVALID_ARG
+    for op in (N.OP_RESIDUAL_P3, N.OP_BACKWARD_P3):
+        assert lib.fem_set_tuning(op, 3, mg.LAPLACE, mg.RULE_TET11, N.F32, ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
     t = N.fem_tuning(N.STRATEGY_LANE, 1, 4, 0)
     assert lib.fem_set_tuning(N.OP_RESIDUAL_P3, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) \
         == N.FEM_ERR_UNSUPPORTED

@@ -1,7 +1,8 @@
 """GPU parity of third-order (P3) elements through the C ABI against the
 FP64 oracle (order 3), with the bars of the P1 and P2 tests: scaled
 per-element error and aggregate error <= 1e-5 in FP32, <= 1e-12 in FP64.
-Also: launch-shape independence (bitwise), K_e u_e of the oracle's element
+The adjoint (du, dcoef) likewise, and through autograd against central
+differences. Also: launch-shape independence (bitwise), K_e u_e of the oracle's element
 matrices, empty input, rejected rules, and the full-size meshes (sampled
 elements against the oracle)."""
 import numpy as np
@@ -55,10 +56,11 @@ def _reset_tuning():
     saved = {}
     for dim, phys in KINDS:
         for dt in DTYPES:
-            saved[(dim, phys, dt)] = api.fem_get_tuning(dim, phys, RULE[dim], dt, op=N.OP_RESIDUAL_P3)
+            for op in (N.OP_RESIDUAL_P3, N.OP_BACKWARD_P3):
+                saved[(dim, phys, dt, op)] = api.fem_get_tuning(dim, phys, RULE[dim], dt, op=op)
     yield
-    for (dim, phys, dt), t in saved.items():
-        api.fem_set_tuning(dim, phys, RULE[dim], dt, op=N.OP_RESIDUAL_P3, **t)
+    for (dim, phys, dt, op), t in saved.items():
+        api.fem_set_tuning(dim, phys, RULE[dim], dt, op=op, **t)
 
 
 @pytest.mark.parametrize("dim,phys", KINDS)
@@ -71,6 +73,69 @@ def test_p3_forward_matches_oracle(dim, phys, dtype, space):
     R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, dev(p3.u, dtype), dev(cf, dtype), coef_space=space)
     ref, ref_abs = reference(wl, p3.u, cf, space, dtype)
     assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"P3 {dim}D phys {phys} space {space}")
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("space", SPACES)
+def test_p3_backward_matches_oracle(dim, phys, dtype, space):
+    """du and dcoef against the oracle's P3 adjoint; du is also bitwise the
+    forward kernel applied to w."""
+    wl, p3 = workload(dim, phys, 1025, seed=87)
+    cf = coefficients(wl, p3, space)
+    w = np.random.default_rng(88).uniform(-1, 1, p3.u.shape)
+    ij, dj = geometry(wl, dtype)
+    rule = RULE[dim]
+    du, dc = api.fem_integrate_residual_p3_backward(dim, phys, rule, ij, dj, dev(p3.u, dtype), dev(cf, dtype),
+                                                    dev(w, dtype), coef_space=space)
+    rij, rdj, _ = oracle.geometry(wl.coords, wl.conn)
+    ur, cr, wr = rounded(p3.u, dtype), rounded(cf, dtype), rounded(w, dtype)
+    rdu, rdc = oracle.backward(dim, phys, rule, rij, rdj, ur, cr, wr, space=space, order=3)
+    du_abs = oracle.integrate_abs(dim, phys, rule, rij, rdj, wr, cr, space=space, order=3)
+    assert_close(du.cpu().numpy(), rdu, du_abs, dtype, "du")
+    # dcoef scale: |w| . R_abs(u; unit coefficient word)
+    nco, nw, n = rdc.shape
+    dc_abs = np.zeros_like(rdc)
+    for m in range(nco):
+        for k in range(nw):
+            unit = np.zeros_like(rdc)
+            unit[m, k] = 1.0
+            dc_abs[m, k] = np.sum(np.abs(wr) * oracle.integrate_abs(dim, phys, rule, rij, rdj, ur, unit,
+                                                                    space=space, order=3), axis=0)
+    assert_close(dc.cpu().numpy().reshape(nco * nw, n), rdc.reshape(nco * nw, n), dc_abs.reshape(nco * nw, n),
+                 dtype, "dcoef")
+    R_w = api.fem_integrate_residual_p3(dim, phys, rule, ij, dj, dev(w, dtype), dev(cf, dtype), coef_space=space)
+    assert torch.equal(du, R_w)
+
+
+def test_p3_autograd_central_differences():
+    dt = torch.float64
+    wl, p3 = workload(3, mg.ELASTICITY, 64, seed=89)
+    ij, dj = geometry(wl, dt)
+    u = dev(p3.u, dt).requires_grad_(True)
+    cf = dev(p3.coef, dt).requires_grad_(True)
+    w = dev(np.random.default_rng(90).uniform(-1, 1, p3.u.shape), dt)
+    L = (api.integrate_residual(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u, cf, order=3) * w).sum()
+    L.backward()
+    gu, gc = u.grad.cpu().numpy(), cf.grad.cpu().numpy()
+    rng = np.random.default_rng(4)
+
+    def Lof(uu, cc):
+        return float((api.fem_integrate_residual_p3(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, uu, cc) * w).sum())
+
+    with torch.no_grad():
+        for _ in range(4):
+            j, e = int(rng.integers(u.shape[0])), int(rng.integers(u.shape[1]))
+            up, um = u.detach().clone(), u.detach().clone()
+            up[j, e] += 1e-3
+            um[j, e] -= 1e-3
+            assert abs((Lof(up, cf.detach()) - Lof(um, cf.detach())) / 2e-3 - gu[j, e]) <= 1e-9 * np.abs(gu).max()
+            m, q = int(rng.integers(2)), int(rng.integers(11))
+            cp, cm = cf.detach().clone(), cf.detach().clone()
+            h = 1e-3 * max(1.0, abs(p3.coef[m, q, e]))
+            cp[m, q, e] += h
+            cm[m, q, e] -= h
+            assert abs((Lof(u.detach(), cp) - Lof(u.detach(), cm)) / (2 * h) - gc[m, q, e]) <= 1e-9 * np.abs(gc).max()
 
 
 @pytest.mark.parametrize("dim,phys", [(2, mg.LAPLACE), (3, mg.ELASTICITY)])
