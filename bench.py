@@ -579,6 +579,19 @@ def main():
                 log(f"{wlx.name} P3 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
                     f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
                     f"copy of the same bytes {cp_us:.1f} us")
+                if wlx.dim == 3:
+                    # the adjoint (du and dcoef) on the same inputs, w = u
+                    nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
+                    for c in cps:
+                        c["dc"] = torch.empty_like(c["cf"])
+
+                    def back(c, wlx=wlx, rule_p3=rule_p3):
+                        api.fem_integrate_residual_p3_backward(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"],
+                                                               c["cf"], c["u"], du=c["R"], dcoef=c["dc"])
+                    _, msb = timed_graph(back, cps, 10, 1)
+                    extra[f"{wlx.name}_p3_{tag}_adjoint"] = dict(
+                        n_elem=wlx.n_elem, us=msb * 1e3, gbs=nbb / (msb * 1e-3) / 1e9, bytes_per_elem=nbb / wlx.n_elem)
+                    log(f"{wlx.name} P3 {tag} adjoint: {msb * 1e3:.1f} us ({nbb / (msb * 1e-3) / 1e9:.0f} GB/s)")
                 del cps, ij, dj
             del p3, wlx
 

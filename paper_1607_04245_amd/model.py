@@ -164,3 +164,11 @@ def p3_forward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: i
     """Compulsory bytes per element of fem_integrate_residual_p3."""
     nbt = n_basis(dim, 3) * n_comp(dim, physics)
     return word * ((dim * dim + 1) + 2 * nbt + n_coef(physics) * n_coef_words(dim, rule, coef_space))
+
+
+def p3_backward_bytes(dim: int, physics: int, rule: int, word: int, coef_space: int = 0) -> int:
+    """Compulsory bytes per element of fem_integrate_residual_p3_backward with
+    both outputs: geometry, w, u and coefficients in, du and dcoef out."""
+    nbt = n_basis(dim, 3) * n_comp(dim, physics)
+    ncq = n_coef(physics) * n_coef_words(dim, rule, coef_space)
+    return word * ((dim * dim + 1) + 3 * nbt + 2 * ncq)
