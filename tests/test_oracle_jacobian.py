@@ -27,10 +27,12 @@ from paper_1607_04245_amd import meshgen as mg
 from test_oracle_pins import bary_gradients, element_arrays, random_simplices, voigt_B, voigt_D
 from test_oracle_p2 import (EDGES, geom, p2_nodes, physical_gradient_integrals, reference_gradient_integrals,
                             textbook_mass, vol)
+from test_oracle_p3 import p3_nodes
 
 LAP, EL, MASS = mg.LAPLACE, mg.ELASTICITY, mg.MASS
 RULES = {(2, 1): [mg.RULE_TRI3, mg.RULE_CENTROID], (3, 1): [mg.RULE_TET4, mg.RULE_CENTROID],
-         (2, 2): [mg.RULE_TRI3, mg.RULE_TRI6], (3, 2): [mg.RULE_TET4, mg.RULE_TET11]}
+         (2, 2): [mg.RULE_TRI3, mg.RULE_TRI6], (3, 2): [mg.RULE_TET4, mg.RULE_TET11],
+         (2, 3): [mg.RULE_TRI6], (3, 3): [mg.RULE_TET11]}
 SPACES = [mg.COEF_QUAD, mg.COEF_P1, mg.COEF_P0]
 
 
@@ -174,7 +176,7 @@ def test_p2_elasticity_exact_integration(dim):
 
 # -------------------------------------------------- consistency and structure ---
 
-CASES = [(d, p, o, r, s) for d in (2, 3) for p in (LAP, EL, MASS) for o in (1, 2) for r in RULES[(d, o)]
+CASES = [(d, p, o, r, s) for d in (2, 3) for p in (LAP, EL, MASS) for o in (1, 2, 3) for r in RULES[(d, o)]
          for s in SPACES]
 
 
@@ -218,13 +220,14 @@ def rigid_modes(nodes):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_null_spaces_definiteness_and_rank(dim, order):
     """Laplacian: null space = constants, rank N_b - 1. Elasticity: null space
     = the d(d+1)/2 rigid motions, rank N_bt - d(d+1)/2. Both positive
     semi-definite for positive coefficients. Mass with a rule that is exact
-    for it: positive definite."""
-    rule = RULES[(dim, order)][0 if order == 1 else 1]
+    for it: positive definite. No rule here integrates the P3 mass matrix
+    (degree 6) exactly; with N_q < N_b points it is B^T W B of rank N_q."""
+    rule = RULES[(dim, order)][0 if order == 1 else -1]
     rng = np.random.default_rng(170 + dim + 10 * order)
     n = 12
     x = random_simplices(dim, n, rng)
@@ -234,6 +237,12 @@ def test_null_spaces_definiteness_and_rank(dim, order):
         coef = coefficients(dim, phys, rule, mg.COEF_QUAD, n, rng)
         nbt = nb * ncomp(dim, phys)
         K = as_matrices(oracle.jacobian(dim, phys, rule, ij, dj, coef, order=order), nbt)
+        if phys == MASS and order == 3:
+            nq = oracle.n_qpts(dim, rule)
+            for e in range(n):
+                sv = np.linalg.svd(K[e], compute_uv=False)
+                assert np.sum(sv > 1e-12 * sv[0]) == nq
+            continue
         for e in range(n):
             ev = np.linalg.eigvalsh(0.5 * (K[e] + K[e].T))
             tol = 1e-12 * ev[-1]
@@ -242,13 +251,13 @@ def test_null_spaces_definiteness_and_rank(dim, order):
             if phys == LAP:
                 assert np.abs(K[e] @ np.ones(nbt)).max() <= 1e-13 * np.abs(K[e]).max()
             if phys == EL:
-                nodes = x[e] if order == 1 else p2_nodes(x[e])
+                nodes = x[e] if order == 1 else (p2_nodes(x[e]) if order == 2 else p3_nodes(x[e]))
                 M = rigid_modes(nodes)
                 assert np.abs(K[e] @ M.T).max() <= 1e-12 * np.abs(K[e]).max() * np.abs(M).max()
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 @pytest.mark.parametrize("phys", [LAP, EL, MASS])
 def test_coefficient_spaces_agree_on_constants(dim, order, phys):
     """A coefficient constant on the element gives the same matrix whether it

@@ -162,6 +162,38 @@ def test_p3_elasticity_stiffness_exact(dim):
         assert np.allclose(K[:, :, e], ref, rtol=1e-11, atol=1e-11)
 
 
+@pytest.mark.parametrize("dim,phys", [(2, LAP), (3, LAP), (2, EL), (3, EL)])
+def test_p3_element_matrices_exact(dim, phys):
+    """The oracle's element-matrix routine (written from g0/g3, not from its
+    residual routine) at order 3 against exact integration of the P3
+    gradient products."""
+    rng = np.random.default_rng(170 + dim + 5 * phys)
+    x = random_simplices(dim, 3, rng)
+    ij, dj = geom(x)
+    n = x.shape[0]
+    nq = oracle.n_qpts(dim, HIGH[dim])
+    nb = nb3(dim)
+    I = reference_gradient_integrals3(dim)
+    if phys == LAP:
+        kap = rng.uniform(0.5, 2, n)
+        coef = np.repeat(kap[None, None, :], nq, axis=1)
+    else:
+        lam, mu = rng.uniform(1, 10, n), rng.uniform(0.5, 5, n)
+        coef = np.stack([np.repeat(lam[None, :], nq, 0), np.repeat(mu[None, :], nq, 0)])
+    nbt = nb * (dim if phys == EL else 1)
+    K = oracle.jacobian(dim, phys, HIGH[dim], ij, dj, coef, order=3).reshape(nbt, nbt, n)
+    for e in range(n):
+        A = physical_gradient_integrals(x[e], I)
+        if phys == LAP:
+            ref = kap[e] * np.einsum("iiab->ab", A)
+        else:
+            ref = np.zeros((nbt, nbt))
+            for c in range(dim):
+                for cp in range(dim):
+                    ref[c::dim, cp::dim] = lam[e] * A[c, cp] + mu[e] * ((c == cp) * np.einsum("iiab->ab", A) + A[cp, c])
+        assert np.allclose(K[:, :, e], ref, rtol=1e-11, atol=1e-11)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_p3_basis_integrals(dim):
     """Mass form with u = 1 and unit coefficient gives the integral of every
