@@ -597,7 +597,8 @@ def main():
 
         # ------------------------------------------------- element matrices --
         for cfg, order, rule_k, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
-                                      ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",))):
+                                      ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",)),
+                                      (2, 3, mg.RULE_TET11, ("f32",))):
             wlx = wl if cfg == 2 else mg.config(cfg)
             cf0 = mg.p2_inputs(wlx, rule_k, mg.BASE_SEED + 5000).coef
             nbt = model.n_basis(wlx.dim, order) * wlx.n_comp

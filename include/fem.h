@@ -112,7 +112,8 @@ enum fem_op {
     FEM_OP_JACOBIAN = 7,        /* fem_integrate_jacobian, order 1 */
     FEM_OP_JACOBIAN_P2 = 8,     /* fem_integrate_jacobian, order 2 */
     FEM_OP_RESIDUAL_P3 = 9,     /* fem_integrate_residual_p3 */
-    FEM_OP_BACKWARD_P3 = 10     /* fem_integrate_residual_p3_backward */
+    FEM_OP_BACKWARD_P3 = 10,    /* fem_integrate_residual_p3_backward */
+    FEM_OP_JACOBIAN_P3 = 11     /* fem_integrate_jacobian, order 3 */
 };
 
 /* ------------------------------------------------------------------ */
@@ -314,7 +315,7 @@ fem_status fem_integrate_residual_gather_planned(const fem_mesh_plan* plan, int 
 /* to the closure (Eq. (2) of Section 2 differentiated in u).          */
 /* ------------------------------------------------------------------ */
 
-/* K_e = dR_e / du_e for P1 (order 1) or P2 (order 2) elements from
+/* K_e = dR_e / du_e for P1 (order 1), P2 (order 2) or P3 (order 3) elements from
  * precomputed affine geometry: per quadrature point, the derivatives of the
  * pointwise functions, g0 = d f0 / d u and g3 = d f1 / d grad u, between the
  * basis values and physical gradients,
@@ -331,7 +332,9 @@ fem_status fem_integrate_residual_gather_planned(const fem_mesh_plan* plan, int 
  * The matrices are symmetric and written so exactly (each entry below the
  * diagonal is a copy of its mirror). Rules: order 1 takes FEM_RULE_TRI3 /
  * FEM_RULE_TET4 or FEM_RULE_CENTROID; order 2 takes the degree-2 rule or
- * FEM_RULE_TRI6 / FEM_RULE_TET11. Arrays are device memory owned by the
+ * FEM_RULE_TRI6 / FEM_RULE_TET11; order 3 takes FEM_RULE_TRI6 /
+ * FEM_RULE_TET11 (node order as fem_integrate_residual_p3; its columns are
+ * the residuals of unit closures). Arrays are device memory owned by the
  * caller; elem_mat may not overlap the inputs. Errors as
  * fem_integrate_residual (FEM_ERR_UNSUPPORTED for another order or rule). */
 fem_status fem_integrate_jacobian(int dim, int physics, int rule, int coef_space, int order, int dtype,

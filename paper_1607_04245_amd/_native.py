@@ -29,7 +29,7 @@ STRATEGY_LANE, STRATEGY_TRANSPOSE = 0, 1
 OP_RESIDUAL, OP_RESIDUAL_MESH, OP_GEOMETRY, OP_BACKWARD, OP_RESIDUAL_GATHER = 0, 1, 2, 3, 4
 OP_RESIDUAL_P2, OP_BACKWARD_P2 = 5, 6
 OP_JACOBIAN, OP_JACOBIAN_P2 = 7, 8
-OP_RESIDUAL_P3, OP_BACKWARD_P3 = 9, 10
+OP_RESIDUAL_P3, OP_BACKWARD_P3, OP_JACOBIAN_P3 = 9, 10, 11
 COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
 
 

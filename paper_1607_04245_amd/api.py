@@ -330,9 +330,9 @@ def fem_integrate_residual_p3_backward(dim: int, physics: int, rule: int, inv_j,
 def fem_integrate_jacobian(dim: int, physics: int, rule: int, inv_j, det_j, coef, out=None, *,
                            coef_space=N.COEF_QUAD, order=1):
     """Element matrices K = dR_e/du_e [N_bt*N_bt, n] (row r*N_bt + s: test
-    function r = b*N_comp + c, trial function s), for P1 (order 1) or P2
-    (order 2) elements from precomputed affine geometry. For these linear
-    forms K_e u_e is the element residual."""
+    function r = b*N_comp + c, trial function s), for P1 (order 1), P2
+    (order 2) or P3 (order 3) elements from precomputed affine geometry. For
+    these linear forms K_e u_e is the element residual."""
     dtype = det_j.dtype
     if dtype not in _DT:
         raise TypeError("geometry must be float32 or float64")

@@ -93,13 +93,14 @@ static fem_status check_combo_p3(const char* fn, int dim, int phys, int rule, in
 // Rules of the element-matrix entry point for each order.
 static bool valid_rule_jac(int dim, int order, int rule) {
     const int low = dim == 2 ? FEM_RULE_TRI3 : FEM_RULE_TET4, high = dim == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
+    if (order == 3) return rule == high;
     return rule == low || (order == 1 && rule == FEM_RULE_CENTROID) || (order == 2 && rule == high);
 }
 
 static fem_status check_combo_jac(const char* fn, int dim, int phys, int order, int rule, int dtype) {
     if (!valid_dim(dim)) { set_error("%s: dim must be 2 or 3 (got %d)", fn, dim); return FEM_ERR_UNSUPPORTED; }
     if (!valid_phys(phys)) { set_error("%s: unknown physics %d", fn, phys); return FEM_ERR_UNSUPPORTED; }
-    if (order != 1 && order != 2) { set_error("%s: order must be 1 or 2 (got %d)", fn, order); return FEM_ERR_UNSUPPORTED; }
+    if (order < 1 || order > 3) { set_error("%s: order must be 1, 2 or 3 (got %d)", fn, order); return FEM_ERR_UNSUPPORTED; }
     if (!valid_rule_jac(dim, order, rule)) {
         set_error("%s: rule %d is not available for order %d in %dD", fn, rule, order, dim);
         return FEM_ERR_UNSUPPORTED;
@@ -125,14 +126,15 @@ static std::map<TuneKey, fem_tuning> g_tune;
 static bool valid_op(int op) {
     return op == FEM_OP_RESIDUAL || op == FEM_OP_RESIDUAL_MESH || op == FEM_OP_GEOMETRY || op == FEM_OP_BACKWARD ||
            op == FEM_OP_RESIDUAL_GATHER || op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 ||
-           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3;
+           op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3 ||
+           op == FEM_OP_JACOBIAN_P3;
 }
 
 // Ops whose kernels take one element per lane and at most four waves per
 // workgroup (register-heavy elements).
 static bool one_per_lane_op(int op) {
     return op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 ||
-           op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3;
+           op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3 || op == FEM_OP_JACOBIAN_P3;
 }
 
 // The geometry does not depend on physics or rule: one key per (dim, dtype).
@@ -156,6 +158,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     // P3: the 3D elements hold 20-60 closure and output words per lane, and
     // single-wave workgroups measured fastest there; 2D streams better with four
     if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
+    if (op == FEM_OP_JACOBIAN_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0};
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
     if (op == FEM_OP_RESIDUAL_MESH) {
@@ -240,6 +243,7 @@ static fem_status check_tuning_args(const char* fn, int op, int dim, int physics
     if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return check_combo_p3(fn, dim, physics, rule, dtype);
     if (op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2)
         return check_combo_jac(fn, dim, physics, op == FEM_OP_JACOBIAN ? 1 : 2, rule, dtype);
+    if (op == FEM_OP_JACOBIAN_P3) return check_combo_jac(fn, dim, physics, 3, rule, dtype);
     return check_combo(fn, dim, physics, rule, dtype);
 }
 
@@ -464,10 +468,12 @@ fem_status fem_integrate_jacobian(int dim, int physics, int rule, int coef_space
         set_error("fem_integrate_jacobian: NULL array");
         return FEM_ERR_INVALID_ARG;
     }
-    const fem_tuning t = get_tuning(order == 1 ? FEM_OP_JACOBIAN : FEM_OP_JACOBIAN_P2, dim, physics, rule, dtype);
+    const int op = order == 1 ? FEM_OP_JACOBIAN : order == 2 ? FEM_OP_JACOBIAN_P2 : FEM_OP_JACOBIAN_P3;
+    const fem_tuning t = get_tuning(op, dim, physics, rule, dtype);
     JacobianArgs a{n_elem, inv_j, det_j, coef, elem_mat};
     Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
-    hipError_t e = launch_jacobian(dim, physics, order, rule, coef_space, dtype, a, l);
+    hipError_t e = order == 3 ? launch_jacobian_p3(dim, physics, coef_space, dtype, a, l)
+                              : launch_jacobian(dim, physics, order, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_jacobian launch");
 }
 

@@ -71,6 +71,7 @@ hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dt
 // Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
 hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
 hipError_t launch_backward_p3(int dim, int phys, int space, int dtype, const BackwardArgs& a, const Launch& l);
+hipError_t launch_jacobian_p3(int dim, int phys, int space, int dtype, const JacobianArgs& a, const Launch& l);
 hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                               const Launch& l);
 hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,

@@ -1,5 +1,5 @@
-// residual_p3.hip -- element residuals of third-order (P3) Lagrange elements
-// and their adjoint from precomputed affine geometry.
+// residual_p3.hip -- element residuals of third-order (P3) Lagrange elements,
+// their adjoint and element matrices from precomputed affine geometry.
 //
 // One lane per element, as the P1 and P2 lane kernels: every SoA row
 // (inverse Jacobian, det J, the N_b * N_comp closure rows, the coefficient
@@ -127,6 +127,49 @@ backward_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const R
     }
 }
 
+// Element matrices: the three forms are linear in u, so column s of K_e is
+// R_e(e_s), the residual of the unit closure e_s. Columns run in a loop
+// (the element arithmetic is inlined once); column s stores the entries
+// r <= s at (r, s) and (s, r), so the matrix is exactly symmetric.
+template <int DIM, int PHYS, typename Real>
+__global__ void __launch_bounds__(256)
+jacobian_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
+                   const Real* __restrict__ coef, Real* __restrict__ out) {
+    constexpr int RULE = DIM == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    constexpr int M = E::NBT;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        Real ij[E::NG], aq[E::NCQ];
+#pragma unroll
+        for (int f = 0; f < E::NG; ++f) ij[f] = __builtin_nontemporal_load(inv_j + f * n + e);
+        const Real dj = __builtin_nontemporal_load(det_j + e);
+        p3_coef_points<DIM, PHYS, RULE, Real>(space, coef, n, e, aq);
+#pragma unroll 1
+        for (int s = 0; s < M; ++s) {
+            Real uu[M], r[M];
+#pragma unroll
+            for (int f = 0; f < M; ++f) uu[f] = Real(f == s ? 1 : 0);
+            element_residual_p3<DIM, PHYS, RULE, Real>(ij, dj, uu, aq, r);
+#pragma unroll
+            for (int f = 0; f < M; ++f) {
+                if (f <= s) {
+                    __builtin_nontemporal_store(r[f], out + (int64_t)(f * M + s) * n + e);
+                    __builtin_nontemporal_store(r[f], out + (int64_t)(s * M + f) * n + e);
+                }
+            }
+        }
+    }
+}
+
+template <int DIM, int PHYS, typename Real>
+static hipError_t launch_jac(int space, const JacobianArgs& a, const Launch& l) {
+    hipLaunchKernelGGL((jacobian_p3_kernel<DIM, PHYS, Real>), dim3(l.grid), dim3(l.block), 0, l.stream, a.n, space,
+                       static_cast<const Real*>(a.inv_j), static_cast<const Real*>(a.det_j),
+                       static_cast<const Real*>(a.coef), static_cast<Real*>(a.out));
+    return hipGetLastError();
+}
+
 template <int DIM, int PHYS, typename Real>
 static hipError_t launch_bwd(int space, const BackwardArgs& a, const Launch& l) {
     hipLaunchKernelGGL((backward_p3_kernel<DIM, PHYS, Real>), dim3(l.grid), dim3(l.block), 0, l.stream, a.n, space,
@@ -183,6 +226,18 @@ struct P3Bwd {
     template <int D, int P, typename Real>
     hipError_t operator()() const { return launch_bwd<D, P, Real>(space, a, l); }
 };
+
+struct P3Jac {
+    int space;
+    const JacobianArgs& a;
+    const Launch& l;
+    template <int D, int P, typename Real>
+    hipError_t operator()() const { return launch_jac<D, P, Real>(space, a, l); }
+};
+
+hipError_t launch_jacobian_p3(int dim, int phys, int space, int dtype, const JacobianArgs& a, const Launch& l) {
+    return p3_dispatch(dim, phys, space, dtype, P3Jac{space, a, l});
+}
 
 hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l) {
     return p3_dispatch(dim, phys, space, dtype, P3Fwd{space, a, l});

@@ -227,9 +227,9 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
         set_error("fem_autotune: n_elem_probe must be in [4096, 2^28]");
         return FEM_ERR_INVALID_ARG;
     }
-    const bool jac = op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2;
+    const bool jac = op == FEM_OP_JACOBIAN || op == FEM_OP_JACOBIAN_P2 || op == FEM_OP_JACOBIAN_P3;
     const bool p2 = op == FEM_OP_RESIDUAL_P2 || op == FEM_OP_BACKWARD_P2 || op == FEM_OP_JACOBIAN_P2;
-    const bool p3 = op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3;
+    const bool p3 = op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3 || op == FEM_OP_JACOBIAN_P3;
     const bool one = p2 || p3 || jac;  // one element per lane
     const int nc = physics == FEM_ELASTICITY ? dim : 1;
     const int nbt = (p3 ? (dim + 1) * (dim + 2) * (dim + 3) / 6 : p2 ? (dim + 1) * (dim + 2) / 2 : dim + 1) * nc;
@@ -314,7 +314,9 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
                                                       c.w, c.du, c.dc, nullptr);
         case FEM_OP_JACOBIAN:
         case FEM_OP_JACOBIAN_P2:
-            return fem_integrate_jacobian(dim, physics, rule, FEM_COEF_QUAD, op == FEM_OP_JACOBIAN ? 1 : 2, dtype, n, c.ij,
+        case FEM_OP_JACOBIAN_P3:
+            return fem_integrate_jacobian(dim, physics, rule, FEM_COEF_QUAD,
+                                          op == FEM_OP_JACOBIAN ? 1 : op == FEM_OP_JACOBIAN_P2 ? 2 : 3, dtype, n, c.ij,
                                           c.dj, c.cf, c.out, nullptr);
         case FEM_OP_RESIDUAL:
             return fem_integrate_residual(dim, physics, rule, FEM_COEF_QUAD, dtype, n, c.ij, c.dj, c.u, c.cf, c.out, nullptr);

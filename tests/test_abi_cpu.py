@@ -123,7 +123,7 @@ def test_tuning_roundtrip(lib):
     assert lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_OK
     lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
-    assert lib.fem_set_tuning(11, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(12, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
 
 
 def test_batch_plan_validation(lib):
@@ -149,7 +149,7 @@ def test_autotune_validation(lib):
     R = N.OP_RESIDUAL
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 10, None) == N.FEM_ERR_INVALID_ARG
-    assert lib.fem_autotune(11, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_autotune(12, 2, mg.LAPLACE, mg.RULE_TRI3, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
     assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG
 
 
@@ -281,7 +281,8 @@ def test_jacobian_validation(lib):
     # (dim, physics, rule, coef_space, order, dtype)
     ok1 = (3, mg.ELASTICITY, mg.RULE_CENTROID, N.COEF_P1, 1, N.F64)
     ok2 = (2, mg.MASS, mg.RULE_TRI6, N.COEF_P0, 2, N.F32)
-    for ok in (ok1, ok2):
+    ok3 = (3, mg.ELASTICITY, mg.RULE_TET11, N.COEF_P1, 3, N.F64)
+    for ok in (ok1, ok2, ok3):
         assert f(*ok, 0, None, None, None, None, None) == N.FEM_OK
         assert f(*ok, -1, _v(), _v(), _v(), _v(), None) == N.FEM_ERR_INVALID_ARG
         for k in range(4):
@@ -291,13 +292,15 @@ def test_jacobian_validation(lib):
     for bad in [(2, mg.LAPLACE, mg.RULE_TRI6, 0, 1, N.F32),       # degree-4 rule with order 1
                 (3, mg.LAPLACE, mg.RULE_CENTROID, 0, 2, N.F32),   # centroid with order 2
                 (2, mg.LAPLACE, mg.RULE_TET4, 0, 1, N.F32),       # tet rule in 2D
-                (3, mg.LAPLACE, mg.RULE_TET4, 0, 3, N.F32),       # order 3
+                (3, mg.LAPLACE, mg.RULE_TET4, 0, 3, N.F32),       # order 3 with a degree-2 rule
+                (3, mg.LAPLACE, mg.RULE_TET11, 0, 4, N.F32),      # order 4
                 (3, 9, mg.RULE_TET4, 0, 1, N.F32), (3, mg.LAPLACE, mg.RULE_TET4, 4, 1, N.F32),
                 (3, mg.LAPLACE, mg.RULE_TET4, 0, 1, 2), (4, mg.LAPLACE, mg.RULE_TET4, 0, 1, N.F32)]:
         assert f(*bad, 5, _v(), _v(), _v(), _v(), None) == N.FEM_ERR_UNSUPPORTED, bad
         assert N.last_error()
     t = N.fem_tuning(N.STRATEGY_LANE, 1, 4, 2)
-    for op, rule in ((N.OP_JACOBIAN, mg.RULE_CENTROID), (N.OP_JACOBIAN_P2, mg.RULE_TET11)):
+    for op, rule in ((N.OP_JACOBIAN, mg.RULE_CENTROID), (N.OP_JACOBIAN_P2, mg.RULE_TET11),
+                     (N.OP_JACOBIAN_P3, mg.RULE_TET11)):
         assert lib.fem_set_tuning(op, 3, mg.LAPLACE, rule, N.F32, ctypes.byref(t)) == N.FEM_OK
         for bad_t in (N.fem_tuning(N.STRATEGY_LANE, 2, 4, 0), N.fem_tuning(N.STRATEGY_LANE, 1, 8, 0)):
             assert lib.fem_set_tuning(op, 3, mg.LAPLACE, rule, N.F32, ctypes.byref(bad_t)) == N.FEM_ERR_INVALID_ARG

@@ -56,7 +56,7 @@ def _reset_tuning():
     saved = {}
     for dim, phys in KINDS:
         for dt in DTYPES:
-            for op in (N.OP_RESIDUAL_P3, N.OP_BACKWARD_P3):
+            for op in (N.OP_RESIDUAL_P3, N.OP_BACKWARD_P3, N.OP_JACOBIAN_P3):
                 saved[(dim, phys, dt, op)] = api.fem_get_tuning(dim, phys, RULE[dim], dt, op=op)
     yield
     for (dim, phys, dt, op), t in saved.items():
@@ -169,6 +169,52 @@ def test_p3_launch_shapes_bitwise(dtype, dim, phys):
         assert torch.equal(R, first), (waves, bpc)
     with pytest.raises(N.FemError):
         api.fem_set_tuning(dim, phys, RULE[dim], dtype, vec=1, waves_per_block=8, op=N.OP_RESIDUAL_P3)
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("space", SPACES)
+def test_p3_element_matrices_match_oracle(dim, phys, dtype, space):
+    """fem_integrate_jacobian(order=3) against the oracle's element matrices
+    (per element, Euclidean norms over the N_bt^2 entries, scaled by the
+    absolute-value sums); the output is exactly symmetric."""
+    wl, p3 = workload(dim, phys, 700, seed=91)
+    cf = coefficients(wl, p3, space)
+    ij, dj = geometry(wl, dtype)
+    rule = RULE[dim]
+    K = api.fem_integrate_jacobian(dim, phys, rule, ij, dj, dev(cf, dtype), coef_space=space, order=3)
+    rij, rdj, _ = oracle.geometry(wl.coords, wl.conn)
+    cr = rounded(cf, dtype)
+    ref = oracle.jacobian(dim, phys, rule, rij, rdj, cr, space=space, order=3)
+    ref_abs = oracle.jacobian_abs(dim, phys, rule, rij, rdj, cr, space=space, order=3)
+    assert_close(K.cpu().numpy(), ref, ref_abs, dtype, f"P3 K {dim}D phys {phys} space {space}")
+    m = p3.u.shape[0]
+    Km = K.reshape(m, m, -1)
+    assert torch.equal(Km, Km.transpose(0, 1)), "output not exactly symmetric"
+
+
+def test_p3_element_matrices_full_size_laplace3d():
+    """The 2^20-tetrahedron mesh, FP32: every entry finite, exactly symmetric;
+    4096 sampled elements against the oracle."""
+    wl = mg.config(2)
+    p3 = mg.p3_inputs(wl, mg.RULE_TET11, mg.BASE_SEED + 7800)
+    dt = torch.float32
+    ij, dj = geometry(wl, dt)
+    K = api.fem_integrate_jacobian(3, mg.LAPLACE, mg.RULE_TET11, ij, dj, dev(p3.coef, dt), order=3)
+    assert bool(torch.isfinite(K).all())
+    Km = K.reshape(20, 20, -1)
+    for r in range(20):
+        assert torch.equal(Km[r], Km[:, r]), r
+    rng = np.random.default_rng(11)
+    cols = np.unique(np.concatenate([[0, wl.n_elem - 1], rng.integers(0, wl.n_elem, 4094)]))
+    got = K[:, torch.from_numpy(cols).to("cuda")].cpu().numpy()
+    del K, Km
+    rij, rdj, _ = oracle.geometry(wl.coords, wl.conn)
+    cr = rounded(p3.coef, dt)[..., cols]
+    ref = oracle.jacobian(3, mg.LAPLACE, mg.RULE_TET11, rij[:, cols], rdj[cols], cr, order=3)
+    ref_abs = oracle.jacobian_abs(3, mg.LAPLACE, mg.RULE_TET11, rij[:, cols], rdj[cols], cr, order=3)
+    mx, agg = assert_close(got, ref, ref_abs, dt, "P3 K laplace3d 2^20")
+    print(f"P3 element matrices laplace3d 2^20 f32: scaled max {mx:.2e} aggregate {agg:.2e}", flush=True)
 
 
 def test_p3_empty_and_rejected():
