@@ -76,7 +76,7 @@ hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype,
                               const Launch& l);
 hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
                               const Launch& l);
-// Element matrices (jacobian.hip); order 1 or 2.
+// Element matrices: order 1 or 2 (jacobian.hip), order 3 (residual_p3.hip).
 hipError_t launch_jacobian(int dim, int phys, int order, int rule, int space, int dtype, const JacobianArgs& a,
                            const Launch& l);
 hipError_t launch_backward_lane(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,
