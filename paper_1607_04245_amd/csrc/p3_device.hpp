@@ -84,6 +84,22 @@ struct P3Basis {
     }
 };
 
+// The basis values and barycentric derivatives at the points as a table,
+// for lookups with a run-time (wave-uniform) function index.
+template <int DIM, int RULE>
+struct P3Table {
+    static constexpr int NQ = RuleP2<DIM, RULE>::NQ, NB = ElemP3<DIM, 0, RULE, 0>::NB, NV = DIM + 1;
+    double phi[NQ][NB];
+    double dl[NQ][NB][NV];
+    constexpr P3Table() : phi(), dl() {
+        for (int q = 0; q < NQ; ++q)
+            for (int b = 0; b < NB; ++b) {
+                phi[q][b] = P3Basis<DIM, RULE>::phi(q, b);
+                for (int v = 0; v < NV; ++v) dl[q][b][v] = P3Basis<DIM, RULE>::dl(q, b, v);
+            }
+    }
+};
+
 // Calls f(std::integral_constant<int, i>) for i = B .. E-1, so the basis
 // values at a point are constant expressions: zero entries drop out at
 // compile time and no loop is left to the optimizer's unrolling limits.

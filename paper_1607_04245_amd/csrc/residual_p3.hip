@@ -128,29 +128,107 @@ backward_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const R
 }
 
 // Element matrices: the three forms are linear in u, so column s of K_e is
-// R_e(e_s), the residual of the unit closure e_s. Columns run in a loop
-// (the element arithmetic is inlined once); column s stores the entries
-// r <= s at (r, s) and (s, r), so the matrix is exactly symmetric.
+// R_e(e_s), the residual of the unit closure e_s = (basis function b_s,
+// component c_s). Its value and gradient at a point are phi_{b_s} and
+// sum_v dphi_{b_s}/dlam_v g_v in component c_s alone, read from a table
+// with the wave-uniform index b_s; the basis phase is the residual's, over
+// the rows r <= s only. Column s stores those entries at (r, s) and (s, r),
+// so the matrix is exactly symmetric. Columns run in a loop (the arithmetic
+// is inlined once).
+__constant__ P3Table<2, FEM_RULE_TRI6> kP3Table2;
+__constant__ P3Table<3, FEM_RULE_TET11> kP3Table3;
+
+template <int DIM>
+__device__ __forceinline__ const auto& p3_table() {
+    if constexpr (DIM == 2) return kP3Table2;
+    else return kP3Table3;
+}
+
 template <int DIM, int PHYS, typename Real>
 __global__ void __launch_bounds__(256)
 jacobian_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
                    const Real* __restrict__ coef, Real* __restrict__ out) {
     constexpr int RULE = DIM == 2 ? FEM_RULE_TRI6 : FEM_RULE_TET11;
     using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
-    constexpr int M = E::NBT;
+    using Q = RuleP2<DIM, RULE>;
+    using T = P3Basis<DIM, RULE>;
+    using P = Physics<PHYS>;
+    constexpr int M = E::NBT, NC = E::NC, NV = E::NV, NB = E::NB;
+    const auto& tab = p3_table<DIM>();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         Real ij[E::NG], aq[E::NCQ];
 #pragma unroll
         for (int f = 0; f < E::NG; ++f) ij[f] = __builtin_nontemporal_load(inv_j + f * n + e);
-        const Real dj = __builtin_nontemporal_load(det_j + e);
+        const Real adj = fabs(__builtin_nontemporal_load(det_j + e));
         p3_coef_points<DIM, PHYS, RULE, Real>(space, coef, n, e, aq);
+        Real g[NV][DIM];
+        p2_bary_grads<DIM, Real>(ij, g);
 #pragma unroll 1
         for (int s = 0; s < M; ++s) {
-            Real uu[M], r[M];
+            const int bs = s / NC, cs = s - bs * NC;
+            Real r[M];
 #pragma unroll
-            for (int f = 0; f < M; ++f) uu[f] = Real(f == s ? 1 : 0);
-            element_residual_p3<DIM, PHYS, RULE, Real>(ij, dj, uu, aq, r);
+            for (int f = 0; f < M; ++f) r[f] = Real(0);
+            unroll_for<0, E::NQ>([&](auto q_c) {
+                constexpr int q = decltype(q_c)::value;
+                Real uq[NC], gq[NC][DIM];
+                if constexpr (P::NEEDS_U) {
+                    const Real ph = Real(tab.phi[q][bs]);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) uq[c] = c == cs ? ph : Real(0);
+                }
+                if constexpr (P::HAS_F1) {
+                    Real gs[DIM];
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        Real t = Real(tab.dl[q][bs][0]) * g[0][i];
+#pragma unroll
+                        for (int v = 1; v < NV; ++v) t = fmadd(Real(tab.dl[q][bs][v]), g[v][i], t);
+                        gs[i] = t;
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int i = 0; i < DIM; ++i) gq[c][i] = c == cs ? gs[i] : Real(0);
+                }
+                Real a[E::NCOEF];
+#pragma unroll
+                for (int m = 0; m < E::NCOEF; ++m) a[m] = aq[m * E::NQ + q];
+                Real f0[NC], f1[NC][DIM];
+                P::template point<DIM, Real>(uq, gq, a, f0, f1);
+                const Real w = Real(Q::w(q)) * adj;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if constexpr (P::HAS_F1) {
+                        Real h[NV];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            Real t = g[v][0] * f1[c][0];
+#pragma unroll
+                            for (int i = 1; i < DIM; ++i) t = fmadd(g[v][i], f1[c][i], t);
+                            h[v] = w * t;
+                        }
+                        unroll_for<0, NB>([&](auto b_c) {
+                            constexpr int b = decltype(b_c)::value;
+                            if (b * NC + c <= s) {
+                                unroll_for<0, NV>([&](auto v_c) {
+                                    constexpr int v = decltype(v_c)::value;
+                                    constexpr double d = T::dl(q, b, v);
+                                    if constexpr (d != 0.0) r[b * NC + c] = fmadd(Real(d), h[v], r[b * NC + c]);
+                                });
+                            }
+                        });
+                    }
+                    if constexpr (P::HAS_F0) {
+                        const Real sf = w * f0[c];
+                        unroll_for<0, NB>([&](auto b_c) {
+                            constexpr int b = decltype(b_c)::value;
+                            if (b * NC + c <= s) r[b * NC + c] = fmadd(Real(T::phi(q, b)), sf, r[b * NC + c]);
+                        });
+                    }
+                }
+            });
 #pragma unroll
             for (int f = 0; f < M; ++f) {
                 if (f <= s) {
