@@ -504,7 +504,9 @@ def fem_restrict(conn, vertex_vec, out=None):
 class MeshPlan:
     """Distinct vertices of every 64-element tile of a mesh
     (fem_mesh_plan_create), for repeated from-mesh residuals. Building it
-    copies the connectivity to the host once and synchronizes the stream."""
+    copies the connectivity to the host once and synchronizes the stream.
+    It pays on tetrahedral meshes; on triangles the unplanned entry points
+    measured faster."""
 
     def __init__(self, conn: torch.Tensor, n_vert: int):
         _need(conn, "conn", torch.int32)
