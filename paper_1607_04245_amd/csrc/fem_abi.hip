@@ -158,9 +158,7 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     // P3: the 3D elements hold 20-60 closure and output words per lane, and
     // single-wave workgroups measured fastest there; 2D streams better with four
     if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
-    // P3 matrices: two waves per workgroup, eight workgroups per CU in 3D
-    // (400 against 474 us with four waves, 3D Laplacian); 2D is insensitive
-    if (op == FEM_OP_JACOBIAN_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, dim == 3 ? 8 : 0};
+    if (op == FEM_OP_JACOBIAN_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0};
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     if (op == FEM_OP_RESIDUAL_GATHER) return fem_tuning{FEM_STRATEGY_LANE, 2, 1, 0};
     if (op == FEM_OP_RESIDUAL_MESH) {
