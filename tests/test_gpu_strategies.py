@@ -409,3 +409,46 @@ def test_batched_workload_full():
         worst = max(worst, mx)
     plan.close()
     print(f"batched 64 meshes: worst scaled error {worst:.2e}", flush=True)
+
+
+def test_third_order_entry_points_under_graph_capture():
+    """The P3 residual, adjoint and element matrices and the planned geometry
+    in one captured graph: every replay equals the eager results."""
+    dtype = torch.float32
+    wl = small_workload(3, mg.ELASTICITY, 20000, seed=45)
+    p3 = mg.p3_inputs(wl, mg.RULE_TET11, mg.BASE_SEED + 79)
+    coords, conn = dev(wl.coords, torch.float64), dev(wl.conn, torch.int32)
+    ij, dj = api.fem_geometry(coords, conn, dtype)
+    u3, cf3 = dev(p3.u, dtype), dev(p3.coef, dtype)
+    w3 = dev(np.random.default_rng(6).uniform(-1, 1, p3.u.shape), dtype)
+    mplan = api.MeshPlan(conn, wl.n_vert)
+    R3, d3, dc3 = torch.empty_like(u3), torch.empty_like(u3), torch.empty_like(cf3)
+    K3 = torch.empty((60 * 60, wl.n_elem), dtype=dtype, device="cuda")
+    gij, gdj = torch.empty_like(ij), torch.empty_like(dj)
+
+    def work():
+        api.fem_integrate_residual_p3(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u3, cf3, out=R3)
+        api.fem_integrate_residual_p3_backward(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, u3, cf3, w3, du=d3, dcoef=dc3)
+        api.fem_integrate_jacobian(3, mg.ELASTICITY, mg.RULE_TET11, ij, dj, cf3, out=K3, order=3)
+        mplan.geometry(coords, dtype, inv_j=gij, det_j=gdj)
+
+    outs = (R3, d3, dc3, K3, gij, gdj)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        work()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, eager):
+            assert torch.equal(a, b), f"graph replay {rep} differs"
+    mplan.close()
