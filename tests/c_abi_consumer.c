@@ -14,6 +14,8 @@
  *     vectors (bit for bit: same values, same order, FP64);
  *   - fem_integrate_jacobian (element matrices) against the oracle's
  *     (max |dK| relative to max |K| <= 1e-12), and K_e u_e against R_e;
+ *   - fem_integrate_residual_p3 (third order, eleven-point rule) against
+ *     fem_oracle_integrate_p on the oracle's geometry (<= 1e-12 relative);
  *   - the error paths of a few calls (status codes, fem_last_error).
  * Exit status 0 on success; messages on stderr.
  */
@@ -37,6 +39,8 @@ int64_t fem_oracle_geometry(int dim, int64_t n_elem, int64_t n_vert, const doubl
                             double *inv_j, double *det_j);
 int fem_oracle_jacobian_p(int order, int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
                           const double *det_j, const double *coef, double *elem_mat, int absmode);
+int fem_oracle_integrate_p(int order, int dim, int physics, int rule, int space, int64_t n_elem, const double *inv_j,
+                           const double *det_j, const double *u, const double *coef, double *elem_vec, int absmode);
 
 static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
 static double uniform(double lo, double hi) {
@@ -202,6 +206,47 @@ int main(void) {
         }
     if (!(kmax <= 1e-12 * kref)) { fprintf(stderr, "element matrices vs oracle: %.3e relative\n", kmax / kref); ++fails; }
     if (!(kumax <= 1e-12 * rmax)) { fprintf(stderr, "K u vs R: %.3e relative\n", kumax / rmax); ++fails; }
+
+    /* third order: P3 closure (20 rows) and a coefficient at the 11 points,
+     * on the oracle's geometry */
+    {
+        const int nb3 = 20, nq3 = 11;
+        double *u3 = malloc(sizeof(double) * nb3 * n_elem), *c3 = malloc(sizeof(double) * nq3 * n_elem);
+        double *R3_ref = malloc(sizeof(double) * nb3 * n_elem), *R3 = malloc(sizeof(double) * nb3 * n_elem);
+        if (!u3 || !c3 || !R3_ref || !R3) return 4;
+        for (int64_t i = 0; i < nb3 * n_elem; ++i) u3[i] = uniform(-1.0, 1.0);
+        for (int64_t i = 0; i < nq3 * n_elem; ++i) c3[i] = uniform(0.5, 2.0);
+        if (fem_oracle_integrate_p(3, 3, FEM_LAPLACE, FEM_RULE_TET11, FEM_COEF_QUAD, n_elem, ij_ref, dj_ref, u3, c3,
+                                   R3_ref, 0) != 0)
+            return 5;
+        double *dij3, *ddj3, *du3, *dc3, *dR3;
+        CHECK_HIP(hipMalloc((void**)&dij3, sizeof(double) * 9 * n_elem));
+        CHECK_HIP(hipMalloc((void**)&ddj3, sizeof(double) * n_elem));
+        CHECK_HIP(hipMalloc((void**)&du3, sizeof(double) * nb3 * n_elem));
+        CHECK_HIP(hipMalloc((void**)&dc3, sizeof(double) * nq3 * n_elem));
+        CHECK_HIP(hipMalloc((void**)&dR3, sizeof(double) * nb3 * n_elem));
+        CHECK_HIP(hipMemcpy(dij3, ij_ref, sizeof(double) * 9 * n_elem, hipMemcpyHostToDevice));
+        CHECK_HIP(hipMemcpy(ddj3, dj_ref, sizeof(double) * n_elem, hipMemcpyHostToDevice));
+        CHECK_HIP(hipMemcpy(du3, u3, sizeof(double) * nb3 * n_elem, hipMemcpyHostToDevice));
+        CHECK_HIP(hipMemcpy(dc3, c3, sizeof(double) * nq3 * n_elem, hipMemcpyHostToDevice));
+        CHECK_FEM(fem_integrate_residual_p3(3, FEM_LAPLACE, FEM_RULE_TET11, FEM_COEF_QUAD, FEM_F64, n_elem, dij3, ddj3,
+                                            du3, dc3, dR3, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        CHECK_HIP(hipMemcpy(R3, dR3, sizeof(double) * nb3 * n_elem, hipMemcpyDeviceToHost));
+        double d3 = 0.0, r3 = 0.0;
+        for (int64_t i = 0; i < nb3 * n_elem; ++i) {
+            d3 = fmax(d3, fabs(R3[i] - R3_ref[i]));
+            r3 = fmax(r3, fabs(R3_ref[i]));
+        }
+        if (!(d3 <= 1e-12 * r3)) { fprintf(stderr, "P3 residual vs oracle: %.3e relative\n", d3 / r3); ++fails; }
+        if (fem_integrate_residual_p3(3, FEM_LAPLACE, FEM_RULE_TET4, FEM_COEF_QUAD, FEM_F64, n_elem, dij3, ddj3, du3,
+                                      dc3, dR3, stream) != FEM_ERR_UNSUPPORTED) {
+            fprintf(stderr, "expected FEM_ERR_UNSUPPORTED for P3 with a degree-2 rule\n");
+            ++fails;
+        }
+        hipFree(dij3); hipFree(ddj3); hipFree(du3); hipFree(dc3); hipFree(dR3);
+        free(u3); free(c3); free(R3_ref); free(R3);
+    }
 
     /* error paths */
     if (fem_integrate_residual(3, FEM_LAPLACE, FEM_RULE_TRI3, FEM_COEF_QUAD, FEM_F64, n_elem, dij, ddj, du, dcoef,
