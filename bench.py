@@ -8,21 +8,30 @@ residuals from coordinates, connectivity, closure and coefficients, in FP32,
 with geometry and integration fused in one kernel
 (fem_integrate_residual_mesh). The same step as two calls (fem_geometry, then
 fem_integrate_residual) is reported beside it. All inputs are resident in HBM before the
-timed region. They are replicated into several copies (> 512 MB in total) and
-the steps rotate through them, so the 256 MB last-level cache cannot serve a
-step from the data of the one before.
+timed region. They are replicated into at least 8 copies (> 600 MB of the
+fused kernel's bytes in total) and the steps rotate through them, so the
+256 MB last-level cache cannot serve a step from the data of the one before.
 
 The timed region is one replay of a HIP graph holding the `--steps` steps
 (captured with torch's graph capture on the stream the library launches on),
 bracketed by one pair of HIP events; launching through Python one call at a
 time would otherwise cost more host time than a step takes on the GPU.
 
-Prints ONE JSON line on stdout (progress goes to stderr). `value` is
-elements per second of the step (wall clock around the replay). The roofline
-object is for the step's kernel, its duration being the events' elapsed time
-over the replay divided by the number of launches in it. Extra sections (outside `value`): FP64, the elasticity
-workloads, the adjoint, the batched launch against 64 separate launches, the
-achievable bandwidth of a plain copy kernel, and the FP64 CPU oracle.
+Prints ONE compact JSON line, last on stdout and below 4 KB (a few progress
+lines go to stderr; --verbose prints one per section). `value` is elements
+per second of the step (wall clock around the replay). The roofline object is
+for the step's kernel, its duration being the events' elapsed time over the
+replay divided by the number of launches in it. The line also summarises the
+FP64 step, the integrate-only kernel (the paper's form, geometry precomputed),
+the batched launch against the same 64 launches recorded in one graph, the
+thread transposition against the lane kernel, and the FP64 CPU oracle. The
+full record, with every extra section (elasticity, coefficient spaces,
+gather form, mesh plans, P2/P3, element matrices, assembly, adjoint), is
+written to gpurun_out/bench_extra.json (--extra-out).
+
+Every timed section rotates through copies of its inputs sized on the bytes
+its own kernel touches per launch: at least 8 copies and more than 600 MB in
+total (2 copies when one launch alone moves more than that).
 """
 from __future__ import annotations
 
@@ -40,10 +49,18 @@ sys.path.insert(0, str(ROOT))
 METRIC = "element-integration GF/s & elements/s (FP32, FP64); % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
 ROTATE_BYTES = 600e6  # rotate through input copies totalling at least this much
+MIN_COPIES = 8       # and through at least this many copies
+MAX_LINE = 4000      # the JSON line on stdout stays below this many bytes
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+VERBOSE = False
+EXTRA_PATH = ROOT / "gpurun_out" / "bench_extra.json"
+
+
+def log(msg, always=False):
+    """Progress on stderr: a few lines by default, every section with --verbose."""
+    if always or VERBOSE:
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -53,6 +70,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--quick", action="store_true", help="main step only (no extra sections, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--verbose", action="store_true", help="one progress line per section on stderr")
+    p.add_argument("--extra-out", default=str(EXTRA_PATH),
+                   help="file that receives the full result with every extra section")
     return p.parse_args()
 
 
@@ -87,7 +107,9 @@ def measured_traffic(kernel, workload):
 
 
 def main():
+    global VERBOSE
     args = parse()
+    VERBOSE = args.verbose
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the element stream shards with no "
               "communication, so each GPU would run this same single-GPU workload on its slice.",
@@ -104,7 +126,7 @@ def main():
     torch.cuda.set_device(dev)
     props = torch.cuda.get_device_properties(dev)
     log(f"device {props.name} {getattr(props, 'gcnArchName', '')} CUs {props.multi_processor_count} "
-        f"mem {props.total_memory / 2**30:.0f} GiB")
+        f"mem {props.total_memory / 2**30:.0f} GiB", always=True)
 
     def to_dev(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
@@ -115,7 +137,13 @@ def main():
         return e
 
     def n_copies(bytes_per_copy):
-        return int(max(2, min(16, -(-ROTATE_BYTES // max(bytes_per_copy, 1)))))
+        """Copies of a timed section's inputs, sized on the bytes its own
+        kernel touches per launch: at least MIN_COPIES and more than
+        ROTATE_BYTES in total, so that no launch finds its inputs in the
+        256 MB last-level cache left behind by the launches before it."""
+        if bytes_per_copy >= ROTATE_BYTES:
+            return 2   # one launch alone overruns the last-level cache
+        return int(max(MIN_COPIES, min(64, -(-ROTATE_BYTES // max(bytes_per_copy, 1)))))
 
     # -------------------------------------------------------------- main step --
     t0 = time.time()
@@ -125,8 +153,10 @@ def main():
     flops = model.model_flops(dim, phys, rule)
 
     def step_copies(dt):
+        # sized on the fused kernel's bytes, the smallest per-launch footprint
+        # of the kernels that rotate through these copies
         word = 4 if dt == torch.float32 else 8
-        per = (model.geometry_bytes(dim, n, wl.n_vert, word) + model.forward_bytes(dim, phys, rule, word)) * n
+        per = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, word) * n
         base = dict(coords=to_dev(wl.coords, torch.float64), conn=to_dev(wl.conn, torch.int32),
                     u=to_dev(wl.u, dt), coef=to_dev(wl.coef, dt))
         cs = []
@@ -198,7 +228,7 @@ def main():
     value = n * args.steps / wall
     log(f"FP32 fused step {ms_per_step * 1e3:.1f} us ({value:.3e} elem/s), kernel {fused_ms * 1e3:.1f} us; "
         f"two-call step {1e6 * swall / args.steps:.1f} us (geometry {geo_ms * 1e3:.1f} us, integrate "
-        f"{int_ms * 1e3:.1f} us)")
+        f"{int_ms * 1e3:.1f} us)", always=True)
 
     fused_bytes = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 4) * n
     int_bytes = model.forward_bytes(dim, phys, rule, 4) * n
@@ -233,7 +263,7 @@ def main():
     roofline["achievable_gbs"] = big_gbs
     roofline["frac_of_achievable"] = dk["gbs"] / big_gbs
     roofline["achievable_gbs_same_bytes"] = same_gbs
-    log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the fused kernel's byte count")
+    log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the fused kernel's byte count", always=True)
 
     result = {
         "metric": METRIC,
@@ -342,7 +372,7 @@ def main():
 
         # ---------------------------------------------- coefficient spaces --
         # The paper's GPU runs take the coefficient as a P1 field or per cell
-        # (Section 5); P1 coefficients are the closure of a vertex field.
+        # (Section 4); P1 coefficients are the closure of a vertex field.
         for cfg in (2, "3a"):
             wlx = wl if cfg == 2 else mg.config(cfg)
             for space, sname in ((mg.COEF_P1, "p1"), (mg.COEF_P0, "p0")):
@@ -767,18 +797,107 @@ def main():
             separate_launches_us=sep_us, separate_launches_in_a_graph_us=sep_graph_ms * 1e3,
             persistent_launch_us=run_us, graph_replay_us=rep_us,
             graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
-            speedup_vs_separate=sep_us / rep_us, autotuned_launch=shape,
-            note="the meshes total about 0.9 GB, above the last-level cache; medians of 10")
+            speedup_vs_separate=sep_graph_ms * 1e3 / rep_us,
+            speedup_vs_separate_issued_from_python=sep_us / rep_us, autotuned_launch=shape,
+            note="speedup_vs_separate: the 64 single-mesh launches recorded in one graph against the one "
+                 "persistent launch; the meshes total about 0.9 GB, above the last-level cache; medians of 10")
         log(f"batched: 64 launches {sep_us:.1f} us ({sep_graph_ms * 1e3:.1f} us as one graph), persistent "
             f"{run_us:.1f} us, graph {rep_us:.1f} us "
-            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s); autotuned launch {shape}")
+            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s, {sep_graph_ms * 1e3 / rep_us:.2f}x the graph of 64); "
+            f"autotuned launch {shape}", always=True)
         del meshes
         result["extra"] = extra
 
     if not args.quick and not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(wl, flops)
 
-    print(json.dumps(result), flush=True)
+    # The full record, every extra section included, goes to a file; stdout
+    # gets one compact line, last.
+    out = pathlib.Path(args.extra_out)
+    try:
+        out.parent.mkdir(parents=True, exist_ok=True)
+        out.write_text(json.dumps(result, indent=1))
+        result["extra_file"] = str(out.relative_to(ROOT) if out.is_relative_to(ROOT) else out)
+    except OSError as exc:
+        log(f"could not write {out}: {exc}", always=True)
+    print(json.dumps(compact(result)), flush=True)
+
+
+def _r(x, digits=4):
+    """x rounded to `digits` significant digits (None stays None)."""
+    return None if x is None else float(f"{x:.{digits}g}")
+
+
+def compact(res):
+    """The stdout record: the contract's keys, the roofline of the step's
+    kernel, the CPU baseline, and one short object per headline variant
+    (FP64 step, integrate-only kernel, two-call step, copy yardstick,
+    batched launch, thread transposition, elasticity)."""
+    rf = res["roofline"]
+    k = res["kernels"]
+    line = {key: res[key] for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                      "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    line["value"] = _r(line["value"], 6)
+    line["ms_per_step"] = _r(line["ms_per_step"], 5)
+    line["config"] = {"workload": res["config"]["workload"], "n_elem": res["config"]["n_elem"],
+                      "n_vert": res["config"]["n_vert"]}
+    line["model_gflops"] = _r(res["model_gflops"])
+    line["roofline"] = {"bound": rf["bound"], "kernel": rf["kernel"], "achieved": _r(rf["achieved"]),
+                        "peak": rf["peak"], "unit": rf["unit"], "frac": _r(rf["frac"]),
+                        "traffic": rf["traffic"], "algorithmic_bytes_per_launch": rf["algorithmic_bytes_per_launch"],
+                        "kernel_us": _r(k[rf["kernel"]]["avg_us"]), "achievable_gbs": _r(rf.get("achievable_gbs")),
+                        "frac_of_achievable": _r(rf.get("frac_of_achievable")),
+                        "copy_same_bytes_gbs": _r(rf.get("achievable_gbs_same_bytes"))}
+    ki = k["fem_integrate_residual"]
+    line["integrate_only"] = {"kernel": "fem_integrate_residual", "us": _r(ki["avg_us"]),
+                              "elements_per_s": _r(ki["elements_per_s"]), "gbs": _r(ki["gbs"]),
+                              "frac": _r(ki["gbs"] / HBM_PEAK_GBS), "model_gflops": _r(ki["model_gflops"]),
+                              "algorithmic_bytes_per_launch": ki["algorithmic_bytes"]}
+    kg = k["fem_geometry"]
+    line["geometry_only"] = {"us": _r(kg["avg_us"]), "gbs": _r(kg["gbs"]), "frac": _r(kg["gbs"] / HBM_PEAK_GBS)}
+    line["two_call_step"] = {"elements_per_s": _r(res["two_call_step"]["elements_per_s"]),
+                             "ms_per_step": _r(res["two_call_step"]["ms_per_step"])}
+    ex = res.get("extra", {})
+    if "fp64_step" in ex:
+        f = ex["fp64_step"]
+        line["fp64"] = {"value": _r(f["elements_per_s"]), "ms_per_step": _r(f["ms_per_step"]),
+                        "kernel_us": _r(f["fused_us"]), "frac": _r(f["fused_gbs"] / HBM_PEAK_GBS),
+                        "integrate_us": _r(f["integrate_us"]), "integrate_frac": _r(f["integrate_gbs"] / HBM_PEAK_GBS)}
+    el = {}
+    for key, tag in (("elasticity2d_2p22_f32_integrate", "2d_f32"), ("elasticity3d_2p21_f32_integrate", "3d_f32"),
+                     ("elasticity2d_2p22_f64_integrate", "2d_f64"), ("elasticity3d_2p21_f64_integrate", "3d_f64")):
+        if key in ex:
+            el[tag] = {"elements_per_s": _r(ex[key]["elements_per_s"]), "frac": _r(ex[key]["frac_of_peak"])}
+    if el:
+        line["elasticity_integrate"] = el
+    if "adjoint_laplace3d_2p21_f32" in ex:
+        a = ex["adjoint_laplace3d_2p21_f32"]
+        line["adjoint"] = {"us": _r(a["us"]), "frac": _r(a["frac_of_peak"])}
+    if "batched_64_meshes_f32" in ex:
+        b = ex["batched_64_meshes_f32"]
+        line["batched"] = {"graph_replay_us": _r(b["graph_replay_us"]),
+                           "elements_per_s": _r(b["graph_replay_elements_per_s"]),
+                           "frac": _r(b["graph_replay_gbs"] / HBM_PEAK_GBS),
+                           "separate_in_one_graph_us": _r(b["separate_launches_in_a_graph_us"]),
+                           "speedup_vs_separate": _r(b["speedup_vs_separate"])}
+    tt = {k2[len("strategies_"):]: {"lane_us": _r(v["lane_us"]), "transpose_us": _r(v["transpose_us"])}
+          for k2, v in ex.items() if k2.startswith("strategies_")}
+    if tt:
+        line["transposition"] = tt
+    cb = res.get("cpu_baseline")
+    if cb:
+        line["cpu_baseline"] = {"value": _r(cb["value"]), "unit": cb["unit"], "cores": cb["cores"], "kind": cb["kind"],
+                                "sample": cb["sample"],
+                                "single_thread": _r(cb["single_thread"]["value"])}
+    if "extra_file" in res:
+        line["extra_file"] = res["extra_file"]
+    # stay below MAX_LINE bytes whatever the variants hold: drop the optional
+    # objects last-added first
+    for key in ("transposition", "elasticity_integrate", "adjoint", "geometry_only", "two_call_step", "batched"):
+        if len(json.dumps(line)) <= MAX_LINE:
+            break
+        line.pop(key, None)
+    return line
 
 
 def cpu_baseline(wl, flops):
@@ -821,7 +940,7 @@ def cpu_baseline(wl, flops):
         reps += 1
     assert nd == 0 and np.isfinite(R).all()
     eps_1 = wl.n_elem * reps / t_total
-    log(f"CPU oracle: {eps_mt:.3e} elements/s on {threads} threads, {eps_1:.3e} on one")
+    log(f"CPU oracle: {eps_mt:.3e} elements/s on {threads} threads, {eps_1:.3e} on one", always=True)
     return {"value": eps_mt, "unit": "elements/s", "cores": threads, "kind": "oracle",
             "sample": f"fem_oracle_residual (FP64 geometry + residual) over all {wl.n_elem} elements of the step "
                       f"workload, split into {threads} contiguous chunks on {threads} threads; median of 5 passes "

@@ -13,7 +13,7 @@
  * follow the paper's integration routine (Appendix): per-element geometry
  * (inverse Jacobian and determinant), the element closure of u, and per
  * element outputs. Auxiliary coefficients live on quadrature points
- * (Section 5, "Variable Coefficients").
+ * (Section 4, "Variable Coefficients").
  *
  * Conventions shared by every call:
  *  - All array arguments are DEVICE pointers owned by the caller. The library
@@ -27,7 +27,7 @@
  *    with N_b = dim+1, N_comp = 1 (Laplacian, mass) or dim (elasticity),
  *    N_coef = 1 (kappa) or 2 (lambda, mu), N_q from the rule, and N_w the
  *    words of one coefficient field per element in its space (below).
- *  - Coefficient spaces (paper Section 5, "Variable Coefficients": an
+ *  - Coefficient spaces (paper Section 4, "Variable Coefficients": an
  *    auxiliary field may live on quadrature points, in the space of u, or be
  *    constant per cell):
  *      FEM_COEF_QUAD  values at the quadrature points, N_w = N_q
@@ -173,7 +173,7 @@ fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_
  *   u_vertex [n_vert][N_comp]  dtype, component c of vertex v at v*N_comp + c
  *   coef     FEM_COEF_P1: [n_vert][N_coef] vertex values (coefficient m of
  *            vertex v at v*N_coef + m), gathered the same way (the paper's
- *            auxiliary field in the space of u, Section 5);
+ *            auxiliary field in the space of u, Section 4);
  *            FEM_COEF_QUAD, FEM_COEF_P0: per element as for
  *            fem_integrate_residual.
  * Everything else (geometry outputs, counts, layouts, bitwise agreement

@@ -48,7 +48,7 @@
  *    linear elasticity f1 = lambda tr(eps) I + 2 mu eps, eps the symmetric
  *    gradient (the paper's Lame function in Section 6 is lambda = 0,
  *    mu = 1/2); mass/reaction f0 = kappa u, f1 = 0;
- *  - coefficients (Section 5, "Variable Coefficients") live on quadrature
+ *  - coefficients (Section 4, "Variable Coefficients") live on quadrature
  *    points, or in the P1 space of u (nodal values, evaluated at point q
  *    with the same tabulation as u), or in P0 (one value per cell); they
  *    are evaluated at every quadrature point before the physics.

@@ -41,7 +41,7 @@ def n_basis(dim: int, order: int = 1) -> int:
 
 def n_coef_words(dim: int, rule: int, coef_space: int = N.COEF_QUAD) -> int:
     """Words per coefficient and element: N_q values at the points, the
-    N_b = d+1 vertex values of a P1 field, or one cell value (Section 5)."""
+    N_b = d+1 vertex values of a P1 field, or one cell value (Section 4)."""
     if coef_space == N.COEF_QUAD:
         return n_qpts(dim, rule)
     if coef_space == N.COEF_P1:

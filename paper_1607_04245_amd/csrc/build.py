@@ -49,11 +49,23 @@ def _compile(src: str, verbose: bool) -> pathlib.Path:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> pathlib.Path:
+def _stale(src: str) -> bool:
+    """Whether src's object is missing or older than src or any header."""
+    obj = BUILD / (pathlib.Path(src).stem + ".o")
+    if not obj.exists():
+        return True
+    deps = [HERE / src, *HERE.glob("*.hpp"), *(ROOT / "include").glob("*.h")]
+    return obj.stat().st_mtime < max(d.stat().st_mtime for d in deps)
+
+
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> pathlib.Path:
+    """Compile every source (or, with incremental, the stale ones) and link."""
     BUILD.mkdir(exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    todo = [s for s in SOURCES if not incremental or _stale(s)]
+    jobs = jobs or min(max(len(todo), 1), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        list(ex.map(lambda s: _compile(s, verbose), todo))
+    objs = [BUILD / (pathlib.Path(s).stem + ".o") for s in SOURCES]
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs)]
     if verbose:
@@ -64,4 +76,5 @@ def build(verbose: bool = False, jobs: int | None = None) -> pathlib.Path:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

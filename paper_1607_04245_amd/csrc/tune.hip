@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cctype>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -123,6 +124,11 @@ static bool read_file(const char* path, std::string& out) {
     return true;
 }
 
+// A JSON number as an int: values that are not finite or lie outside
+// +-1e9 become -1 (which no field accepts) instead of an undefined
+// conversion.
+static int as_int(double x) { return (std::isfinite(x) && x > -1e9 && x < 1e9) ? (int)x : -1; }
+
 // Parses the objects inside the "entries" array. Unknown keys are ignored;
 // malformed input yields no entries rather than an error.
 static std::vector<CacheEntry> parse_cache(const std::string& s) {
@@ -159,15 +165,15 @@ static std::vector<CacheEntry> parse_cache(const std::string& s) {
                 char* end = nullptr;
                 double x = std::strtod(obj.c_str() + v, &end);
                 size_t used = end ? (size_t)(end - obj.c_str()) : v;
-                if (key == "op") e.op = (int)x;
-                else if (key == "dim") e.dim = (int)x;
-                else if (key == "physics") e.physics = (int)x;
-                else if (key == "rule") e.rule = (int)x;
-                else if (key == "dtype") e.dtype = (int)x;
-                else if (key == "strategy") e.t.strategy = (int)x;
-                else if (key == "vec") e.t.vec = (int)x;
-                else if (key == "waves_per_block") e.t.waves_per_block = (int)x;
-                else if (key == "blocks_per_cu") e.t.blocks_per_cu = (int)x;
+                if (key == "op") e.op = as_int(x);
+                else if (key == "dim") e.dim = as_int(x);
+                else if (key == "physics") e.physics = as_int(x);
+                else if (key == "rule") e.rule = as_int(x);
+                else if (key == "dtype") e.dtype = as_int(x);
+                else if (key == "strategy") e.t.strategy = as_int(x);
+                else if (key == "vec") e.t.vec = as_int(x);
+                else if (key == "waves_per_block") e.t.waves_per_block = as_int(x);
+                else if (key == "blocks_per_cu") e.t.blocks_per_cu = as_int(x);
                 else if (key == "us") e.us = x;
                 p = used > v ? used : v + 1;
             }

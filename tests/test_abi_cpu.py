@@ -153,6 +153,57 @@ def test_autotune_validation(lib):
     assert lib.fem_load_tuning(None) == N.FEM_ERR_INVALID_ARG
 
 
+def _cache_entry(arch, op=0, dim=2, physics=2, rule=2, dtype=1, strategy=0, vec=2, waves=2, bpc=8, extra=""):
+    return (f'{{"arch": "{arch}", "op": {op}, "dim": {dim}, "physics": {physics}, "rule": {rule}, '
+            f'"dtype": {dtype}, "strategy": {strategy}, "vec": {vec}, "waves_per_block": {waves}, '
+            f'"blocks_per_cu": {bpc}{extra}, "us": 1.0}}')
+
+
+def test_load_tuning_malformed_cache(lib, tmp_path):
+    """fem_load_tuning on malformed, truncated or out-of-range cache files:
+    FEM_ERR_NO_TUNING, no crash, and the configuration in force unchanged.
+    Every file names both the architecture of a GPU here and "unknown" (what
+    the library reports with no GPU), so the valid entries apply anywhere."""
+    key = (N.OP_RESIDUAL, 2, mg.MASS, mg.RULE_CENTROID, N.F64)
+    base = N.fem_tuning(N.STRATEGY_LANE, 1, 4, 0)
+    assert lib.fem_set_tuning(*key, ctypes.byref(base)) == N.FEM_OK
+
+    def current():
+        t = N.fem_tuning()
+        assert lib.fem_get_tuning(*key, ctypes.byref(t)) == N.FEM_OK
+        return (t.strategy, t.vec, t.waves_per_block, t.blocks_per_cu)
+
+    def both(**kw):
+        return ", ".join(_cache_entry(a, **kw) for a in ("unknown", "gfx950"))
+
+    bad = {
+        "empty": "",
+        "not json": "\x00\xff garbage {{{ ]]] \"",
+        "no entries key": '{"version": 1, "items": [' + both() + ']}',
+        "truncated object": '{"version": 1, "entries": [{"arch": "unknown", "op": 0, "dim"',
+        "unterminated string": '{"entries": [{"arch": "unkn',
+        "array closed first": '{"entries": ]' + both() + '}',
+        "value without number": '{"entries": [' + both(extra=', "vec": abc') + ']}',
+        "huge numbers": '{"entries": [' + ", ".join(
+            _cache_entry(a, dim="1e400", vec="-1e300", waves="nan") for a in ("unknown", "gfx950")) + ']}',
+        "invalid launch shape": '{"entries": [' + both(vec=3, waves=5) + ']}',
+        "unsupported op": '{"entries": [' + both(op=99) + ']}',
+        "colon missing": '{"entries": [{"arch" "unknown" "op" 0}]}',
+    }
+    for name, text in bad.items():
+        f = tmp_path / (name.replace(" ", "_") + ".json")
+        f.write_text(text)
+        assert lib.fem_load_tuning(str(f).encode()) == N.FEM_ERR_NO_TUNING, name
+        assert current() == (0, 1, 4, 0), name
+    assert lib.fem_load_tuning(str(tmp_path / "missing.json").encode()) == N.FEM_ERR_NO_TUNING
+    # a malformed entry next to a valid one: the valid one is applied
+    f = tmp_path / "mixed.json"
+    f.write_text('{"version": 1, "entries": [' + both(vec=3) + ", " + both(vec=2, waves=2, bpc=8) + ']}')
+    assert lib.fem_load_tuning(str(f).encode()) == N.FEM_OK
+    assert current() == (0, 2, 2, 8)
+    assert lib.fem_set_tuning(*key, ctypes.byref(base)) == N.FEM_OK
+
+
 def test_residual_mesh_validation(lib):
     c = (3, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, N.F32)
     f = lib.fem_integrate_residual_mesh

@@ -1,4 +1,4 @@
-"""GPU parity of the coefficient spaces (paper Section 5: an auxiliary field
+"""GPU parity of the coefficient spaces (paper Section 4, "Variable Coefficients": an auxiliary field
 given at the quadrature points, in the P1 space of u, or constant per cell).
 
 Every kernel kind (lane, thread transposition, fused from-mesh, batched

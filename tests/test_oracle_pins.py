@@ -504,6 +504,61 @@ def test_abs_mode_bounds():
     assert np.all(Ra >= np.abs(R) * (1 - 1e-15))
 
 
+def test_abs_mode_equals_residual_for_nonnegative_factors():
+    """Upper pin of the abs-mode scale. The P1 mass form with u >= 0 and a
+    positive coefficient has only nonnegative factors under the degree-2 and
+    centroid rules (positive weights, barycentric values >= 0 at the points),
+    so the |.| sums are the residual itself, bit for bit, in every
+    coefficient space. An abs mode that inflated any factor would fail."""
+    rng = np.random.default_rng(16)
+    for dim, rule in ((2, TRI3), (3, TET4), (2, CEN), (3, CEN)):
+        x = random_simplices(dim, 40, rng)
+        coords, conn = mesh_from_simplices(x)
+        ij, dj, nd = oracle.geometry(coords, conn)
+        assert nd == 0
+        n = len(x)
+        for space in (0, 1, 2):
+            u = rng.uniform(0.0, 1.0, (dim + 1, n))
+            cf = rng.uniform(0.5, 2.0, (1, oracle.oracle.coef_words(dim, rule, space), n))
+            R = oracle.integrate(dim, MASS, rule, ij, dj, u, cf, space=space)
+            Ra = oracle.integrate_abs(dim, MASS, rule, ij, dj, u, cf, space=space)
+            assert np.array_equal(R, Ra), (dim, rule, space)
+
+
+def test_abs_mode_negative_weight_closed_form():
+    """The 11-point tetrahedral rule has one negative weight, -148/1875 times
+    1/6, at the centroid; every P2 edge function 4 lam_i lam_j is >= 0 on the
+    element and equals 1/4 there. For the P2 mass form with kappa = 1 and the
+    closure of edge function s as u, each edge row r of the |.| sums exceeds
+    the residual by exactly twice the centroid's term,
+    2 (148/1875/6) |det J| (1/4)(1/4). With the six-point triangle rule (all
+    weights positive) the same rows agree bit for bit."""
+    rng = np.random.default_rng(17)
+    x = random_simplices(3, 12, rng)
+    coords, conn = mesh_from_simplices(x)
+    ij, dj, _ = oracle.geometry(coords, conn)
+    n = len(x)
+    vol6 = np.abs([np.linalg.det((xe[1:] - xe[0]).T) for xe in x])   # |det J|, not from the oracle
+    cf = np.ones((1, 11, n))
+    for s in range(4, 10):
+        u = np.zeros((10, n))
+        u[s] = 1.0
+        R = oracle.integrate(3, MASS, mg.RULE_TET11, ij, dj, u, cf, order=2)
+        Ra = oracle.integrate_abs(3, MASS, mg.RULE_TET11, ij, dj, u, cf, order=2)
+        expect = 2.0 * (148.0 / 1875.0 / 6.0) * vol6 / 16.0
+        np.testing.assert_allclose(Ra[4:10] - R[4:10], np.broadcast_to(expect, (6, n)), rtol=1e-9, atol=0)
+    x2 = random_simplices(2, 12, rng)
+    coords, conn = mesh_from_simplices(x2)
+    ij, dj, _ = oracle.geometry(coords, conn)
+    cf = np.ones((1, 6, len(x2)))
+    for s in range(3, 6):
+        u = np.zeros((6, len(x2)))
+        u[s] = 1.0
+        R = oracle.integrate(2, MASS, mg.RULE_TRI6, ij, dj, u, cf, order=2)
+        Ra = oracle.integrate_abs(2, MASS, mg.RULE_TRI6, ij, dj, u, cf, order=2)
+        assert np.array_equal(R[3:6], Ra[3:6])
+
+
 # ----------------------------------------------------------------- adjoint --
 
 def per_element_L(dim, phys, rule, ij, dj, u, coef, w):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's coefficient spaces (paper Section 5: an auxiliary
+"""Pins of the oracle's coefficient spaces (paper Section 4, "Variable Coefficients": an auxiliary
 field on quadrature points, in the P1 space of u, or constant per cell)."""
 import numpy as np
 import pytest
