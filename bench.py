@@ -413,24 +413,33 @@ def main():
         # N_q = 1 case; best of the transposition's workgroup sizes.
         wlq = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
                                rule=mg.RULE_CENTROID)
-        for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
-            saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
-            lane = integrate_only(wlx, torch.float32)
+        def best_of(wlx, strategy, shapes):
+            """Fastest launch shape of a strategy: (shape, result) or None."""
             best = None
-            for waves in (1, 2, 4, 8):
-                api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, strategy=N.STRATEGY_TRANSPOSE, vec=1,
-                                   waves_per_block=waves, blocks_per_cu=0)
+            for waves, bpc in shapes:
+                api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, strategy=strategy, vec=1,
+                                   waves_per_block=waves, blocks_per_cu=bpc)
                 try:
                     r = integrate_only(wlx, torch.float32)
                 except N.FemError:  # workgroup too large for this element's LDS tile
                     continue
                 if best is None or r["us"] < best[1]["us"]:
-                    best = (waves, r)
+                    best = ((waves, bpc), r)
+            return best
+
+        shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 8)]
+        for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
+            saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
+            lane = integrate_only(wlx, torch.float32)
+            tt = best_of(wlx, N.STRATEGY_TRANSPOSE, shapes)
+            sh = best_of(wlx, N.STRATEGY_SHUFFLE, shapes)
             api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, **saved)
-            extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=best[1]["us"],
-                                              transpose_gbs=best[1]["gbs"], transpose_waves_per_block=best[0])
-            log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition "
-                f"{best[1]['us']:.1f} us ({best[1]['gbs']:.0f} GB/s, {best[0]} waves per workgroup)")
+            extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=tt[1]["us"],
+                                              transpose_gbs=tt[1]["gbs"], transpose_shape=tt[0],
+                                              shuffle_us=sh[1]["us"], shuffle_gbs=sh[1]["gbs"], shuffle_shape=sh[0])
+            log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition through "
+                f"LDS {tt[1]['us']:.1f} us ({tt[1]['gbs']:.0f} GB/s, shape {tt[0]}), through quad permutations "
+                f"{sh[1]['us']:.1f} us ({sh[1]['gbs']:.0f} GB/s, shape {sh[0]})", always=True)
         del wlq
 
         # ------------------------------------------------------ gather form --
@@ -598,17 +607,35 @@ def main():
                 def go(c, wlx=wlx, rule_p3=rule_p3):
                     api.fem_integrate_residual_p3(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"], c["cf"],
                                                   out=c["R"])
+                saved = api.fem_get_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3)
+                api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_LANE,
+                                   vec=1, waves_per_block=1 if wlx.dim == 3 else 4, blocks_per_cu=0)
                 _, ms = timed_graph(go, cps, 10, 1)
                 us = ms * 1e3
+                mfma = None
+                if wlx.dim == 3:
+                    # the transposition on the matrix cores, best launch shape
+                    for waves, bpc in ((1, 0), (2, 0), (4, 0), (4, 2), (4, 4), (2, 4)):
+                        api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3,
+                                           strategy=N.STRATEGY_MFMA, vec=1, waves_per_block=waves, blocks_per_cu=bpc)
+                        _, msm = timed_graph(go, cps, 10, 1)
+                        if mfma is None or msm * 1e3 < mfma[1]:
+                            mfma = ((waves, bpc), msm * 1e3)
+                api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, **saved)
                 f = model.p3_model_flops(wlx.dim, wlx.physics, rule_p3)
                 cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 10)
                 extra[f"{wlx.name}_p3_{tag}_integrate"] = dict(
                     n_elem=wlx.n_elem, rule=rule_p3, us=us, gbs=nb / (us * 1e-6) / 1e9,
                     elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
                     bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
-                log(f"{wlx.name} P3 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
-                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
-                    f"copy of the same bytes {cp_us:.1f} us")
+                if mfma:
+                    extra[f"{wlx.name}_p3_{tag}_integrate"].update(
+                        mfma_us=mfma[1], mfma_shape=mfma[0], mfma_gbs=nb / (mfma[1] * 1e-6) / 1e9,
+                        mfma_frac_of_copy_same_bytes=cp_us / mfma[1])
+                log(f"{wlx.name} P3 {tag} integrate: lane kernel {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)"
+                    + (f", matrix-core transposition {mfma[1]:.1f} us (shape {mfma[0]})" if mfma else "")
+                    + f"; copy of the same bytes {cp_us:.1f} us", always=wlx.dim == 3)
                 if wlx.dim == 3:
                     # the adjoint (du and dcoef) on the same inputs, w = u
                     nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
@@ -880,8 +907,16 @@ def compact(res):
                            "frac": _r(b["graph_replay_gbs"] / HBM_PEAK_GBS),
                            "separate_in_one_graph_us": _r(b["separate_launches_in_a_graph_us"]),
                            "speedup_vs_separate": _r(b["speedup_vs_separate"])}
-    tt = {k2[len("strategies_"):]: {"lane_us": _r(v["lane_us"]), "transpose_us": _r(v["transpose_us"])}
+    tt = {k2[len("strategies_"):]: {"lane_us": _r(v["lane_us"]), "lds_us": _r(v["transpose_us"]),
+                                     "shuffle_us": _r(v.get("shuffle_us"))}
           for k2, v in ex.items() if k2.startswith("strategies_")}
+    p3 = {}
+    for key, v in ex.items():
+        if key.endswith("_integrate") and "_p3_" in key and "mfma_us" in v:
+            p3[key[:-len("_integrate")]] = {"lane_us": _r(v["us"]), "mfma_us": _r(v["mfma_us"]),
+                                            "copy_us": _r(v["copy_same_bytes_us"])}
+    if p3:
+        line["p3_transposition"] = p3
     if tt:
         line["transposition"] = tt
     cb = res.get("cpu_baseline")
@@ -893,7 +928,8 @@ def compact(res):
         line["extra_file"] = res["extra_file"]
     # stay below MAX_LINE bytes whatever the variants hold: drop the optional
     # objects last-added first
-    for key in ("transposition", "elasticity_integrate", "adjoint", "geometry_only", "two_call_step", "batched"):
+    for key in ("p3_transposition", "transposition", "elasticity_integrate", "adjoint", "geometry_only",
+                "two_call_step", "batched"):
         if len(json.dumps(line)) <= MAX_LINE:
             break
         line.pop(key, None)

@@ -95,10 +95,25 @@ enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
  *                          basis phases run in registers.
  *  FEM_STRATEGY_TRANSPOSE  the paper's thread transposition (Section 3):
  *                          lanes work per (element, quadrature point) in the
- *                          quadrature phase, write weighted f0/f1 to LDS, and
+ *                          quadrature phase, write weighted, pulled-back
+ *                          f0/f1 to LDS, and
  *                          switch to one lane per (element, basis function)
- *                          for the basis phase, with no cross-lane reduction. */
-enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1 };
+ *                          for the basis phase, with no cross-lane reduction.
+ *  FEM_STRATEGY_MFMA       the same transposition for P3 tetrahedra (Laplacian,
+ *                          elasticity; FEM_OP_RESIDUAL_P3 only) with the two
+ *                          tabulation contractions on the matrix cores: four
+ *                          lanes share an element, each evaluates the
+ *                          pointwise physics at its own quadrature points,
+ *                          and the products switch between the point- and
+ *                          basis-parallel layouts. Agrees with the lane
+ *                          kernel to rounding (another summation order).
+ *  FEM_STRATEGY_SHUFFLE    the transposition of FEM_STRATEGY_TRANSPOSE for
+ *                          scalar fields (Laplacian, mass; FEM_OP_RESIDUAL
+ *                          only) with cross-lane permutations instead of LDS:
+ *                          four lanes share an element, lane r being point r
+ *                          and then basis function r. */
+enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1, FEM_STRATEGY_MFMA = 2,
+                    FEM_STRATEGY_SHUFFLE = 3 };
 
 /* Operations; each has its own launch configuration (see fem_tuning). */
 enum fem_op {

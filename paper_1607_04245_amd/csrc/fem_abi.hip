@@ -173,9 +173,16 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     return t;
 }
 
+// The matrix-core transposition exists for P3 tetrahedra with an f1 physics.
+static bool mfma_available(int op, int dim, int phys) {
+    return op == FEM_OP_RESIDUAL_P3 && dim == 3 && (phys == FEM_LAPLACE || phys == FEM_ELASTICITY);
+}
+
 static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
-                             (t.strategy == FEM_STRATEGY_TRANSPOSE && op == FEM_OP_RESIDUAL);
+                             ((t.strategy == FEM_STRATEGY_TRANSPOSE || t.strategy == FEM_STRATEGY_SHUFFLE) &&
+                              op == FEM_OP_RESIDUAL) ||
+                             (t.strategy == FEM_STRATEGY_MFMA && op == FEM_OP_RESIDUAL_P3);
     const bool one = one_per_lane_op(op);
     const bool vec_ok = one ? t.vec == 1 : (t.vec == 1 || t.vec == 2 || t.vec == 4);
     const bool waves_ok = t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
@@ -267,6 +274,14 @@ fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, con
     fem_status st = check_tuning_args("fem_set_tuning", op, dim, physics, rule, dtype);
     if (st) return st;
     if (!t || !valid_tuning(op, *t)) { set_error("fem_set_tuning: invalid tuning for op %d", op); return FEM_ERR_INVALID_ARG; }
+    if (t->strategy == FEM_STRATEGY_SHUFFLE && physics == FEM_ELASTICITY) {
+        set_error("fem_set_tuning: the quad-permutation strategy covers scalar fields (Laplacian, mass)");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (t->strategy == FEM_STRATEGY_MFMA && !mfma_available(op, dim, physics)) {
+        set_error("fem_set_tuning: the matrix-core strategy covers P3 tetrahedra with the Laplacian or elasticity");
+        return FEM_ERR_UNSUPPORTED;
+    }
     put_tuning(op, dim, physics, rule, dtype, *t);
     return FEM_OK;
 }
@@ -307,6 +322,13 @@ fem_status fem_integrate_residual(int dim, int physics, int rule, int coef_space
         Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
         l.block = threads;
         e = launch_residual_transpose(dim, physics, rule, coef_space, dtype, a, l);
+    } else if (t.strategy == FEM_STRATEGY_SHUFFLE) {
+        if (physics == FEM_ELASTICITY) {
+            set_error("fem_integrate_residual: the quad-permutation strategy covers scalar fields");
+            return FEM_ERR_UNSUPPORTED;
+        }
+        Launch l = make_launch(t, (n_elem + 15) / 16 * 64, 1, static_cast<hipStream_t>(stream));
+        e = launch_residual_shuffle(dim, physics, rule, coef_space, dtype, a, l);
     } else {
         const void* ptrs[5] = {inv_j, det_j, u, coef, elem_vec};
         int vec = usable_vec(t.vec, n_elem, word, ptrs, 5);
@@ -413,8 +435,15 @@ fem_status fem_integrate_residual_p3(int dim, int physics, int rule, int coef_sp
     }
     const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_P3, dim, physics, rule, dtype);
     ResidualArgs a{n_elem, inv_j, det_j, u, coef, elem_vec};
-    Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
-    hipError_t e = launch_residual_p3(dim, physics, coef_space, dtype, a, l);
+    hipError_t e;
+    if (t.strategy == FEM_STRATEGY_MFMA && mfma_available(FEM_OP_RESIDUAL_P3, dim, physics)) {
+        // one wave per 16 elements
+        Launch l = make_launch(t, (n_elem + 15) / 16 * 64, 1, static_cast<hipStream_t>(stream));
+        e = launch_residual_p3_mfma(physics, coef_space, dtype, a, l);
+    } else {
+        Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
+        e = launch_residual_p3(dim, physics, coef_space, dtype, a, l);
+    }
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_p3 launch");
 }
 

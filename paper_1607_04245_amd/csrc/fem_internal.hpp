@@ -63,6 +63,10 @@ hipError_t launch_residual_lane(int dim, int phys, int rule, int space, int dtyp
                                 const Launch& l);
 hipError_t launch_residual_transpose(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                                      const Launch& l);
+// The transposition through quad permutations (scalar fields; four lanes per
+// element, a wave takes 16 elements at a time).
+hipError_t launch_residual_shuffle(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
+                                   const Launch& l);
 hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                 const Launch& l);
 // u and a P1 coefficient per vertex (MeshArgs.u, MeshArgs.coef), gathered.
@@ -70,6 +74,10 @@ hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dt
                                   const Launch& l);
 // Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
 hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
+// P3 tetrahedra, Laplacian or elasticity, with the transposition on the
+// matrix cores (residual_p3_mfma.hip); four lanes per element, a wave takes
+// 16 elements at a time.
+hipError_t launch_residual_p3_mfma(int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
 hipError_t launch_backward_p3(int dim, int phys, int space, int dtype, const BackwardArgs& a, const Launch& l);
 hipError_t launch_jacobian_p3(int dim, int phys, int space, int dtype, const JacobianArgs& a, const Launch& l);
 hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,

@@ -1,22 +1,37 @@
-// residual_transpose.hip -- element residual with the paper's thread
+// residual_transpose.hip -- element residuals with the paper's thread
 // transposition (Section 3, Fig. 1 and 3): the quadrature phase runs one lane
 // per (element, quadrature point, component), the basis phase one lane per
-// (element, basis function, component), and the weighted f0/f1 values pass
-// between the two phases through LDS, so every output sum is formed by a
-// single lane in a fixed order and no cross-lane reduction is needed.
+// (element, basis function, component), and the weighted, pulled-back f0/f1
+// values pass from the first phase to the second, so every output sum is
+// formed by a single lane in a fixed order and no reduction is needed.
 //
-// Redesign for gfx950 (wave64, LDS): each wavefront owns a private LDS slab
-// and a tile of 64 elements. Only wave-level synchronization is needed, so
-// the waves of a workgroup never wait for each other.
-//   load phase     lane = element, one coalesced word per SoA row -> LDS
-//   quadrature     item (e, q, c), e-major over the tile; reads geometry,
-//                  closure and its coefficient from LDS, evaluates f0/f1 at
-//                  point q, weights by w_q |det J| and pulls f1 back to
-//                  reference coordinates -> LDS flux tile
-//   basis          item (e, b, c); sums over q in order -> LDS
+// Two exchanges, two kernels:
+//
+// LDS (FEM_STRATEGY_TRANSPOSE, every P1 combination). Each wavefront owns a
+// private LDS slab and a tile of 64 elements; only wave-level
+// synchronization is needed, so the waves of a workgroup never wait for
+// each other.
+//   load phase     lane = element, one coalesced word per SoA row; the lane
+//                  forms what every point of its element shares (the
+//                  physical gradient of u, the weighted measure w |det J|)
+//                  and stages it with J^{-1} and the coefficient words
+//   quadrature     item (e, q, c), e-major over the tile: f0/f1 at point q
+//                  from the staged words, weighted and pulled back to
+//                  reference coordinates -> flux tile
+//   basis          item (e, b, c): sums over q in order -> output tile
 //   store phase    lane = element, one coalesced word per SoA row
-// The per-element strides of the flux and output tiles are odd so that the
-// lanes of a half-wave hit distinct LDS banks.
+// Per-element strides of the flux and output tiles are odd, so the lanes of
+// a half-wave hit distinct LDS banks. The slab size per workgroup is checked
+// against the device's LDS per workgroup.
+//
+// Cross-lane (FEM_STRATEGY_SHUFFLE, scalar fields: Laplacian and mass, any
+// P1 rule). Four consecutive lanes (a quad) share an element, lane r of the
+// quad being point r in the quadrature phase and basis function r in the
+// basis phase (N_q, N_b <= 4). Each lane loads a quarter of its element's
+// geometry words, its own closure value and its own point's coefficient;
+// quad broadcasts (DPP quad permutations, no LDS) give every lane the shared
+// words, and after the quadrature phase they give basis lane b the pulled-
+// back flux of every point, which it sums in point order.
 #include "fem_device.hpp"
 #include "fem_internal.hpp"
 
@@ -28,19 +43,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ------------------------------------------------------------------- LDS --
+
 template <int DIM, int PHYS, int RULE>
 struct TTLayout {
     using E = Elem<DIM, PHYS, RULE>;
     using P = Physics<PHYS>;
     static constexpr int TILE = 64;
-    static constexpr int IN_ROWS = E::NG + 1 + E::NBT + E::NCQ;    // [row][TILE]
-    static constexpr int OFF_DJ = E::NG, OFF_U = E::NG + 1, OFF_CF = E::NG + 1 + E::NBT;
+    // staged per element, [word][TILE]
+    static constexpr int N_IJ = P::HAS_F1 ? E::NG : 0;          // J^{-1} for the pull-back
+    static constexpr int N_GRAD = P::HAS_F1 ? E::NC * DIM : 0;  // physical gradient g[c][i]
+    static constexpr int N_U = P::NEEDS_U ? E::NBT : 0;         // nodal values for f0
+    static constexpr int OFF_IJ = 0, OFF_S = N_IJ, OFF_G = OFF_S + 1, OFF_U = OFF_G + N_GRAD,
+                         OFF_CF = OFF_U + N_U;
+    static constexpr int IN_ROWS = OFF_CF + E::NCQ;
     static constexpr int NFX = (P::HAS_F1 ? DIM : 0) + (P::HAS_F0 ? 1 : 0);  // per (q, c)
     static constexpr int FX_WORDS = E::NQ * E::NC * NFX;
     static constexpr int FX_STRIDE = FX_WORDS | 1;                  // per element, odd
     static constexpr int OUT_STRIDE = E::NBT | 1;                   // per element, odd
     static constexpr int WAVE_WORDS = IN_ROWS * TILE + FX_STRIDE * TILE;
-    static_assert(OUT_STRIDE * TILE <= IN_ROWS * TILE, "output tile aliases the input tile");
+    static_assert(OUT_STRIDE <= IN_ROWS, "the output tile reuses the staged words");
 };
 
 template <int DIM, int PHYS, int RULE, typename Real>
@@ -58,7 +80,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
     const int waves = blockDim.x >> 6;
     Real* in_s = reinterpret_cast<Real*>(smem_raw) + (size_t)wave * L::WAVE_WORDS;
     Real* fx_s = in_s + L::IN_ROWS * T;
-    Real* out_s = in_s;  // the input tile is dead after the quadrature phase
+    Real* out_s = in_s;  // the staged words are dead after the quadrature phase
 
     const int64_t n_tiles = (n + T - 1) / T;
     for (int64_t tile = (int64_t)blockIdx.x * waves + wave; tile < n_tiles; tile += (int64_t)gridDim.x * waves) {
@@ -66,14 +88,32 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
         const int64_t e = e0 + lane;
         const bool valid = e < n;
 
-        // ---- load phase: coalesced rows into the wave's LDS slab
+        // ---- load phase: coalesced rows; per-element shared quantities
+        {
+            Real ij[E::NG], uu[E::NBT];
 #pragma unroll
-        for (int f = 0; f < E::NG; ++f) in_s[f * T + lane] = valid ? inv_j[f * n + e] : Real(0);
-        in_s[L::OFF_DJ * T + lane] = valid ? det_j[e] : Real(0);
+            for (int f = 0; f < E::NG; ++f) ij[f] = valid ? inv_j[f * n + e] : Real(0);
+            const Real dj = valid ? det_j[e] : Real(0);
 #pragma unroll
-        for (int f = 0; f < E::NBT; ++f) in_s[(L::OFF_U + f) * T + lane] = valid ? u[f * n + e] : Real(0);
+            for (int f = 0; f < E::NBT; ++f) uu[f] = valid ? u[f * n + e] : Real(0);
+            in_s[L::OFF_S * T + lane] = Real(Q::W) * fabs(dj);
+            if constexpr (P::HAS_F1) {
+                Real g[NC][DIM];
+                physical_gradient<DIM, NC>(ij, uu, g);
 #pragma unroll
-        for (int f = 0; f < E::NCQ; ++f) in_s[(L::OFF_CF + f) * T + lane] = valid ? coef[f * n + e] : Real(0);
+                for (int f = 0; f < E::NG; ++f) in_s[(L::OFF_IJ + f) * T + lane] = ij[f];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) in_s[(L::OFF_G + c * DIM + i) * T + lane] = g[c][i];
+            }
+            if constexpr (P::NEEDS_U) {
+#pragma unroll
+                for (int f = 0; f < E::NBT; ++f) in_s[(L::OFF_U + f) * T + lane] = uu[f];
+            }
+#pragma unroll
+            for (int f = 0; f < E::NCQ; ++f) in_s[(L::OFF_CF + f) * T + lane] = valid ? coef[f * n + e] : Real(0);
+        }
         wave_sync();
 
         // ---- quadrature phase: one item per (element, point, component)
@@ -83,19 +123,18 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
             const int el = it / (NQ * NC);
             const int qc = it - el * (NQ * NC);
             const int q = qc / NC, c = qc - q * NC;
-            Real ij[E::NG], uu[E::NBT], a[E::NCOEF];
-#pragma unroll
-            for (int f = 0; f < E::NG; ++f) ij[f] = in_s[f * T + el];
-            const Real dj = in_s[L::OFF_DJ * T + el];
-#pragma unroll
-            for (int f = 0; f < E::NBT; ++f) uu[f] = in_s[(L::OFF_U + f) * T + el];
-            Real cfl[E::NCQ];
+            Real a[E::NCOEF], cfl[E::NCQ];
 #pragma unroll
             for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
 #pragma unroll
             for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
             Real g[NC][DIM];
-            physical_gradient<DIM, NC>(ij, uu, g);
+            if constexpr (P::HAS_F1) {
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) g[cc][i] = in_s[(L::OFF_G + cc * DIM + i) * T + el];
+            }
             Real uq[NC];
             if constexpr (P::NEEDS_U) {
 #pragma unroll
@@ -103,13 +142,14 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                     // phi_b at point q: LA at vertex q, LB elsewhere
                     Real v = Real(0);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) v = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), uu[b * NC + cc], v);
+                    for (int b = 0; b < NB; ++b)
+                        v = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), in_s[(L::OFF_U + b * NC + cc) * T + el], v);
                     uq[cc] = v;
                 }
             }
             Real f0[NC], f1[NC][DIM];
             P::template point<DIM, Real>(uq, g, a, f0, f1);
-            const Real s = Real(Q::W) * fabs(dj);
+            const Real s = in_s[L::OFF_S * T + el];
             Real* fx = fx_s + el * L::FX_STRIDE + qc * L::NFX;
             if constexpr (P::HAS_F1) {
                 Real t[DIM];
@@ -117,9 +157,9 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                 for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
 #pragma unroll
                 for (int kk = 0; kk < DIM; ++kk) {
-                    Real fh = ij[kk * DIM + 0] * t[0];
+                    Real fh = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
 #pragma unroll
-                    for (int i = 1; i < DIM; ++i) fh = fmadd(ij[kk * DIM + i], t[i], fh);
+                    for (int i = 1; i < DIM; ++i) fh = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh);
                     fx[kk] = fh;
                 }
             }
@@ -169,20 +209,193 @@ static size_t tt_bytes_per_wave() {
     return (size_t)TTLayout<DIM, PHYS, RULE>::WAVE_WORDS * sizeof(Real);
 }
 
-constexpr size_t kMaxLdsPerBlock = 64 * 1024;
+// LDS a workgroup may use on the current device (read once per device).
+static size_t lds_per_block() {
+    static size_t cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        cached[dev] = (size_t)v;
+    }
+    return cached[dev];
+}
 
 template <int DIM, int PHYS, int RULE, typename Real>
 static hipError_t launch_tt(const ResidualArgs& a, const Launch& l) {
     const size_t lds = (size_t)(l.block / 64) * tt_bytes_per_wave<DIM, PHYS, RULE, Real>();
-    if (lds > kMaxLdsPerBlock || l.block % 64) return hipErrorInvalidValue;
+    if (lds > lds_per_block() || l.block % 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((residual_transpose_kernel<DIM, PHYS, RULE, Real>), dim3(l.grid), dim3(l.block), lds,
                        l.stream, a.n, static_cast<const Real*>(a.inv_j), static_cast<const Real*>(a.det_j),
                        static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef), static_cast<Real*>(a.out));
     return hipGetLastError();
 }
 
-// Dispatch helper: calls f.template operator()<DIM, PHYS, SCHEME, Real>() for a
-// runtime combination; returns fallback for an unknown one.
+// ----------------------------------------------------------- cross-lane --
+
+// Value of lane (quad base + k) in every lane of the quad: a DPP quad
+// permutation, no LDS.
+template <int K>
+__device__ __forceinline__ float quad_bcast(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), K * 0x55, 0xF, 0xF, false));
+}
+template <int K>
+__device__ __forceinline__ double quad_bcast(double x) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, K * 0x55, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), K * 0x55, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Every lane of the quad receives the values x of lanes 0..N-1 in out[0..N-1].
+template <int N, typename Real, int M>
+__device__ __forceinline__ void quad_gather(Real x, Real (&out)[M]) {
+    static_assert(N <= M && N <= 4, "at most the quad's four lanes");
+    if constexpr (N > 0) out[0] = quad_bcast<0>(x);
+    if constexpr (N > 1) out[1] = quad_bcast<1>(x);
+    if constexpr (N > 2) out[2] = quad_bcast<2>(x);
+    if constexpr (N > 3) out[3] = quad_bcast<3>(x);
+}
+
+template <int DIM, int PHYS, int RULE, typename Real>
+__global__ void __launch_bounds__(512)
+residual_shuffle_kernel(int64_t n, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
+                        const Real* __restrict__ u, const Real* __restrict__ coef, Real* __restrict__ out) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using P = Physics<PHYS>;
+    using Q = Rule<DIM, RULE>;
+    constexpr int NQ = E::NQ, NB = E::NB, NG = E::NG, NW = E::NW;
+    static_assert(E::NC == 1 && NQ <= 4 && NB <= 4, "one scalar field, at most four points and basis functions");
+    constexpr int NGEO = NG + 1;                 // J^{-1} words and det J
+    constexpr int GEO_PER_LANE = (NGEO + 3) / 4; // geometry words loaded per lane
+
+    const int lane = threadIdx.x & 63, r = lane & 3;
+    const int64_t n_groups = (n + 15) >> 4;     // 16 elements per wave
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp < n_groups; grp += waves) {
+        const int64_t e = grp * 16 + (lane >> 2);
+        const bool valid = e < n;
+        const int64_t ec = valid ? e : n - 1;
+        // ---- loads: a quarter of the geometry, the own closure value, the
+        // coefficient words of the own point (or the shared ones)
+        Real geo[GEO_PER_LANE];
+#pragma unroll
+        for (int t = 0; t < GEO_PER_LANE; ++t) {
+            const int w = r + 4 * t;
+            const Real* p = w < NG ? inv_j + (int64_t)w * n : det_j;
+            geo[t] = w <= NG ? __builtin_nontemporal_load(p + ec) : Real(0);
+        }
+        const Real ur = r < NB ? __builtin_nontemporal_load(u + (int64_t)(r < NB ? r : 0) * n + ec) : Real(0);
+        Real cw = Real(0);
+        if constexpr (E::SPACE == FEM_COEF_P0) {
+            cw = __builtin_nontemporal_load(coef + ec);
+        } else {
+            constexpr int NCW = E::SPACE == FEM_COEF_QUAD ? NQ : NW;
+            cw = r < NCW ? __builtin_nontemporal_load(coef + (int64_t)(r < NCW ? r : 0) * n + ec) : Real(0);
+        }
+
+        // ---- quad broadcasts: every lane gets the element's shared words
+        Real ij[NG], dj;
+        {
+            Real g0[4], g1[4], g2[4];
+            quad_gather<4>(geo[0], g0);
+            if constexpr (GEO_PER_LANE > 1) quad_gather<4>(geo[1], g1);
+            if constexpr (GEO_PER_LANE > 2) quad_gather<4>(geo[2], g2);
+#pragma unroll
+            for (int w = 0; w <= NG; ++w) {
+                const Real x = w < 4 ? g0[w] : (w < 8 ? g1[w - 4] : g2[w - 8]);
+                if (w < NG) ij[w] = x; else dj = x;
+            }
+        }
+        Real ub[4];
+        quad_gather<NB>(ur, ub);
+        const Real s = Real(Q::W) * fabs(dj);
+
+        // ---- quadrature phase: lane r is point r
+        Real a;
+        if constexpr (E::SPACE == FEM_COEF_P1) {
+            Real av[4];
+            quad_gather<NB>(cw, av);
+            // the P1 interpolant at this lane's point: LA at vertex r, LB elsewhere
+            a = Real(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) a = fmadd(b == r ? Real(Q::LA) : Real(Q::LB), av[b], a);
+        } else {
+            a = cw;
+        }
+        Real fx[DIM + 1];   // pulled-back weighted f1, then weighted f0
+        if constexpr (P::HAS_F1) {
+            Real g[1][DIM];
+            physical_gradient<DIM, 1>(ij, ub, g);
+            Real uq[1], f0[1], f1[1][DIM], am[1] = {a};
+            P::template point<DIM, Real>(uq, g, am, f0, f1);
+            Real t[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) t[i] = s * f1[0][i];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                Real fh = ij[k * DIM] * t[0];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) fh = fmadd(ij[k * DIM + i], t[i], fh);
+                fx[k] = fh;
+            }
+        }
+        if constexpr (P::HAS_F0) {
+            Real uq = Real(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) uq = fmadd(b == r ? Real(Q::LA) : Real(Q::LB), ub[b], uq);
+            Real f0[1], f1[1][DIM], am[1] = {a}, uqa[1] = {uq}, g[1][DIM];
+            P::template point<DIM, Real>(uqa, g, am, f0, f1);
+            fx[DIM] = s * f0[0];
+        }
+
+        // ---- basis phase: lane r is basis function r; the points' values
+        // come from the quad's lanes, summed in point order
+        Real res = Real(0);
+        if constexpr (P::HAS_F1) {
+            Real fq[DIM][4];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) quad_gather<NQ>(fx[k], fq[k]);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                Real sum = fq[0][q];
+#pragma unroll
+                for (int k = 1; k < DIM; ++k) sum += fq[k][q];
+                Real pick = fq[0][q];
+#pragma unroll
+                for (int k = 1; k < DIM; ++k) pick = r == k + 1 ? fq[k][q] : pick;
+                res = r == 0 ? res - sum : res + pick;
+            }
+        }
+        if constexpr (P::HAS_F0) {
+            Real f0q[4];
+            quad_gather<NQ>(fx[DIM], f0q);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) res = fmadd(r == q ? Real(Q::LA) : Real(Q::LB), f0q[q], res);
+        }
+        if (valid && r < NB) __builtin_nontemporal_store(res, out + (int64_t)r * n + e);
+    }
+}
+
+template <int DIM, int PHYS, int RULE, typename Real>
+static hipError_t launch_shuffle(const ResidualArgs& a, const Launch& l) {
+    if constexpr (Elem<DIM, PHYS, RULE>::NC != 1) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((residual_shuffle_kernel<DIM, PHYS, RULE, Real>), dim3(l.grid), dim3(l.block), 0,
+                           l.stream, a.n, static_cast<const Real*>(a.inv_j), static_cast<const Real*>(a.det_j),
+                           static_cast<const Real*>(a.u), static_cast<const Real*>(a.coef),
+                           static_cast<Real*>(a.out));
+        return hipGetLastError();
+    }
+}
+
+// ------------------------------------------------------------- dispatch --
+
+// Calls f.template operator()<DIM, PHYS, SCHEME, Real>() for a runtime
+// combination; returns fallback for an unknown one.
 template <typename F, typename R>
 struct TTByType {
     const F& f;
@@ -206,6 +419,13 @@ struct TTLaunch {
     hipError_t operator()() const { return launch_tt<D, P, RU, Real>(a, l); }
 };
 
+struct ShuffleLaunch {
+    const ResidualArgs& a;
+    const Launch& l;
+    template <int D, int P, int RU, typename Real>
+    hipError_t operator()() const { return launch_shuffle<D, P, RU, Real>(a, l); }
+};
+
 struct TTBytes {
     template <int D, int P, int RU, typename Real>
     size_t operator()() const { return tt_bytes_per_wave<D, P, RU, Real>(); }
@@ -216,12 +436,19 @@ hipError_t launch_residual_transpose(int dim, int phys, int rule, int space, int
     return tt_dispatch(dim, phys, rule, space, dtype, TTLaunch{a, l}, hipErrorInvalidValue);
 }
 
+hipError_t launch_residual_shuffle(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
+                                   const Launch& l) {
+    if (phys == FEM_ELASTICITY) return hipErrorInvalidValue;
+    return tt_dispatch(dim, phys, rule, space, dtype, ShuffleLaunch{a, l}, hipErrorInvalidValue);
+}
+
 int transpose_block_threads(int dim, int phys, int rule, int space, int dtype, int waves_per_block) {
     const size_t per_wave = tt_dispatch(dim, phys, rule, space, dtype, TTBytes{}, (size_t)0);
     if (per_wave == 0) return 0;
+    const size_t cap = lds_per_block();
     int w = waves_per_block;
-    while (w > 1 && (size_t)w * per_wave > kMaxLdsPerBlock) w >>= 1;
-    return (size_t)w * per_wave <= kMaxLdsPerBlock ? 64 * w : 0;
+    while (w > 1 && (size_t)w * per_wave > cap) w >>= 1;
+    return (size_t)w * per_wave <= cap ? 64 * w : 0;
 }
 
 }  // namespace femq

@@ -8,6 +8,8 @@ import pytest
 from paper_1607_04245_amd import _native as N
 from paper_1607_04245_amd import meshgen as mg
 
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
 
 @pytest.fixture(scope="module")
 def lib():
@@ -124,6 +126,26 @@ def test_tuning_roundtrip(lib):
     lib.fem_set_tuning(N.OP_RESIDUAL_MESH, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved))
     assert lib.fem_set_tuning(N.OP_GEOMETRY, 3, 99, 99, N.F32, ctypes.byref(four)) == N.FEM_OK  # physics ignored
     assert lib.fem_set_tuning(12, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(four)) == N.FEM_ERR_UNSUPPORTED
+
+
+def test_mfma_strategy_availability(lib):
+    """The matrix-core strategy exists for the P3 residual of tetrahedra with
+    the Laplacian or elasticity only; elsewhere fem_set_tuning refuses it."""
+    P3, R11 = N.OP_RESIDUAL_P3, mg.RULE_TET11
+    saved = N.fem_tuning()
+    lib.fem_get_tuning(P3, 3, mg.ELASTICITY, R11, N.F32, ctypes.byref(saved))
+    t = N.fem_tuning(N.STRATEGY_MFMA, 1, 4, 0)
+    for phys in (mg.LAPLACE, mg.ELASTICITY):
+        for dt in (N.F32, N.F64):
+            assert lib.fem_set_tuning(P3, 3, phys, R11, dt, ctypes.byref(t)) == N.FEM_OK
+    assert lib.fem_set_tuning(P3, 3, mg.MASS, R11, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(P3, 2, mg.ELASTICITY, mg.RULE_TRI6, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    for op in (N.OP_RESIDUAL, N.OP_RESIDUAL_P2, N.OP_BACKWARD_P3, N.OP_JACOBIAN_P3):
+        assert lib.fem_set_tuning(op, 3, mg.LAPLACE, R11 if op != N.OP_RESIDUAL else mg.RULE_TET4, N.F32,
+                                  ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
+    for phys in (mg.LAPLACE, mg.ELASTICITY):
+        for dt in (N.F32, N.F64):
+            assert lib.fem_set_tuning(P3, 3, phys, R11, dt, ctypes.byref(saved)) == N.FEM_OK
 
 
 def test_batch_plan_validation(lib):

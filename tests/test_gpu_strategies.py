@@ -64,6 +64,57 @@ def test_transpose_matches_oracle(dim, phys, dtype, n_elem, rule_kind):
                 assert np.array_equal(R, first), "transpose result depends on the launch shape"
 
 
+@pytest.mark.parametrize("dim,phys", [k for k in KINDS if k[1] != mg.ELASTICITY])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n_elem", [1, 15, 17, 1000, 20004])
+@pytest.mark.parametrize("rule_kind", ["default", "centroid"])
+@pytest.mark.parametrize("space", [mg.COEF_QUAD, mg.COEF_P1, mg.COEF_P0])
+def test_shuffle_matches_oracle(dim, phys, dtype, n_elem, rule_kind, space):
+    """The transposition through quad permutations (four lanes per element,
+    16 elements per wave: partial groups, several waves, a ragged tail)
+    against the oracle in every coefficient space; launch shapes give the
+    same bits."""
+    rule = mg.default_rule(dim) if rule_kind == "default" else mg.RULE_CENTROID
+    wl = small_workload(dim, phys, n_elem, rule=rule)
+    cf = wl.coef if space == mg.COEF_QUAD else mg.space_coefficients(wl, space, mg.BASE_SEED + 1000)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+    ij, dj = geometry(wl, dtype)
+    u, c = dev(wl.u, dtype), dev(cf, dtype)
+    first = None
+    for waves, bpc in ((4, 0), (1, 0), (8, 4), (2, 1)):
+        api.fem_set_tuning(dim, phys, rule, dtype, strategy=N.STRATEGY_SHUFFLE, vec=1, waves_per_block=waves,
+                           blocks_per_cu=bpc)
+        R = api.fem_integrate_residual(dim, phys, rule, ij, dj, u, c, coef_space=space).cpu().numpy()
+        if first is None:
+            first = R
+            assert_close(R, ref, ref_abs, dtype, f"shuffle {dim}D phys {phys} space {space}")
+        else:
+            assert np.array_equal(R, first), "shuffle result depends on the launch shape"
+
+
+@pytest.mark.parametrize("dim,phys", KINDS)
+@pytest.mark.parametrize("space", [mg.COEF_P1, mg.COEF_P0])
+def test_transpose_coefficient_spaces(dim, phys, space):
+    """The LDS transposition in the P1 and P0 coefficient spaces."""
+    dtype = torch.float32
+    rule = mg.default_rule(dim)
+    wl = small_workload(dim, phys, 1000, rule=rule)
+    cf = mg.space_coefficients(wl, space, mg.BASE_SEED + 1000)
+    ref, ref_abs, _, _ = oracle_reference(wl, dtype, coef=cf, space=space)
+    ij, dj = geometry(wl, dtype)
+    api.fem_set_tuning(dim, phys, rule, dtype, strategy=N.STRATEGY_TRANSPOSE, vec=1, waves_per_block=4,
+                       blocks_per_cu=0)
+    R = api.fem_integrate_residual(dim, phys, rule, ij, dj, dev(wl.u, dtype), dev(cf, dtype),
+                                   coef_space=space).cpu().numpy()
+    assert_close(R, ref, ref_abs, dtype, f"transpose {dim}D phys {phys} space {space}")
+
+
+def test_shuffle_refused_for_elasticity():
+    with pytest.raises(N.FemError) as ei:
+        api.fem_set_tuning(3, mg.ELASTICITY, mg.RULE_TET4, torch.float32, strategy=N.STRATEGY_SHUFFLE)
+    assert ei.value.status == N.FEM_ERR_UNSUPPORTED
+
+
 # ------------------------------------------------------------------ batched --
 
 def batch_meshes(dtype, sizes, rules=None):
