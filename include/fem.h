@@ -405,6 +405,24 @@ fem_status fem_batch_replay(fem_batch_plan* plan, void* stream);
 /* Frees the plan's device memory and graph. Safe on NULL. */
 void fem_batch_plan_destroy(fem_batch_plan* plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * persistent launch as fem_batch_run, with bitwise-equal element vectors,
+ * without a plan. The descriptor table goes to a fixed device array inside
+ * the library (one per GPU, FEM_BATCH_NOALLOC_MAX_MESHES entries, about
+ * 72 KB, held until the process ends) by a stream-ordered copy from host
+ * memory, and each workgroup finds its mesh by a binary search over that
+ * table, so the call allocates nothing and needs no tile table. Meshes, dtype
+ * and arrays as fem_batch_plan_create; launch shape as
+ * fem_batch_plan_set_launch (waves per workgroup 1, 2, 4, 8; workgroups per
+ * compute unit 0..64). More than FEM_BATCH_NOALLOC_MAX_MESHES meshes give
+ * FEM_ERR_INVALID_ARG. Every call on a GPU shares that GPU's table: calls
+ * in order on one stream are safe, calls that overlap (other streams, other
+ * host threads) race and may integrate another call's meshes. */
+#define FEM_BATCH_NOALLOC_MAX_MESHES 1024
+fem_status fem_batch_run_noalloc(const fem_mesh_desc* meshes, int n_mesh, int dtype, int waves_per_block,
+                                 int blocks_per_cu, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Launch configuration and autotuning (analog of the paper's sweep of  */
 /* blocks per batch and batches per chunk, Section 6, Table 2).         */

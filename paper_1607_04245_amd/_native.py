@@ -31,6 +31,7 @@ OP_RESIDUAL_P2, OP_BACKWARD_P2 = 5, 6
 OP_JACOBIAN, OP_JACOBIAN_P2 = 7, 8
 OP_RESIDUAL_P3, OP_BACKWARD_P3, OP_JACOBIAN_P3 = 9, 10, 11
 COEF_QUAD, COEF_P1, COEF_P0 = 0, 1, 2
+BATCH_NOALLOC_MAX_MESHES = 1024
 
 
 class FemError(RuntimeError):
@@ -81,6 +82,7 @@ SIGNATURES = {
     "fem_batch_plan_set_launch": (_i, [_vp, _i, _i]),
     "fem_batch_plan_autotune": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "fem_batch_run": (_i, [_vp, _vp]),
+    "fem_batch_run_noalloc": (_i, [ctypes.POINTER(fem_mesh_desc), _i, _i, _i, _i, _vp]),
     "fem_batch_capture": (_i, [_vp, _vp]),
     "fem_batch_replay": (_i, [_vp, _vp]),
     "fem_batch_plan_destroy": (None, [_vp]),

@@ -414,6 +414,37 @@ def fem_load_tuning(cache_path: str) -> int:
 
 # ----------------------------------------------------------------- batched --
 
+def _mesh_descs(meshes: list[dict]):
+    """Checked descriptor array of a mesh list (see BatchPlan) and its dtype."""
+    if not meshes:
+        raise ValueError("no meshes")
+    dtype = meshes[0]["det_j"].dtype
+    descs = (N.fem_mesh_desc * len(meshes))()
+    for i, m in enumerate(meshes):
+        n = m["det_j"].shape[0]
+        space = m.get("coef_space", N.COEF_QUAD)
+        sij, sdj, su, scf = _shapes(m["dim"], m["physics"], m["rule"], n, space)
+        _need(m["inv_j"], "inv_j", dtype, sij)
+        _need(m["det_j"], "det_j", dtype, sdj)
+        _need(m["u"], "u", dtype, su)
+        _need(m["coef"], "coef", dtype, scf)
+        _need(m["out"], "out", dtype, su)
+        descs[i] = N.fem_mesh_desc(m["dim"], m["physics"], m["rule"], space, n, m["inv_j"].data_ptr(),
+                                   m["det_j"].data_ptr(), m["u"].data_ptr(), m["coef"].data_ptr(),
+                                   m["out"].data_ptr())
+    return descs, dtype
+
+
+def batch_run_noalloc(meshes: list[dict], waves_per_block: int = 8, blocks_per_cu: int = 0):
+    """The batched launch without a plan and without any device allocation
+    (fem_batch_run_noalloc): the descriptor table goes to the library's fixed
+    per-GPU array. Mesh dicts as for BatchPlan; at most
+    BATCH_NOALLOC_MAX_MESHES meshes. Calls that overlap on one GPU race."""
+    descs, dtype = _mesh_descs(meshes)
+    N.check(N.lib().fem_batch_run_noalloc(descs, len(meshes), _DT[dtype], waves_per_block, blocks_per_cu,
+                                          _stream()), "fem_batch_run_noalloc")
+
+
 class BatchPlan:
     """Many meshes (mixed dim/physics) integrated by one persistent launch.
 
@@ -424,25 +455,9 @@ class BatchPlan:
     """
 
     def __init__(self, meshes: list[dict]):
-        if not meshes:
-            raise ValueError("no meshes")
-        dtype = meshes[0]["det_j"].dtype
-        descs = (N.fem_mesh_desc * len(meshes))()
-        self._keep = []
-        for i, m in enumerate(meshes):
-            n = m["det_j"].shape[0]
-            space = m.get("coef_space", N.COEF_QUAD)
-            sij, sdj, su, scf = _shapes(m["dim"], m["physics"], m["rule"], n, space)
-            _need(m["inv_j"], "inv_j", dtype, sij)
-            _need(m["det_j"], "det_j", dtype, sdj)
-            _need(m["u"], "u", dtype, su)
-            _need(m["coef"], "coef", dtype, scf)
-            _need(m["out"], "out", dtype, su)
-            descs[i] = N.fem_mesh_desc(m["dim"], m["physics"], m["rule"], space, n, m["inv_j"].data_ptr(),
-                                       m["det_j"].data_ptr(), m["u"].data_ptr(), m["coef"].data_ptr(),
-                                       m["out"].data_ptr())
-            self._keep.append(m)
         self._plan = ctypes.c_void_p()
+        descs, dtype = _mesh_descs(meshes)
+        self._keep = list(meshes)
         N.check(N.lib().fem_batch_plan_create(descs, len(meshes), _DT[dtype], ctypes.byref(self._plan)),
                 "fem_batch_plan_create")
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -78,14 +79,28 @@ __device__ __forceinline__ void batch_tile(const BatchMesh& M, int64_t t) {
 
 // Each workgroup owns a contiguous run of tiles, which mostly lies in one
 // mesh: the descriptor is read once and kept until the run crosses into the
-// next mesh (tiles of a mesh are consecutive).
+// next mesh (tiles of a mesh are consecutive). The mesh of the first tile
+// comes from the per-tile table, or, without one, from a binary search over
+// the descriptors' tile ranges (every mesh in the table is non-empty, so the
+// tile_begin values strictly increase).
 template <typename Real>
 __global__ void __launch_bounds__(512)
-batch_kernel(const BatchMesh* __restrict__ meshes, const int32_t* __restrict__ tile_mesh, int64_t n_tiles) {
+batch_kernel(const BatchMesh* __restrict__ meshes, int n_mesh, const int32_t* __restrict__ tile_mesh,
+             int64_t n_tiles) {
     const int64_t t_begin = (int64_t)blockIdx.x * n_tiles / gridDim.x;
     const int64_t t_end = ((int64_t)blockIdx.x + 1) * n_tiles / gridDim.x;
     if (t_begin >= t_end) return;
-    int m = tile_mesh[t_begin];
+    int m;
+    if (tile_mesh) {
+        m = tile_mesh[t_begin];
+    } else {
+        int lo = 0, hi = n_mesh - 1;   // last mesh with tile_begin <= t_begin
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (meshes[mid].tile_begin <= t_begin) lo = mid; else hi = mid - 1;
+        }
+        m = lo;
+    }
     BatchMesh M = meshes[m];
     for (int64_t t = t_begin; t < t_end; ++t) {
         while (t >= M.tile_end) M = meshes[++m];
@@ -93,15 +108,15 @@ batch_kernel(const BatchMesh* __restrict__ meshes, const int32_t* __restrict__ t
     }
 }
 
-hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, const int32_t* d_tile_mesh, int64_t n_tiles,
-                        int tile_elems, const Launch& l) {
-    if (tile_elems != l.block) return hipErrorInvalidValue;
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, const int32_t* d_tile_mesh,
+                        int64_t n_tiles, int tile_elems, const Launch& l) {
+    if (tile_elems != l.block || n_mesh < 1) return hipErrorInvalidValue;
     if (dtype == FEM_F32)
-        hipLaunchKernelGGL(batch_kernel<float>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, d_tile_mesh,
-                           n_tiles);
+        hipLaunchKernelGGL(batch_kernel<float>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh,
+                           d_tile_mesh, n_tiles);
     else
-        hipLaunchKernelGGL(batch_kernel<double>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, d_tile_mesh,
-                           n_tiles);
+        hipLaunchKernelGGL(batch_kernel<double>, dim3(l.grid), dim3(l.block), 0, l.stream, d_meshes, n_mesh,
+                           d_tile_mesh, n_tiles);
     return hipGetLastError();
 }
 
@@ -125,29 +140,88 @@ struct fem_batch_plan {
     hipGraphExec_t exec = nullptr;
 };
 
-static fem_status plan_launch(fem_batch_plan* p, hipStream_t s) {
-    if (p->n_tiles == 0) return FEM_OK;
+// Launch shape of the persistent kernel: one workgroup per tile, or
+// blocks_per_cu workgroups per compute unit, each taking a contiguous run.
+static Launch batch_shape(int64_t n_tiles, int waves_per_block, int blocks_per_cu, hipStream_t s) {
     Launch l;
-    l.block = 64 * p->waves_per_block;
+    l.block = 64 * waves_per_block;
     l.vec = 1;
     l.stream = s;
     int cus = device_cus();
-    int64_t grid = (int64_t)p->blocks_per_cu * (cus > 0 ? cus : 256);
-    if (p->blocks_per_cu == 0 || grid > p->n_tiles) grid = p->n_tiles;
+    int64_t grid = (int64_t)blocks_per_cu * (cus > 0 ? cus : 256);
+    if (blocks_per_cu == 0 || grid > n_tiles) grid = n_tiles;
     if (grid > (1 << 22)) grid = 1 << 22;
     l.grid = (int)grid;
-    hipError_t e = launch_batch(p->dtype, p->d_meshes, p->d_tile_mesh, p->n_tiles, l.block, l);
+    return l;
+}
+
+static bool valid_batch_shape(int waves_per_block, int blocks_per_cu) {
+    return (waves_per_block == 1 || waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8) &&
+           blocks_per_cu >= 0 && blocks_per_cu <= 64;
+}
+
+// Global tile ranges of the meshes (consecutive, in table order); returns
+// the number of tiles.
+static int64_t assign_tiles(BatchMesh* m, int n, int tile) {
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) {
+        m[i].tile_begin = t;
+        t += (m[i].n_elem + tile - 1) / tile;
+        m[i].tile_end = t;
+    }
+    return t;
+}
+
+// Checks the caller's mesh list and writes the device descriptor of every
+// non-empty mesh to out (room for n_mesh); *n_out = their number.
+static fem_status fill_descriptors(const char* fn, const fem_mesh_desc* meshes, int n_mesh, BatchMesh* out,
+                                   int* n_out, int64_t* total_out) {
+    int k = 0;
+    int64_t total = 0;
+    for (int i = 0; i < n_mesh; ++i) {
+        const fem_mesh_desc& d = meshes[i];
+        const bool dim_ok = d.dim == 2 || d.dim == 3;
+        const bool phys_ok = d.physics == FEM_LAPLACE || d.physics == FEM_ELASTICITY || d.physics == FEM_MASS;
+        const bool rule_ok = d.rule == FEM_RULE_CENTROID || (d.dim == 2 && d.rule == FEM_RULE_TRI3) ||
+                             (d.dim == 3 && d.rule == FEM_RULE_TET4);
+        const bool space_ok = d.coef_space == FEM_COEF_QUAD || d.coef_space == FEM_COEF_P1 ||
+                              d.coef_space == FEM_COEF_P0;
+        if (!dim_ok || !phys_ok || !rule_ok || !space_ok) {
+            set_error("%s: mesh %d has an unsupported (dim, physics, rule, coef_space)", fn, i);
+            return FEM_ERR_UNSUPPORTED;
+        }
+        if (d.n_elem < 0) { set_error("%s: mesh %d has negative n_elem", fn, i); return FEM_ERR_INVALID_ARG; }
+        if (d.n_elem == 0) continue;
+        if (!d.inv_j || !d.det_j || !d.u || !d.coef || !d.elem_vec) {
+            set_error("%s: mesh %d has a NULL array", fn, i);
+            return FEM_ERR_INVALID_ARG;
+        }
+        BatchMesh& m = out[k++];
+        std::memset(&m, 0, sizeof m);
+        m.type = type_code(d.dim, d.physics, d.rule, d.coef_space);
+        m.n_elem = d.n_elem;
+        m.inv_j = d.inv_j;
+        m.det_j = d.det_j;
+        m.u = d.u;
+        m.coef = d.coef;
+        m.out = d.elem_vec;
+        total += d.n_elem;
+    }
+    *n_out = k;
+    *total_out = total;
+    return FEM_OK;
+}
+
+static fem_status plan_launch(fem_batch_plan* p, hipStream_t s) {
+    if (p->n_tiles == 0) return FEM_OK;
+    const Launch l = batch_shape(p->n_tiles, p->waves_per_block, p->blocks_per_cu, s);
+    hipError_t e = launch_batch(p->dtype, p->d_meshes, p->n_mesh, p->d_tile_mesh, p->n_tiles, l.block, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch launch");
 }
 
 static fem_status plan_build_table(fem_batch_plan* p) {
     const int tile = 64 * p->waves_per_block;
-    int64_t t = 0;
-    for (auto& m : p->h_meshes) {
-        m.tile_begin = t;
-        t += (m.n_elem + tile - 1) / tile;
-        m.tile_end = t;
-    }
+    const int64_t t = assign_tiles(p->h_meshes.data(), (int)p->h_meshes.size(), tile);
     p->n_tiles = t;
     if (p->h_meshes.empty()) return FEM_OK;
     hipError_t e = hipMemcpy(p->d_meshes, p->h_meshes.data(), p->h_meshes.size() * sizeof(BatchMesh),
@@ -171,6 +245,39 @@ static fem_status plan_build_table(fem_batch_plan* p) {
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch tile table upload");
 }
 
+// ------------------------------------------------- no-allocation launch --
+//
+// The descriptor table of fem_batch_run_noalloc lives in this file-scope
+// device array, one copy per GPU, for the life of the process. Host code
+// never passes the array's name to a kernel or a copy: on the host that name
+// stands for a host-side shadow, not a device address. The device address of
+// each GPU's copy is looked up once per device (hipGetSymbolAddress, with
+// that device current) and used everywhere instead.
+static __device__ __align__(256) BatchMesh scratch[FEM_BATCH_NOALLOC_MAX_MESHES];
+
+static std::mutex g_scratch_mu;
+static BatchMesh* g_scratch_ptr[64] = {};
+
+// Device address of the current device's descriptor array (NULL on failure,
+// with the error set).
+static BatchMesh* scratch_table(const char* fn) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { hip_fail(e, fn); return nullptr; }
+    if (dev < 0 || dev >= 64) { set_error("%s: device %d out of range", fn, dev); return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        BatchMesh* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, fn);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 static void plan_drop_graph(fem_batch_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -185,38 +292,12 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
     *out = nullptr;
     if (n_mesh < 0 || (n_mesh > 0 && !meshes)) { set_error("fem_batch_plan_create: bad mesh list"); return FEM_ERR_INVALID_ARG; }
     if (dtype != FEM_F32 && dtype != FEM_F64) { set_error("fem_batch_plan_create: unknown dtype %d", dtype); return FEM_ERR_UNSUPPORTED; }
-    std::vector<BatchMesh> hm;
+    std::vector<BatchMesh> hm((size_t)n_mesh);
+    int n_used = 0;
     int64_t total = 0;
-    for (int i = 0; i < n_mesh; ++i) {
-        const fem_mesh_desc& d = meshes[i];
-        const bool dim_ok = d.dim == 2 || d.dim == 3;
-        const bool phys_ok = d.physics == FEM_LAPLACE || d.physics == FEM_ELASTICITY || d.physics == FEM_MASS;
-        const bool rule_ok = d.rule == FEM_RULE_CENTROID || (d.dim == 2 && d.rule == FEM_RULE_TRI3) ||
-                             (d.dim == 3 && d.rule == FEM_RULE_TET4);
-        const bool space_ok = d.coef_space == FEM_COEF_QUAD || d.coef_space == FEM_COEF_P1 ||
-                              d.coef_space == FEM_COEF_P0;
-        if (!dim_ok || !phys_ok || !rule_ok || !space_ok) {
-            set_error("fem_batch_plan_create: mesh %d has an unsupported (dim, physics, rule, coef_space)", i);
-            return FEM_ERR_UNSUPPORTED;
-        }
-        if (d.n_elem < 0) { set_error("fem_batch_plan_create: mesh %d has negative n_elem", i); return FEM_ERR_INVALID_ARG; }
-        if (d.n_elem == 0) continue;
-        if (!d.inv_j || !d.det_j || !d.u || !d.coef || !d.elem_vec) {
-            set_error("fem_batch_plan_create: mesh %d has a NULL array", i);
-            return FEM_ERR_INVALID_ARG;
-        }
-        BatchMesh m;
-        std::memset(&m, 0, sizeof m);
-        m.type = type_code(d.dim, d.physics, d.rule, d.coef_space);
-        m.n_elem = d.n_elem;
-        m.inv_j = d.inv_j;
-        m.det_j = d.det_j;
-        m.u = d.u;
-        m.coef = d.coef;
-        m.out = d.elem_vec;
-        hm.push_back(m);
-        total += d.n_elem;
-    }
+    fem_status vst = fill_descriptors("fem_batch_plan_create", meshes, n_mesh, hm.data(), &n_used, &total);
+    if (vst) return vst;
+    hm.resize((size_t)n_used);
     fem_batch_plan* p = new (std::nothrow) fem_batch_plan();
     if (!p) { set_error("fem_batch_plan_create: out of host memory"); return FEM_ERR_INVALID_ARG; }
     p->dtype = dtype;
@@ -237,8 +318,7 @@ fem_status fem_batch_plan_create(const fem_mesh_desc* meshes, int n_mesh, int dt
 
 fem_status fem_batch_plan_set_launch(fem_batch_plan* plan, int waves_per_block, int blocks_per_cu) {
     if (!plan) { set_error("fem_batch_plan_set_launch: NULL plan"); return FEM_ERR_INVALID_ARG; }
-    if (!(waves_per_block == 1 || waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8) ||
-        blocks_per_cu < 0 || blocks_per_cu > 64) {
+    if (!valid_batch_shape(waves_per_block, blocks_per_cu)) {
         set_error("fem_batch_plan_set_launch: invalid launch shape");
         return FEM_ERR_INVALID_ARG;
     }
@@ -297,6 +377,36 @@ fem_status fem_batch_plan_autotune(fem_batch_plan* plan, void* stream, int* wave
 fem_status fem_batch_run(fem_batch_plan* plan, void* stream) {
     if (!plan) { set_error("fem_batch_run: NULL plan"); return FEM_ERR_INVALID_ARG; }
     return plan_launch(plan, static_cast<hipStream_t>(stream));
+}
+
+fem_status fem_batch_run_noalloc(const fem_mesh_desc* meshes, int n_mesh, int dtype, int waves_per_block,
+                                 int blocks_per_cu, void* stream) {
+    static const char* fn = "fem_batch_run_noalloc";
+    if (n_mesh < 0 || (n_mesh > 0 && !meshes)) { set_error("%s: bad mesh list", fn); return FEM_ERR_INVALID_ARG; }
+    if (n_mesh > FEM_BATCH_NOALLOC_MAX_MESHES) {
+        set_error("%s: %d meshes exceed the limit of %d (use a plan)", fn, n_mesh, FEM_BATCH_NOALLOC_MAX_MESHES);
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (dtype != FEM_F32 && dtype != FEM_F64) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
+    if (!valid_batch_shape(waves_per_block, blocks_per_cu)) { set_error("%s: invalid launch shape", fn); return FEM_ERR_INVALID_ARG; }
+    // host staging of the table: per thread, fixed size, no allocation per call
+    static thread_local BatchMesh host_table[FEM_BATCH_NOALLOC_MAX_MESHES];
+    int n_used = 0;
+    int64_t total = 0;
+    fem_status st = fill_descriptors(fn, meshes, n_mesh, host_table, &n_used, &total);
+    if (st) return st;
+    if (n_used == 0) return FEM_OK;
+    const int64_t n_tiles = assign_tiles(host_table, n_used, 64 * waves_per_block);
+    BatchMesh* table = scratch_table(fn);
+    if (!table) return FEM_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // stream-ordered upload; from pageable memory the call returns once the
+    // host table has been consumed, so the next call may overwrite it
+    hipError_t e = hipMemcpyAsync(table, host_table, (size_t)n_used * sizeof(BatchMesh), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "fem_batch_run_noalloc: descriptor upload");
+    const Launch l = batch_shape(n_tiles, waves_per_block, blocks_per_cu, s);
+    e = launch_batch(dtype, table, n_used, nullptr, n_tiles, l.block, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_batch_run_noalloc launch");
 }
 
 fem_status fem_batch_capture(fem_batch_plan* plan, void* stream) {

@@ -108,8 +108,10 @@ struct BatchMesh {              // device-side descriptor, one per mesh
     void* out;
 };
 
-hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, const int32_t* d_tile_mesh, int64_t n_tiles,
-                        int tile_elems, const Launch& l);
+// d_tile_mesh may be NULL: each workgroup then finds its first mesh by a
+// binary search over the n_mesh descriptors' tile ranges.
+hipError_t launch_batch(int dtype, const BatchMesh* d_meshes, int n_mesh, const int32_t* d_tile_mesh,
+                        int64_t n_tiles, int tile_elems, const Launch& l);
 
 // Threads the transpose kernel needs per workgroup for a given tuning, or 0 if
 // the combination is not supported by that strategy.

@@ -167,6 +167,33 @@ def test_batch_plan_validation(lib):
     lib.fem_batch_plan_destroy(None)
 
 
+def test_batch_noalloc_validation(lib):
+    """The no-allocation batched launch rejects bad input before any HIP call."""
+    run = lib.fem_batch_run_noalloc
+    assert N.BATCH_NOALLOC_MAX_MESHES == 1024
+    assert "#define FEM_BATCH_NOALLOC_MAX_MESHES 1024" in N.HEADER.read_text()
+    assert run(None, 1, N.F32, 8, 0, None) == N.FEM_ERR_INVALID_ARG
+    assert run(None, -1, N.F32, 8, 0, None) == N.FEM_ERR_INVALID_ARG
+    big = (N.fem_mesh_desc * (N.BATCH_NOALLOC_MAX_MESHES + 1))()
+    assert run(big, N.BATCH_NOALLOC_MAX_MESHES + 1, N.F32, 8, 0, None) == N.FEM_ERR_INVALID_ARG
+    assert "limit" in N.last_error()
+    d = (N.fem_mesh_desc * 1)()
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, 10, 1, 1, 1, 1, 1)
+    assert run(d, 1, 9, 8, 0, None) == N.FEM_ERR_UNSUPPORTED
+    assert run(d, 1, N.F32, 3, 0, None) == N.FEM_ERR_INVALID_ARG
+    assert run(d, 1, N.F32, 8, 65, None) == N.FEM_ERR_INVALID_ARG
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, 10, 1, 1, 1, 1, 1)
+    assert run(d, 1, N.F32, 8, 0, None) == N.FEM_ERR_UNSUPPORTED
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, -1, 1, 1, 1, 1, 1)
+    assert run(d, 1, N.F32, 8, 0, None) == N.FEM_ERR_INVALID_ARG
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, 10, 1, 1, None, 1, 1)
+    assert run(d, 1, N.F32, 8, 0, None) == N.FEM_ERR_INVALID_ARG
+    # nothing to do: empty list and empty meshes return before any HIP call
+    assert run(None, 0, N.F32, 8, 0, None) == N.FEM_OK
+    d[0] = N.fem_mesh_desc(2, mg.LAPLACE, mg.RULE_TRI3, N.COEF_QUAD, 0, None, None, None, None, None)
+    assert run(d, 1, N.F32, 8, 0, None) == N.FEM_OK
+
+
 def test_autotune_validation(lib):
     R = N.OP_RESIDUAL
     assert lib.fem_autotune(R, 2, mg.LAPLACE, mg.RULE_TET4, N.F32, 1 << 16, None) == N.FEM_ERR_UNSUPPORTED
