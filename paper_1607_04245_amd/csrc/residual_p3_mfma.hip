@@ -67,12 +67,32 @@ __host__ __device__ constexpr int cls(int p, int g) {
 __host__ __device__ constexpr int use(int v, int s) { return s == 0 ? (v < 2 ? 0 : 1) : s + 1; }
 // point of lane group g, local index p (-1: padding)
 __host__ __device__ constexpr int point(int g, int p) { return g < 3 ? 3 * g + p : (p < 2 ? 9 + p : -1); }
-// point of product row i (rows 4g + p hold lane group g's points)
-__host__ __device__ constexpr int row_point(int i) { return (i % 4) == 3 ? -1 : point(i / 4, i % 4); }
-// basis function of output row i in block 0 (lane group g = i / 4 holds
-// class {0, 2, 3, 4}[g]) and block 1 (class 1, rows 0..3)
-__host__ __device__ constexpr int out_row0(int i) { return cls(i / 4 == 0 ? 0 : i / 4 + 1, i % 4); }
-__host__ __device__ constexpr int out_row1(int i) { return i < 4 ? cls(1, i) : -1; }
+
+// Where row i of a 16x16 result lands: lane group g (lanes 16 g .. 16 g + 15,
+// one column each) and accumulator register r. The FP32 product puts rows
+// 4g .. 4g + 3 in lane group g; the FP64 product puts rows g, g + 4, g + 8,
+// g + 12 there (both checked on the device). The left-operand tables below
+// order their rows so that lane group g's register r always receives the
+// quantity of (g, r), whichever the type.
+template <typename Real> __host__ __device__ constexpr int row_g(int i);
+template <typename Real> __host__ __device__ constexpr int row_r(int i);
+template <> __host__ __device__ constexpr int row_g<float>(int i) { return i / 4; }
+template <> __host__ __device__ constexpr int row_r<float>(int i) { return i % 4; }
+template <> __host__ __device__ constexpr int row_g<double>(int i) { return i % 4; }
+template <> __host__ __device__ constexpr int row_r<double>(int i) { return i / 4; }
+
+// point of product row i (register p of lane group g holds point (g, p))
+template <typename Real>
+__host__ __device__ constexpr int row_point(int i) { return row_r<Real>(i) == 3 ? -1 : point(row_g<Real>(i), row_r<Real>(i)); }
+// basis function of output row i in block 0 (lane group g holds class
+// {0, 2, 3, 4}[g], register r its member r) and block 1 (class 1, in lane
+// group 0)
+template <typename Real>
+__host__ __device__ constexpr int out_row0(int i) {
+    return cls(row_g<Real>(i) == 0 ? 0 : row_g<Real>(i) + 1, row_r<Real>(i));
+}
+template <typename Real>
+__host__ __device__ constexpr int out_row1(int i) { return row_g<Real>(i) == 0 ? cls(1, row_r<Real>(i)) : -1; }
 
 constexpr int STEPS_U = 16;   // 4 directions x 4 classes
 constexpr int STEPS_R0 = 12;  // 4 directions x 3 local points
@@ -88,15 +108,15 @@ struct Tab {
             const int g = l / 16, j = l % 16;
             for (int v = 0; v < 4; ++v)
                 for (int s = 0; s < 4; ++s) {
-                    const int q = row_point(j);
+                    const int q = row_point<Real>(j);
                     a[v * 4 + s][l] = q < 0 ? Real(0) : Real(Basis::dl(q, cls(use(v, s), g), v));
                 }
             for (int s = 0; s < STEPS_R0; ++s) {
                 const int q = point(g, s % 3), v = s / 3;
-                a[STEPS_U + s][l] = q < 0 ? Real(0) : Real(Basis::dl(q, out_row0(j), v));
+                a[STEPS_U + s][l] = q < 0 ? Real(0) : Real(Basis::dl(q, out_row0<Real>(j), v));
             }
             for (int s = 0; s < STEPS_R1; ++s) {
-                const int q = point(g, s % 3), v = 2 + s / 3, b = out_row1(j);
+                const int q = point(g, s % 3), v = 2 + s / 3, b = out_row1<Real>(j);
                 a[STEPS_U + STEPS_R0 + s][l] = (q < 0 || b < 0) ? Real(0) : Real(Basis::dl(q, b, v));
             }
         }
