@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--quick", action="store_true", help="main step only (no extra sections, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--verbose", action="store_true", help="one progress line per section on stderr")
+    p.add_argument("--only", default="",
+                   help="comma-separated extra sections to run (default: all): fp64, physics, spaces, paper, "
+                        "transposition, gather, plan, dedup, p2, p3, jacobian, assembly, fwdbwd, adjoint, batched")
     p.add_argument("--extra-out", default=str(EXTRA_PATH),
                    help="file that receives the full result with every extra section")
     return p.parse_args()
@@ -291,26 +294,32 @@ def main():
         "stream_copy": dict(gbs_2gib=big_gbs, us_2gib=big_us, gbs_same_bytes=same_gbs, us_same_bytes=same_us),
     }
 
+    only = {x.strip() for x in args.only.split(",") if x.strip()}
+
+    def want(section):
+        return not only or section in only
+
     if not args.quick:
         extra = {}
 
         # ------------------------------------------------------ FP64 step --
-        cs = step_copies(torch.float64)
-        steps64 = max(10, args.steps // 2)
-        wall64, f64 = timed_graph(fused, cs, steps64, 2)
-        swall64, _ = timed_graph(split, cs, steps64, 2)
-        g64, i64 = breakdown(cs)
-        del cs
-        b64 = model.forward_bytes(dim, phys, rule, 8) * n
-        fb64 = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 8) * n
-        extra["fp64_step"] = dict(elements_per_s=n * steps64 / wall64, ms_per_step=1e3 * wall64 / steps64,
-                                  fused_us=f64 * 1e3, fused_gbs=fb64 / (f64 * 1e-3) / 1e9,
-                                  fused_model_gflops=n * flops / (f64 * 1e-3) / 1e9,
-                                  two_call_elements_per_s=n * steps64 / swall64,
-                                  integrate_us=i64 * 1e3, integrate_gbs=b64 / (i64 * 1e-3) / 1e9,
-                                  integrate_model_gflops=n * flops / (i64 * 1e-3) / 1e9, geometry_us=g64 * 1e3)
-        log(f"FP64 fused step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us ({extra['fp64_step']['fused_gbs']:.0f}"
-            f" GB/s); integrate alone {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
+        if want("fp64"):
+            cs = step_copies(torch.float64)
+            steps64 = max(10, args.steps // 2)
+            wall64, f64 = timed_graph(fused, cs, steps64, 2)
+            swall64, _ = timed_graph(split, cs, steps64, 2)
+            g64, i64 = breakdown(cs)
+            del cs
+            b64 = model.forward_bytes(dim, phys, rule, 8) * n
+            fb64 = model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 8) * n
+            extra["fp64_step"] = dict(elements_per_s=n * steps64 / wall64, ms_per_step=1e3 * wall64 / steps64,
+                                      fused_us=f64 * 1e3, fused_gbs=fb64 / (f64 * 1e-3) / 1e9,
+                                      fused_model_gflops=n * flops / (f64 * 1e-3) / 1e9,
+                                      two_call_elements_per_s=n * steps64 / swall64,
+                                      integrate_us=i64 * 1e3, integrate_gbs=b64 / (i64 * 1e-3) / 1e9,
+                                      integrate_model_gflops=n * flops / (i64 * 1e-3) / 1e9, geometry_us=g64 * 1e3)
+            log(f"FP64 fused step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us ({extra['fp64_step']['fused_gbs']:.0f}"
+                f" GB/s); integrate alone {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
 
         # --------------------------------------------------- other physics --
         def integrate_only(wlx, dt, reps=20, space=mg.COEF_QUAD, coef=None):
@@ -358,89 +367,93 @@ def main():
             return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
                         model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
-        for cfg in ("3a", "3b"):
-            wlx = mg.config(cfg)
-            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-                r = integrate_only(wlx, dt)
-                extra[f"{wlx.name}_{tag}_integrate"] = r
-                log(f"{wlx.name} {tag} integrate: {r['us']:.1f} us, {r['gbs']:.0f} GB/s, {r['model_gflops']:.0f} model GF/s")
-                r = fused_only(wlx, dt)
-                extra[f"{wlx.name}_{tag}_from_mesh"] = r
-                log(f"{wlx.name} {tag} from mesh: {r['us']:.1f} us ({r['elements_per_s']:.3e} elem/s), "
-                    f"{r['gbs']:.0f} GB/s")
-            del wlx
+        if want("physics"):
+            for cfg in ("3a", "3b"):
+                wlx = mg.config(cfg)
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    r = integrate_only(wlx, dt)
+                    extra[f"{wlx.name}_{tag}_integrate"] = r
+                    log(f"{wlx.name} {tag} integrate: {r['us']:.1f} us, {r['gbs']:.0f} GB/s, {r['model_gflops']:.0f} model GF/s")
+                    r = fused_only(wlx, dt)
+                    extra[f"{wlx.name}_{tag}_from_mesh"] = r
+                    log(f"{wlx.name} {tag} from mesh: {r['us']:.1f} us ({r['elements_per_s']:.3e} elem/s), "
+                        f"{r['gbs']:.0f} GB/s")
+                del wlx
 
         # ---------------------------------------------- coefficient spaces --
         # The paper's GPU runs take the coefficient as a P1 field or per cell
         # (Section 4); P1 coefficients are the closure of a vertex field.
-        for cfg in (2, "3a"):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            for space, sname in ((mg.COEF_P1, "p1"), (mg.COEF_P0, "p0")):
-                cf = mg.space_coefficients(wlx, space, mg.BASE_SEED + 1000)
-                r = integrate_only(wlx, torch.float32, space=space, coef=cf)
-                extra[f"{wlx.name}_f32_coef_{sname}_integrate"] = r
-                r2 = fused_only(wlx, torch.float32, space=space, coef=cf)
-                extra[f"{wlx.name}_f32_coef_{sname}_from_mesh"] = r2
-                log(f"{wlx.name} f32 coefficient {sname}: integrate {r['us']:.1f} us ({r['gbs']:.0f} GB/s), "
-                    f"from mesh {r2['us']:.1f} us ({r2['elements_per_s']:.3e} elem/s, {r2['gbs']:.0f} GB/s)")
-                del cf
-            del wlx
+        if want("spaces"):
+            for cfg in (2, "3a"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                for space, sname in ((mg.COEF_P1, "p1"), (mg.COEF_P0, "p0")):
+                    cf = mg.space_coefficients(wlx, space, mg.BASE_SEED + 1000)
+                    r = integrate_only(wlx, torch.float32, space=space, coef=cf)
+                    extra[f"{wlx.name}_f32_coef_{sname}_integrate"] = r
+                    r2 = fused_only(wlx, torch.float32, space=space, coef=cf)
+                    extra[f"{wlx.name}_f32_coef_{sname}_from_mesh"] = r2
+                    log(f"{wlx.name} f32 coefficient {sname}: integrate {r['us']:.1f} us ({r['gbs']:.0f} GB/s), "
+                        f"from mesh {r2['us']:.1f} us ({r2['elements_per_s']:.3e} elem/s, {r2['gbs']:.0f} GB/s)")
+                    del cf
+                del wlx
 
         # ----------------------------------------------------- paper analog --
         # The paper's headline case: 2D P1 Laplacian, variable coefficient in
         # the P1 space, one quadrature point (its flop model, Section 3), on
         # the 2^22-triangle mesh; model GF/s with the paper's per-cell formula.
-        wlp = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
-                               rule=mg.RULE_CENTROID)
-        cfp = mg.space_coefficients(wlp, mg.COEF_P1, mg.BASE_SEED + 1000)
-        f1 = model.paper_flops_per_cell(2, 3, 1, 1)
-        for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-            r = integrate_only(wlp, dt, space=mg.COEF_P1, coef=cfp)
-            r2 = fused_only(wlp, dt, space=mg.COEF_P1, coef=cfp)
-            for rr in (r, r2):
-                rr["paper_model_gflops"] = rr["elements_per_s"] * f1 / 1e9
-            extra[f"paper_analog_laplace2d_p1coef_nq1_{tag}_integrate"] = r
-            extra[f"paper_analog_laplace2d_p1coef_nq1_{tag}_from_mesh"] = r2
-            log(f"2D Laplacian, P1 coefficient, N_q = 1, {tag}: integrate {r['elements_per_s']:.3e} el/s "
-                f"({r['paper_model_gflops']:.0f} GF/s in the paper's model, {r['gbs']:.0f} GB/s), from mesh "
-                f"{r2['elements_per_s']:.3e} el/s ({r2['paper_model_gflops']:.0f} GF/s)")
-        del wlp, cfp
+        if want("paper"):
+            wlp = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
+                                   rule=mg.RULE_CENTROID)
+            cfp = mg.space_coefficients(wlp, mg.COEF_P1, mg.BASE_SEED + 1000)
+            f1 = model.paper_flops_per_cell(2, 3, 1, 1)
+            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                r = integrate_only(wlp, dt, space=mg.COEF_P1, coef=cfp)
+                r2 = fused_only(wlp, dt, space=mg.COEF_P1, coef=cfp)
+                for rr in (r, r2):
+                    rr["paper_model_gflops"] = rr["elements_per_s"] * f1 / 1e9
+                extra[f"paper_analog_laplace2d_p1coef_nq1_{tag}_integrate"] = r
+                extra[f"paper_analog_laplace2d_p1coef_nq1_{tag}_from_mesh"] = r2
+                log(f"2D Laplacian, P1 coefficient, N_q = 1, {tag}: integrate {r['elements_per_s']:.3e} el/s "
+                    f"({r['paper_model_gflops']:.0f} GF/s in the paper's model, {r['gbs']:.0f} GB/s), from mesh "
+                    f"{r2['elements_per_s']:.3e} el/s ({r2['paper_model_gflops']:.0f} GF/s)")
+            del wlp, cfp
 
         # ------------------------------------------ thread transposition --
         # The paper's strategy (Section 3: quadrature-point-parallel work, an
         # LDS transposition, basis-function-parallel work) against the default
         # one-element-per-lane kernel, on the step mesh and the paper's 2D
         # N_q = 1 case; best of the transposition's workgroup sizes.
-        wlq = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
-                               rule=mg.RULE_CENTROID)
-        def best_of(wlx, strategy, shapes):
-            """Fastest launch shape of a strategy: (shape, result) or None."""
-            best = None
-            for waves, bpc in shapes:
-                api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, strategy=strategy, vec=1,
-                                   waves_per_block=waves, blocks_per_cu=bpc)
-                try:
-                    r = integrate_only(wlx, torch.float32)
-                except N.FemError:  # workgroup too large for this element's LDS tile
-                    continue
-                if best is None or r["us"] < best[1]["us"]:
-                    best = ((waves, bpc), r)
-            return best
+        if want("transposition"):
+            wlq = mg.make_workload("laplace2d_2p22_centroid", 2, mg.LAPLACE, 1449, 1 << 22, mg.BASE_SEED + 6,
+                                   rule=mg.RULE_CENTROID)
+            def best_of(wlx, strategy, shapes):
+                """Fastest launch shape of a strategy: (shape, result) or None."""
+                best = None
+                for waves, bpc in shapes:
+                    api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, strategy=strategy, vec=1,
+                                       waves_per_block=waves, blocks_per_cu=bpc)
+                    try:
+                        r = integrate_only(wlx, torch.float32)
+                    except N.FemError:  # workgroup too large for this element's LDS tile
+                        continue
+                    if best is None or r["us"] < best[1]["us"]:
+                        best = ((waves, bpc), r)
+                return best
 
-        shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 8)]
-        for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
-            saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
-            lane = integrate_only(wlx, torch.float32)
-            tt = best_of(wlx, N.STRATEGY_TRANSPOSE, shapes)
-            sh = best_of(wlx, N.STRATEGY_SHUFFLE, shapes)
-            api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, **saved)
-            extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=tt[1]["us"],
-                                              transpose_gbs=tt[1]["gbs"], transpose_shape=tt[0],
-                                              shuffle_us=sh[1]["us"], shuffle_gbs=sh[1]["gbs"], shuffle_shape=sh[0])
-            log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition through "
-                f"LDS {tt[1]['us']:.1f} us ({tt[1]['gbs']:.0f} GB/s, shape {tt[0]}), through quad permutations "
-                f"{sh[1]['us']:.1f} us ({sh[1]['gbs']:.0f} GB/s, shape {sh[0]})", always=True)
-        del wlq
+            shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 8)]
+            for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
+                saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
+                lane = integrate_only(wlx, torch.float32)
+                tt = best_of(wlx, N.STRATEGY_TRANSPOSE, shapes)
+                sh = best_of(wlx, N.STRATEGY_SHUFFLE, shapes)
+                api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, **saved)
+                extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=tt[1]["us"],
+                                                  transpose_gbs=tt[1]["gbs"], transpose_shape=tt[0],
+                                                  shuffle_us=sh[1]["us"], shuffle_gbs=sh[1]["gbs"], shuffle_shape=sh[0])
+                log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition through "
+                    f"LDS {tt[1]['us']:.1f} us ({tt[1]['gbs']:.0f} GB/s, shape {tt[0]}), through quad permutations "
+                    f"{sh[1]['us']:.1f} us ({sh[1]['gbs']:.0f} GB/s, shape {sh[0]})", always=True)
+            del wlq
 
         # ------------------------------------------------------ gather form --
         # u per vertex (and a P1 coefficient per vertex), gathered in the kernel.
@@ -471,368 +484,403 @@ def main():
                         model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, bytes_per_elem=nb / wlx.n_elem,
                         frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
-        for cfg in (2, "3b"):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            for space, sname in ((mg.COEF_QUAD, "quad"), (mg.COEF_P1, "p1")):
-                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-                    r = gather_only(wlx, dt, space)
-                    extra[f"{wlx.name}_{tag}_coef_{sname}_gather"] = r
-                    log(f"{wlx.name} {tag} gather, coefficient {sname}: {r['us']:.1f} us "
-                        f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
-            del wlx
+        if want("gather"):
+            for cfg in (2, "3b"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                for space, sname in ((mg.COEF_QUAD, "quad"), (mg.COEF_P1, "p1")):
+                    for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                        r = gather_only(wlx, dt, space)
+                        extra[f"{wlx.name}_{tag}_coef_{sname}_gather"] = r
+                        log(f"{wlx.name} {tag} gather, coefficient {sname}: {r['us']:.1f} us "
+                            f"({r['elements_per_s']:.3e} elem/s, {r['bytes_per_elem']:.1f} B/elem, {r['gbs']:.0f} GB/s)")
+                del wlx
 
         # ------------------------------------------------------- mesh plans --
         # The from-mesh residual through a per-mesh plan of each tile's
         # distinct vertices (built once, outside the timed region; its build
         # time is reported), beside the unplanned fused and gather kernels.
-        for cfg in (2, "3a", "3b"):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            conn0 = to_dev(wlx.conn, torch.int32)
-            t0 = time.perf_counter()
-            plan0 = api.MeshPlan(conn0, wlx.n_vert)
-            build_s = time.perf_counter() - t0
-            info = plan0.info()
-            plan0.close()
-            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-                word = 4 if dt == torch.float32 else 8
-                row = dict(n_elem=wlx.n_elem, plan_build_s=build_s, tile_vertices_per_elem=info["tile_vertices"] / wlx.n_elem)
-                for gather in (False, True):
-                    nb = model.planned_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert,
-                                             info["tile_vertices"], word, gather=gather) * wlx.n_elem
-                    base = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0,
-                                u=to_dev(wlx.u_vertex if gather else wlx.u, dt), cf=to_dev(wlx.coef, dt))
+        if want("plan"):
+            for cfg in (2, "3a", "3b"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                conn0 = to_dev(wlx.conn, torch.int32)
+                t0 = time.perf_counter()
+                plan0 = api.MeshPlan(conn0, wlx.n_vert)
+                build_s = time.perf_counter() - t0
+                info = plan0.info()
+                plan0.close()
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    word = 4 if dt == torch.float32 else 8
+                    row = dict(n_elem=wlx.n_elem, plan_build_s=build_s, tile_vertices_per_elem=info["tile_vertices"] / wlx.n_elem)
+                    for gather in (False, True):
+                        nb = model.planned_bytes(wlx.dim, wlx.physics, wlx.rule, wlx.n_elem, wlx.n_vert,
+                                                 info["tile_vertices"], word, gather=gather) * wlx.n_elem
+                        base = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0,
+                                    u=to_dev(wlx.u_vertex if gather else wlx.u, dt), cf=to_dev(wlx.coef, dt))
+                        cps = []
+                        for _ in range(n_copies(nb)):
+                            c = {k: v.clone() for k, v in base.items()}
+                            c["plan"] = api.MeshPlan(c["conn"], wlx.n_vert)
+                            c["R"] = torch.empty(wlx.u.shape, dtype=dt, device=dev)
+                            cps.append(c)
+                        del base
+
+                        def go(c, wlx=wlx, gather=gather):
+                            f = c["plan"].gather if gather else c["plan"].integrate
+                            f(wlx.physics, wlx.rule, c["X"], c["u"], c["cf"], out=c["R"])
+                        _, ms = timed_graph(go, cps, 20, 1)
+                        for c in cps:
+                            c["plan"].close()
+                        del cps
+                        unplanned = (gather_only(wlx, dt, mg.COEF_QUAD) if gather else fused_only(wlx, dt))["us"]
+                        form = "gather" if gather else "closure"
+                        row[f"{form}_us"] = ms * 1e3
+                        row[f"{form}_elements_per_s"] = wlx.n_elem / (ms * 1e-3)
+                        row[f"{form}_gbs"] = nb / (ms * 1e-3) / 1e9
+                        row[f"{form}_unplanned_us"] = unplanned
+                    # the geometry alone, through the plan and through fem_geometry
+                    nb = model.geometry_bytes(wlx.dim, wlx.n_elem, wlx.n_vert, word) * wlx.n_elem
                     cps = []
                     for _ in range(n_copies(nb)):
-                        c = {k: v.clone() for k, v in base.items()}
+                        c = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0.clone())
                         c["plan"] = api.MeshPlan(c["conn"], wlx.n_vert)
-                        c["R"] = torch.empty(wlx.u.shape, dtype=dt, device=dev)
+                        c["ij"] = torch.empty((wlx.dim * wlx.dim, wlx.n_elem), dtype=dt, device=dev)
+                        c["dj"] = torch.empty((wlx.n_elem,), dtype=dt, device=dev)
                         cps.append(c)
-                    del base
 
-                    def go(c, wlx=wlx, gather=gather):
-                        f = c["plan"].gather if gather else c["plan"].integrate
-                        f(wlx.physics, wlx.rule, c["X"], c["u"], c["cf"], out=c["R"])
-                    _, ms = timed_graph(go, cps, 20, 1)
+                    def geo_plain(c, dt=dt):
+                        api.fem_geometry(c["X"], c["conn"], dt, inv_j=c["ij"], det_j=c["dj"])
+
+                    def geo_planned(c, dt=dt):
+                        c["plan"].geometry(c["X"], dt, inv_j=c["ij"], det_j=c["dj"])
+                    _, ms_g = timed_graph(geo_plain, cps, 20, 1)
+                    _, ms_gp = timed_graph(geo_planned, cps, 20, 1)
                     for c in cps:
                         c["plan"].close()
                     del cps
-                    unplanned = (gather_only(wlx, dt, mg.COEF_QUAD) if gather else fused_only(wlx, dt))["us"]
-                    form = "gather" if gather else "closure"
-                    row[f"{form}_us"] = ms * 1e3
-                    row[f"{form}_elements_per_s"] = wlx.n_elem / (ms * 1e-3)
-                    row[f"{form}_gbs"] = nb / (ms * 1e-3) / 1e9
-                    row[f"{form}_unplanned_us"] = unplanned
-                # the geometry alone, through the plan and through fem_geometry
-                nb = model.geometry_bytes(wlx.dim, wlx.n_elem, wlx.n_vert, word) * wlx.n_elem
-                cps = []
-                for _ in range(n_copies(nb)):
-                    c = dict(X=to_dev(wlx.coords, torch.float64), conn=conn0.clone())
-                    c["plan"] = api.MeshPlan(c["conn"], wlx.n_vert)
-                    c["ij"] = torch.empty((wlx.dim * wlx.dim, wlx.n_elem), dtype=dt, device=dev)
-                    c["dj"] = torch.empty((wlx.n_elem,), dtype=dt, device=dev)
-                    cps.append(c)
+                    row.update(geometry_us=ms_gp * 1e3, geometry_unplanned_us=ms_g * 1e3,
+                               geometry_gbs=nb / (ms_gp * 1e-3) / 1e9)
+                    extra[f"{wlx.name}_{tag}_mesh_plan"] = row
+                    log(f"{wlx.name} {tag} mesh plan (built in {build_s:.2f} s, "
+                        f"{row['tile_vertices_per_elem']:.2f} tile vertices per element): closure "
+                        f"{row['closure_us']:.1f} us (unplanned {row['closure_unplanned_us']:.1f}), gather "
+                        f"{row['gather_us']:.1f} us (unplanned {row['gather_unplanned_us']:.1f}), geometry "
+                        f"{row['geometry_us']:.1f} us (unplanned {row['geometry_unplanned_us']:.1f})")
+                del conn0, wlx
 
-                def geo_plain(c, dt=dt):
-                    api.fem_geometry(c["X"], c["conn"], dt, inv_j=c["ij"], det_j=c["dj"])
-
-                def geo_planned(c, dt=dt):
-                    c["plan"].geometry(c["X"], dt, inv_j=c["ij"], det_j=c["dj"])
-                _, ms_g = timed_graph(geo_plain, cps, 20, 1)
-                _, ms_gp = timed_graph(geo_planned, cps, 20, 1)
-                for c in cps:
-                    c["plan"].close()
-                del cps
-                row.update(geometry_us=ms_gp * 1e3, geometry_unplanned_us=ms_g * 1e3,
-                           geometry_gbs=nb / (ms_gp * 1e-3) / 1e9)
-                extra[f"{wlx.name}_{tag}_mesh_plan"] = row
-                log(f"{wlx.name} {tag} mesh plan (built in {build_s:.2f} s, "
-                    f"{row['tile_vertices_per_elem']:.2f} tile vertices per element): closure "
-                    f"{row['closure_us']:.1f} us (unplanned {row['closure_unplanned_us']:.1f}), gather "
-                    f"{row['gather_us']:.1f} us (unplanned {row['gather_unplanned_us']:.1f}), geometry "
-                    f"{row['geometry_us']:.1f} us (unplanned {row['geometry_unplanned_us']:.1f})")
-            del conn0, wlx
+        # ------------------------------------------- run-time vertex dedup --
+        # The fused from-mesh residual with each wave's distinct vertices
+        # gathered once into LDS (FEM_STRATEGY_DEDUP), against the per-lane
+        # gathers of the default strategy; best of a few launch shapes.
+        if want("dedup"):
+            for cfg in (2, "3a", "3b"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, dt, op=N.OP_RESIDUAL_MESH)
+                    lane = fused_only(wlx, dt)
+                    best = None
+                    for waves, bpc in ((2, 0), (4, 0), (2, 8), (4, 4)):
+                        api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, dt, strategy=N.STRATEGY_DEDUP, vec=1,
+                                           waves_per_block=waves, blocks_per_cu=bpc, op=N.OP_RESIDUAL_MESH)
+                        r = fused_only(wlx, dt)
+                        if best is None or r["us"] < best[1]["us"]:
+                            best = ((waves, bpc), r)
+                    api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, dt, op=N.OP_RESIDUAL_MESH, **saved)
+                    extra[f"{wlx.name}_{tag}_dedup"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"],
+                                                             dedup_us=best[1]["us"], dedup_gbs=best[1]["gbs"],
+                                                             dedup_shape=best[0])
+                    log(f"{wlx.name} {tag} from mesh: per-lane gathers {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), "
+                        f"run-time dedup {best[1]['us']:.1f} us ({best[1]['gbs']:.0f} GB/s, shape {best[0]})",
+                        always=True)
+                del wlx
 
         # ------------------------------------------------- second order (P2) --
-        for cfg, rule_p2 in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            p2 = mg.p2_inputs(wlx, rule_p2, mg.BASE_SEED + 5000)
-            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-                word = 4 if dt == torch.float32 else 8
-                nb = model.p2_forward_bytes(wlx.dim, wlx.physics, rule_p2, word) * wlx.n_elem
-                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
-                base = dict(ij=ij, dj=dj, u=to_dev(p2.u, dt), cf=to_dev(p2.coef, dt))
-                cps = []
-                for _ in range(n_copies(nb)):
-                    c = {k: v.clone() for k, v in base.items()}
-                    c["R"] = torch.empty_like(c["u"])
-                    cps.append(c)
-                del base
+        if want("p2"):
+            for cfg, rule_p2 in ((2, mg.RULE_TET11), ("3b", mg.RULE_TET11), ("3a", mg.RULE_TRI6)):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                p2 = mg.p2_inputs(wlx, rule_p2, mg.BASE_SEED + 5000)
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    word = 4 if dt == torch.float32 else 8
+                    nb = model.p2_forward_bytes(wlx.dim, wlx.physics, rule_p2, word) * wlx.n_elem
+                    ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                    base = dict(ij=ij, dj=dj, u=to_dev(p2.u, dt), cf=to_dev(p2.coef, dt))
+                    cps = []
+                    for _ in range(n_copies(nb)):
+                        c = {k: v.clone() for k, v in base.items()}
+                        c["R"] = torch.empty_like(c["u"])
+                        cps.append(c)
+                    del base
 
-                def go(c, wlx=wlx, rule_p2=rule_p2):
-                    api.fem_integrate_residual_p2(wlx.dim, wlx.physics, rule_p2, c["ij"], c["dj"], c["u"], c["cf"],
-                                                  out=c["R"])
-                _, ms = timed_graph(go, cps, 20, 1)
-                us = ms * 1e3
-                f = model.p2_model_flops(wlx.dim, wlx.physics, rule_p2)
-                # a copy of the same bytes: how much of the kernel's time the
-                # stream itself needs, whatever unit does the arithmetic
-                cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 20)
-                extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
-                    n_elem=wlx.n_elem, rule=rule_p2, us=us, gbs=nb / (us * 1e-6) / 1e9,
-                    elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
-                    bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
-                log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
-                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
-                    f"copy of the same bytes {cp_us:.1f} us")
-                del cps, ij, dj
-            del p2, wlx
+                    def go(c, wlx=wlx, rule_p2=rule_p2):
+                        api.fem_integrate_residual_p2(wlx.dim, wlx.physics, rule_p2, c["ij"], c["dj"], c["u"], c["cf"],
+                                                      out=c["R"])
+                    _, ms = timed_graph(go, cps, 20, 1)
+                    us = ms * 1e3
+                    f = model.p2_model_flops(wlx.dim, wlx.physics, rule_p2)
+                    # a copy of the same bytes: how much of the kernel's time the
+                    # stream itself needs, whatever unit does the arithmetic
+                    cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 20)
+                    extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
+                        n_elem=wlx.n_elem, rule=rule_p2, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                        elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
+                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
+                    log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                        f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
+                        f"copy of the same bytes {cp_us:.1f} us")
+                    del cps, ij, dj
+                del p2, wlx
 
         # -------------------------------------------------- third order (P3) --
-        for cfg in (2, "3b", "3a"):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            rule_p3 = mg.RULE_TET11 if wlx.dim == 3 else mg.RULE_TRI6
-            p3 = mg.p3_inputs(wlx, rule_p3, mg.BASE_SEED + 7700)
-            for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-                word = 4 if dt == torch.float32 else 8
-                nb = model.p3_forward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
-                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
-                base = dict(ij=ij, dj=dj, u=to_dev(p3.u, dt), cf=to_dev(p3.coef, dt))
-                cps = []
-                for _ in range(n_copies(nb)):
-                    c = {k: v.clone() for k, v in base.items()}
-                    c["R"] = torch.empty_like(c["u"])
-                    cps.append(c)
-                del base
+        if want("p3"):
+            for cfg in (2, "3b", "3a"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                rule_p3 = mg.RULE_TET11 if wlx.dim == 3 else mg.RULE_TRI6
+                p3 = mg.p3_inputs(wlx, rule_p3, mg.BASE_SEED + 7700)
+                for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+                    word = 4 if dt == torch.float32 else 8
+                    nb = model.p3_forward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
+                    ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                    base = dict(ij=ij, dj=dj, u=to_dev(p3.u, dt), cf=to_dev(p3.coef, dt))
+                    cps = []
+                    for _ in range(n_copies(nb)):
+                        c = {k: v.clone() for k, v in base.items()}
+                        c["R"] = torch.empty_like(c["u"])
+                        cps.append(c)
+                    del base
 
-                def go(c, wlx=wlx, rule_p3=rule_p3):
-                    api.fem_integrate_residual_p3(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"], c["cf"],
-                                                  out=c["R"])
-                saved = api.fem_get_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3)
-                api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_LANE,
-                                   vec=1, waves_per_block=1 if wlx.dim == 3 else 4, blocks_per_cu=0)
-                _, ms = timed_graph(go, cps, 10, 1)
-                us = ms * 1e3
-                mfma = None
-                if wlx.dim == 3:
-                    # the transposition on the matrix cores, best launch shape
-                    for waves, bpc in ((1, 0), (2, 0), (4, 0), (4, 2), (4, 4), (2, 4)):
-                        api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3,
-                                           strategy=N.STRATEGY_MFMA, vec=1, waves_per_block=waves, blocks_per_cu=bpc)
-                        _, msm = timed_graph(go, cps, 10, 1)
-                        if mfma is None or msm * 1e3 < mfma[1]:
-                            mfma = ((waves, bpc), msm * 1e3)
-                api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, **saved)
-                f = model.p3_model_flops(wlx.dim, wlx.physics, rule_p3)
-                cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 10)
-                extra[f"{wlx.name}_p3_{tag}_integrate"] = dict(
-                    n_elem=wlx.n_elem, rule=rule_p3, us=us, gbs=nb / (us * 1e-6) / 1e9,
-                    elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
-                    bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
-                if mfma:
-                    extra[f"{wlx.name}_p3_{tag}_integrate"].update(
-                        mfma_us=mfma[1], mfma_shape=mfma[0], mfma_gbs=nb / (mfma[1] * 1e-6) / 1e9,
-                        mfma_frac_of_copy_same_bytes=cp_us / mfma[1])
-                log(f"{wlx.name} P3 {tag} integrate: lane kernel {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
-                    f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)"
-                    + (f", matrix-core transposition {mfma[1]:.1f} us (shape {mfma[0]})" if mfma else "")
-                    + f"; copy of the same bytes {cp_us:.1f} us", always=wlx.dim == 3)
-                if wlx.dim == 3:
-                    # the adjoint (du and dcoef) on the same inputs, w = u
-                    nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
-                    for c in cps:
-                        c["dc"] = torch.empty_like(c["cf"])
+                    def go(c, wlx=wlx, rule_p3=rule_p3):
+                        api.fem_integrate_residual_p3(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"], c["cf"],
+                                                      out=c["R"])
+                    saved = api.fem_get_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3)
+                    api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_LANE,
+                                       vec=1, waves_per_block=1 if wlx.dim == 3 else 4, blocks_per_cu=0)
+                    _, ms = timed_graph(go, cps, 10, 1)
+                    us = ms * 1e3
+                    mfma = None
+                    if wlx.dim == 3:
+                        # the transposition on the matrix cores, best launch shape
+                        for waves, bpc in ((1, 0), (2, 0), (4, 0), (4, 2), (4, 4), (2, 4)):
+                            api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3,
+                                               strategy=N.STRATEGY_MFMA, vec=1, waves_per_block=waves, blocks_per_cu=bpc)
+                            _, msm = timed_graph(go, cps, 10, 1)
+                            if mfma is None or msm * 1e3 < mfma[1]:
+                                mfma = ((waves, bpc), msm * 1e3)
+                    api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, **saved)
+                    f = model.p3_model_flops(wlx.dim, wlx.physics, rule_p3)
+                    cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 10)
+                    extra[f"{wlx.name}_p3_{tag}_integrate"] = dict(
+                        n_elem=wlx.n_elem, rule=rule_p3, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                        elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
+                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
+                    if mfma:
+                        extra[f"{wlx.name}_p3_{tag}_integrate"].update(
+                            mfma_us=mfma[1], mfma_shape=mfma[0], mfma_gbs=nb / (mfma[1] * 1e-6) / 1e9,
+                            mfma_frac_of_copy_same_bytes=cp_us / mfma[1])
+                    log(f"{wlx.name} P3 {tag} integrate: lane kernel {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                        f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)"
+                        + (f", matrix-core transposition {mfma[1]:.1f} us (shape {mfma[0]})" if mfma else "")
+                        + f"; copy of the same bytes {cp_us:.1f} us", always=wlx.dim == 3)
+                    if wlx.dim == 3:
+                        # the adjoint (du and dcoef) on the same inputs, w = u
+                        nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
+                        for c in cps:
+                            c["dc"] = torch.empty_like(c["cf"])
 
-                    def back(c, wlx=wlx, rule_p3=rule_p3):
-                        api.fem_integrate_residual_p3_backward(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"],
-                                                               c["cf"], c["u"], du=c["R"], dcoef=c["dc"])
-                    _, msb = timed_graph(back, cps, 10, 1)
-                    extra[f"{wlx.name}_p3_{tag}_adjoint"] = dict(
-                        n_elem=wlx.n_elem, us=msb * 1e3, gbs=nbb / (msb * 1e-3) / 1e9, bytes_per_elem=nbb / wlx.n_elem)
-                    log(f"{wlx.name} P3 {tag} adjoint: {msb * 1e3:.1f} us ({nbb / (msb * 1e-3) / 1e9:.0f} GB/s)")
-                del cps, ij, dj
-            del p3, wlx
+                        def back(c, wlx=wlx, rule_p3=rule_p3):
+                            api.fem_integrate_residual_p3_backward(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"],
+                                                                   c["cf"], c["u"], du=c["R"], dcoef=c["dc"])
+                        _, msb = timed_graph(back, cps, 10, 1)
+                        extra[f"{wlx.name}_p3_{tag}_adjoint"] = dict(
+                            n_elem=wlx.n_elem, us=msb * 1e3, gbs=nbb / (msb * 1e-3) / 1e9, bytes_per_elem=nbb / wlx.n_elem)
+                        log(f"{wlx.name} P3 {tag} adjoint: {msb * 1e3:.1f} us ({nbb / (msb * 1e-3) / 1e9:.0f} GB/s)")
+                    del cps, ij, dj
+                del p3, wlx
 
         # ------------------------------------------------- element matrices --
-        for cfg, order, rule_k, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
-                                      ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",)),
-                                      (2, 3, mg.RULE_TET11, ("f32",))):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            cf0 = mg.p2_inputs(wlx, rule_k, mg.BASE_SEED + 5000).coef
-            nbt = model.n_basis(wlx.dim, order) * wlx.n_comp
-            for tag in dts:
-                dt = torch.float32 if tag == "f32" else torch.float64
-                word = 4 if dt == torch.float32 else 8
-                nb = model.jacobian_bytes(wlx.dim, wlx.physics, rule_k, word, order=order) * wlx.n_elem
-                ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
-                base = dict(ij=ij, dj=dj, cf=to_dev(cf0, dt))
-                cps = []
-                for _ in range(n_copies(nb)):
-                    c = {k: v.clone() for k, v in base.items()}
-                    c["K"] = torch.empty((nbt * nbt, wlx.n_elem), dtype=dt, device=dev)
-                    cps.append(c)
-                del base, ij, dj
+        if want("jacobian"):
+            for cfg, order, rule_k, dts in ((2, 1, mg.RULE_TET4, ("f32", "f64")), (2, 2, mg.RULE_TET11, ("f32", "f64")),
+                                          ("3b", 1, mg.RULE_TET4, ("f32", "f64")), ("3b", 2, mg.RULE_TET11, ("f32",)),
+                                          (2, 3, mg.RULE_TET11, ("f32",))):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                cf0 = mg.p2_inputs(wlx, rule_k, mg.BASE_SEED + 5000).coef
+                nbt = model.n_basis(wlx.dim, order) * wlx.n_comp
+                for tag in dts:
+                    dt = torch.float32 if tag == "f32" else torch.float64
+                    word = 4 if dt == torch.float32 else 8
+                    nb = model.jacobian_bytes(wlx.dim, wlx.physics, rule_k, word, order=order) * wlx.n_elem
+                    ij, dj = api.fem_geometry(to_dev(wlx.coords, torch.float64), to_dev(wlx.conn, torch.int32), dt)
+                    base = dict(ij=ij, dj=dj, cf=to_dev(cf0, dt))
+                    cps = []
+                    for _ in range(n_copies(nb)):
+                        c = {k: v.clone() for k, v in base.items()}
+                        c["K"] = torch.empty((nbt * nbt, wlx.n_elem), dtype=dt, device=dev)
+                        cps.append(c)
+                    del base, ij, dj
 
-                def go(c, wlx=wlx, rule_k=rule_k, order=order):
-                    api.fem_integrate_jacobian(wlx.dim, wlx.physics, rule_k, c["ij"], c["dj"], c["cf"], out=c["K"],
-                                               order=order)
-                _, ms = timed_graph(go, cps, 10, 1)
-                us = ms * 1e3
-                extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
-                    n_elem=wlx.n_elem, rule=rule_k, us=us, gbs=nb / (us * 1e-6) / 1e9,
-                    elements_per_s=wlx.n_elem / (us * 1e-6), bytes_per_elem=nb / wlx.n_elem,
-                    frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
-                log(f"{wlx.name} element matrices P{order} {tag}: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
-                    f"{nb / wlx.n_elem:.0f} B/elem, {nb / (us * 1e-6) / 1e9:.0f} GB/s)")
-                del cps
-            del cf0, wlx
+                    def go(c, wlx=wlx, rule_k=rule_k, order=order):
+                        api.fem_integrate_jacobian(wlx.dim, wlx.physics, rule_k, c["ij"], c["dj"], c["cf"], out=c["K"],
+                                                   order=order)
+                    _, ms = timed_graph(go, cps, 10, 1)
+                    us = ms * 1e3
+                    extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
+                        n_elem=wlx.n_elem, rule=rule_k, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                        elements_per_s=wlx.n_elem / (us * 1e-6), bytes_per_elem=nb / wlx.n_elem,
+                        frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                    log(f"{wlx.name} element matrices P{order} {tag}: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
+                        f"{nb / wlx.n_elem:.0f} B/elem, {nb / (us * 1e-6) / 1e9:.0f} GB/s)")
+                    del cps
+                del cf0, wlx
 
         # --------------------------------------------------------- assembly --
         # global residual: element vectors summed onto vertices (deterministic gather)
-        for cfg in (2, "3b"):
-            wlx = wl if cfg == 2 else mg.config(cfg)
-            nc = wlx.n_comp
-            conn_d = to_dev(wlx.conn, torch.int32)
-            plan = api.AssemblyPlan(conn_d, wlx.n_vert)
-            nb = model.assemble_bytes(wlx.dim, nc, wlx.n_elem, wlx.n_vert, 4) * wlx.n_elem
-            R0 = torch.randn(((wlx.dim + 1) * nc, wlx.n_elem), device=dev)
-            cps = [dict(R=R0.clone(), F=torch.empty((wlx.n_vert, nc), device=dev)) for _ in range(n_copies(nb))]
-            del R0
+        if want("assembly"):
+            for cfg in (2, "3b"):
+                wlx = wl if cfg == 2 else mg.config(cfg)
+                nc = wlx.n_comp
+                conn_d = to_dev(wlx.conn, torch.int32)
+                plan = api.AssemblyPlan(conn_d, wlx.n_vert)
+                nb = model.assemble_bytes(wlx.dim, nc, wlx.n_elem, wlx.n_vert, 4) * wlx.n_elem
+                R0 = torch.randn(((wlx.dim + 1) * nc, wlx.n_elem), device=dev)
+                cps = [dict(R=R0.clone(), F=torch.empty((wlx.n_vert, nc), device=dev)) for _ in range(n_copies(nb))]
+                del R0
 
-            def go(c, plan=plan, nc=nc):
-                plan.assemble(c["R"], nc, out=c["F"])
-            _, ms = timed_graph(go, cps, 20, 1)
-            us = ms * 1e3
-            extra[f"{wlx.name}_f32_assemble"] = dict(n_elem=wlx.n_elem, n_vert=wlx.n_vert, us=us,
-                                                     gbs=nb / (us * 1e-6) / 1e9,
-                                                     elements_per_s=wlx.n_elem / (us * 1e-6))
-            log(f"{wlx.name} f32 assembly: {us:.1f} us ({nb / (us * 1e-6) / 1e9:.0f} GB/s)")
-            del cps, plan, conn_d, wlx
+                def go(c, plan=plan, nc=nc):
+                    plan.assemble(c["R"], nc, out=c["F"])
+                _, ms = timed_graph(go, cps, 20, 1)
+                us = ms * 1e3
+                extra[f"{wlx.name}_f32_assemble"] = dict(n_elem=wlx.n_elem, n_vert=wlx.n_vert, us=us,
+                                                         gbs=nb / (us * 1e-6) / 1e9,
+                                                         elements_per_s=wlx.n_elem / (us * 1e-6))
+                log(f"{wlx.name} f32 assembly: {us:.1f} us ({nb / (us * 1e-6) / 1e9:.0f} GB/s)")
+                del cps, plan, conn_d, wlx
 
         # ------------------------------------- forward and adjoint, one step --
         # Every row of the path on the step workload: the fused residual
         # (storing the geometry), then the adjoint (du and dcoef) of
         # L = sum w . R from that geometry.
-        dt = torch.float32
-        nb_fb = (model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 4, store_geometry=True)
-                 + model.backward_bytes(dim, phys, rule, 4)) * n
-        base = dict(X=to_dev(wl.coords, torch.float64), conn=to_dev(wl.conn, torch.int32), u=to_dev(wl.u, dt),
-                    cf=to_dev(wl.coef, dt), w=to_dev(wl.w, dt))
-        cps = []
-        for _ in range(n_copies(nb_fb)):
-            c = {k: v.clone() for k, v in base.items()}
-            c["R"], c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["u"]), torch.empty_like(c["cf"])
-            c["ij"], c["dj"] = torch.empty((dim * dim, n), dtype=dt, device=dev), torch.empty(n, dtype=dt, device=dev)
-            cps.append(c)
-        del base
+        if want("fwdbwd"):
+            dt = torch.float32
+            nb_fb = (model.residual_mesh_bytes(dim, phys, rule, n, wl.n_vert, 4, store_geometry=True)
+                     + model.backward_bytes(dim, phys, rule, 4)) * n
+            base = dict(X=to_dev(wl.coords, torch.float64), conn=to_dev(wl.conn, torch.int32), u=to_dev(wl.u, dt),
+                        cf=to_dev(wl.coef, dt), w=to_dev(wl.w, dt))
+            cps = []
+            for _ in range(n_copies(nb_fb)):
+                c = {k: v.clone() for k, v in base.items()}
+                c["R"], c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["u"]), torch.empty_like(c["cf"])
+                c["ij"], c["dj"] = torch.empty((dim * dim, n), dtype=dt, device=dev), torch.empty(n, dtype=dt, device=dev)
+                cps.append(c)
+            del base
 
-        def fwd_bwd(c):
-            api.fem_integrate_residual_mesh(dim, phys, rule, c["X"], c["conn"], c["u"], c["cf"], out=c["R"],
-                                            inv_j=c["ij"], det_j=c["dj"])
-            api.fem_integrate_residual_backward(dim, phys, rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
-                                                du=c["du"], dcoef=c["dc"])
-        _, ms = timed_graph(fwd_bwd, cps, 20, 1)
-        for c in cps:
-            c["plan"] = api.MeshPlan(c["conn"], wl.n_vert)
+            def fwd_bwd(c):
+                api.fem_integrate_residual_mesh(dim, phys, rule, c["X"], c["conn"], c["u"], c["cf"], out=c["R"],
+                                                inv_j=c["ij"], det_j=c["dj"])
+                api.fem_integrate_residual_backward(dim, phys, rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
+                                                    du=c["du"], dcoef=c["dc"])
+            _, ms = timed_graph(fwd_bwd, cps, 20, 1)
+            for c in cps:
+                c["plan"] = api.MeshPlan(c["conn"], wl.n_vert)
 
-        def fwd_bwd_planned(c):
-            c["plan"].integrate(phys, rule, c["X"], c["u"], c["cf"], out=c["R"], inv_j=c["ij"], det_j=c["dj"])
-            api.fem_integrate_residual_backward(dim, phys, rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
-                                                du=c["du"], dcoef=c["dc"])
-        _, ms_p = timed_graph(fwd_bwd_planned, cps, 20, 1)
-        for c in cps:
-            c["plan"].close()
-        extra["forward_and_adjoint_step_laplace3d_2p20_f32"] = dict(
-            us=ms * 1e3, elements_per_s=n / (ms * 1e-3), algorithmic_bytes=nb_fb, gbs=nb_fb / (ms * 1e-3) / 1e9,
-            with_mesh_plan_us=ms_p * 1e3)
-        log(f"forward (geometry stored) and adjoint, one step: {ms * 1e3:.1f} us ({n / (ms * 1e-3):.3e} elem/s, "
-            f"{nb_fb / (ms * 1e-3) / 1e9:.0f} GB/s); with a mesh plan {ms_p * 1e3:.1f} us")
-        del cps
+            def fwd_bwd_planned(c):
+                c["plan"].integrate(phys, rule, c["X"], c["u"], c["cf"], out=c["R"], inv_j=c["ij"], det_j=c["dj"])
+                api.fem_integrate_residual_backward(dim, phys, rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
+                                                    du=c["du"], dcoef=c["dc"])
+            _, ms_p = timed_graph(fwd_bwd_planned, cps, 20, 1)
+            for c in cps:
+                c["plan"].close()
+            extra["forward_and_adjoint_step_laplace3d_2p20_f32"] = dict(
+                us=ms * 1e3, elements_per_s=n / (ms * 1e-3), algorithmic_bytes=nb_fb, gbs=nb_fb / (ms * 1e-3) / 1e9,
+                with_mesh_plan_us=ms_p * 1e3)
+            log(f"forward (geometry stored) and adjoint, one step: {ms * 1e3:.1f} us ({n / (ms * 1e-3):.3e} elem/s, "
+                f"{nb_fb / (ms * 1e-3) / 1e9:.0f} GB/s); with a mesh plan {ms_p * 1e3:.1f} us")
+            del cps
 
         # --------------------------------------------------------- adjoint --
-        wl5 = mg.config(5)
-        dt = torch.float32
-        nb = model.backward_bytes(3, mg.LAPLACE, wl5.rule, 4) * wl5.n_elem
-        ij, dj = api.fem_geometry(to_dev(wl5.coords, torch.float64), to_dev(wl5.conn, torch.int32), dt)
-        base = dict(ij=ij, dj=dj, u=to_dev(wl5.u, dt), cf=to_dev(wl5.coef, dt), w=to_dev(wl5.w, dt))
-        cps = []
-        for _ in range(n_copies(nb)):
-            c = {k: v.clone() for k, v in base.items()}
-            c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["cf"])
-            cps.append(c)
-        del base, ij, dj
+        if want("adjoint"):
+            wl5 = mg.config(5)
+            dt = torch.float32
+            nb = model.backward_bytes(3, mg.LAPLACE, wl5.rule, 4) * wl5.n_elem
+            ij, dj = api.fem_geometry(to_dev(wl5.coords, torch.float64), to_dev(wl5.conn, torch.int32), dt)
+            base = dict(ij=ij, dj=dj, u=to_dev(wl5.u, dt), cf=to_dev(wl5.coef, dt), w=to_dev(wl5.w, dt))
+            cps = []
+            for _ in range(n_copies(nb)):
+                c = {k: v.clone() for k, v in base.items()}
+                c["du"], c["dc"] = torch.empty_like(c["u"]), torch.empty_like(c["cf"])
+                cps.append(c)
+            del base, ij, dj
 
-        def bwd(c):
-            api.fem_integrate_residual_backward(3, mg.LAPLACE, wl5.rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
-                                                du=c["du"], dcoef=c["dc"])
-        _, ms = timed_graph(bwd, cps, 20, 1)
-        us = ms * 1e3
-        extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
-                                                   elements_per_s=wl5.n_elem / (us * 1e-6),
-                                                   frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
-        log(f"adjoint: {us:.1f} us, {nb / (us * 1e-6) / 1e9:.0f} GB/s")
-        del cps, wl5
+            def bwd(c):
+                api.fem_integrate_residual_backward(3, mg.LAPLACE, wl5.rule, c["ij"], c["dj"], c["u"], c["cf"], c["w"],
+                                                    du=c["du"], dcoef=c["dc"])
+            _, ms = timed_graph(bwd, cps, 20, 1)
+            us = ms * 1e3
+            extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                                                       elements_per_s=wl5.n_elem / (us * 1e-6),
+                                                       frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+            log(f"adjoint: {us:.1f} us, {nb / (us * 1e-6) / 1e9:.0f} GB/s")
+            del cps, wl5
 
         # --------------------------------------------------------- batched --
-        t0 = time.time()
-        wls = mg.batch_workloads()
-        dt = torch.float32
-        meshes, nbytes, ntot = [], 0, 0
-        for w in wls:
-            ij, dj = api.fem_geometry(to_dev(w.coords, torch.float64), to_dev(w.conn, torch.int32), dt)
-            meshes.append(dict(dim=w.dim, physics=w.physics, rule=w.rule, inv_j=ij, det_j=dj, u=to_dev(w.u, dt),
-                               coef=to_dev(w.coef, dt), out=torch.empty(w.u.shape, dtype=dt, device=dev)))
-            nbytes += model.forward_bytes(w.dim, w.physics, w.rule, 4) * w.n_elem
-            ntot += w.n_elem
-        del wls
-        log(f"batched: {len(meshes)} meshes, {ntot} elements, {nbytes / 1e6:.0f} MB (built in {time.time() - t0:.1f}s)")
+        if want("batched"):
+            t0 = time.time()
+            wls = mg.batch_workloads()
+            dt = torch.float32
+            meshes, nbytes, ntot = [], 0, 0
+            for w in wls:
+                ij, dj = api.fem_geometry(to_dev(w.coords, torch.float64), to_dev(w.conn, torch.int32), dt)
+                meshes.append(dict(dim=w.dim, physics=w.physics, rule=w.rule, inv_j=ij, det_j=dj, u=to_dev(w.u, dt),
+                                   coef=to_dev(w.coef, dt), out=torch.empty(w.u.shape, dtype=dt, device=dev)))
+                nbytes += model.forward_bytes(w.dim, w.physics, w.rule, 4) * w.n_elem
+                ntot += w.n_elem
+            del wls
+            log(f"batched: {len(meshes)} meshes, {ntot} elements, {nbytes / 1e6:.0f} MB (built in {time.time() - t0:.1f}s)")
 
-        def separate():
-            for m in meshes:
-                api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
-                                           m["coef"], out=m["out"])
+            def separate():
+                for m in meshes:
+                    api.fem_integrate_residual(m["dim"], m["physics"], m["rule"], m["inv_j"], m["det_j"], m["u"],
+                                               m["coef"], out=m["out"])
 
-        plan = api.BatchPlan(meshes)
-        side = torch.cuda.Stream()
-        with torch.cuda.stream(side):
-            shape = plan.autotune()   # launch shape from the plan's own meshes
-            plan.capture()
-        torch.cuda.synchronize()
-
-        def timeit(fn, reps, stream=None):
-            for _ in range(3):
-                fn()
+            plan = api.BatchPlan(meshes)
+            side = torch.cuda.Stream()
+            with torch.cuda.stream(side):
+                shape = plan.autotune()   # launch shape from the plan's own meshes
+                plan.capture()
             torch.cuda.synchronize()
-            pairs = []
-            for _ in range(reps):
-                s = ev()
-                fn()
-                pairs.append((s, ev()))
-            torch.cuda.synchronize()
-            return 1e3 * sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
 
-        def replay():
-            plan.replay()
+            def timeit(fn, reps, stream=None):
+                for _ in range(3):
+                    fn()
+                torch.cuda.synchronize()
+                pairs = []
+                for _ in range(reps):
+                    s = ev()
+                    fn()
+                    pairs.append((s, ev()))
+                torch.cuda.synchronize()
+                return 1e3 * sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
 
-        sep_us = timeit(separate, 10)
-        _, sep_graph_ms = timed_graph(lambda _: separate(), [0], 5, 1)
-        run_us = timeit(plan.run, 10)
-        with torch.cuda.stream(side):
-            rep_us = timeit(replay, 10)
-        plan.close()
-        extra["batched_64_meshes_f32"] = dict(
-            n_mesh=len(meshes), n_elem=ntot, algorithmic_bytes=nbytes,
-            separate_launches_us=sep_us, separate_launches_in_a_graph_us=sep_graph_ms * 1e3,
-            persistent_launch_us=run_us, graph_replay_us=rep_us,
-            graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
-            speedup_vs_separate=sep_graph_ms * 1e3 / rep_us,
-            speedup_vs_separate_issued_from_python=sep_us / rep_us, autotuned_launch=shape,
-            note="speedup_vs_separate: the 64 single-mesh launches recorded in one graph against the one "
-                 "persistent launch; the meshes total about 0.9 GB, above the last-level cache; medians of 10")
-        log(f"batched: 64 launches {sep_us:.1f} us ({sep_graph_ms * 1e3:.1f} us as one graph), persistent "
-            f"{run_us:.1f} us, graph {rep_us:.1f} us "
-            f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s, {sep_graph_ms * 1e3 / rep_us:.2f}x the graph of 64); "
-            f"autotuned launch {shape}", always=True)
-        del meshes
+            def replay():
+                plan.replay()
+
+            sep_us = timeit(separate, 10)
+            _, sep_graph_ms = timed_graph(lambda _: separate(), [0], 5, 1)
+            run_us = timeit(plan.run, 10)
+            with torch.cuda.stream(side):
+                rep_us = timeit(replay, 10)
+            plan.close()
+            extra["batched_64_meshes_f32"] = dict(
+                n_mesh=len(meshes), n_elem=ntot, algorithmic_bytes=nbytes,
+                separate_launches_us=sep_us, separate_launches_in_a_graph_us=sep_graph_ms * 1e3,
+                persistent_launch_us=run_us, graph_replay_us=rep_us,
+                graph_replay_gbs=nbytes / (rep_us * 1e-6) / 1e9, graph_replay_elements_per_s=ntot / (rep_us * 1e-6),
+                speedup_vs_separate=sep_graph_ms * 1e3 / rep_us,
+                speedup_vs_separate_issued_from_python=sep_us / rep_us, autotuned_launch=shape,
+                note="speedup_vs_separate: the 64 single-mesh launches recorded in one graph against the one "
+                     "persistent launch; the meshes total about 0.9 GB, above the last-level cache; medians of 10")
+            log(f"batched: 64 launches {sep_us:.1f} us ({sep_graph_ms * 1e3:.1f} us as one graph), persistent "
+                f"{run_us:.1f} us, graph {rep_us:.1f} us "
+                f"({nbytes / (rep_us * 1e-6) / 1e9:.0f} GB/s, {sep_graph_ms * 1e3 / rep_us:.2f}x the graph of 64); "
+                f"autotuned launch {shape}", always=True)
+            del meshes
         result["extra"] = extra
 
     if not args.quick and not args.no_cpu:

@@ -113,7 +113,15 @@ enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
  *                          four lanes share an element, lane r being point r
  *                          and then basis function r. */
 enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1, FEM_STRATEGY_MFMA = 2,
-                    FEM_STRATEGY_SHUFFLE = 3 };
+                    FEM_STRATEGY_SHUFFLE = 3, FEM_STRATEGY_DEDUP = 4 };
+
+/*  FEM_STRATEGY_DEDUP      (FEM_OP_RESIDUAL_MESH only; vec 1, two or four
+ *                          waves per workgroup) each wave
+ *                          deduplicates its 64-element tile's vertex indices
+ *                          in an LDS hash table and gathers every distinct
+ *                          vertex record once, then reads the elements'
+ *                          vertices from LDS; bitwise equal to the lane
+ *                          strategy. */
 
 /* Operations; each has its own launch configuration (see fem_tuning). */
 enum fem_op {
@@ -429,7 +437,7 @@ fem_status fem_batch_run_noalloc(const fem_mesh_desc* meshes, int n_mesh, int dt
 /* ------------------------------------------------------------------ */
 
 typedef struct fem_tuning {
-    int strategy;        /* enum fem_strategy; FEM_STRATEGY_TRANSPOSE only for FEM_OP_RESIDUAL */
+    int strategy;        /* enum fem_strategy (each strategy names the operations it serves) */
     int vec;             /* elements per lane: RESIDUAL and BACKWARD read 1, 2 or 4
                           * consecutive elements per vector access; GEOMETRY,
                           * RESIDUAL_MESH and RESIDUAL_GATHER (1, 2, 4) give each lane that

@@ -182,7 +182,8 @@ static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              ((t.strategy == FEM_STRATEGY_TRANSPOSE || t.strategy == FEM_STRATEGY_SHUFFLE) &&
                               op == FEM_OP_RESIDUAL) ||
-                             (t.strategy == FEM_STRATEGY_MFMA && op == FEM_OP_RESIDUAL_P3);
+                             (t.strategy == FEM_STRATEGY_MFMA && op == FEM_OP_RESIDUAL_P3) ||
+                             (t.strategy == FEM_STRATEGY_DEDUP && op == FEM_OP_RESIDUAL_MESH && t.vec == 1);
     const bool one = one_per_lane_op(op);
     const bool vec_ok = one ? t.vec == 1 : (t.vec == 1 || t.vec == 2 || t.vec == 4);
     const bool waves_ok = t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4 ||
@@ -278,6 +279,10 @@ fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, con
         set_error("fem_set_tuning: the quad-permutation strategy covers scalar fields (Laplacian, mass)");
         return FEM_ERR_UNSUPPORTED;
     }
+    if (t->strategy == FEM_STRATEGY_DEDUP && t->waves_per_block != 2 && t->waves_per_block != 4) {
+        set_error("fem_set_tuning: the deduplicating strategy runs two or four waves per workgroup");
+        return FEM_ERR_UNSUPPORTED;
+    }
     if (t->strategy == FEM_STRATEGY_MFMA && !mfma_available(op, dim, physics)) {
         set_error("fem_set_tuning: the matrix-core strategy covers P3 tetrahedra with the Laplacian or elasticity");
         return FEM_ERR_UNSUPPORTED;
@@ -355,7 +360,8 @@ fem_status fem_integrate_residual_mesh(int dim, int physics, int rule, int coef_
     const fem_tuning t = get_tuning(FEM_OP_RESIDUAL_MESH, dim, physics, rule, dtype);
     MeshArgs a{n_elem, n_vert, coords, conn, u, coef, elem_vec, inv_j, det_j, counts};
     Launch l = make_tile_launch(t, n_elem, static_cast<hipStream_t>(stream));
-    hipError_t e = launch_residual_mesh(dim, physics, rule, coef_space, dtype, a, l);
+    hipError_t e = t.strategy == FEM_STRATEGY_DEDUP ? launch_residual_dedup(dim, physics, rule, coef_space, dtype, a, l)
+                                                    : launch_residual_mesh(dim, physics, rule, coef_space, dtype, a, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_integrate_residual_mesh launch");
 }
 

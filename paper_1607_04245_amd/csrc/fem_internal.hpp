@@ -69,6 +69,10 @@ hipError_t launch_residual_shuffle(int dim, int phys, int rule, int space, int d
                                    const Launch& l);
 hipError_t launch_residual_mesh(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                 const Launch& l);
+// The fused from-mesh kernel with per-wave run-time vertex deduplication in
+// LDS (residual_dedup.hip); one element per lane, block = 64 x waves (2 or 4).
+hipError_t launch_residual_dedup(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
+                                 const Launch& l);
 // u and a P1 coefficient per vertex (MeshArgs.u, MeshArgs.coef), gathered.
 hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                   const Launch& l);

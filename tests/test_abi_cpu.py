@@ -167,6 +167,33 @@ def test_batch_plan_validation(lib):
     lib.fem_batch_plan_destroy(None)
 
 
+def test_dedup_strategy_availability(lib):
+    """Run-time vertex deduplication serves the fused from-mesh residual
+    only, one element per lane."""
+    M, R = N.OP_RESIDUAL_MESH, N.OP_RESIDUAL
+    saved = N.fem_tuning()
+    assert lib.fem_get_tuning(M, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(saved)) == N.FEM_OK
+    try:
+        for dim, rule in ((2, mg.RULE_TRI3), (3, mg.RULE_TET4)):
+            for waves in (1, 8):
+                t = N.fem_tuning(N.STRATEGY_DEDUP, 1, waves, 0)
+                assert lib.fem_set_tuning(M, dim, mg.LAPLACE, rule, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+            for waves in (2, 4):
+                t = N.fem_tuning(N.STRATEGY_DEDUP, 1, waves, 0)
+                assert lib.fem_set_tuning(M, dim, mg.LAPLACE, rule, N.F32, ctypes.byref(t)) == N.FEM_OK
+                back = N.fem_tuning()
+                assert lib.fem_get_tuning(M, dim, mg.LAPLACE, rule, N.F32, ctypes.byref(back)) == N.FEM_OK
+                assert (back.strategy, back.vec, back.waves_per_block) == (N.STRATEGY_DEDUP, 1, waves)
+        for op in (R, N.OP_GEOMETRY, N.OP_BACKWARD, N.OP_RESIDUAL_GATHER):
+            t = N.fem_tuning(N.STRATEGY_DEDUP, 1, 4, 0)
+            assert lib.fem_set_tuning(op, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
+        t = N.fem_tuning(N.STRATEGY_DEDUP, 2, 4, 0)
+        assert lib.fem_set_tuning(M, 3, mg.LAPLACE, mg.RULE_TET4, N.F32, ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
+    finally:
+        for dim, rule in ((2, mg.RULE_TRI3), (3, mg.RULE_TET4)):
+            assert lib.fem_set_tuning(M, dim, mg.LAPLACE, rule, N.F32, ctypes.byref(saved)) == N.FEM_OK
+
+
 def test_batch_noalloc_validation(lib):
     """The no-allocation batched launch rejects bad input before any HIP call."""
     run = lib.fem_batch_run_noalloc
