@@ -157,6 +157,22 @@ template <typename Real> struct Acc;
 template <> struct Acc<float> { typedef f32x4 T; };
 template <> struct Acc<double> { typedef f64x4 T; };
 
+// Element data accesses. A wave touches 16 consecutive elements of a row
+// per access: 64 bytes in FP32, half a 128-byte cache line whose other half
+// a neighbouring wave touches, so FP32 uses ordinary (cached) accesses and
+// the other half comes from L2 (streaming accesses measured 1.3-1.9x the
+// row bytes fetched from HBM); FP64 rows fill whole lines and stream.
+template <typename Real>
+__device__ __forceinline__ Real ld(const Real* p) {
+    if constexpr (sizeof(Real) == 4) return *p;
+    else return __builtin_nontemporal_load(p);
+}
+template <typename Real>
+__device__ __forceinline__ void st(Real v, Real* p) {
+    if constexpr (sizeof(Real) == 4) *p = v;
+    else __builtin_nontemporal_store(v, p);
+}
+
 // D = A B + C for one 16x4 by 4x16 step (lane layout above).
 __device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -210,26 +226,26 @@ residual_p3_mfma_kernel(int64_t n, int space, const Real* __restrict__ inv_j, co
         // coefficients at this lane's points
         Real ij[9];
 #pragma unroll
-        for (int f = 0; f < 9; ++f) ij[f] = __builtin_nontemporal_load(inv_j + f * n + ec);
-        const Real adj = fabs(__builtin_nontemporal_load(det_j + ec));
+        for (int f = 0; f < 9; ++f) ij[f] = ld(inv_j + f * n + ec);
+        const Real adj = fabs(ld(det_j + ec));
         Real ub[5][NC];
 #pragma unroll
         for (int p = 0; p < 5; ++p)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ub[p][c] = __builtin_nontemporal_load(u + (int64_t)(urow[p] * NC + c) * n + ec);
+            for (int c = 0; c < NC; ++c) ub[p][c] = ld(u + (int64_t)(urow[p] * NC + c) * n + ec);
         Real a[NCOEF][3];
         if (space == FEM_COEF_QUAD) {
 #pragma unroll
             for (int m = 0; m < NCOEF; ++m)
 #pragma unroll
                 for (int p = 0; p < 3; ++p)
-                    a[m][p] = __builtin_nontemporal_load(coef + (int64_t)(m * E::NQ + qrow[p]) * n + ec);
+                    a[m][p] = ld(coef + (int64_t)(m * E::NQ + qrow[p]) * n + ec);
         } else if (space == FEM_COEF_P1) {
 #pragma unroll
             for (int m = 0; m < NCOEF; ++m) {
                 Real cv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) cv[v] = __builtin_nontemporal_load(coef + (int64_t)(m * 4 + v) * n + ec);
+                for (int v = 0; v < 4; ++v) cv[v] = ld(coef + (int64_t)(m * 4 + v) * n + ec);
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
                     const Real* lam = pts<Real>().lam[g][p];
@@ -242,7 +258,7 @@ residual_p3_mfma_kernel(int64_t n, int space, const Real* __restrict__ inv_j, co
         } else {
 #pragma unroll
             for (int m = 0; m < NCOEF; ++m) {
-                const Real cc = __builtin_nontemporal_load(coef + (int64_t)m * n + ec);
+                const Real cc = ld(coef + (int64_t)m * n + ec);
 #pragma unroll
                 for (int p = 0; p < 3; ++p) a[m][p] = cc;
             }
@@ -327,11 +343,11 @@ residual_p3_mfma_kernel(int64_t n, int space, const Real* __restrict__ inv_j, co
             if (valid) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    __builtin_nontemporal_store(r0[r], out + (int64_t)(orow0[r] * NC + c) * n + e);
+                    st(r0[r], out + (int64_t)(orow0[r] * NC + c) * n + e);
                 if (g == 0) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        __builtin_nontemporal_store(r1[r], out + (int64_t)(cls(1, r) * NC + c) * n + e);
+                        st(r1[r], out + (int64_t)(cls(1, r) * NC + c) * n + e);
                 }
             }
         }
