@@ -418,9 +418,11 @@ void fem_batch_plan_destroy(fem_batch_plan* plan);
  * persistent launch as fem_batch_run, with bitwise-equal element vectors,
  * without a plan. The descriptor table goes to a fixed device array inside
  * the library (one per GPU, FEM_BATCH_NOALLOC_MAX_MESHES entries, about
- * 72 KB, held until the process ends) by a stream-ordered copy from host
- * memory, and each workgroup finds its mesh by a binary search over that
- * table, so the call allocates nothing and needs no tile table. Meshes, dtype
+ * 72 KB, held until the process ends), written on `stream` by small kernels
+ * that receive the descriptors as kernel arguments (32 per launch), and each
+ * workgroup finds its mesh by a binary search over that table, so the call
+ * allocates nothing, copies nothing from host memory and needs no tile
+ * table. Meshes, dtype
  * and arrays as fem_batch_plan_create; launch shape as
  * fem_batch_plan_set_launch (waves per workgroup 1, 2, 4, 8; workgroups per
  * compute unit 0..64). More than FEM_BATCH_NOALLOC_MAX_MESHES meshes give

@@ -172,8 +172,21 @@ static int64_t assign_tiles(BatchMesh* m, int n, int tile) {
     return t;
 }
 
-// Checks the caller's mesh list and writes the device descriptor of every
-// non-empty mesh to out (room for n_mesh); *n_out = their number.
+// Device descriptor of one caller mesh (tile range left to assign_tiles).
+static void make_descriptor(const fem_mesh_desc& d, BatchMesh& m) {
+    std::memset(&m, 0, sizeof m);
+    m.type = type_code(d.dim, d.physics, d.rule, d.coef_space);
+    m.n_elem = d.n_elem;
+    m.inv_j = d.inv_j;
+    m.det_j = d.det_j;
+    m.u = d.u;
+    m.coef = d.coef;
+    m.out = d.elem_vec;
+}
+
+// Checks the caller's mesh list and, when out is not NULL, writes the
+// device descriptor of every non-empty mesh to out (room for n_mesh);
+// *n_out = their number, *total_out = their elements.
 static fem_status fill_descriptors(const char* fn, const fem_mesh_desc* meshes, int n_mesh, BatchMesh* out,
                                    int* n_out, int64_t* total_out) {
     int k = 0;
@@ -196,15 +209,8 @@ static fem_status fill_descriptors(const char* fn, const fem_mesh_desc* meshes, 
             set_error("%s: mesh %d has a NULL array", fn, i);
             return FEM_ERR_INVALID_ARG;
         }
-        BatchMesh& m = out[k++];
-        std::memset(&m, 0, sizeof m);
-        m.type = type_code(d.dim, d.physics, d.rule, d.coef_space);
-        m.n_elem = d.n_elem;
-        m.inv_j = d.inv_j;
-        m.det_j = d.det_j;
-        m.u = d.u;
-        m.coef = d.coef;
-        m.out = d.elem_vec;
+        if (out) make_descriptor(d, out[k]);
+        ++k;
         total += d.n_elem;
     }
     *n_out = k;
@@ -254,6 +260,19 @@ static fem_status plan_build_table(fem_batch_plan* p) {
 // each GPU's copy is looked up once per device (hipGetSymbolAddress, with
 // that device current) and used everywhere instead.
 static __device__ __align__(256) BatchMesh scratch[FEM_BATCH_NOALLOC_MAX_MESHES];
+
+// Descriptors travel to the device array as kernel arguments (a chunk per
+// launch, copied by the runtime when the launch is enqueued), so no host
+// buffer has to outlive the call and nothing is copied from pageable memory.
+constexpr int kDescChunk = 32;   // 32 x 72 bytes of kernel arguments
+struct DescChunk {
+    BatchMesh m[kDescChunk];
+};
+
+__global__ void __launch_bounds__(kDescChunk) store_descriptors_kernel(BatchMesh* table, DescChunk chunk, int k) {
+    const int i = threadIdx.x;
+    if (i < k) table[i] = chunk.m[i];
+}
 
 static std::mutex g_scratch_mu;
 static BatchMesh* g_scratch_ptr[64] = {};
@@ -389,20 +408,35 @@ fem_status fem_batch_run_noalloc(const fem_mesh_desc* meshes, int n_mesh, int dt
     }
     if (dtype != FEM_F32 && dtype != FEM_F64) { set_error("%s: unknown dtype %d", fn, dtype); return FEM_ERR_UNSUPPORTED; }
     if (!valid_batch_shape(waves_per_block, blocks_per_cu)) { set_error("%s: invalid launch shape", fn); return FEM_ERR_INVALID_ARG; }
-    // host staging of the table: per thread, fixed size, no allocation per call
-    static thread_local BatchMesh host_table[FEM_BATCH_NOALLOC_MAX_MESHES];
+    // every mesh is checked before the first HIP call
     int n_used = 0;
     int64_t total = 0;
-    fem_status st = fill_descriptors(fn, meshes, n_mesh, host_table, &n_used, &total);
+    fem_status st = fill_descriptors(fn, meshes, n_mesh, nullptr, &n_used, &total);
     if (st) return st;
     if (n_used == 0) return FEM_OK;
-    const int64_t n_tiles = assign_tiles(host_table, n_used, 64 * waves_per_block);
     BatchMesh* table = scratch_table(fn);
     if (!table) return FEM_ERR_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // stream-ordered upload; from pageable memory the call returns once the
-    // host table has been consumed, so the next call may overwrite it
-    hipError_t e = hipMemcpyAsync(table, host_table, (size_t)n_used * sizeof(BatchMesh), hipMemcpyHostToDevice, s);
+    // the table goes up in stream-ordered launches of kDescChunk descriptors
+    DescChunk chunk;
+    const int tile = 64 * waves_per_block;
+    int k = 0, sent = 0;
+    int64_t n_tiles = 0;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n_mesh && e == hipSuccess; ++i) {
+        if (meshes[i].n_elem == 0) continue;
+        BatchMesh& m = chunk.m[k++];
+        make_descriptor(meshes[i], m);
+        m.tile_begin = n_tiles;
+        n_tiles += (m.n_elem + tile - 1) / tile;
+        m.tile_end = n_tiles;
+        if (k == kDescChunk || sent + k == n_used) {
+            hipLaunchKernelGGL(store_descriptors_kernel, dim3(1), dim3(kDescChunk), 0, s, table + sent, chunk, k);
+            e = hipGetLastError();
+            sent += k;
+            k = 0;
+        }
+    }
     if (e != hipSuccess) return hip_fail(e, "fem_batch_run_noalloc: descriptor upload");
     const Launch l = batch_shape(n_tiles, waves_per_block, blocks_per_cu, s);
     e = launch_batch(dtype, table, n_used, nullptr, n_tiles, l.block, l);

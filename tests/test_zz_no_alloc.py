@@ -6,6 +6,7 @@ and at several launch shapes. The first call's outputs are checked to stay
 untouched by the second, and one mesh of each call against the FP64 oracle."""
 import ctypes
 
+import numpy as np
 import pytest
 import torch
 
@@ -95,6 +96,25 @@ def test_noalloc_matches_plan_two_calls(dtype, waves, bpc):
     for wl, g in ((wl1[4], got1[4]), (wl2[0], got2[0])):
         ref, ref_abs, _, _ = oracle_reference(wl, dtype)
         assert_close(g.cpu().numpy(), ref, ref_abs, dtype, f"noalloc {wl.name}")
+
+
+def test_noalloc_many_meshes_chunked_upload():
+    """More meshes than one descriptor upload carries (32): 70 meshes, some
+    empty, against the plan; then 33 meshes in a second call."""
+    dtype = torch.float32
+    rng = np.random.default_rng(mg.BASE_SEED + 310)
+    sizes = [int(x) for x in rng.integers(0, 3000, size=70)]
+    sizes[5] = sizes[40] = 0
+    meshes, wls = _meshes(dtype, sizes, 600)
+    ref = _plan_outputs(meshes, dtype, 4, 0)
+    got = _noalloc(meshes, dtype, 4, 0)
+    for g, r, wl in zip(got, ref, wls):
+        assert torch.equal(g, r), f"{wl.name} ({wl.n_elem} elements) differs from the plan"
+    fewer = meshes[:33]
+    ref2 = _plan_outputs(fewer, dtype, 2, 4)
+    got2 = _noalloc(fewer, dtype, 2, 4)
+    for g, r in zip(got2, ref2):
+        assert torch.equal(g, r)
 
 
 def test_noalloc_python_binding_and_limit():
