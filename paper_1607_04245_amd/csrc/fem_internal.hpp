@@ -76,7 +76,7 @@ hipError_t launch_residual_dedup(int dim, int phys, int rule, int space, int dty
 // u and a P1 coefficient per vertex (MeshArgs.u, MeshArgs.coef), gathered.
 hipError_t launch_residual_gather(int dim, int phys, int rule, int space, int dtype, const MeshArgs& a,
                                   const Launch& l);
-// Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
+// Third-order elements (residual_p3.hip), degree-4 rules (TRI6, TET11).
 hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
 // P3 tetrahedra, Laplacian or elasticity, with the transposition on the
 // matrix cores (residual_p3_mfma.hip); four lanes per element, a wave takes
@@ -84,6 +84,7 @@ hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const Res
 hipError_t launch_residual_p3_mfma(int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
 hipError_t launch_backward_p3(int dim, int phys, int space, int dtype, const BackwardArgs& a, const Launch& l);
 hipError_t launch_jacobian_p3(int dim, int phys, int space, int dtype, const JacobianArgs& a, const Launch& l);
+// Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
 hipError_t launch_residual_p2(int dim, int phys, int rule, int space, int dtype, const ResidualArgs& a,
                               const Launch& l);
 hipError_t launch_backward_p2(int dim, int phys, int rule, int space, int dtype, const BackwardArgs& a,

@@ -109,6 +109,30 @@ def test_transpose_coefficient_spaces(dim, phys, space):
     assert_close(R, ref, ref_abs, dtype, f"transpose {dim}D phys {phys} space {space}")
 
 
+@pytest.mark.parametrize("cfg", [2, "3a", "3b"])
+def test_transpositions_full_size(cfg):
+    """Both transposition forms at the benchmark sizes (the 2^20-tet
+    Laplacian, 2^22-triangle and 2^21-tet elasticity; the quad-permutation
+    form only for the scalar field) against the oracle, FP32 and FP64, at the
+    launch shapes the benchmark times."""
+    wl = mg.config(cfg)
+    for dtype in DTYPES:
+        ref, ref_abs, _, _ = oracle_reference(wl, dtype)
+        ij, dj = geometry(wl, dtype)
+        u, cf = dev(wl.u, dtype), dev(wl.coef, dtype)
+        forms = [(N.STRATEGY_TRANSPOSE, 1, 0), (N.STRATEGY_TRANSPOSE, 4, 8)]
+        if wl.physics != mg.ELASTICITY:
+            forms += [(N.STRATEGY_SHUFFLE, 8, 0), (N.STRATEGY_SHUFFLE, 4, 0)]
+        for strategy, waves, bpc in forms:
+            api.fem_set_tuning(wl.dim, wl.physics, wl.rule, dtype, strategy=strategy, vec=1,
+                               waves_per_block=waves, blocks_per_cu=bpc)
+            R = api.fem_integrate_residual(wl.dim, wl.physics, wl.rule, ij, dj, u, cf).cpu().numpy()
+            mx, agg = assert_close(R, ref, ref_abs, dtype, f"strategy {strategy} config {cfg}")
+            print(f"strategy {strategy} ({waves}, {bpc}) config {cfg} {dtype}: scaled max {mx:.2e} "
+                  f"aggregate {agg:.2e}", flush=True)
+        del ij, dj, u, cf
+
+
 def test_shuffle_refused_for_elasticity():
     with pytest.raises(N.FemError) as ei:
         api.fem_set_tuning(3, mg.ELASTICITY, mg.RULE_TET4, torch.float32, strategy=N.STRATEGY_SHUFFLE)
