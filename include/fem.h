@@ -466,7 +466,10 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
                         const char* cache_path);
 /* Load tuned configurations from a JSON cache written by fem_autotune.
  * Returns FEM_ERR_NO_TUNING if the file is missing or holds no entry for
- * this device's architecture (defaults stay in force). */
+ * this device's architecture (defaults stay in force). The library also
+ * loads the cache named by the environment variable FEM_TUNE_CACHE, once,
+ * before its first tuning lookup or change (explicit settings made later
+ * take precedence; a missing or unusable file leaves the defaults). */
 fem_status fem_load_tuning(const char* cache_path);
 
 /* ------------------------------------------------------------------ */

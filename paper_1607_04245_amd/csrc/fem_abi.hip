@@ -6,8 +6,10 @@
 // synchronize.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -192,13 +194,36 @@ static bool valid_tuning(int op, const fem_tuning& t) {
            t.blocks_per_cu >= 0 && t.blocks_per_cu <= 64;
 }
 
+// The tuning cache named by the FEM_TUNE_CACHE environment variable is loaded
+// once, before the first lookup or change of a tuning, so that explicit
+// settings made afterwards take precedence. A missing file, or one without
+// entries for this device, leaves the defaults (and the caller's error
+// message) untouched. Lookups from other threads while the file is being
+// read see the defaults.
+static std::atomic<int> g_env_cache{0};   // 0 not loaded, 1 loading, 2 done
+
+static void load_env_cache() {
+    if (g_env_cache.load(std::memory_order_acquire) == 2) return;
+    int expected = 0;
+    if (!g_env_cache.compare_exchange_strong(expected, 1)) return;   // loaded or being loaded
+    const char* path = std::getenv("FEM_TUNE_CACHE");
+    if (path && *path) {
+        const std::string saved = g_error;
+        (void)fem_load_tuning(path);   // its fem_set_tuning calls return here at once
+        g_error = saved;
+    }
+    g_env_cache.store(2, std::memory_order_release);
+}
+
 fem_tuning get_tuning(int op, int dim, int phys, int rule, int dtype) {
+    load_env_cache();
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(tune_key(op, dim, phys, rule, dtype));
     return it != g_tune.end() ? it->second : default_tuning(op, dim, phys, rule, dtype);
 }
 
 void put_tuning(int op, int dim, int phys, int rule, int dtype, const fem_tuning& t) {
+    load_env_cache();
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[tune_key(op, dim, phys, rule, dtype)] = t;
 }

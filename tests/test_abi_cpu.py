@@ -450,3 +450,45 @@ def test_header_is_plain_c(tmp_path, std):
     r = subprocess.run(["gcc", f"-std={std}", "-Wall", "-Wextra", "-pedantic", "-Werror", f"-I{inc}", "-fsyntax-only",
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_no_device_gives_hip_error_not_a_crash(lib):
+    """On a host without a GPU a call that passes validation fails with
+    FEM_ERR_HIP and the runtime's message; nothing is launched. (Skipped where
+    a GPU is visible: there the placeholder pointers would be dereferenced.)"""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible; this case needs a host without one")
+    ptr = [0x1000 * (k + 1) for k in range(8)]
+    st = lib.fem_integrate_residual(3, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, N.F32, 1000, *ptr[:5], None)
+    assert st == N.FEM_ERR_HIP and "fem_integrate_residual" in N.last_error()
+    st = lib.fem_geometry(3, 1000, 500, ptr[0], ptr[1], N.F32, ptr[2], ptr[3], None, None)
+    assert st == N.FEM_ERR_HIP and "fem_geometry" in N.last_error()
+    d = (N.fem_mesh_desc * 1)()
+    d[0] = N.fem_mesh_desc(3, mg.LAPLACE, mg.RULE_TET4, N.COEF_QUAD, 10, *ptr[:5])
+    assert lib.fem_batch_run_noalloc(d, 1, N.F32, 8, 0, None) == N.FEM_ERR_HIP
+    assert "fem_batch_run_noalloc" in N.last_error()
+
+
+def test_env_tuning_cache_unusable_keeps_defaults(tmp_path):
+    """FEM_TUNE_CACHE naming a missing or malformed file leaves the default
+    tunings (compared with a fresh process without the variable) and no error."""
+    import os
+    import subprocess
+    import sys
+    root = pathlib.Path(__file__).resolve().parents[1]
+    code = ("from paper_1607_04245_amd import api, _native as N, meshgen as mg; "
+            "print([api.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, 0, op=o) for o in range(5)], "
+            "repr(N.last_error()))")
+    def run(extra):
+        env = {k: v for k, v in os.environ.items() if k != "FEM_TUNE_CACHE"}
+        env.update(extra)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300,
+                           cwd=str(root))
+        assert r.returncode == 0, r.stderr
+        return r.stdout.strip().splitlines()[-1]
+    bad = tmp_path / "bad.json"
+    bad.write_text("{ not json")
+    base = run({})
+    assert run({"FEM_TUNE_CACHE": str(tmp_path / "missing.json")}) == base
+    assert run({"FEM_TUNE_CACHE": str(bad)}) == base

@@ -1,7 +1,12 @@
 """GPU: the thread-transposition strategy, the batched persistent launch and
 its HIP graph, and the autotuner, each against the FP64 oracle and against
 the lane kernel."""
+import ast
 import json
+import os
+import pathlib
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -13,6 +18,7 @@ from paper_1607_04245_amd import _native as N
 from _parity import assert_close, dev, oracle_reference
 
 pytestmark = pytest.mark.gpu
+ROOT = pathlib.Path(__file__).resolve().parents[1]
 
 DTYPES = [torch.float32, torch.float64]
 KINDS = [(2, mg.LAPLACE), (3, mg.LAPLACE), (2, mg.ELASTICITY), (3, mg.ELASTICITY), (2, mg.MASS), (3, mg.MASS)]
@@ -244,7 +250,8 @@ def test_batch_plan_argument_errors():
 def test_autotune_picks_a_valid_configuration(tmp_path):
     cache = tmp_path / "tune.json"
     t = api.fem_autotune(3, mg.LAPLACE, mg.RULE_TET4, torch.float32, 1 << 16, str(cache))
-    assert t["strategy"] in (0, 1) and t["vec"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4, 8)
+    assert t["strategy"] in (N.STRATEGY_LANE, N.STRATEGY_TRANSPOSE, N.STRATEGY_SHUFFLE)
+    assert t["vec"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4, 8)
     data = json.loads(cache.read_text())
     (entry,) = data["entries"]
     assert entry["arch"].startswith("gfx") and entry["op"] == 0 and entry["dim"] == 3 and entry["us"] > 0
@@ -264,6 +271,13 @@ def test_autotune_picks_a_valid_configuration(tmp_path):
                                    dev(wl.coef, torch.float32)).cpu().numpy()
     ref, ref_abs, _, _ = oracle_reference(wl, torch.float32)
     assert_close(R, ref, ref_abs, torch.float32, "tuned")
+    # a fresh process loads the cache named by FEM_TUNE_CACHE before its first lookup
+    code = ("import torch; from paper_1607_04245_amd import api, meshgen as mg; "
+            "print(api.fem_get_tuning(3, mg.LAPLACE, mg.RULE_TET4, torch.float32))")
+    run = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, FEM_TUNE_CACHE=str(cache)),
+                         capture_output=True, text=True, timeout=300, cwd=str(ROOT))
+    assert run.returncode == 0, run.stderr
+    assert ast.literal_eval(run.stdout.strip().splitlines()[-1]) == t
 
 
 # ------------------------------------------------ fused geometry + residual --
