@@ -34,6 +34,7 @@
 // back flux of every point, which it sums in point order.
 #include "fem_device.hpp"
 #include "fem_internal.hpp"
+#include "quad_dpp.hpp"
 
 namespace femq {
 
@@ -234,30 +235,6 @@ static hipError_t launch_tt(const ResidualArgs& a, const Launch& l) {
 }
 
 // ----------------------------------------------------------- cross-lane --
-
-// Value of lane (quad base + k) in every lane of the quad: a DPP quad
-// permutation, no LDS.
-template <int K>
-__device__ __forceinline__ float quad_bcast(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), K * 0x55, 0xF, 0xF, false));
-}
-template <int K>
-__device__ __forceinline__ double quad_bcast(double x) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, K * 0x55, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), K * 0x55, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-// Every lane of the quad receives the values x of lanes 0..N-1 in out[0..N-1].
-template <int N, typename Real, int M>
-__device__ __forceinline__ void quad_gather(Real x, Real (&out)[M]) {
-    static_assert(N <= M && N <= 4, "at most the quad's four lanes");
-    if constexpr (N > 0) out[0] = quad_bcast<0>(x);
-    if constexpr (N > 1) out[1] = quad_bcast<1>(x);
-    if constexpr (N > 2) out[2] = quad_bcast<2>(x);
-    if constexpr (N > 3) out[3] = quad_bcast<3>(x);
-}
 
 template <int DIM, int PHYS, int RULE, typename Real>
 __global__ void __launch_bounds__(512)
