@@ -261,12 +261,29 @@ def main():
         _, ms = timed_graph(lambda p: api.fem_stream_copy(p[0], p[1]), pairs, reps, 1)
         return 2 * nbytes / (ms * 1e-3) / 1e9, ms * 1e3
 
+    def rows_us(n_cols, n_in, n_out, dt, reps):
+        """fem_stream_rows over the row structure of a kernel (n_in rows of
+        n_cols words read, n_out written), rotated like the kernel's inputs."""
+        word = 4 if dt == torch.float32 else 8
+        k = n_copies((n_in + n_out) * n_cols * word)
+        pairs = [(torch.ones(n_in, n_cols, dtype=dt, device=dev), torch.empty(n_out, n_cols, dtype=dt, device=dev))
+                 for _ in range(k)]
+        _, ms = timed_graph(lambda p: api.fem_stream_rows(p[0], p[1]), pairs, reps, 1)
+        del pairs
+        return ms * 1e3
+
     big_gbs, big_us = copy_gbs(2 << 30, 10)
     same_gbs, same_us = copy_gbs(int(dk["algorithmic_bytes"] // 2) // 16 * 16, 20)
     roofline["achievable_gbs"] = big_gbs
     roofline["frac_of_achievable"] = dk["gbs"] / big_gbs
     roofline["achievable_gbs_same_bytes"] = same_gbs
     log(f"copy: {big_gbs:.0f} GB/s on 2 GiB, {same_gbs:.0f} GB/s at the fused kernel's byte count", always=True)
+    # the integrate-only kernel's rows (inverse Jacobian, det J, closure and
+    # coefficient rows in; element-vector rows out) streamed without arithmetic
+    nbt = api.n_basis(dim) * api.n_comp(dim, phys)
+    int_rows = (dim * dim + 1 + nbt + api.n_coef(phys) * api.n_coef_words(dim, rule), nbt)
+    kernels["fem_integrate_residual"]["stream_rows"] = list(int_rows)
+    kernels["fem_integrate_residual"]["stream_rows_us"] = rows_us(n, int_rows[0], int_rows[1], torch.float32, 20)
 
     result = {
         "metric": METRIC,
@@ -339,10 +356,14 @@ def main():
                                            out=c["R"], coef_space=space)
             _, ms = timed_graph(go, cps, reps, 1)
             us = ms * 1e3
+            r_in = sum(cps[0][key].numel() for key in ("ij", "dj", "u", "cf")) // wlx.n_elem
+            r_out = cps[0]["u"].shape[0]
             del cps
+            rw = rows_us(wlx.n_elem, r_in, r_out, dt, reps)
             f = model.model_flops(wlx.dim, wlx.physics, wlx.rule)
             return dict(n_elem=wlx.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9, elements_per_s=wlx.n_elem / (us * 1e-6),
-                        model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                        model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9, frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                        stream_rows=[r_in, r_out], stream_rows_us=rw, frac_of_stream_rows=rw / us)
 
         def fused_only(wlx, dt, reps=20, space=mg.COEF_QUAD, coef=None):
             word = 4 if dt == torch.float32 else 8
@@ -664,21 +685,44 @@ def main():
                             _, msm = timed_graph(go, cps, 10, 1)
                             if mfma is None or msm * 1e3 < mfma[1]:
                                 mfma = ((waves, bpc), msm * 1e3)
+                    comp = None
+                    if wlx.dim == 3 and wlx.physics == mg.ELASTICITY:
+                        # three waves per tile, one per component, best launch shape
+                        shapes = ((1, 0), (1, 2), (1, 4), (1, 8)) + (((2, 0), (2, 2), (2, 4)) if tag == "f32" else ())
+                        for waves, bpc in shapes:
+                            api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3,
+                                               strategy=N.STRATEGY_COMPONENT, vec=1, waves_per_block=waves,
+                                               blocks_per_cu=bpc)
+                            _, msc = timed_graph(go, cps, 10, 1)
+                            if comp is None or msc * 1e3 < comp[1]:
+                                comp = ((waves, bpc), msc * 1e3)
                     api.fem_set_tuning(wlx.dim, wlx.physics, rule_p3, dt, op=N.OP_RESIDUAL_P3, **saved)
                     f = model.p3_model_flops(wlx.dim, wlx.physics, rule_p3)
                     cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 10)
+                    # the same rows streamed without arithmetic: geometry, closure
+                    # and coefficient rows in, the element-vector rows out
+                    nbt = c["u"].shape[0]
+                    r_in = sum(c[key].numel() for key in ("ij", "dj", "u", "cf")) // wlx.n_elem
+                    rw_us = rows_us(wlx.n_elem, r_in, nbt, dt, 10)
                     extra[f"{wlx.name}_p3_{tag}_integrate"] = dict(
                         n_elem=wlx.n_elem, rule=rule_p3, us=us, gbs=nb / (us * 1e-6) / 1e9,
                         elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
-                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
+                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us,
+                        stream_rows=[r_in, nbt], stream_rows_us=rw_us, frac_of_stream_rows=rw_us / us)
                     if mfma:
                         extra[f"{wlx.name}_p3_{tag}_integrate"].update(
                             mfma_us=mfma[1], mfma_shape=mfma[0], mfma_gbs=nb / (mfma[1] * 1e-6) / 1e9,
                             mfma_frac_of_copy_same_bytes=cp_us / mfma[1])
+                    if comp:
+                        extra[f"{wlx.name}_p3_{tag}_integrate"].update(
+                            component_us=comp[1], component_shape=comp[0], component_gbs=nb / (comp[1] * 1e-6) / 1e9,
+                            component_frac_of_copy_same_bytes=cp_us / comp[1])
                     log(f"{wlx.name} P3 {tag} integrate: lane kernel {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
                         f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s)"
                         + (f", matrix-core transposition {mfma[1]:.1f} us (shape {mfma[0]})" if mfma else "")
-                        + f"; copy of the same bytes {cp_us:.1f} us", always=wlx.dim == 3)
+                        + (f", component lanes {comp[1]:.1f} us (shape {comp[0]})" if comp else "")
+                        + f"; copy of the same bytes {cp_us:.1f} us, the same {r_in} + {nbt} rows streamed "
+                          f"{rw_us:.1f} us", always=wlx.dim == 3)
                     if wlx.dim == 3:
                         # the adjoint (du and dcoef) on the same inputs, w = u
                         nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
@@ -928,6 +972,9 @@ def compact(res):
                               "elements_per_s": _r(ki["elements_per_s"]), "gbs": _r(ki["gbs"]),
                               "frac": _r(ki["gbs"] / HBM_PEAK_GBS), "model_gflops": _r(ki["model_gflops"]),
                               "algorithmic_bytes_per_launch": ki["algorithmic_bytes"]}
+    if "stream_rows_us" in ki:
+        line["integrate_only"]["rows_us"] = _r(ki["stream_rows_us"])
+        line["integrate_only"]["frac_of_rows"] = _r(ki["stream_rows_us"] / ki["avg_us"])
     kg = k["fem_geometry"]
     line["geometry_only"] = {"us": _r(kg["avg_us"]), "gbs": _r(kg["gbs"]), "frac": _r(kg["gbs"] / HBM_PEAK_GBS)}
     line["two_call_step"] = {"elements_per_s": _r(res["two_call_step"]["elements_per_s"]),
@@ -943,6 +990,8 @@ def compact(res):
                      ("elasticity2d_2p22_f64_integrate", "2d_f64"), ("elasticity3d_2p21_f64_integrate", "3d_f64")):
         if key in ex:
             el[tag] = {"elements_per_s": _r(ex[key]["elements_per_s"]), "frac": _r(ex[key]["frac_of_peak"])}
+            if "frac_of_stream_rows" in ex[key]:
+                el[tag]["frac_of_rows"] = _r(ex[key]["frac_of_stream_rows"])
     if el:
         line["elasticity_integrate"] = el
     if "adjoint_laplace3d_2p21_f32" in ex:
@@ -963,6 +1012,10 @@ def compact(res):
         if key.endswith("_integrate") and "_p3_" in key and "mfma_us" in v:
             p3[key[:-len("_integrate")]] = {"lane_us": _r(v["us"]), "mfma_us": _r(v["mfma_us"]),
                                             "copy_us": _r(v["copy_same_bytes_us"])}
+            if "component_us" in v:
+                p3[key[:-len("_integrate")]]["component_us"] = _r(v["component_us"])
+            if "stream_rows_us" in v:
+                p3[key[:-len("_integrate")]]["rows_us"] = _r(v["stream_rows_us"])
     if p3:
         line["p3_transposition"] = p3
     if tt:

@@ -113,7 +113,7 @@ enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
  *                          four lanes share an element, lane r being point r
  *                          and then basis function r. */
 enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1, FEM_STRATEGY_MFMA = 2,
-                    FEM_STRATEGY_SHUFFLE = 3, FEM_STRATEGY_DEDUP = 4 };
+                    FEM_STRATEGY_SHUFFLE = 3, FEM_STRATEGY_DEDUP = 4, FEM_STRATEGY_COMPONENT = 5 };
 
 /*  FEM_STRATEGY_DEDUP      (FEM_OP_RESIDUAL_MESH only; vec 1, two or four
  *                          waves per workgroup) each wave
@@ -121,7 +121,18 @@ enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1, FEM_STRAT
  *                          in an LDS hash table and gathers every distinct
  *                          vertex record once, then reads the elements'
  *                          vertices from LDS; bitwise equal to the lane
- *                          strategy. */
+ *                          strategy.
+ *  FEM_STRATEGY_COMPONENT  (FEM_OP_RESIDUAL_P3 with 3D elasticity only; vec
+ *                          1) three waves per 64-element tile, wave c holding
+ *                          displacement component c of every element: its
+ *                          closure words, its gradient at each point and its
+ *                          output sums. The stress row of a point takes the
+ *                          trace and the paired off-diagonal gradient entries
+ *                          from the two other waves through LDS (Section 3's
+ *                          transposition, split by component).
+ *                          waves_per_block counts three-wave groups (1 or 2).
+ *                          Agrees with the lane kernel to rounding (another
+ *                          summation order). */
 
 /* Operations; each has its own launch configuration (see fem_tuning). */
 enum fem_op {
@@ -522,6 +533,21 @@ fem_status fem_restrict(int dim, int n_comp, int dtype, int64_t n_elem, int64_t 
  * multiples of 16). Used to measure the achievable HBM bandwidth and to
  * calibrate hardware byte counters. */
 fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream);
+
+/* The structure-of-arrays streaming yardstick. Reads n_in rows of n words
+ * (row r at src + r * n) and writes n_out rows (row w at dst + w * n), one
+ * lane per column: dst[w][e] = (sum over r of src[r][e]) + w, the sum taken
+ * in row order, words of dtype (FEM_F32 or FEM_F64). An element kernel
+ * reads and writes its SoA data as such rows (inverse Jacobian, det J,
+ * closure and coefficient rows in; the element-vector rows out), and the
+ * rate at which rows stream falls as their number grows; this kernel has
+ * the row structure without the arithmetic, so its time is what any kernel
+ * with the same rows needs. Both buffers are device memory owned by the
+ * caller (n_in * n and n_out * n words). Errors: FEM_ERR_UNSUPPORTED for an
+ * unknown dtype; FEM_ERR_INVALID_ARG for negative n, row counts outside
+ * 1..FEM_STREAM_ROWS_MAX or NULL buffers (n = 0 does nothing). */
+#define FEM_STREAM_ROWS_MAX 256
+fem_status fem_stream_rows(int dtype, int64_t n, int n_in, int n_out, const void* src, void* dst, void* stream);
 
 /* Message describing the last error on this thread ("" if none). */
 const char* fem_last_error(void);

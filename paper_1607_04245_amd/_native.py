@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "FEM_OK", -1: "FEM_ERR_INVALID_ARG", -2: "FEM_ERR_UNSUPPORTED
                 -3: "FEM_ERR_DEGENERATE", -4: "FEM_ERR_HIP", -5: "FEM_ERR_NO_TUNING"}
 
 F32, F64 = 0, 1
-STRATEGY_LANE, STRATEGY_TRANSPOSE, STRATEGY_MFMA, STRATEGY_SHUFFLE, STRATEGY_DEDUP = 0, 1, 2, 3, 4
+STRATEGY_LANE, STRATEGY_TRANSPOSE, STRATEGY_MFMA, STRATEGY_SHUFFLE, STRATEGY_DEDUP, STRATEGY_COMPONENT = 0, 1, 2, 3, 4, 5
 OP_RESIDUAL, OP_RESIDUAL_MESH, OP_GEOMETRY, OP_BACKWARD, OP_RESIDUAL_GATHER = 0, 1, 2, 3, 4
 OP_RESIDUAL_P2, OP_BACKWARD_P2 = 5, 6
 OP_JACOBIAN, OP_JACOBIAN_P2 = 7, 8
@@ -96,6 +96,7 @@ SIGNATURES = {
     "fem_autotune": (_i, [_i, _i, _i, _i, _i, _i64, ctypes.c_char_p]),
     "fem_load_tuning": (_i, [ctypes.c_char_p]),
     "fem_stream_copy": (_i, [_vp, _vp, _i64, _vp]),
+    "fem_stream_rows": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp]),
     "fem_last_error": (ctypes.c_char_p, []),
 }
 

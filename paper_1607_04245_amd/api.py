@@ -387,6 +387,19 @@ def fem_stream_copy(src: torch.Tensor, dst: torch.Tensor):
     N.check(N.lib().fem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream()), "fem_stream_copy")
 
 
+def fem_stream_rows(src: torch.Tensor, dst: torch.Tensor):
+    """The SoA streaming yardstick: src [n_in, n] and dst [n_out, n] of one
+    float dtype; dst[w] = src.sum(0) (in row order) + w."""
+    _need(src, "src")
+    _need(dst, "dst")
+    if src.dim() != 2 or dst.dim() != 2 or src.shape[1] != dst.shape[1] or src.dtype != dst.dtype:
+        raise ValueError("src [n_in, n] and dst [n_out, n] of one dtype")
+    if src.dtype not in _DT:
+        raise TypeError("float32 or float64")
+    N.check(N.lib().fem_stream_rows(_DT[src.dtype], src.shape[1], src.shape[0], dst.shape[0], _ptr(src), _ptr(dst),
+                                    _stream()), "fem_stream_rows")
+
+
 # ------------------------------------------------------------------ tuning --
 
 def fem_get_tuning(dim, physics, rule, dtype, op=N.OP_RESIDUAL) -> dict:

@@ -21,8 +21,8 @@ BUILD = PKG / "_build"
 LIB = PKG / "libfemq.so"
 SOURCES = ["fem_abi.hip", "geometry.hip", "residual_lane.hip", "residual_transpose.hip", "residual_mesh.hip",
            "residual_gather.hip", "backward_lane.hip", "batch.hip", "tune.hip", "assembly.hip",
-           "residual_p2.hip", "residual_p3.hip", "residual_p3_mfma.hip", "jacobian.hip", "mesh_plan.hip",
-           "residual_dedup.hip"]
+           "residual_p2.hip", "residual_p3.hip", "residual_p3_mfma.hip", "residual_p3_comp.hip", "jacobian.hip", "mesh_plan.hip",
+           "residual_dedup.hip", "stream_rows.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

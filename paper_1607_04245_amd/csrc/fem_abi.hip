@@ -158,7 +158,10 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
         return op == FEM_OP_JACOBIAN_P2 ? fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0} : fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
     }
     // P3: the 3D elements hold 20-60 closure and output words per lane, and
-    // single-wave workgroups measured fastest there; 2D streams better with four
+    // single-wave workgroups measured fastest there; 2D streams better with
+    // four. 3D elasticity splits its elements over three waves by component
+    // (measured faster than the lane kernel in FP32, level in FP64).
+    if (op == FEM_OP_RESIDUAL_P3 && dim == 3 && phys == FEM_ELASTICITY) return fem_tuning{FEM_STRATEGY_COMPONENT, 1, 1, 0};
     if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
     if (op == FEM_OP_JACOBIAN_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0};
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};
@@ -180,11 +183,17 @@ static bool mfma_available(int op, int dim, int phys) {
     return op == FEM_OP_RESIDUAL_P3 && dim == 3 && (phys == FEM_LAPLACE || phys == FEM_ELASTICITY);
 }
 
+// The component-parallel kernel exists for P3 tetrahedra with elasticity.
+static bool component_available(int op, int dim, int phys) {
+    return op == FEM_OP_RESIDUAL_P3 && dim == 3 && phys == FEM_ELASTICITY;
+}
+
 static bool valid_tuning(int op, const fem_tuning& t) {
     const bool strategy_ok = t.strategy == FEM_STRATEGY_LANE ||
                              ((t.strategy == FEM_STRATEGY_TRANSPOSE || t.strategy == FEM_STRATEGY_SHUFFLE) &&
                               op == FEM_OP_RESIDUAL) ||
-                             (t.strategy == FEM_STRATEGY_MFMA && op == FEM_OP_RESIDUAL_P3) ||
+                             ((t.strategy == FEM_STRATEGY_MFMA || t.strategy == FEM_STRATEGY_COMPONENT) &&
+                              op == FEM_OP_RESIDUAL_P3) ||
                              (t.strategy == FEM_STRATEGY_DEDUP && op == FEM_OP_RESIDUAL_MESH && t.vec == 1);
     const bool one = one_per_lane_op(op);
     const bool vec_ok = one ? t.vec == 1 : (t.vec == 1 || t.vec == 2 || t.vec == 4);
@@ -310,6 +319,15 @@ fem_status fem_set_tuning(int op, int dim, int physics, int rule, int dtype, con
     }
     if (t->strategy == FEM_STRATEGY_MFMA && !mfma_available(op, dim, physics)) {
         set_error("fem_set_tuning: the matrix-core strategy covers P3 tetrahedra with the Laplacian or elasticity");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (t->strategy == FEM_STRATEGY_COMPONENT && !component_available(op, dim, physics)) {
+        set_error("fem_set_tuning: the component-parallel strategy covers P3 tetrahedra with elasticity");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (t->strategy == FEM_STRATEGY_COMPONENT && t->waves_per_block > comp_max_groups(dtype)) {
+        set_error("fem_set_tuning: the component-parallel strategy runs at most %d three-wave group(s) per workgroup "
+                  "for this dtype", comp_max_groups(dtype));
         return FEM_ERR_UNSUPPORTED;
     }
     put_tuning(op, dim, physics, rule, dtype, *t);
@@ -471,6 +489,13 @@ fem_status fem_integrate_residual_p3(int dim, int physics, int rule, int coef_sp
         // one wave per 16 elements
         Launch l = make_launch(t, (n_elem + 15) / 16 * 64, 1, static_cast<hipStream_t>(stream));
         e = launch_residual_p3_mfma(physics, coef_space, dtype, a, l);
+    } else if (t.strategy == FEM_STRATEGY_COMPONENT && component_available(FEM_OP_RESIDUAL_P3, dim, physics)) {
+        // three waves per 64-element tile; waves_per_block counts the
+        // three-wave groups of a workgroup
+        fem_tuning tg = t;
+        tg.waves_per_block = 3 * t.waves_per_block;
+        Launch l = make_launch(tg, (n_elem + 63) / 64 * 192, 1, static_cast<hipStream_t>(stream));
+        e = launch_residual_p3_comp(coef_space, dtype, a, l);
     } else {
         Launch l = make_launch(t, n_elem, 1, static_cast<hipStream_t>(stream));
         e = launch_residual_p3(dim, physics, coef_space, dtype, a, l);
@@ -549,6 +574,20 @@ fem_status fem_stream_copy(const void* src, void* dst, int64_t n_bytes, void* st
     Launch l = make_launch(t, n_bytes / 16, 1, static_cast<hipStream_t>(stream));
     hipError_t e = launch_stream_copy(src, dst, n_bytes, l);
     return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_stream_copy launch");
+}
+
+fem_status fem_stream_rows(int dtype, int64_t n, int n_in, int n_out, const void* src, void* dst, void* stream) {
+    if (!valid_dtype(dtype)) { set_error("fem_stream_rows: unknown dtype %d", dtype); return FEM_ERR_UNSUPPORTED; }
+    if (n < 0 || n_in < 1 || n_in > FEM_STREAM_ROWS_MAX || n_out < 1 || n_out > FEM_STREAM_ROWS_MAX) {
+        set_error("fem_stream_rows: n must be >= 0 and the row counts in 1..%d", FEM_STREAM_ROWS_MAX);
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (n == 0) return FEM_OK;
+    if (!src || !dst) { set_error("fem_stream_rows: NULL pointer"); return FEM_ERR_INVALID_ARG; }
+    fem_tuning t{FEM_STRATEGY_LANE, 1, 4, 0};
+    Launch l = make_launch(t, n, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_stream_rows(dtype, n, n_in, n_out, src, dst, l);
+    return e == hipSuccess ? FEM_OK : hip_fail(e, "fem_stream_rows launch");
 }
 
 }  // extern "C"

@@ -82,6 +82,12 @@ hipError_t launch_residual_p3(int dim, int phys, int space, int dtype, const Res
 // matrix cores (residual_p3_mfma.hip); four lanes per element, a wave takes
 // 16 elements at a time.
 hipError_t launch_residual_p3_mfma(int phys, int space, int dtype, const ResidualArgs& a, const Launch& l);
+// P3 tetrahedral elasticity with one wave per displacement component
+// (residual_p3_comp.hip): three waves per 64-element tile, up to
+// comp_max_groups(dtype) such groups per workgroup (l.block 192 or 384).
+hipError_t launch_residual_p3_comp(int space, int dtype, const ResidualArgs& a, const Launch& l);
+int comp_max_groups(int dtype);
+size_t p3_comp_shared_bytes(int dtype, int groups);   // dynamic LDS of a workgroup
 hipError_t launch_backward_p3(int dim, int phys, int space, int dtype, const BackwardArgs& a, const Launch& l);
 hipError_t launch_jacobian_p3(int dim, int phys, int space, int dtype, const JacobianArgs& a, const Launch& l);
 // Second-order elements (residual_p2.hip); rules TRI3/TRI6 (2D), TET4/TET11 (3D).
@@ -98,6 +104,9 @@ hipError_t launch_geometry(int dim, int dtype, int64_t n_elem, int64_t n_vert, c
                            const int32_t* conn, void* inv_j, void* det_j, int32_t* counts,
                            const Launch& l);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t n_bytes, const Launch& l);
+// The structure-of-arrays streaming yardstick (stream_rows.hip).
+hipError_t launch_stream_rows(int dtype, int64_t n, int n_in, int n_out, const void* src, void* dst,
+                              const Launch& l);
 
 // Batched persistent kernel (batch.hip).
 struct BatchMesh {              // device-side descriptor, one per mesh

@@ -111,6 +111,47 @@ __device__ __forceinline__ void unroll_for(const F& f) {
     }
 }
 
+// The coefficient words of element e turned into values at the points: the
+// space is a uniform run-time branch (one kernel per dimension, physics and
+// type), the arithmetic after it is the same for every space. STREAM: the
+// loads bypass the caches' retention (each word is read once); kernels whose
+// tiles share cache lines read through the caches.
+template <int DIM, int PHYS, int RULE, typename Real, bool STREAM = true>
+__device__ __forceinline__ void p3_coef_points(int space, const Real* __restrict__ coef, int64_t n, int64_t e,
+                                               Real (&aq)[ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>::NCQ]) {
+    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
+    using Q = RuleP2<DIM, RULE>;
+    auto load = [](const Real* p) {
+        if constexpr (STREAM) return __builtin_nontemporal_load(p);
+        else return *p;
+    };
+    if (space == FEM_COEF_QUAD) {
+#pragma unroll
+        for (int f = 0; f < E::NCQ; ++f) aq[f] = load(coef + f * n + e);
+    } else if (space == FEM_COEF_P1) {
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            Real c[E::NV];
+#pragma unroll
+            for (int v = 0; v < E::NV; ++v) c[v] = load(coef + (m * E::NV + v) * n + e);
+#pragma unroll
+            for (int q = 0; q < E::NQ; ++q) {
+                Real t = Real(Q::lam(q, 0)) * c[0];
+#pragma unroll
+                for (int v = 1; v < E::NV; ++v) t = fmadd(Real(Q::lam(q, v)), c[v], t);
+                aq[m * E::NQ + q] = t;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E::NCOEF; ++m) {
+            const Real c = load(coef + m * n + e);
+#pragma unroll
+            for (int q = 0; q < E::NQ; ++q) aq[m * E::NQ + q] = c;
+        }
+    }
+}
+
 // Residual of one P3 element: r[b*NC + c], from invJ ij[k*DIM + i], det J,
 // closure u[b*NC + c] and the coefficient values at the points
 // aq[m*NQ + q].

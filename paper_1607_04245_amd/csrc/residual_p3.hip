@@ -13,41 +13,6 @@
 
 namespace femq {
 
-// The coefficient words of element e turned into values at the points: the
-// space is a uniform run-time branch (one kernel per dimension, physics and
-// type), the arithmetic after it is the same for every space.
-template <int DIM, int PHYS, int RULE, typename Real>
-__device__ __forceinline__ void p3_coef_points(int space, const Real* __restrict__ coef, int64_t n, int64_t e,
-                                               Real (&aq)[ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>::NCQ]) {
-    using E = ElemP3<DIM, PHYS, RULE, FEM_COEF_QUAD>;
-    using Q = RuleP2<DIM, RULE>;
-    if (space == FEM_COEF_QUAD) {
-#pragma unroll
-        for (int f = 0; f < E::NCQ; ++f) aq[f] = __builtin_nontemporal_load(coef + f * n + e);
-    } else if (space == FEM_COEF_P1) {
-#pragma unroll
-        for (int m = 0; m < E::NCOEF; ++m) {
-            Real c[E::NV];
-#pragma unroll
-            for (int v = 0; v < E::NV; ++v) c[v] = __builtin_nontemporal_load(coef + (m * E::NV + v) * n + e);
-#pragma unroll
-            for (int q = 0; q < E::NQ; ++q) {
-                Real t = Real(Q::lam(q, 0)) * c[0];
-#pragma unroll
-                for (int v = 1; v < E::NV; ++v) t = fmadd(Real(Q::lam(q, v)), c[v], t);
-                aq[m * E::NQ + q] = t;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < E::NCOEF; ++m) {
-            const Real c = __builtin_nontemporal_load(coef + m * n + e);
-#pragma unroll
-            for (int q = 0; q < E::NQ; ++q) aq[m * E::NQ + q] = c;
-        }
-    }
-}
-
 template <int DIM, int PHYS, typename Real>
 __global__ void __launch_bounds__(256)
 residual_p3_kernel(int64_t n, int space, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,

@@ -357,6 +357,9 @@ fem_status fem_autotune(int op, int dim, int physics, int rule, int dtype, int64
     if (op == FEM_OP_RESIDUAL_P3 && dim == 3 && physics != FEM_MASS)
         for (int w : {1, 2, 4})
             for (int b : {0, 2, 4, 8}) cands.push_back(fem_tuning{FEM_STRATEGY_MFMA, 1, w, b});
+    if (op == FEM_OP_RESIDUAL_P3 && dim == 3 && physics == FEM_ELASTICITY)
+        for (int w = 1; w <= comp_max_groups(dtype); ++w)   // three-wave groups per workgroup
+            for (int b : {0, 2, 4, 8}) cands.push_back(fem_tuning{FEM_STRATEGY_COMPONENT, 1, w, b});
 
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);

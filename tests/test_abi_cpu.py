@@ -132,8 +132,11 @@ def test_mfma_strategy_availability(lib):
     """The matrix-core strategy exists for the P3 residual of tetrahedra with
     the Laplacian or elasticity only; elsewhere fem_set_tuning refuses it."""
     P3, R11 = N.OP_RESIDUAL_P3, mg.RULE_TET11
-    saved = N.fem_tuning()
-    lib.fem_get_tuning(P3, 3, mg.ELASTICITY, R11, N.F32, ctypes.byref(saved))
+    saved = {}
+    for phys in (mg.LAPLACE, mg.ELASTICITY):
+        for dt in (N.F32, N.F64):
+            saved[phys, dt] = N.fem_tuning()
+            lib.fem_get_tuning(P3, 3, phys, R11, dt, ctypes.byref(saved[phys, dt]))
     t = N.fem_tuning(N.STRATEGY_MFMA, 1, 4, 0)
     for phys in (mg.LAPLACE, mg.ELASTICITY):
         for dt in (N.F32, N.F64):
@@ -143,9 +146,54 @@ def test_mfma_strategy_availability(lib):
     for op in (N.OP_RESIDUAL, N.OP_RESIDUAL_P2, N.OP_BACKWARD_P3, N.OP_JACOBIAN_P3):
         assert lib.fem_set_tuning(op, 3, mg.LAPLACE, R11 if op != N.OP_RESIDUAL else mg.RULE_TET4, N.F32,
                                   ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
-    for phys in (mg.LAPLACE, mg.ELASTICITY):
-        for dt in (N.F32, N.F64):
-            assert lib.fem_set_tuning(P3, 3, phys, R11, dt, ctypes.byref(saved)) == N.FEM_OK
+    for (phys, dt), t in saved.items():
+        assert lib.fem_set_tuning(P3, 3, phys, R11, dt, ctypes.byref(t)) == N.FEM_OK
+
+
+def test_stream_rows_validation(lib):
+    """fem_stream_rows checks its arguments before any HIP call."""
+    vp = ctypes.c_void_p(16)
+    assert lib.fem_stream_rows(7, 10, 1, 1, vp, vp, None) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_stream_rows(N.F32, -1, 1, 1, vp, vp, None) == N.FEM_ERR_INVALID_ARG
+    for n_in, n_out in ((0, 1), (1, 0), (257, 1), (1, 257)):
+        assert lib.fem_stream_rows(N.F32, 10, n_in, n_out, vp, vp, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_stream_rows(N.F64, 10, 2, 2, None, vp, None) == N.FEM_ERR_INVALID_ARG
+    assert lib.fem_stream_rows(N.F64, 0, 2, 2, None, None, None) == N.FEM_OK
+
+
+def test_component_strategy_availability(lib):
+    """The component-parallel strategy exists for the P3 residual of
+    tetrahedra with elasticity only (vec 1, one or two three-wave groups per
+    workgroup in FP32, one in FP64); elsewhere fem_set_tuning refuses it."""
+    P3, R11 = N.OP_RESIDUAL_P3, mg.RULE_TET11
+    saved = {dt: N.fem_tuning() for dt in (N.F32, N.F64)}
+    for dt in saved:
+        lib.fem_get_tuning(P3, 3, mg.ELASTICITY, R11, dt, ctypes.byref(saved[dt]))
+    # three-wave groups per workgroup: one or two in FP32, one in FP64
+    for dt, groups in ((N.F32, (1, 2)), (N.F64, (1,))):
+        for waves in groups:
+            t = N.fem_tuning(N.STRATEGY_COMPONENT, 1, waves, 0)
+            assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, dt, ctypes.byref(t)) == N.FEM_OK
+            back = N.fem_tuning()
+            lib.fem_get_tuning(P3, 3, mg.ELASTICITY, R11, dt, ctypes.byref(back))
+            assert (back.strategy, back.waves_per_block) == (N.STRATEGY_COMPONENT, waves)
+    t = N.fem_tuning(N.STRATEGY_COMPONENT, 1, 2, 0)
+    assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, N.F64, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    t = N.fem_tuning(N.STRATEGY_COMPONENT, 1, 4, 0)
+    assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    t = N.fem_tuning(N.STRATEGY_COMPONENT, 1, 8, 0)   # no P3 strategy takes eight waves
+    assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, N.F32, ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
+    t = N.fem_tuning(N.STRATEGY_COMPONENT, 1, 2, 0)
+    for phys in (mg.LAPLACE, mg.MASS):
+        assert lib.fem_set_tuning(P3, 3, phys, R11, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    assert lib.fem_set_tuning(P3, 2, mg.ELASTICITY, mg.RULE_TRI6, N.F32, ctypes.byref(t)) == N.FEM_ERR_UNSUPPORTED
+    for op in (N.OP_RESIDUAL, N.OP_RESIDUAL_P2, N.OP_BACKWARD_P3, N.OP_JACOBIAN_P3):
+        assert lib.fem_set_tuning(op, 3, mg.ELASTICITY, R11 if op != N.OP_RESIDUAL else mg.RULE_TET4, N.F32,
+                                  ctypes.byref(t)) == N.FEM_ERR_INVALID_ARG
+    wide = N.fem_tuning(N.STRATEGY_COMPONENT, 2, 2, 0)
+    assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, N.F32, ctypes.byref(wide)) == N.FEM_ERR_INVALID_ARG
+    for dt in saved:
+        assert lib.fem_set_tuning(P3, 3, mg.ELASTICITY, R11, dt, ctypes.byref(saved[dt])) == N.FEM_OK
 
 
 def test_batch_plan_validation(lib):
