@@ -640,13 +640,18 @@ def main():
                     # a copy of the same bytes: how much of the kernel's time the
                     # stream itself needs, whatever unit does the arithmetic
                     cp_gbs, cp_us = copy_gbs(int(nb // 2) // 16 * 16, 20)
+                    # and the same rows streamed without arithmetic
+                    r_in = sum(cps[0][key].numel() for key in ("ij", "dj", "u", "cf")) // wlx.n_elem
+                    r_out = cps[0]["u"].shape[0]
+                    rw_us = rows_us(wlx.n_elem, r_in, r_out, dt, 20)
                     extra[f"{wlx.name}_p2_{tag}_integrate"] = dict(
                         n_elem=wlx.n_elem, rule=rule_p2, us=us, gbs=nb / (us * 1e-6) / 1e9,
                         elements_per_s=wlx.n_elem / (us * 1e-6), model_gflops=wlx.n_elem * f / (us * 1e-6) / 1e9,
-                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us)
+                        bytes_per_elem=nb / wlx.n_elem, copy_same_bytes_us=cp_us, frac_of_copy_same_bytes=cp_us / us,
+                        stream_rows=[r_in, r_out], stream_rows_us=rw_us, frac_of_stream_rows=rw_us / us)
                     log(f"{wlx.name} P2 {tag} integrate: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
                         f"{nb / (us * 1e-6) / 1e9:.0f} GB/s, {wlx.n_elem * f / (us * 1e-6) / 1e12:.1f} model TF/s); "
-                        f"copy of the same bytes {cp_us:.1f} us")
+                        f"copy of the same bytes {cp_us:.1f} us, the same {r_in} + {r_out} rows streamed {rw_us:.1f} us")
                     del cps, ij, dj
                 del p2, wlx
 
