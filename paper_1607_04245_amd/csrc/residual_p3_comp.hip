@@ -150,21 +150,20 @@ residual_p3_comp_kernel(int64_t n, int space, const Real* __restrict__ inv_j, co
             // du_{c+2}/dx_{c+2} and du_{c+2}/dx_c from wave c + 2
             const Real d1 = sh.grad[q][c1][0][lane], o1 = sh.grad[q][c1][2][lane];
             const Real d2 = sh.grad[q][c2][0][lane], o2 = sh.grad[q][c2][1][lane];
-            const Real half = Real(0.5);
-            const Real lam_tr = aq[q] * ((G[0] + d1) + d2);
-            const Real two_mu = aq[NQ + q] + aq[NQ + q];
-            Real f[DIM];   // row c of f1, rotated axes
-            f[0] = fmadd(two_mu, half * (G[0] + G[0]), lam_tr);
-            f[1] = two_mu * (half * (G[1] + o1));
-            f[2] = two_mu * (half * (G[2] + o2));
+            // w_q |J| times row c of f1 in rotated axes: lambda tr delta_ci +
+            // mu (du_c/dx_i + du_i/dx_c), the weight folded into lambda and mu
             const Real sw = Real(Q::w(q)) * adj;
+            const Real lam = aq[q] * sw, mu = aq[NQ + q] * sw;
+            Real f[DIM];
+            f[0] = fmadd(mu + mu, G[0], lam * ((G[0] + d1) + d2));
+            f[1] = mu * (G[1] + o1);
+            f[2] = mu * (G[2] + o2);
             Real h[NV];   // g_v . (w_q |J| f1_c)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 Real s = g[v][0] * f[0];
                 s = fmadd(g[v][1], f[1], s);
-                s = fmadd(g[v][2], f[2], s);
-                h[v] = sw * s;
+                h[v] = fmadd(g[v][2], f[2], s);
             }
             unroll_for<0, NB>([&](auto b_c) {
                 constexpr int b = decltype(b_c)::value;
