@@ -33,6 +33,7 @@ def _result(n_extra):
                          "algorithmic_bytes_per_launch": 73699864.0, "achievable_gbs": 6428.0,
                          "frac_of_achievable": 0.68, "achievable_gbs_same_bytes": 5317.0},
                two_call_step={"elements_per_s": 3.0e10, "ms_per_step": 0.0349},
+               hot_step={"elements_per_s": 6.9e10, "ms_per_step": 0.0152, "note": "information only"},
                cpu_baseline={"value": 8.7e7, "unit": "elements/s", "cores": 16, "kind": "oracle",
                              "sample": "all elements of the step workload on 16 threads",
                              "single_thread": {"value": 6.6e6}})
