@@ -1,7 +1,8 @@
 """GPU check of the structure-of-arrays streaming yardstick
 (fem_stream_rows): every output word is its column's row sum plus the row
-index, for row counts below, at and above the 16-row load chunk, single
-columns, ragged column counts and both word sizes. Integer-valued inputs
+index, for row counts below, at and above the 16-row load chunk, past one
+128-row chunk and at the 256-row limit, single columns, ragged column counts
+and both word sizes. Integer-valued inputs
 keep every sum exact, so the comparison is bitwise."""
 import pytest
 import torch
@@ -12,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("n_in,n_out", [(1, 1), (15, 3), (16, 1), (17, 20), (92, 60)])
+@pytest.mark.parametrize("n_in,n_out", [(1, 1), (15, 3), (16, 1), (17, 20), (92, 60), (200, 2), (256, 256)])
 @pytest.mark.parametrize("n", [1, 63, 4099])
 def test_stream_rows_values(dtype, n_in, n_out, n):
     g = torch.Generator().manual_seed(1000 * n_in + n)
