@@ -8,10 +8,13 @@ soname), which lets the library run on torch's streams and memory.
 from __future__ import annotations
 
 import ctypes
+import os
 import pathlib
 import re
 
-LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfemq.so"
+# FEMQ_LIB names another build of the same library (the host-sanitized build
+# that the sanitizer test loads); unset, the in-tree library is used.
+LIB_PATH = pathlib.Path(os.environ.get("FEMQ_LIB") or pathlib.Path(__file__).resolve().parent / "libfemq.so")
 HEADER = pathlib.Path(__file__).resolve().parents[1] / "include" / "fem.h"
 
 FEM_OK = 0
