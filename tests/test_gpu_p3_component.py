@@ -155,3 +155,42 @@ def test_default_is_the_component_split():
         assert api.fem_get_tuning(3, EL, R11, dt, op=N.OP_RESIDUAL_P3)["strategy"] == N.STRATEGY_COMPONENT
         assert api.fem_get_tuning(3, mg.LAPLACE, R11, dt, op=N.OP_RESIDUAL_P3)["strategy"] == N.STRATEGY_LANE
         assert api.fem_get_tuning(3, EL, R11, dt, op=N.OP_BACKWARD_P3)["strategy"] == N.STRATEGY_LANE
+
+
+def test_component_under_graph_capture():
+    """The component split (dynamic LDS, workgroup barriers) captured in a
+    HIP graph through torch, beside the P3 lane kernel and the rows
+    yardstick: every replay, with eager work between, equals the eager
+    results."""
+    dtype = torch.float32
+    wl, p3 = workload(20000, seed=197)
+    ij, dj = api.fem_geometry(dev(wl.coords, torch.float64), dev(wl.conn, torch.int32), dtype)
+    u, c = dev(p3.u, dtype), dev(p3.coef, dtype)
+    R1, R2 = torch.empty_like(u), torch.empty_like(u)
+    src, dst = u[:17].contiguous(), torch.empty((5, wl.n_elem), dtype=dtype, device="cuda")
+
+    def work():
+        set_strategy(dtype, N.STRATEGY_COMPONENT, 2, 2)
+        api.fem_integrate_residual_p3(3, EL, R11, ij, dj, u, c, out=R1)
+        set_strategy(dtype, N.STRATEGY_LANE, 1, 0)
+        api.fem_integrate_residual_p3(3, EL, R11, ij, dj, u, c, out=R2)
+        api.fem_stream_rows(src, dst)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        work()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in (R1, R2, dst)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    for rep in range(3):
+        for t in (R1, R2, dst):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((R1, R2, dst), eager):
+            assert torch.equal(a, b), f"graph replay {rep} differs"
