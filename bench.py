@@ -16,6 +16,10 @@ The timed region is one replay of a HIP graph holding the `--steps` steps
 (captured with torch's graph capture on the stream the library launches on),
 bracketed by one pair of HIP events; launching through Python one call at a
 time would otherwise cost more host time than a step takes on the GPU.
+Before it come the `--warmup` steps and then replays of the same graph until
+the GPU has been busy for 0.1 s, so that the timed steps run at the clocks of
+a loaded GPU (the first milliseconds after the host work between sections
+run slower); every section is timed this way.
 
 Prints ONE compact JSON line, last on stdout and below 4 KB (a few progress
 lines go to stderr; --verbose prints one per section). `value` is elements
@@ -51,6 +55,7 @@ HBM_PEAK_GBS = 8000.0
 ROTATE_BYTES = 600e6  # rotate through input copies totalling at least this much
 MIN_COPIES = 8       # and through at least this many copies
 MAX_LINE = 4000      # the JSON line on stdout stays below this many bytes
+PREHEAT_S = 0.1      # each timed section first keeps the GPU busy this long (untimed)
 
 
 VERBOSE = False
@@ -66,7 +71,7 @@ def log(msg, always=False):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--quick", action="store_true", help="main step only (no extra sections, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -199,11 +204,20 @@ def main():
 
     def timed_graph(fn, cs, steps, warmup):
         """The timed region: one replay of a graph of `steps` steps, bracketed
-        by a pair of events; returns (wall seconds, event ms per step)."""
+        by a pair of events; returns (wall seconds, event ms per step). Before
+        it, the warm-up steps and then more replays until the GPU has run the
+        section for PREHEAT_S: after the host work between sections the GPU
+        has idled, and its first milliseconds of work run at lower clocks
+        (the step measured 17.5-18.3 us per launch after 5 warm-up steps,
+        15.9 us after 3000)."""
         g = graph_of(fn, cs, steps)
         for _ in range(max(1, warmup // steps + 1)):
             g.replay()
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < PREHEAT_S:
+            g.replay()
+            torch.cuda.synchronize()
         t = time.perf_counter()
         s = ev()
         g.replay()
