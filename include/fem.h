@@ -132,8 +132,8 @@ enum fem_strategy { FEM_STRATEGY_LANE = 0, FEM_STRATEGY_TRANSPOSE = 1, FEM_STRAT
  *                          transposition, split by component).
  *                          waves_per_block counts three-wave groups (1 or 2
  *                          in FP32, 1 in FP64; FEM_ERR_UNSUPPORTED beyond).
- *                          The default for that case. Agrees with the lane
- *                          kernel to rounding (another summation order). */
+ *                          Agrees with the lane kernel to rounding (another
+ *                          summation order). */
 
 /* Operations; each has its own launch configuration (see fem_tuning). */
 enum fem_op {

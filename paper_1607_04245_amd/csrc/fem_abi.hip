@@ -159,10 +159,8 @@ static fem_tuning default_tuning(int op, int dim, int phys, int rule, int dtype)
     }
     // P3: the 3D elements hold 20-60 closure and output words per lane, and
     // single-wave workgroups measured fastest there; 2D streams better with
-    // four. 3D elasticity splits its elements over three waves by component
-    // (measured 2-4 % faster than the lane kernel in FP64; in FP32 level by
-    // kernel duration and mostly faster per launch including dispatch).
-    if (op == FEM_OP_RESIDUAL_P3 && dim == 3 && phys == FEM_ELASTICITY) return fem_tuning{FEM_STRATEGY_COMPONENT, 1, 1, 0};
+    // four. (The component split of 3D elasticity measured 5-10 % slower than
+    // the lane kernel with both timed on a warmed-up GPU.)
     if (op == FEM_OP_RESIDUAL_P3 || op == FEM_OP_BACKWARD_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, dim == 3 ? 1 : 4, 0};
     if (op == FEM_OP_JACOBIAN_P3) return fem_tuning{FEM_STRATEGY_LANE, 1, 4, 0};
     if (one_per_lane_op(op)) return fem_tuning{FEM_STRATEGY_LANE, 1, 2, 0};

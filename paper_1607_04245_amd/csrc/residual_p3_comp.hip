@@ -32,8 +32,11 @@
 // Results agree with the lane kernel to rounding (the trace and the dot
 // products g_v . f1_c are summed in rotated order, and the quadrature weight
 // scales lambda and mu instead of the flux). Measured against the lane
-// kernel: level in FP32, where both are bound by the vector arithmetic, and
-// a few per cent faster in FP64.
+// kernel with both timed on a warmed-up GPU it is 5-10 % slower: in FP32
+// both are bound by the vector arithmetic, of which the split issues about
+// 5 % more, and in FP64 three groups per CU (the LDS bound) keep fewer bytes
+// in flight than the lane kernel's single wave per SIMD with all its
+// element's loads issued at once.
 #include "fem_internal.hpp"
 #include "p3_device.hpp"
 

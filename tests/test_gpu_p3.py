@@ -73,12 +73,12 @@ def test_p3_forward_matches_oracle(dim, phys, dtype, space):
     R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, dev(p3.u, dtype), dev(cf, dtype), coef_space=space)
     ref, ref_abs = reference(wl, p3.u, cf, space, dtype)
     assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"P3 {dim}D phys {phys} space {space}")
-    if (dim, phys) == (3, mg.ELASTICITY):   # the default there is the component split: the lane kernel too
-        api.fem_set_tuning(dim, phys, RULE[dim], dtype, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_LANE, vec=1,
+    if (dim, phys) == (3, mg.ELASTICITY):   # the component split too
+        api.fem_set_tuning(dim, phys, RULE[dim], dtype, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_COMPONENT, vec=1,
                            waves_per_block=1, blocks_per_cu=0)
         R = api.fem_integrate_residual_p3(dim, phys, RULE[dim], ij, dj, dev(p3.u, dtype), dev(cf, dtype),
                                           coef_space=space)
-        assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"P3 lane {dim}D phys {phys} space {space}")
+        assert_close(R.cpu().numpy(), ref, ref_abs, dtype, f"P3 component {dim}D phys {phys} space {space}")
 
 
 @pytest.mark.parametrize("dim,phys", KINDS)
@@ -110,8 +110,8 @@ def test_p3_backward_matches_oracle(dim, phys, dtype, space):
                                                                     space=space, order=3), axis=0)
     assert_close(dc.cpu().numpy().reshape(nco * nw, n), rdc.reshape(nco * nw, n), dc_abs.reshape(nco * nw, n),
                  dtype, "dcoef")
-    # the lane kernel's arithmetic (3D elasticity runs the component split
-    # by default, which sums in another order)
+    # the lane kernel's arithmetic (the component split of 3D elasticity
+    # sums in another order), whatever the tuning
     api.fem_set_tuning(dim, phys, rule, dtype, op=N.OP_RESIDUAL_P3, strategy=N.STRATEGY_LANE, vec=1,
                        waves_per_block=1 if dim == 3 else 4, blocks_per_cu=0)
     R_w = api.fem_integrate_residual_p3(dim, phys, rule, ij, dj, dev(w, dtype), dev(cf, dtype), coef_space=space)
