@@ -302,6 +302,17 @@ def main():
     int_rows = (dim * dim + 1 + nbt + api.n_coef(phys) * api.n_coef_words(dim, rule), nbt)
     kernels["fem_integrate_residual"]["stream_rows"] = list(int_rows)
     kernels["fem_integrate_residual"]["stream_rows_us"] = rows_us(n, int_rows[0], int_rows[1], torch.float32, 20)
+    # the geometry kernel's bytes as rows: connectivity (dim + 1 words) and
+    # the FP64 coordinates spread over the elements in; det J and J^{-1} out
+    coord_words = max(1, round(8 * dim * wl.n_vert / (4 * n)))
+    geo_rows = (dim + 1 + coord_words, dim * dim + 1)
+    kernels["fem_geometry"]["stream_rows"] = list(geo_rows)
+    kernels["fem_geometry"]["stream_rows_us"] = rows_us(n, geo_rows[0], geo_rows[1], torch.float32, 20)
+    # and the fused kernel's: connectivity, coordinates, closure and
+    # coefficient rows in, element-vector rows out
+    mesh_rows = (dim + 1 + coord_words + nbt + api.n_coef(phys) * api.n_coef_words(dim, rule), nbt)
+    roofline["same_rows_us"] = rows_us(n, mesh_rows[0], mesh_rows[1], torch.float32, 20)
+    roofline["frac_of_rows"] = roofline["same_rows_us"] / dk["avg_us"]
 
     result = {
         "metric": METRIC,
@@ -992,6 +1003,9 @@ def compact(res):
                         "kernel_us": _r(k[rf["kernel"]]["avg_us"]), "achievable_gbs": _r(rf.get("achievable_gbs")),
                         "frac_of_achievable": _r(rf.get("frac_of_achievable")),
                         "copy_same_bytes_gbs": _r(rf.get("achievable_gbs_same_bytes"))}
+    if "same_rows_us" in rf:
+        line["roofline"]["same_rows_us"] = _r(rf["same_rows_us"])
+        line["roofline"]["frac_of_rows"] = _r(rf["frac_of_rows"])
     ki = k["fem_integrate_residual"]
     line["integrate_only"] = {"kernel": "fem_integrate_residual", "us": _r(ki["avg_us"]),
                               "elements_per_s": _r(ki["elements_per_s"]), "gbs": _r(ki["gbs"]),
@@ -1002,6 +1016,9 @@ def compact(res):
         line["integrate_only"]["frac_of_rows"] = _r(ki["stream_rows_us"] / ki["avg_us"])
     kg = k["fem_geometry"]
     line["geometry_only"] = {"us": _r(kg["avg_us"]), "gbs": _r(kg["gbs"]), "frac": _r(kg["gbs"] / HBM_PEAK_GBS)}
+    if "stream_rows_us" in kg:
+        line["geometry_only"]["rows_us"] = _r(kg["stream_rows_us"])
+        line["geometry_only"]["frac_of_rows"] = _r(kg["stream_rows_us"] / kg["avg_us"])
     line["two_call_step"] = {"elements_per_s": _r(res["two_call_step"]["elements_per_s"]),
                              "ms_per_step": _r(res["two_call_step"]["ms_per_step"])}
     if "hot_step" in res:
