@@ -492,7 +492,7 @@ def main():
                         best = ((waves, bpc), r)
                 return best
 
-            shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 8)]
+            shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 2, 4, 8)]
             for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
                 saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
                 lane = integrate_only(wlx, torch.float32)

@@ -20,6 +20,8 @@
 //                  reference coordinates -> flux tile
 //   basis          item (e, b, c): sums over q in order -> output tile
 //   store phase    lane = element, one coalesced word per SoA row
+// The next tile's rows are requested before the current tile's LDS phases,
+// so a wave waits for memory only when it runs ahead of the stream.
 // Per-element strides of the flux and output tiles are odd, so the lanes of
 // a half-wave hit distinct LDS banks. The slab size per workgroup is checked
 // against the device's LDS per workgroup.
@@ -58,13 +60,40 @@ struct TTLayout {
     static constexpr int OFF_IJ = 0, OFF_S = N_IJ, OFF_G = OFF_S + 1, OFF_U = OFF_G + N_GRAD,
                          OFF_CF = OFF_U + N_U;
     static constexpr int IN_ROWS = OFF_CF + E::NCQ;
-    static constexpr int NFX = (P::HAS_F1 ? DIM : 0) + (P::HAS_F0 ? 1 : 0);  // per (q, c)
+    // per (q, c): the pulled-back flux (DIM words) and their sum, then the
+    // weighted f0
+    static constexpr int NFX = (P::HAS_F1 ? DIM + 1 : 0) + (P::HAS_F0 ? 1 : 0);
     static constexpr int FX_WORDS = E::NQ * E::NC * NFX;
     static constexpr int FX_STRIDE = FX_WORDS | 1;                  // per element, odd
     static constexpr int OUT_STRIDE = E::NBT | 1;                   // per element, odd
     static constexpr int WAVE_WORDS = IN_ROWS * TILE + FX_STRIDE * TILE;
     static_assert(OUT_STRIDE <= IN_ROWS, "the output tile reuses the staged words");
 };
+
+// The per-element words of one tile: what the load phase reads.
+template <int DIM, int PHYS, int RULE, typename Real>
+struct TTStage {
+    using E = Elem<DIM, PHYS, RULE>;
+    Real ij[E::NG], dj, uu[E::NBT], cf[E::NCQ];
+};
+
+// Requests the words of element e without a condition: an index past the end
+// is clamped to the last element (n >= 1), whose data then fills the unused
+// slots of the tail tile and is never stored.
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void tt_load(TTStage<DIM, PHYS, RULE, Real>& st, int64_t e, int64_t n,
+                                        const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
+                                        const Real* __restrict__ u, const Real* __restrict__ coef) {
+    using E = Elem<DIM, PHYS, RULE>;
+    const int64_t ec = e < n ? e : n - 1;
+#pragma unroll
+    for (int f = 0; f < E::NG; ++f) st.ij[f] = __builtin_nontemporal_load(inv_j + f * n + ec);
+    st.dj = __builtin_nontemporal_load(det_j + ec);
+#pragma unroll
+    for (int f = 0; f < E::NBT; ++f) st.uu[f] = __builtin_nontemporal_load(u + f * n + ec);
+#pragma unroll
+    for (int f = 0; f < E::NCQ; ++f) st.cf[f] = __builtin_nontemporal_load(coef + f * n + ec);
+}
 
 template <int DIM, int PHYS, int RULE, typename Real>
 __global__ void __launch_bounds__(512)
@@ -84,25 +113,28 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
     Real* out_s = in_s;  // the staged words are dead after the quadrature phase
 
     const int64_t n_tiles = (n + T - 1) / T;
-    for (int64_t tile = (int64_t)blockIdx.x * waves + wave; tile < n_tiles; tile += (int64_t)gridDim.x * waves) {
+    const int64_t step = (int64_t)gridDim.x * waves;
+    int64_t tile = (int64_t)blockIdx.x * waves + wave;
+    // software pipeline: the next tile's words are in flight while this tile
+    // goes through its LDS phases
+    TTStage<DIM, PHYS, RULE, Real> nxt;
+    if (tile < n_tiles) tt_load<DIM, PHYS, RULE, Real>(nxt, tile * T + lane, n, inv_j, det_j, u, coef);
+    for (; tile < n_tiles; tile += step) {
         const int64_t e0 = tile * T;
         const int64_t e = e0 + lane;
         const bool valid = e < n;
+        const TTStage<DIM, PHYS, RULE, Real> cur = nxt;
+        if (tile + step < n_tiles)
+            tt_load<DIM, PHYS, RULE, Real>(nxt, (tile + step) * T + lane, n, inv_j, det_j, u, coef);
 
         // ---- load phase: coalesced rows; per-element shared quantities
         {
-            Real ij[E::NG], uu[E::NBT];
-#pragma unroll
-            for (int f = 0; f < E::NG; ++f) ij[f] = valid ? inv_j[f * n + e] : Real(0);
-            const Real dj = valid ? det_j[e] : Real(0);
-#pragma unroll
-            for (int f = 0; f < E::NBT; ++f) uu[f] = valid ? u[f * n + e] : Real(0);
-            in_s[L::OFF_S * T + lane] = Real(Q::W) * fabs(dj);
+            in_s[L::OFF_S * T + lane] = Real(Q::W) * fabs(cur.dj);
             if constexpr (P::HAS_F1) {
                 Real g[NC][DIM];
-                physical_gradient<DIM, NC>(ij, uu, g);
+                physical_gradient<DIM, NC>(cur.ij, cur.uu, g);
 #pragma unroll
-                for (int f = 0; f < E::NG; ++f) in_s[(L::OFF_IJ + f) * T + lane] = ij[f];
+                for (int f = 0; f < E::NG; ++f) in_s[(L::OFF_IJ + f) * T + lane] = cur.ij[f];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -110,10 +142,10 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
             }
             if constexpr (P::NEEDS_U) {
 #pragma unroll
-                for (int f = 0; f < E::NBT; ++f) in_s[(L::OFF_U + f) * T + lane] = uu[f];
+                for (int f = 0; f < E::NBT; ++f) in_s[(L::OFF_U + f) * T + lane] = cur.uu[f];
             }
 #pragma unroll
-            for (int f = 0; f < E::NCQ; ++f) in_s[(L::OFF_CF + f) * T + lane] = valid ? coef[f * n + e] : Real(0);
+            for (int f = 0; f < E::NCQ; ++f) in_s[(L::OFF_CF + f) * T + lane] = cur.cf[f];
         }
         wave_sync();
 
@@ -124,11 +156,18 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
             const int el = it / (NQ * NC);
             const int qc = it - el * (NQ * NC);
             const int q = qc / NC, c = qc - q * NC;
-            Real a[E::NCOEF], cfl[E::NCQ];
+            Real a[E::NCOEF];
+            if constexpr (E::SPACE == FEM_COEF_QUAD) {
+                // the item's own point: one staged word per coefficient
 #pragma unroll
-            for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
+                for (int m = 0; m < E::NCOEF; ++m) a[m] = in_s[(L::OFF_CF + m * E::NW + q) * T + el];
+            } else {
+                Real cfl[E::NCQ];
 #pragma unroll
-            for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
+                for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
+#pragma unroll
+                for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
+            }
             Real g[NC][DIM];
             if constexpr (P::HAS_F1) {
 #pragma unroll
@@ -156,13 +195,21 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
                 Real t[DIM];
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
+                Real fh[DIM];
 #pragma unroll
                 for (int kk = 0; kk < DIM; ++kk) {
-                    Real fh = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
+                    fh[kk] = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
 #pragma unroll
-                    for (int i = 1; i < DIM; ++i) fh = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh);
-                    fx[kk] = fh;
+                    for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh[kk]);
+                    fx[kk] = fh[kk];
                 }
+                // the vertex at the origin takes minus the sum (its reference
+                // gradient is -(1, ..., 1)): formed once here, not by every
+                // basis lane
+                Real sum = fh[0];
+#pragma unroll
+                for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
+                fx[DIM] = sum;
             }
             if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
         }
@@ -181,14 +228,12 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
             for (int q = 0; q < NQ; ++q) {
                 const Real* f = fx + (q * NC + c) * L::NFX;
                 if constexpr (P::HAS_F1) {
-                    if (b > 0) {
-                        r += f[b - 1];
-                    } else {
-                        Real sum = f[0];
-#pragma unroll
-                        for (int kk = 1; kk < DIM; ++kk) sum += f[kk];
-                        r -= sum;
-                    }
+                    // the pulled-back flux dotted with the reference gradient
+                    // of phi_b: entry b - 1, or minus the stored sum for the
+                    // vertex at the origin (one word per lane, no branch: b
+                    // differs between the lanes of a wave)
+                    const Real fb = f[b > 0 ? b - 1 : DIM];
+                    r = b > 0 ? r + fb : r - fb;
                 }
                 if constexpr (P::HAS_F0) r = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), f[L::NFX - 1], r);
             }
