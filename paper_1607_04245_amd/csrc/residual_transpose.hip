@@ -95,6 +95,117 @@ __device__ __forceinline__ void tt_load(TTStage<DIM, PHYS, RULE, Real>& st, int6
     for (int f = 0; f < E::NCQ; ++f) st.cf[f] = __builtin_nontemporal_load(coef + f * n + ec);
 }
 
+// Quadrature phase of one tile: item (element, point, component), e-major
+// over the tile. It reads only the staged words and writes only the flux
+// tile (restrict: the compiler may overlap one item's reads with another's
+// arithmetic and stores).
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Real* __restrict__ fx_s, int lane) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using P = Physics<PHYS>;
+    using Q = Rule<DIM, RULE>;
+    using L = TTLayout<DIM, PHYS, RULE>;
+    constexpr int T = L::TILE, NC = E::NC, NQ = E::NQ, NB = E::NB;
+#pragma unroll
+    for (int k = 0; k < NQ * NC; ++k) {
+        const int it = k * T + lane;
+        const int el = it / (NQ * NC);
+        const int qc = it - el * (NQ * NC);
+        const int q = qc / NC, c = qc - q * NC;
+        Real a[E::NCOEF];
+        if constexpr (E::SPACE == FEM_COEF_QUAD) {
+            // the item's own point: one staged word per coefficient
+#pragma unroll
+            for (int m = 0; m < E::NCOEF; ++m) a[m] = in_s[(L::OFF_CF + m * E::NW + q) * T + el];
+        } else {
+            Real cfl[E::NCQ];
+#pragma unroll
+            for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
+#pragma unroll
+            for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
+        }
+        Real g[NC][DIM];
+        if constexpr (P::HAS_F1) {
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) g[cc][i] = in_s[(L::OFF_G + cc * DIM + i) * T + el];
+        }
+        Real uq[NC];
+        if constexpr (P::NEEDS_U) {
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                // phi_b at point q: LA at vertex q, LB elsewhere
+                Real v = Real(0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    v = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), in_s[(L::OFF_U + b * NC + cc) * T + el], v);
+                uq[cc] = v;
+            }
+        }
+        Real f0[NC], f1[NC][DIM];
+        P::template point<DIM, Real>(uq, g, a, f0, f1);
+        const Real s = in_s[L::OFF_S * T + el];
+        Real* fx = fx_s + el * L::FX_STRIDE + qc * L::NFX;
+        if constexpr (P::HAS_F1) {
+            Real t[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
+            Real fh[DIM];
+#pragma unroll
+            for (int kk = 0; kk < DIM; ++kk) {
+                fh[kk] = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh[kk]);
+                fx[kk] = fh[kk];
+            }
+            // the vertex at the origin takes minus the sum (its reference
+            // gradient is -(1, ..., 1)): formed once here, not by every
+            // basis lane
+            Real sum = fh[0];
+#pragma unroll
+            for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
+            fx[DIM] = sum;
+        }
+        if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
+    }
+}
+
+// Basis phase of one tile: item (element, basis function, component), the
+// sum over the points in order. Reads only the flux tile, writes only the
+// output tile.
+template <int DIM, int PHYS, int RULE, typename Real>
+__device__ __forceinline__ void tt_basis(const Real* __restrict__ fx_s, Real* __restrict__ out_s, int lane) {
+    using E = Elem<DIM, PHYS, RULE>;
+    using P = Physics<PHYS>;
+    using Q = Rule<DIM, RULE>;
+    using L = TTLayout<DIM, PHYS, RULE>;
+    constexpr int T = L::TILE, NC = E::NC, NQ = E::NQ;
+#pragma unroll
+    for (int k = 0; k < E::NBT; ++k) {
+        const int it = k * T + lane;
+        const int el = it / E::NBT;
+        const int bc = it - el * E::NBT;
+        const int b = bc / NC, c = bc - b * NC;
+        const Real* fx = fx_s + el * L::FX_STRIDE;
+        Real r = Real(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const Real* f = fx + (q * NC + c) * L::NFX;
+            if constexpr (P::HAS_F1) {
+                // the pulled-back flux dotted with the reference gradient
+                // of phi_b: entry b - 1, or minus the stored sum for the
+                // vertex at the origin (one word per lane, no branch: b
+                // differs between the lanes of a wave)
+                const Real fb = f[b > 0 ? b - 1 : DIM];
+                r = b > 0 ? r + fb : r - fb;
+            }
+            if constexpr (P::HAS_F0) r = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), f[L::NFX - 1], r);
+        }
+        out_s[el * L::OUT_STRIDE + bc] = r;
+    }
+}
+
 template <int DIM, int PHYS, int RULE, typename Real>
 __global__ void __launch_bounds__(512)
 residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real* __restrict__ det_j,
@@ -103,7 +214,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
     using P = Physics<PHYS>;
     using Q = Rule<DIM, RULE>;
     using L = TTLayout<DIM, PHYS, RULE>;
-    constexpr int T = L::TILE, NC = E::NC, NQ = E::NQ, NB = E::NB;
+    constexpr int T = L::TILE, NC = E::NC;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -150,95 +261,11 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
         wave_sync();
 
         // ---- quadrature phase: one item per (element, point, component)
-#pragma unroll
-        for (int k = 0; k < NQ * NC; ++k) {
-            const int it = k * T + lane;
-            const int el = it / (NQ * NC);
-            const int qc = it - el * (NQ * NC);
-            const int q = qc / NC, c = qc - q * NC;
-            Real a[E::NCOEF];
-            if constexpr (E::SPACE == FEM_COEF_QUAD) {
-                // the item's own point: one staged word per coefficient
-#pragma unroll
-                for (int m = 0; m < E::NCOEF; ++m) a[m] = in_s[(L::OFF_CF + m * E::NW + q) * T + el];
-            } else {
-                Real cfl[E::NCQ];
-#pragma unroll
-                for (int f = 0; f < E::NCQ; ++f) cfl[f] = in_s[(L::OFF_CF + f) * T + el];
-#pragma unroll
-                for (int m = 0; m < E::NCOEF; ++m) a[m] = coef_at<DIM, PHYS, RULE, Real>(cfl, m, q);
-            }
-            Real g[NC][DIM];
-            if constexpr (P::HAS_F1) {
-#pragma unroll
-                for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-                    for (int i = 0; i < DIM; ++i) g[cc][i] = in_s[(L::OFF_G + cc * DIM + i) * T + el];
-            }
-            Real uq[NC];
-            if constexpr (P::NEEDS_U) {
-#pragma unroll
-                for (int cc = 0; cc < NC; ++cc) {
-                    // phi_b at point q: LA at vertex q, LB elsewhere
-                    Real v = Real(0);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        v = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), in_s[(L::OFF_U + b * NC + cc) * T + el], v);
-                    uq[cc] = v;
-                }
-            }
-            Real f0[NC], f1[NC][DIM];
-            P::template point<DIM, Real>(uq, g, a, f0, f1);
-            const Real s = in_s[L::OFF_S * T + el];
-            Real* fx = fx_s + el * L::FX_STRIDE + qc * L::NFX;
-            if constexpr (P::HAS_F1) {
-                Real t[DIM];
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
-                Real fh[DIM];
-#pragma unroll
-                for (int kk = 0; kk < DIM; ++kk) {
-                    fh[kk] = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
-#pragma unroll
-                    for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh[kk]);
-                    fx[kk] = fh[kk];
-                }
-                // the vertex at the origin takes minus the sum (its reference
-                // gradient is -(1, ..., 1)): formed once here, not by every
-                // basis lane
-                Real sum = fh[0];
-#pragma unroll
-                for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
-                fx[DIM] = sum;
-            }
-            if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
-        }
+        tt_quadrature<DIM, PHYS, RULE, Real>(in_s, fx_s, lane);
         wave_sync();
 
         // ---- basis phase: one item per (element, basis function, component)
-#pragma unroll
-        for (int k = 0; k < E::NBT; ++k) {
-            const int it = k * T + lane;
-            const int el = it / E::NBT;
-            const int bc = it - el * E::NBT;
-            const int b = bc / NC, c = bc - b * NC;
-            const Real* fx = fx_s + el * L::FX_STRIDE;
-            Real r = Real(0);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const Real* f = fx + (q * NC + c) * L::NFX;
-                if constexpr (P::HAS_F1) {
-                    // the pulled-back flux dotted with the reference gradient
-                    // of phi_b: entry b - 1, or minus the stored sum for the
-                    // vertex at the origin (one word per lane, no branch: b
-                    // differs between the lanes of a wave)
-                    const Real fb = f[b > 0 ? b - 1 : DIM];
-                    r = b > 0 ? r + fb : r - fb;
-                }
-                if constexpr (P::HAS_F0) r = fmadd(b == q ? Real(Q::LA) : Real(Q::LB), f[L::NFX - 1], r);
-            }
-            out_s[el * L::OUT_STRIDE + bc] = r;
-        }
+        tt_basis<DIM, PHYS, RULE, Real>(fx_s, out_s, lane);
         wave_sync();
 
         // ---- store phase: coalesced rows
