@@ -493,19 +493,24 @@ def main():
                 return best
 
             shapes = [(w, b) for w in (1, 2, 4, 8) for b in (0, 2, 4, 8)]
-            for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32")):
+            wle = mg.config("3b")   # 3D elasticity: the quad-permutation form covers scalar fields only
+            for wlx, tag in ((wl, "laplace3d_2p20_f32"), (wlq, "laplace2d_2p22_centroid_f32"),
+                             (wle, "elasticity3d_2p21_f32")):
                 saved = api.fem_get_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32)
                 lane = integrate_only(wlx, torch.float32)
                 tt = best_of(wlx, N.STRATEGY_TRANSPOSE, shapes)
-                sh = best_of(wlx, N.STRATEGY_SHUFFLE, shapes)
+                sh = best_of(wlx, N.STRATEGY_SHUFFLE, shapes) if wlx.physics != mg.ELASTICITY else None
                 api.fem_set_tuning(wlx.dim, wlx.physics, wlx.rule, torch.float32, **saved)
-                extra[f"strategies_{tag}"] = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=tt[1]["us"],
-                                                  transpose_gbs=tt[1]["gbs"], transpose_shape=tt[0],
-                                                  shuffle_us=sh[1]["us"], shuffle_gbs=sh[1]["gbs"], shuffle_shape=sh[0])
-                log(f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition through "
-                    f"LDS {tt[1]['us']:.1f} us ({tt[1]['gbs']:.0f} GB/s, shape {tt[0]}), through quad permutations "
-                    f"{sh[1]['us']:.1f} us ({sh[1]['gbs']:.0f} GB/s, shape {sh[0]})", always=True)
-            del wlq
+                rec = dict(lane_us=lane["us"], lane_gbs=lane["gbs"], transpose_us=tt[1]["us"],
+                           transpose_gbs=tt[1]["gbs"], transpose_shape=tt[0])
+                msg = (f"{tag}: lane kernel {lane['us']:.1f} us ({lane['gbs']:.0f} GB/s), thread transposition "
+                       f"through LDS {tt[1]['us']:.1f} us ({tt[1]['gbs']:.0f} GB/s, shape {tt[0]})")
+                if sh is not None:
+                    rec.update(shuffle_us=sh[1]["us"], shuffle_gbs=sh[1]["gbs"], shuffle_shape=sh[0])
+                    msg += f", through quad permutations {sh[1]['us']:.1f} us ({sh[1]['gbs']:.0f} GB/s, shape {sh[0]})"
+                extra[f"strategies_{tag}"] = rec
+                log(msg, always=True)
+            del wlq, wle
 
         # ------------------------------------------------------ gather form --
         # u per vertex (and a P1 coefficient per vertex), gathered in the kernel.
@@ -1050,7 +1055,7 @@ def compact(res):
                            "separate_in_one_graph_us": _r(b["separate_launches_in_a_graph_us"]),
                            "speedup_vs_separate": _r(b["speedup_vs_separate"])}
     tt = {k2[len("strategies_"):]: {"lane_us": _r(v["lane_us"]), "lds_us": _r(v["transpose_us"]),
-                                     "shuffle_us": _r(v.get("shuffle_us"))}
+                                     **({"shuffle_us": _r(v["shuffle_us"])} if "shuffle_us" in v else {})}
           for k2, v in ex.items() if k2.startswith("strategies_")}
     p3 = {}
     for key, v in ex.items():

@@ -1,7 +1,7 @@
 // residual_transpose.hip -- element residuals with the paper's thread
 // transposition (Section 3, Fig. 1 and 3): the quadrature phase runs one lane
-// per (element, quadrature point, component), the basis phase one lane per
-// (element, basis function, component), and the weighted, pulled-back f0/f1
+// per (element, quadrature point), the basis phase one lane per (element,
+// basis function, component), and the weighted, pulled-back f0/f1
 // values pass from the first phase to the second, so every output sum is
 // formed by a single lane in a fixed order and no reduction is needed.
 //
@@ -15,8 +15,9 @@
 //                  forms what every point of its element shares (the
 //                  physical gradient of u, the weighted measure w |det J|)
 //                  and stages it with J^{-1} and the coefficient words
-//   quadrature     item (e, q, c), e-major over the tile: f0/f1 at point q
-//                  from the staged words, weighted and pulled back to
+//   quadrature     item (e, q), e-major over the tile: f0/f1 at point q
+//                  from the staged words (every component: the stress of
+//                  elasticity couples them), weighted and pulled back to
 //                  reference coordinates -> flux tile
 //   basis          item (e, b, c): sums over q in order -> output tile
 //   store phase    lane = element, one coalesced word per SoA row
@@ -95,8 +96,9 @@ __device__ __forceinline__ void tt_load(TTStage<DIM, PHYS, RULE, Real>& st, int6
     for (int f = 0; f < E::NCQ; ++f) st.cf[f] = __builtin_nontemporal_load(coef + f * n + ec);
 }
 
-// Quadrature phase of one tile: item (element, point, component), e-major
-// over the tile. It reads only the staged words and writes only the flux
+// Quadrature phase of one tile: item (element, point), e-major over the
+// tile; the item evaluates f0/f1 at its point once and writes the record of
+// every component. It reads only the staged words and writes only the flux
 // tile (restrict: the compiler may overlap one item's reads with another's
 // arithmetic and stores).
 template <int DIM, int PHYS, int RULE, typename Real>
@@ -106,12 +108,14 @@ __device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Rea
     using Q = Rule<DIM, RULE>;
     using L = TTLayout<DIM, PHYS, RULE>;
     constexpr int T = L::TILE, NC = E::NC, NQ = E::NQ, NB = E::NB;
-#pragma unroll
-    for (int k = 0; k < NQ * NC; ++k) {
+    // scalar fields: every item unrolled (their LDS reads overlap); vector
+    // fields: one item at a time (an item holds the whole stress tensor)
+    constexpr int UNROLL = NC > 1 ? 1 : NQ;
+#pragma unroll UNROLL
+    for (int k = 0; k < NQ; ++k) {
         const int it = k * T + lane;
-        const int el = it / (NQ * NC);
-        const int qc = it - el * (NQ * NC);
-        const int q = qc / NC, c = qc - q * NC;
+        const int el = it / NQ;
+        const int q = it - el * NQ;
         Real a[E::NCOEF];
         if constexpr (E::SPACE == FEM_COEF_QUAD) {
             // the item's own point: one staged word per coefficient
@@ -146,28 +150,36 @@ __device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Rea
         Real f0[NC], f1[NC][DIM];
         P::template point<DIM, Real>(uq, g, a, f0, f1);
         const Real s = in_s[L::OFF_S * T + el];
-        Real* fx = fx_s + el * L::FX_STRIDE + qc * L::NFX;
+        Real ij[P::HAS_F1 ? E::NG : 1];
         if constexpr (P::HAS_F1) {
-            Real t[DIM];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
-            Real fh[DIM];
-#pragma unroll
-            for (int kk = 0; kk < DIM; ++kk) {
-                fh[kk] = in_s[(L::OFF_IJ + kk * DIM) * T + el] * t[0];
-#pragma unroll
-                for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(in_s[(L::OFF_IJ + kk * DIM + i) * T + el], t[i], fh[kk]);
-                fx[kk] = fh[kk];
-            }
-            // the vertex at the origin takes minus the sum (its reference
-            // gradient is -(1, ..., 1)): formed once here, not by every
-            // basis lane
-            Real sum = fh[0];
-#pragma unroll
-            for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
-            fx[DIM] = sum;
+            for (int f = 0; f < E::NG; ++f) ij[f] = in_s[(L::OFF_IJ + f) * T + el];
         }
-        if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Real* fx = fx_s + el * L::FX_STRIDE + (q * NC + c) * L::NFX;
+            if constexpr (P::HAS_F1) {
+                Real t[DIM];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) t[i] = s * f1[c][i];
+                Real fh[DIM];
+#pragma unroll
+                for (int kk = 0; kk < DIM; ++kk) {
+                    fh[kk] = ij[kk * DIM] * t[0];
+#pragma unroll
+                    for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(ij[kk * DIM + i], t[i], fh[kk]);
+                    fx[kk] = fh[kk];
+                }
+                // the vertex at the origin takes minus the sum (its reference
+                // gradient is -(1, ..., 1)): formed once here, not by every
+                // basis lane
+                Real sum = fh[0];
+#pragma unroll
+                for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
+                fx[DIM] = sum;
+            }
+            if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
+        }
     }
 }
 
