@@ -64,9 +64,16 @@ struct TTLayout {
     // per (q, c): the pulled-back flux (DIM words) and their sum, then the
     // weighted f0
     static constexpr int NFX = (P::HAS_F1 ? DIM + 1 : 0) + (P::HAS_F0 ? 1 : 0);
-    static constexpr int FX_WORDS = E::NQ * E::NC * NFX;
-    static constexpr int FX_STRIDE = FX_WORDS | 1;                  // per element, odd
     static constexpr int OUT_STRIDE = E::NBT | 1;                   // per element, odd
+    // Vector fields on a four-point rule: the four point items of an element
+    // are the four lanes of a quad, which sum the pulled-back flux over the
+    // points by quad broadcasts (each lane the same sums, in point order) and
+    // write the element vector straight to the output tile; no flux tile,
+    // no basis phase. The output tile then takes the flux tile's place (the
+    // staged words are still being read while it is written).
+    static constexpr bool QUAD_SUM = E::NQ == 4 && E::NC > 1 && P::HAS_F1 && !P::HAS_F0;
+    static constexpr int FX_WORDS = E::NQ * E::NC * NFX;
+    static constexpr int FX_STRIDE = QUAD_SUM ? OUT_STRIDE : (FX_WORDS | 1);  // per element, odd
     static constexpr int WAVE_WORDS = IN_ROWS * TILE + FX_STRIDE * TILE;
     static_assert(OUT_STRIDE <= IN_ROWS, "the output tile reuses the staged words");
 };
@@ -157,7 +164,7 @@ __device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Rea
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            Real* fx = fx_s + el * L::FX_STRIDE + (q * NC + c) * L::NFX;
+            [[maybe_unused]] Real* fx = fx_s + el * L::FX_STRIDE + (q * NC + c) * L::NFX;
             if constexpr (P::HAS_F1) {
                 Real t[DIM];
 #pragma unroll
@@ -168,7 +175,7 @@ __device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Rea
                     fh[kk] = ij[kk * DIM] * t[0];
 #pragma unroll
                     for (int i = 1; i < DIM; ++i) fh[kk] = fmadd(ij[kk * DIM + i], t[i], fh[kk]);
-                    fx[kk] = fh[kk];
+                    if constexpr (!L::QUAD_SUM) fx[kk] = fh[kk];
                 }
                 // the vertex at the origin takes minus the sum (its reference
                 // gradient is -(1, ..., 1)): formed once here, not by every
@@ -176,7 +183,28 @@ __device__ __forceinline__ void tt_quadrature(const Real* __restrict__ in_s, Rea
                 Real sum = fh[0];
 #pragma unroll
                 for (int kk = 1; kk < DIM; ++kk) sum += fh[kk];
-                fx[DIM] = sum;
+                if constexpr (L::QUAD_SUM) {
+                    // R_{b,c} = sum over the points, in point order, of entry
+                    // b - 1 (b > 0) or minus the sum (b = 0): the basis
+                    // phase's arithmetic, on values gathered from the quad
+                    Real rb[DIM + 1];
+#pragma unroll
+                    for (int j = 0; j <= DIM; ++j) {
+                        Real v[4];
+                        quad_gather<4>(j < DIM ? fh[j] : sum, v);
+                        Real r = Real(0);
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) r = j < DIM ? r + v[qq] : r - v[qq];
+                        rb[j < DIM ? j + 1 : 0] = r;
+                    }
+                    // lane q of the quad stores basis function q
+                    Real mine = rb[0];
+#pragma unroll
+                    for (int b = 1; b <= DIM; ++b) mine = q == b ? rb[b] : mine;
+                    fx_s[el * L::OUT_STRIDE + q * NC + c] = mine;
+                } else {
+                    fx[DIM] = sum;
+                }
             }
             if constexpr (P::HAS_F0) fx[L::NFX - 1] = s * f0[c];
         }
@@ -233,7 +261,9 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
     const int waves = blockDim.x >> 6;
     Real* in_s = reinterpret_cast<Real*>(smem_raw) + (size_t)wave * L::WAVE_WORDS;
     Real* fx_s = in_s + L::IN_ROWS * T;
-    Real* out_s = in_s;  // the staged words are dead after the quadrature phase
+    // the staged words are dead after the quadrature phase, unless the
+    // quadrature phase writes the element vectors itself
+    Real* out_s = L::QUAD_SUM ? fx_s : in_s;
 
     const int64_t n_tiles = (n + T - 1) / T;
     const int64_t step = (int64_t)gridDim.x * waves;
@@ -277,8 +307,10 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
         wave_sync();
 
         // ---- basis phase: one item per (element, basis function, component)
-        tt_basis<DIM, PHYS, RULE, Real>(fx_s, out_s, lane);
-        wave_sync();
+        if constexpr (!L::QUAD_SUM) {
+            tt_basis<DIM, PHYS, RULE, Real>(fx_s, out_s, lane);
+            wave_sync();
+        }
 
         // ---- store phase: coalesced rows
         if (valid) {
