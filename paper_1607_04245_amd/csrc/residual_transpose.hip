@@ -302,7 +302,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
         }
         wave_sync();
 
-        // ---- quadrature phase: one item per (element, point, component)
+        // ---- quadrature phase: one item per (element, point)
         tt_quadrature<DIM, PHYS, RULE, Real>(in_s, fx_s, lane);
         wave_sync();
 
@@ -317,7 +317,7 @@ residual_transpose_kernel(int64_t n, const Real* __restrict__ inv_j, const Real*
 #pragma unroll
             for (int f = 0; f < E::NBT; ++f) out[f * n + e] = out_s[lane * L::OUT_STRIDE + f];
         }
-        wave_sync();  // the next tile's loads overwrite the slab
+        wave_sync();  // the next tile's staging overwrites the slab
     }
 }
 
