@@ -806,13 +806,19 @@ def main():
                                                    order=order)
                     _, ms = timed_graph(go, cps, 10, 1)
                     us = ms * 1e3
-                    extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
+                    rec = extra[f"{wlx.name}_jacobian_p{order}_{tag}"] = dict(
                         n_elem=wlx.n_elem, rule=rule_k, us=us, gbs=nb / (us * 1e-6) / 1e9,
                         elements_per_s=wlx.n_elem / (us * 1e-6), bytes_per_elem=nb / wlx.n_elem,
                         frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                    del cps
+                    # the same rows streamed (geometry and coefficient rows in,
+                    # one row per matrix entry out), where the yardstick takes them
+                    n_in = wlx.dim * wlx.dim + 1 + cf0.size // wlx.n_elem
+                    if nbt * nbt <= 256:
+                        rec["stream_rows_us"] = rows_us(wlx.n_elem, n_in, nbt * nbt, dt, 10)
+                        rec["frac_of_stream_rows"] = rec["stream_rows_us"] / us
                     log(f"{wlx.name} element matrices P{order} {tag}: {us:.1f} us ({wlx.n_elem / (us * 1e-6):.3e} elem/s, "
                         f"{nb / wlx.n_elem:.0f} B/elem, {nb / (us * 1e-6) / 1e9:.0f} GB/s)")
-                    del cps
                 del cf0, wlx
 
         # --------------------------------------------------------- assembly --
