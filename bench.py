@@ -765,18 +765,24 @@ def main():
                         + f"; copy of the same bytes {cp_us:.1f} us, the same {r_in} + {nbt} rows streamed "
                           f"{rw_us:.1f} us", always=wlx.dim == 3)
                     if wlx.dim == 3:
-                        # the adjoint (du and dcoef) on the same inputs, w = u
+                        # the adjoint (du and dcoef) on the same inputs, w a
+                        # separate copy of u (its own rows, as a caller's would be)
                         nbb = model.p3_backward_bytes(wlx.dim, wlx.physics, rule_p3, word) * wlx.n_elem
                         for c in cps:
                             c["dc"] = torch.empty_like(c["cf"])
+                            c["w"] = c["u"].clone()
 
                         def back(c, wlx=wlx, rule_p3=rule_p3):
                             api.fem_integrate_residual_p3_backward(wlx.dim, wlx.physics, rule_p3, c["ij"], c["dj"], c["u"],
-                                                                   c["cf"], c["u"], du=c["R"], dcoef=c["dc"])
+                                                                   c["cf"], c["w"], du=c["R"], dcoef=c["dc"])
                         _, msb = timed_graph(back, cps, 10, 1)
+                        ncq = c["cf"].numel() // wlx.n_elem
+                        rb_us = rows_us(wlx.n_elem, r_in + nbt, nbt + ncq, dt, 10)
                         extra[f"{wlx.name}_p3_{tag}_adjoint"] = dict(
-                            n_elem=wlx.n_elem, us=msb * 1e3, gbs=nbb / (msb * 1e-3) / 1e9, bytes_per_elem=nbb / wlx.n_elem)
-                        log(f"{wlx.name} P3 {tag} adjoint: {msb * 1e3:.1f} us ({nbb / (msb * 1e-3) / 1e9:.0f} GB/s)")
+                            n_elem=wlx.n_elem, us=msb * 1e3, gbs=nbb / (msb * 1e-3) / 1e9, bytes_per_elem=nbb / wlx.n_elem,
+                            stream_rows_us=rb_us, frac_of_stream_rows=rb_us / (msb * 1e3))
+                        log(f"{wlx.name} P3 {tag} adjoint: {msb * 1e3:.1f} us ({nbb / (msb * 1e-3) / 1e9:.0f} GB/s); "
+                            f"its rows streamed {rb_us:.1f} us")
                     del cps, ij, dj
                 del p3, wlx
 
@@ -904,11 +910,18 @@ def main():
                                                     du=c["du"], dcoef=c["dc"])
             _, ms = timed_graph(bwd, cps, 20, 1)
             us = ms * 1e3
-            extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
-                                                       elements_per_s=wl5.n_elem / (us * 1e-6),
-                                                       frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
-            log(f"adjoint: {us:.1f} us, {nb / (us * 1e-6) / 1e9:.0f} GB/s")
-            del cps, wl5
+            rec = extra["adjoint_laplace3d_2p21_f32"] = dict(n_elem=wl5.n_elem, us=us, gbs=nb / (us * 1e-6) / 1e9,
+                                                             elements_per_s=wl5.n_elem / (us * 1e-6),
+                                                             frac_of_peak=nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+            del cps
+            # its rows streamed: geometry, u, coefficient and w rows in; du and
+            # dcoef rows out
+            nbt5 = api.n_basis(3) * api.n_comp(3, mg.LAPLACE)
+            ncq5 = api.n_coef(mg.LAPLACE) * api.n_coef_words(3, wl5.rule)
+            rec["stream_rows_us"] = rows_us(wl5.n_elem, 10 + 2 * nbt5 + ncq5, nbt5 + ncq5, dt, 20)
+            rec["frac_of_stream_rows"] = rec["stream_rows_us"] / us
+            log(f"adjoint: {us:.1f} us, {nb / (us * 1e-6) / 1e9:.0f} GB/s; its rows streamed {rec['stream_rows_us']:.1f} us")
+            del wl5
 
         # --------------------------------------------------------- batched --
         if want("batched"):
@@ -1053,6 +1066,8 @@ def compact(res):
     if "adjoint_laplace3d_2p21_f32" in ex:
         a = ex["adjoint_laplace3d_2p21_f32"]
         line["adjoint"] = {"us": _r(a["us"]), "frac": _r(a["frac_of_peak"])}
+        if "frac_of_stream_rows" in a:
+            line["adjoint"]["frac_of_rows"] = _r(a["frac_of_stream_rows"])
     if "batched_64_meshes_f32" in ex:
         b = ex["batched_64_meshes_f32"]
         line["batched"] = {"graph_replay_us": _r(b["graph_replay_us"]),
