@@ -100,9 +100,10 @@ enum fem_coef_space { FEM_COEF_QUAD = 0, FEM_COEF_P1 = 1, FEM_COEF_P0 = 2 };
  *                          switch to one lane per (element, basis function)
  *                          for the basis phase, with no cross-lane reduction
  *                          (P1 only; for vector fields on four-point rules
- *                          the four point lanes of an element pass their
- *                          terms by quad permutations instead, lane b then
- *                          summing basis function b's terms in point order).
+ *                          the four point lanes of an element share their
+ *                          terms by quad permutations instead, form the sums
+ *                          over the points in point order, and lane b stores
+ *                          basis function b's).
  *  FEM_STRATEGY_MFMA       the same transposition for P3 tetrahedra (Laplacian,
  *                          elasticity; FEM_OP_RESIDUAL_P3 only) with the two
  *                          tabulation contractions on the matrix cores: four
