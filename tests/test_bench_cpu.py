@@ -73,6 +73,27 @@ def test_compact_line_contract(n_extra):
     assert line["n_gpus"] == 1 and line["higher_is_better"] is True and line["vs_baseline"] is None
 
 
+def test_compact_line_carries_the_yardsticks():
+    """The rows-streamed yardsticks (fused kernel, geometry, adjoint) and a
+    strategy section without the quad-permutation form reach the compact
+    line with their ratios; absent, they are left out."""
+    res = _result(0)
+    res["roofline"].update(same_rows_us=15.7, frac_of_rows=15.7 / 16.8)
+    res["kernels"]["fem_geometry"].update(stream_rows=[6, 10], stream_rows_us=14.5)
+    res["extra"]["adjoint_laplace3d_2p21_f32"].update(stream_rows_us=48.0, frac_of_stream_rows=48.0 / 46.9)
+    res["extra"]["strategies_elasticity3d_2p21_f32"] = dict(lane_us=62.4, transpose_us=67.7)
+    line = bench.compact(res)
+    assert line["roofline"]["same_rows_us"] == 15.7
+    assert line["roofline"]["frac_of_rows"] == pytest.approx(15.7 / 16.8, rel=1e-3)
+    assert line["geometry_only"]["frac_of_rows"] == pytest.approx(14.5 / 16.7, rel=1e-3)
+    assert line["adjoint"]["frac_of_rows"] == pytest.approx(48.0 / 46.9, rel=1e-3)
+    el = line["transposition"]["elasticity3d_2p21_f32"]
+    assert el == {"lane_us": 62.4, "lds_us": 67.7}
+    plain = bench.compact(_result(0))
+    assert "frac_of_rows" not in plain["roofline"] and "frac_of_rows" not in plain["geometry_only"]
+    assert "frac_of_rows" not in plain["adjoint"]
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
