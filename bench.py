@@ -366,8 +366,17 @@ def main():
                                       two_call_elements_per_s=n * steps64 / swall64,
                                       integrate_us=i64 * 1e3, integrate_gbs=b64 / (i64 * 1e-3) / 1e9,
                                       integrate_model_gflops=n * flops / (i64 * 1e-3) / 1e9, geometry_us=g64 * 1e3)
+            # both kernels' rows streamed, in 8-byte words (the 16-byte
+            # connectivity as two rows, the coordinates per element rounded)
+            ncq = api.n_coef(phys) * api.n_coef_words(dim, rule)
+            cw64 = max(1, round(8 * dim * wl.n_vert / (8 * n)))
+            f64r = rows_us(n, (dim + 1) * 4 // 8 + cw64 + nbt + ncq, nbt, torch.float64, 20)
+            i64r = rows_us(n, dim * dim + 1 + nbt + ncq, nbt, torch.float64, 20)
+            extra["fp64_step"].update(fused_rows_us=f64r, fused_frac_of_rows=f64r / (f64 * 1e3),
+                                      integrate_rows_us=i64r, integrate_frac_of_rows=i64r / (i64 * 1e3))
             log(f"FP64 fused step {extra['fp64_step']['ms_per_step'] * 1e3:.1f} us ({extra['fp64_step']['fused_gbs']:.0f}"
-                f" GB/s); integrate alone {i64 * 1e3:.1f} us ({extra['fp64_step']['integrate_gbs']:.0f} GB/s)")
+                f" GB/s; its rows streamed {f64r:.1f} us); integrate alone {i64 * 1e3:.1f} us "
+                f"({extra['fp64_step']['integrate_gbs']:.0f} GB/s; rows {i64r:.1f} us)")
 
         # --------------------------------------------------- other physics --
         def integrate_only(wlx, dt, reps=20, space=mg.COEF_QUAD, coef=None):
@@ -1054,6 +1063,9 @@ def compact(res):
         line["fp64"] = {"value": _r(f["elements_per_s"]), "ms_per_step": _r(f["ms_per_step"]),
                         "kernel_us": _r(f["fused_us"]), "frac": _r(f["fused_gbs"] / HBM_PEAK_GBS),
                         "integrate_us": _r(f["integrate_us"]), "integrate_frac": _r(f["integrate_gbs"] / HBM_PEAK_GBS)}
+        if "fused_frac_of_rows" in f:
+            line["fp64"]["frac_of_rows"] = _r(f["fused_frac_of_rows"])
+            line["fp64"]["integrate_frac_of_rows"] = _r(f["integrate_frac_of_rows"])
     el = {}
     for key, tag in (("elasticity2d_2p22_f32_integrate", "2d_f32"), ("elasticity3d_2p21_f32_integrate", "3d_f32"),
                      ("elasticity2d_2p22_f64_integrate", "2d_f64"), ("elasticity3d_2p21_f64_integrate", "3d_f64")):
